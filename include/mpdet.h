@@ -1,0 +1,125 @@
+/*
+ * mpdet.h -- C-ABI of libmpdet.so: multiprecision determinant, leading
+ * determinants and last-column minors on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Gaussian elimination without pivoting in multiprecision floating
+ * point (Beliakov & Matiyasevich, "A Parallel Algorithm for Calculation of
+ * Large Determinants with High Accuracy for GPUs and MPI clusters", Sec. 3 and
+ * Algorithm 1).  The determinant and every leading principal determinant are
+ * running products of the pivots (Algorithm 1 step 2.1; Sec. 3 "determinants
+ * of all submatrices in the top left corner"); the signed minors of the last
+ * column follow from the [A I] derivation of Sec. 3 (the last row of L times
+ * |A|), eq. (minorsdef).
+ *
+ * ---------------------------------------------------------------------------
+ * Number format (shared by every entry point)
+ *   value = (-1)^sign * m * 2^(exp - 32*nlimbs)
+ *   m: nlimbs little-endian uint32 limbs (limb 0 least significant), top bit
+ *      of limb nlimbs-1 set (2^(p-1) <= m < 2^p, p = 32*nlimbs);
+ *   exp: int64; sign: int32, 0 (+) or 1 (-).
+ *   Zero is canonical: m = 0, exp = 0, sign = 0.
+ * Every operation is the exact real result truncated toward zero to p bits
+ * (RZ_p).  A product is rounded before it is subtracted (two roundings per
+ * trailing update); a quotient is RZ_p of the exact quotient.
+ * The same mantissa bytes read as 4*nlimbs little-endian 8-bit limbs.
+ *
+ * Matrix layout in device memory (mpdet_mat), element-contiguous mantissas:
+ *   limbs[(i*ld + j)*nlimbs + q], exp[i*ld + j], sign[i*ld + j],
+ *   0 <= i < rows, 0 <= j < cols <= ld.  A vector is a 1 x n matrix.
+ * All pointers in mpdet_mat are device pointers owned by the caller; the
+ * library never frees them.  Exponents of inputs must satisfy |exp| <= 2^48.
+ *
+ * Return codes: every entry point returns MPDET_OK or a negative status for
+ * errors it can detect on the host (bad shapes or pointers, unsupported path,
+ * allocation or launch failure).  Calls are stream ordered and asynchronous.
+ * Numeric outcomes are written to a device int32 `info`, LAPACK getrf style:
+ *   0   success;
+ *   k>0 the pivot of step k (1-based) is exactly zero: D_k..D_n are written as
+ *       zero and the matrix holds the state after k-1 elimination steps;
+ *   -1  a pivot or a leading determinant has |exp| > 2^62: D_k..D_n are zero
+ *       and the matrix contents are unspecified.
+ * One handle per host thread; calls on one handle must not overlap in time on
+ * different streams (the handle's workspace is shared).
+ */
+#ifndef MPDET_H
+#define MPDET_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mpdet_handle mpdet_handle;
+
+typedef struct {
+    uint32_t *limbs; /* device: [rows][ld][nlimbs] */
+    int64_t *exp;    /* device: [rows][ld] */
+    int32_t *sign;   /* device: [rows][ld] */
+    int64_t rows, cols, ld;
+    int32_t nlimbs;
+} mpdet_mat;
+
+enum {
+    MPDET_OK = 0,
+    MPDET_EINVAL = -1,
+    MPDET_ENOMEM = -2,
+    MPDET_EHIP = -3,
+    MPDET_ENOTSUP = -4
+};
+
+enum {
+    MPDET_PATH_AUTO = 0, /* library chooses (MFMA when nlimbs allows it) */
+    MPDET_PATH_VALU = 1, /* 32x32->64-bit integer VALU limb products */
+    MPDET_PATH_MFMA = 2  /* exact INT8 MFMA Toeplitz contraction of 8-bit limbs */
+};
+
+/* Create a handle bound to HIP device `device`.  *h receives the handle. */
+int mpdet_create(mpdet_handle **h, int device);
+/* Release the handle and its workspace (synchronises the device first). */
+int mpdet_destroy(mpdet_handle *h);
+/* Human-readable name of a status code (static storage). */
+const char *mpdet_strerror(int status);
+
+/*
+ * mp_det_factor -- Gaussian elimination without pivoting, in place
+ * (Algorithm 1 steps 1-2.2.2; multipliers stored below the diagonal as in the
+ * Sec. 3 storage paragraph).
+ *   A     n x n (rows == cols == n, n >= 0), overwritten: U on and above the
+ *         diagonal, the multipliers l_ik = a_ik / a_kk below it.
+ *   D     1 x n (cols >= n), same nlimbs: D_k = RZ_p(D_{k-1} * u_kk), D_1 =
+ *         u_11; det(A) = D_n.
+ *   info  device int32, written as described above.
+ *   path  MPDET_PATH_*; MFMA requires nlimbs % 8 == 0 (else MPDET_ENOTSUP).
+ *   stream hipStream_t (NULL = default stream).
+ * nlimbs must be in [2, 1024].  Results are bit-identical for every path.
+ */
+int mp_det_factor(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev,
+                  int path, void *stream);
+
+/*
+ * mp_det_minors -- signed last-column cofactors c_i = (-1)^(i+n) M_{i,n}
+ * (eq. (minorsdef); Sec. 3 [A I] derivation), from mp_det_factor's output.
+ * With L the unit lower factor, x^T L = e_n^T is solved by sweeps j = n..2,
+ * s_i <- RZ(s_i - RZ(x_j l_ji)) for i < j (x_n = 1, x_{j-1} = s_{j-1}), then
+ * c_i = RZ(D_{n-1} x_i), c_n = D_{n-1} (n = 1: c_1 = 1).  sum_i c_i a_in = det.
+ *   LU    n x n factor output (read only);  D  1 x n from mp_det_factor;
+ *   c     1 x n output;  info_dev  the factorisation's info: when it is not 0,
+ *         c is written as all zeros.
+ */
+int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c,
+                  const int32_t *info_dev, void *stream);
+
+/*
+ * mp_to_f64 -- (mantissa, exponent) pairs: mant = (-1)^s * RZ_53(m / 2^p) in
+ * +-[0.5, 1) and exp_out = exp (zero -> 0.0, 0).  x is any rows x cols matrix;
+ * outputs are dense [rows][cols] device arrays.
+ */
+int mp_to_f64(mpdet_handle *h, mpdet_mat x, double *mant_dev, int64_t *exp_dev,
+              void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

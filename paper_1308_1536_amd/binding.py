@@ -1,0 +1,238 @@
+"""Thin ctypes binding over libmpdet.so (C-ABI in include/mpdet.h).
+
+Argument marshalling only: every arithmetic step runs in the library's HIP
+kernels.  PyTorch supplies device memory and the current HIP stream.  The
+library is loaded from this package directory; if it has not been built the
+first call raises (there is no CPU fallback).
+
+Device layout of a multiprecision array (``DeviceMp``): limbs int32 tensor
+[rows, ld, P] holding the uint32 limb bit patterns, exp int64 [rows, ld],
+sign int32 [rows, ld]; value = (-1)^sign * m * 2^(exp - 32P).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmpdet.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "mpdet.h")
+
+MPDET_OK, MPDET_EINVAL, MPDET_ENOMEM, MPDET_EHIP, MPDET_ENOTSUP = 0, -1, -2, -3, -4
+PATH_AUTO, PATH_VALU, PATH_MFMA = 0, 1, 2
+PATHS = {"auto": PATH_AUTO, "valu": PATH_VALU, "mfma": PATH_MFMA}
+
+
+class MpdetMat(ctypes.Structure):
+    _fields_ = [("limbs", ctypes.c_void_p), ("exp", ctypes.c_void_p), ("sign", ctypes.c_void_p),
+                ("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("ld", ctypes.c_int64),
+                ("nlimbs", ctypes.c_int32)]
+
+
+class MpdetError(RuntimeError):
+    def __init__(self, fn: str, status: int):
+        super().__init__(f"{fn} failed: {status} ({strerror(status)})")
+        self.status = status
+
+
+_lib = None
+
+
+def header_functions() -> list[str]:
+    """Names of the functions include/mpdet.h declares."""
+    with open(HEADER) as fh:
+        text = fh.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(\w+)\s*\(", text, flags=re.M)
+
+
+def lib() -> ctypes.CDLL:
+    """Load libmpdet.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1308_1536_amd.build` (no CPU fallback exists)")
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
+        L.mpdet_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]
+        L.mpdet_destroy.argtypes = [vp]
+        L.mpdet_strerror.argtypes = [ctypes.c_int]
+        L.mpdet_strerror.restype = ctypes.c_char_p
+        L.mp_det_factor.argtypes = [vp, MpdetMat, MpdetMat, vp, ctypes.c_int, vp]
+        L.mp_det_minors.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, vp, vp]
+        L.mp_to_f64.argtypes = [vp, MpdetMat, vp, vp, vp]
+        for name in ("mpdet_create", "mpdet_destroy", "mp_det_factor", "mp_det_minors", "mp_to_f64"):
+            getattr(L, name).restype = ctypes.c_int
+        if hasattr(L, "mp_det_batched"):
+            L.mp_det_batched.argtypes = [vp, i64, ctypes.POINTER(MpdetMat), ctypes.POINTER(MpdetMat),
+                                         ctypes.POINTER(MpdetMat), vp, ctypes.c_int, ctypes.c_int, vp]
+            L.mp_det_batched.restype = ctypes.c_int
+        if hasattr(L, "mp_det_adjugate"):
+            L.mp_det_adjugate.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, vp, vp]
+            L.mp_det_adjugate.restype = ctypes.c_int
+        _ = (i32,)
+        _lib = L
+    return _lib
+
+
+def strerror(status: int) -> str:
+    return lib().mpdet_strerror(int(status)).decode()
+
+
+def _check(fn: str, rc: int):
+    if rc != MPDET_OK:
+        raise MpdetError(fn, rc)
+
+
+def _stream(stream=None) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+class Handle:
+    """Owns an mpdet_handle bound to one device."""
+
+    def __init__(self, device: int = 0):
+        self.device = int(device)
+        h = ctypes.c_void_p()
+        _check("mpdet_create", lib().mpdet_create(ctypes.byref(h), self.device))
+        self.ptr = h
+
+    def close(self):
+        if self.ptr:
+            lib().mpdet_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):  # pragma: no cover - interpreter shutdown order varies
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+_handles: dict[int, Handle] = {}
+
+
+def handle(device: int = 0) -> Handle:
+    if device not in _handles:
+        _handles[device] = Handle(device)
+    return _handles[device]
+
+
+@dataclass
+class DeviceMp:
+    """Multiprecision array in device memory (see module docstring)."""
+    limbs: "object"  # torch.int32 [rows, ld, P]
+    exp: "object"    # torch.int64 [rows, ld]
+    sign: "object"   # torch.int32 [rows, ld]
+    rows: int
+    cols: int
+
+    @property
+    def P(self) -> int:
+        return int(self.limbs.shape[-1])
+
+    @property
+    def ld(self) -> int:
+        return int(self.limbs.shape[1])
+
+    def mat(self) -> MpdetMat:
+        return MpdetMat(self.limbs.data_ptr(), self.exp.data_ptr(), self.sign.data_ptr(),
+                        self.rows, self.cols, self.ld, self.P)
+
+    @staticmethod
+    def empty(rows: int, cols: int, P: int, device="cuda", ld: int | None = None) -> "DeviceMp":
+        import torch
+        ld = cols if ld is None else ld
+        return DeviceMp(torch.zeros((rows, ld, P), dtype=torch.int32, device=device),
+                        torch.zeros((rows, ld), dtype=torch.int64, device=device),
+                        torch.zeros((rows, ld), dtype=torch.int32, device=device), rows, cols)
+
+    @staticmethod
+    def from_host(x, device="cuda", ld: int | None = None) -> "DeviceMp":
+        """Upload any host container with .limbs [..., P] uint32, .exp, .sign.
+        A 1-D container becomes a 1 x n row vector."""
+        import torch
+        limbs = np.ascontiguousarray(x.limbs, dtype=np.uint32)
+        exp = np.ascontiguousarray(x.exp, dtype=np.int64)
+        sign = np.ascontiguousarray(x.sign, dtype=np.int32)
+        if exp.ndim == 1:
+            limbs, exp, sign = limbs[None], exp[None], sign[None]
+        rows, cols = exp.shape
+        P = limbs.shape[-1]
+        out = DeviceMp.empty(rows, cols, P, device, ld)
+        out.limbs[:, :cols].copy_(torch.from_numpy(limbs.view(np.int32)))
+        out.exp[:, :cols].copy_(torch.from_numpy(exp))
+        out.sign[:, :cols].copy_(torch.from_numpy(sign))
+        return out
+
+    def to_host(self):
+        """(limbs uint32 [rows, cols, P], exp int64 [rows, cols], sign int32 [rows, cols])."""
+        limbs = self.limbs[:, :self.cols].cpu().numpy().view(np.uint32)
+        return HostMp(limbs, self.exp[:, :self.cols].cpu().numpy(),
+                      self.sign[:, :self.cols].cpu().numpy())
+
+    def row(self, i: int = 0):
+        """Host copy of one row as a 1-D container (vectors: row 0)."""
+        h = self.to_host()
+        return HostMp(h.limbs[i], h.exp[i], h.sign[i])
+
+
+@dataclass
+class HostMp:
+    limbs: np.ndarray
+    exp: np.ndarray
+    sign: np.ndarray
+
+    @property
+    def P(self) -> int:
+        return int(self.limbs.shape[-1])
+
+
+def factor(A: DeviceMp, path: str = "auto", D: DeviceMp | None = None, info=None, stream=None):
+    """mp_det_factor in place on A.  Returns (D, info) device tensors."""
+    import torch
+    n = A.rows
+    if D is None:
+        D = DeviceMp.empty(1, n, A.P, A.limbs.device)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.limbs.device)
+    h = handle(A.limbs.device.index or 0)
+    _check("mp_det_factor", lib().mp_det_factor(h.ptr, A.mat(), D.mat(), info.data_ptr(), PATHS[path],
+                                                _stream(stream)))
+    return D, info
+
+
+def minors(LU: DeviceMp, D: DeviceMp, info, c: DeviceMp | None = None, stream=None) -> DeviceMp:
+    """mp_det_minors: signed last-column cofactors of the factored matrix."""
+    n = LU.rows
+    if c is None:
+        c = DeviceMp.empty(1, n, LU.P, LU.limbs.device)
+    h = handle(LU.limbs.device.index or 0)
+    _check("mp_det_minors", lib().mp_det_minors(h.ptr, LU.mat(), D.mat(), c.mat(), info.data_ptr(),
+                                                _stream(stream)))
+    return c
+
+
+def to_f64(x: DeviceMp, stream=None):
+    """mp_to_f64: (mantissa float64 [rows, cols], exponent int64 [rows, cols]) device tensors."""
+    import torch
+    mant = torch.zeros((x.rows, x.cols), dtype=torch.float64, device=x.limbs.device)
+    e = torch.zeros((x.rows, x.cols), dtype=torch.int64, device=x.limbs.device)
+    h = handle(x.limbs.device.index or 0)
+    _check("mp_to_f64", lib().mp_to_f64(h.ptr, x.mat(), mant.data_ptr(), e.data_ptr(), _stream(stream)))
+    return mant, e
+
+
+def det(A: DeviceMp, path: str = "auto", stream=None):
+    """The whole hot path on A (in place): factor, then minors.
+    Returns (D, c, info); det(A) = D[n-1]."""
+    D, info = factor(A, path, stream=stream)
+    c = minors(A, D, info, stream=stream)
+    return D, c, info

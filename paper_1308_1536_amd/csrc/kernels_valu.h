@@ -1,0 +1,237 @@
+// kernels_valu.h -- elimination, leading determinants, minors and output
+// conversion with wave-cooperative 32x32->64-bit VALU limb arithmetic.
+//
+// Every kernel runs single-wave (64-thread) workgroups; one workgroup owns one
+// multiprecision operation and keeps its operands in LDS (layout `Lds`).
+#pragma once
+
+#include "wave_mp.h"
+
+namespace mpk {
+
+struct MatDev {
+    uint32_t *limbs;  // [rows][ld][P]
+    int64_t *exp;     // [rows][ld]
+    int32_t *sign;    // [rows][ld]
+    int64_t ld;
+};
+
+__device__ __forceinline__ uint32_t *el(const MatDev &A, int64_t i, int64_t j, int P) {
+    return A.limbs + (i * A.ld + j) * (int64_t)P;
+}
+__device__ __forceinline__ int64_t &ex(const MatDev &A, int64_t i, int64_t j) { return A.exp[i * A.ld + j]; }
+__device__ __forceinline__ int32_t &sg(const MatDev &A, int64_t i, int64_t j) { return A.sign[i * A.ld + j]; }
+
+constexpr int64_t kExpLimit = 1LL << 62;
+
+// LDS carve-up shared by all VALU kernels (12P + 138 limbs in total).
+struct Lds {
+    mpw::Scratch sc;  // x, ypad, prod, t0..t3
+    __device__ Lds(uint32_t *base, int P) {
+        sc.x = base;
+        sc.ypad = sc.x + P;
+        sc.prod = sc.ypad + P + 2 * MP_WAVE;
+        sc.t0 = sc.prod + 2 * P + 2;
+        sc.t1 = sc.t0 + 2 * P + 2;
+        sc.t2 = sc.t1 + 2 * P + 2;
+        sc.t3 = sc.t2 + 2 * P + 2;
+    }
+};
+
+__host__ __device__ constexpr size_t lds_bytes(int P) { return (size_t)(12 * P + 138) * 4u; }
+
+// y operand of a product: value at ypad + 64, zero limbs around it
+__device__ __forceinline__ mpw::Hdr load_y(uint32_t *ypad, const uint32_t *src, int64_t e, int32_t s,
+                                           int P) {
+    for (int q = mpw::lane(); q < P + 2 * MP_WAVE; q += MP_WAVE) {
+        int k = q - MP_WAVE;
+        ypad[q] = (k >= 0 && k < P) ? src[k] : 0u;
+    }
+    mpw::wsync();
+    bool z = ypad[MP_WAVE + P - 1] == 0u;
+    return z ? mpw::zero_hdr() : mpw::Hdr{e, s, false};
+}
+
+__device__ void store_zero(uint32_t *l, int64_t *e, int32_t *s, int P) {
+    for (int q = mpw::lane(); q < P; q += MP_WAVE) l[q] = 0u;
+    if (mpw::lane() == 0) {
+        *e = 0;
+        *s = 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step k, part 1 (Algorithm 1 steps 2.1 and 2.2.1).
+// Block 0: D_k = D_{k-1} * pivot (D_1 = pivot), zero / overflow checks, info.
+// Block b >= 1: multiplier of row i = k + b: l_ik = RZ_p(a_ik / a_kk), in place.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_pivot_divide(MatDev A, MatDev D, int32_t *info, int64_t k,
+                                                     int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    Lds L(lds_raw, P);
+    const uint32_t *pm = el(A, k, k, P);
+    const bool piv_zero = pm[P - 1] == 0u;
+    const int64_t pe = ex(A, k, k);
+    const int32_t ps = sg(A, k, k);
+    if (blockIdx.x == 0) {
+        bool bad = false;
+        int32_t code = 0;
+        mpw::Hdr hd{0, 0, true};
+        if (piv_zero) {
+            bad = true;
+            code = (int32_t)(k + 1);
+        } else {
+            mpw::Hdr hp = load_y(L.sc.ypad, pm, pe, ps, P);
+            if (k == 0) {
+                mpw::copy(L.sc.t3, L.sc.ypad + MP_WAVE, P);
+                mpw::wsync();
+                hd = hp;
+            } else {
+                mpw::Hdr hprev = mpw::load(L.sc.x, el(D, 0, k - 1, P), ex(D, 0, k - 1), sg(D, 0, k - 1), P);
+                hd = mpw::mul(L.sc.t3, hprev, hp, P, L.sc);
+            }
+            if (pe > kExpLimit || pe < -kExpLimit || (!hd.zero && (hd.e > kExpLimit || hd.e < -kExpLimit))) {
+                bad = true;
+                code = -1;
+            }
+        }
+        if (bad) {
+            if (mpw::lane() == 0) *info = code;
+            for (int64_t t = k; t < n; ++t) store_zero(el(D, 0, t, P), &ex(D, 0, t), &sg(D, 0, t), P);
+        } else {
+            mpw::store(el(D, 0, k, P), &ex(D, 0, k), &sg(D, 0, k), L.sc.t3, hd, P);
+        }
+        return;
+    }
+    if (piv_zero) return;
+    const int64_t i = k + (int64_t)blockIdx.x;
+    uint32_t *am = el(A, i, k, P);
+    mpw::Hdr ha = mpw::load(L.sc.x, am, ex(A, i, k), sg(A, i, k), P);
+    mpw::Hdr hp = mpw::load(L.sc.ypad, pm, pe, ps, P);
+    // U = prod (2P+2), LO = t0, HI = t1, Q = t2, out = t3
+    mpw::Hdr hq = mpw::div(L.sc.t3, L.sc.x, ha, L.sc.ypad, hp, L.sc.prod, L.sc.t0, L.sc.t1, L.sc.t2, P);
+    mpw::store(am, &ex(A, i, k), &sg(A, i, k), L.sc.t3, hq, P);
+}
+
+// ---------------------------------------------------------------------------
+// Step k, part 2 (Algorithm 1 step 2.2.2): a_ij = RZ_p(a_ij - RZ_p(l_ik u_kj))
+// for k < i, j < n; block (bx) -> i = k+1 + bx / m, j = k+1 + bx % m.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_update_valu(MatDev A, const int32_t *info, int64_t k, int64_t n,
+                                                    int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    const int64_t m = n - k - 1;
+    const int64_t bx = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
+    if (bx >= m * m) return;
+    const int64_t i = k + 1 + bx / m, j = k + 1 + bx % m;
+    const uint32_t *lm = el(A, i, k, P);
+    const uint32_t *um = el(A, k, j, P);
+    if (lm[P - 1] == 0u || um[P - 1] == 0u) return;  // a_ij - 0 = a_ij
+    Lds L(lds_raw, P);
+    mpw::Hdr hl = mpw::load(L.sc.x, lm, ex(A, i, k), sg(A, i, k), P);
+    mpw::Hdr hu = load_y(L.sc.ypad, um, ex(A, k, j), sg(A, k, j), P);
+    mpw::Hdr ht = mpw::mul(L.sc.t3, hl, hu, P, L.sc);
+    ht.s ^= 1;  // subtract
+    uint32_t *am = el(A, i, j, P);
+    mpw::Hdr ha = mpw::load(L.sc.x, am, ex(A, i, j), sg(A, i, j), P);
+    mpw::Hdr hr = mpw::addsub(L.sc.t2, L.sc.x, ha, L.sc.t3, ht, L.sc.t0, L.sc.t1, P);
+    mpw::store(am, &ex(A, i, j), &sg(A, i, j), L.sc.t2, hr, P);
+}
+
+// ---------------------------------------------------------------------------
+// Last-column minors (Sec. 3, [A I] derivation): x^T L = e_n^T by sweeps.
+// ---------------------------------------------------------------------------
+__global__ void k_minors_init(MatDev c, int64_t n, int P) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int64_t total = n * (int64_t)P;
+    if (t < total) c.limbs[(t / P) * (int64_t)P + t % P] = 0u;  // vector: ld irrelevant for row 0
+    if (t < n) {
+        c.exp[t] = 0;
+        c.sign[t] = 0;
+    }
+}
+
+// sweep j: s_i = RZ_p(s_i - RZ_p(x_j l_ji)), i < j; x_{n-1} = 1, x_j = s_j otherwise
+__global__ void __launch_bounds__(64) k_minors_sweep(MatDev LU, MatDev c, const int32_t *info, int64_t j,
+                                                     int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    const int64_t i = blockIdx.x;
+    Lds L(lds_raw, P);
+    const uint32_t *lm = el(LU, j, i, P);
+    if (lm[P - 1] == 0u) return;
+    mpw::Hdr ht;
+    if (j == n - 1) {
+        ht = mpw::load(L.sc.t3, lm, ex(LU, j, i), sg(LU, j, i), P);  // 1 * l_ji, exact
+    } else {
+        mpw::Hdr hx = mpw::load(L.sc.x, el(c, 0, j, P), ex(c, 0, j), sg(c, 0, j), P);
+        if (hx.zero) return;
+        mpw::Hdr hl = load_y(L.sc.ypad, lm, ex(LU, j, i), sg(LU, j, i), P);
+        ht = mpw::mul(L.sc.t3, hx, hl, P, L.sc);
+    }
+    ht.s ^= 1;
+    uint32_t *sm = el(c, 0, i, P);
+    mpw::Hdr hs = mpw::load(L.sc.x, sm, ex(c, 0, i), sg(c, 0, i), P);
+    mpw::Hdr hr = mpw::addsub(L.sc.t2, L.sc.x, hs, L.sc.t3, ht, L.sc.t0, L.sc.t1, P);
+    mpw::store(sm, &ex(c, 0, i), &sg(c, 0, i), L.sc.t2, hr, P);
+}
+
+// c_i = RZ_p(D_{n-1} x_i) for i < n-1 (block i), c_{n-1} = D_{n-1}; n == 1: c = 1
+__global__ void __launch_bounds__(64) k_minors_final(MatDev D, MatDev c, const int32_t *info, int64_t n,
+                                                     int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    const int64_t i = blockIdx.x;
+    uint32_t *cm = el(c, 0, i, P);
+    if (n == 1) {
+        for (int q = mpw::lane(); q < P; q += MP_WAVE) cm[q] = (q == P - 1) ? 0x80000000u : 0u;
+        if (mpw::lane() == 0) {
+            ex(c, 0, 0) = 1;
+            sg(c, 0, 0) = 0;
+        }
+        return;
+    }
+    const uint32_t *dm = el(D, 0, n - 2, P);
+    if (i == n - 1) {
+        for (int q = mpw::lane(); q < P; q += MP_WAVE) cm[q] = dm[q];
+        if (mpw::lane() == 0) {
+            ex(c, 0, i) = ex(D, 0, n - 2);
+            sg(c, 0, i) = sg(D, 0, n - 2);
+        }
+        return;
+    }
+    Lds L(lds_raw, P);
+    mpw::Hdr hd = mpw::load(L.sc.x, dm, ex(D, 0, n - 2), sg(D, 0, n - 2), P);
+    mpw::Hdr hx = load_y(L.sc.ypad, cm, ex(c, 0, i), sg(c, 0, i), P);
+    mpw::Hdr hr = mpw::mul(L.sc.t3, hd, hx, P, L.sc);
+    mpw::store(cm, &ex(c, 0, i), &sg(c, 0, i), L.sc.t3, hr, P);
+}
+
+// ---------------------------------------------------------------------------
+// Output conversion: (-1)^s RZ_53(m / 2^p) and the exponent.
+// ---------------------------------------------------------------------------
+__global__ void k_to_f64(MatDev x, int64_t rows, int64_t cols, int P, double *mant, int64_t *eo) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * cols) return;
+    int64_t i = t / cols, j = t % cols;
+    const uint32_t *m = el(x, i, j, P);
+    uint32_t top = m[P - 1];
+    if (top == 0u) {
+        mant[t] = 0.0;
+        eo[t] = 0;
+        return;
+    }
+    // top 53 bits: 32 from limb P-1, 21 from limb P-2
+    uint64_t v = ((uint64_t)top << 21) | (uint64_t)(m[P - 2] >> 11);
+    double d = ldexp((double)v, -53);
+    mant[t] = sg(x, i, j) ? -d : d;
+    eo[t] = ex(x, i, j);
+}
+
+__global__ void k_set_info(int32_t *info, int32_t v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *info = v;
+}
+
+}  // namespace mpk
