@@ -1,0 +1,185 @@
+#!/usr/bin/env python3
+"""Throughput of the multiprecision determinant hot path on one MI355X.
+
+A step is one pass of the whole path -- Gaussian elimination without pivoting
+(every D_k and det), then the last-column minors -- over every matrix of the
+workload, starting from pristine copies already resident in HBM (the copy
+into the work buffer is inside the timed region).
+
+    python bench.py [--steps K] [--warmup W] [--config 2] [--path auto|valu|mfma]
+
+Prints ONE JSON line.  `value` is algorithmic 8-bit limb MACs per second:
+U(N) * (p/8)^2 per matrix, U(N) = (N-1)N(2N-1)/6 trailing updates, divided by
+the wall time of a step.  `roofline` describes the dominant kernel, timed
+live with HIP events on its launch stream; `cpu_baseline` times the CPU oracle
+on a bounded leading block of the first matrix (same unit), which also checks
+the GPU's D_1..D_K bit for bit (prefix property of elimination without
+pivoting).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Published MI355X peaks (dense) and the derived integer-VALU rate.
+PEAK_INT8_MFMA_TOPS = 5.0e15           # int8 ops/s; a MAC is 2 ops
+PEAK_INT8_MAC = PEAK_INT8_MFMA_TOPS / 2
+# v_mad_u64_u32 (32x32->64 multiply-add) issues at quarter rate: 16 lanes per
+# clock per CU -> 256 CUs * 16 * 2.4 GHz.
+PEAK_VALU_MAC32 = 256 * 16 * 2.4e9
+
+METRIC = "time to det+all D_k+last-col minors at (N,bits); limb-MAC/s vs INT8 MFMA peak"
+
+
+def workload(cfg: int):
+    from paper_1308_1536_amd import inputs
+    if cfg == 1:
+        c = inputs.config_c1()
+        return ("config 1: N=64, 1024-bit: integer-node Cauchy + random integers in [-1000,1000]",
+                [("cauchy", c["cauchy"][0]), ("randint", c["randint"][0])])
+    if cfg == 2:
+        c = inputs.config_c2()
+        return ("config 2: N=512, 4096-bit: dyadic Cauchy (nodes on [0,1000], delta in [1e-6,1e-3]) "
+                "+ random mantissas (exp in [-4,4])",
+                [("cauchy", c["cauchy"][0]), ("randmant", c["randmant"])])
+    if cfg == 3:
+        c = inputs.config_c3()
+        return ("config 3: N=2048, 32768-bit: interlaced dyadic Cauchy on [0,1000]",
+                [("cauchy", c["cauchy"][0])])
+    raise SystemExit(f"bench.py: config {cfg} is not a single-GPU bench workload")
+
+
+def unit_work(mats):
+    from paper_1308_1536_amd.inputs import limb_macs_int8, u_count
+    macs = sum(limb_macs_int8(m.exp.shape[0], m.limbs.shape[-1]) for _, m in mats)
+    upd = sum(u_count(m.exp.shape[0]) for _, m in mats)
+    return macs, upd
+
+
+def cpu_baseline(A, gpu_D, budget_s: float):
+    """Time the oracle (factor + minors) on the leading K x K block of A, K
+    grown until one run takes at least a third of the budget (or K = N)."""
+    import numpy as np
+
+    import oracle
+    from paper_1308_1536_amd.inputs import MpArray, limb_macs_int8
+    oracle.build(force=False)
+    N, P = A.exp.shape[0], A.limbs.shape[-1]
+    threads = oracle.default_threads()
+    K = min(N, 32)
+    while True:
+        sub = MpArray(A.limbs[:K, :K].copy(), A.exp[:K, :K].copy(), A.sign[:K, :K].copy())
+        t0 = time.perf_counter()
+        f, c = oracle.det_pipeline(sub, threads)
+        dt = time.perf_counter() - t0
+        if dt >= budget_s / 3 or K == N:
+            break
+        # time ~ K^3: aim at the budget
+        scale = (budget_s / 2 / max(dt, 1e-3)) ** (1 / 3)
+        K = min(N, max(K + 8, int(K * min(scale, 2.5))))
+    prefix_ok = bool(np.array_equal(gpu_D.limbs[:K], f.D.limbs) and np.array_equal(gpu_D.exp[:K], f.D.exp)
+                     and np.array_equal(gpu_D.sign[:K], f.D.sign))
+    return {"value": limb_macs_int8(K, P) / dt, "unit": "limb-MAC/s", "cores": threads, "kind": "oracle",
+            "sample": f"oracle factor+D_k+minors on the leading {K}x{K} block of the first matrix "
+                      f"({32 * P}-bit), {dt:.2f} s wall",
+            "seconds": dt, "prefix_D_bit_exact": prefix_ok}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma"])
+    ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU (the method's single-GPU share); "
+              "--gpus must be 1", file=sys.stderr, flush=True)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1308_1536_amd import binding
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+
+    desc, mats = workload(args.config)
+    print(f"[bench] {desc}", file=sys.stderr, flush=True)
+    pristine = [binding.DeviceMp.from_host(m) for _, m in mats]
+    work = [binding.DeviceMp.empty(p.rows, p.cols, p.P, dev) for p in pristine]
+    Ds = [binding.DeviceMp.empty(1, p.rows, p.P, dev) for p in pristine]
+    cs = [binding.DeviceMp.empty(1, p.rows, p.P, dev) for p in pristine]
+    infos = [torch.zeros(1, dtype=torch.int32, device=dev) for _ in pristine]
+    path = args.path
+
+    def step():
+        for p, w, D, c, info in zip(pristine, work, Ds, cs, infos):
+            w.limbs.copy_(p.limbs)
+            w.exp.copy_(p.exp)
+            w.sign.copy_(p.sign)
+            binding.factor(w, path, D=D, info=info)
+            binding.minors(w, D, info, c=c)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step()
+        torch.cuda.synchronize()
+        print(f"[bench] step {s + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    bad = [int(i.item()) for i in infos if int(i.item()) != 0]
+    if bad:
+        raise SystemExit(f"bench.py: factorisation reported info {bad}")
+    macs, upd = unit_work(mats)
+    value = macs / (ms / 1e3)
+
+    # live per-kernel timing with HIP events on the launch stream (one extra step)
+    binding.profile_begin()
+    step()
+    prof = binding.profile_end()
+    dom = max(("update_valu", "update_mfma"), key=lambda k: prof[k][0])
+    dom_ms, dom_n = prof[dom]
+    P = mats[0][1].limbs.shape[-1]
+    if dom == "update_valu":
+        work_units = sum((m.exp.shape[0] - 1) * m.exp.shape[0] * (2 * m.exp.shape[0] - 1) // 6
+                         for _, m in mats) * P * P  # 32x32->64 MACs
+        achieved = work_units / dom_n / (dom_ms / dom_n / 1e3)
+        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_MAC32 / 1e12,
+                "unit": "Tmac32/s", "frac": achieved / PEAK_VALU_MAC32, "traffic": None,
+                "kernel": "k_update_valu", "avg_launch_ms": dom_ms / dom_n, "launches": dom_n}
+    else:
+        achieved = macs / dom_n / (dom_ms / dom_n / 1e3)
+        roof = {"bound": "mfma", "achieved": 2 * achieved / 1e12, "peak": PEAK_INT8_MFMA_TOPS / 1e12,
+                "unit": "TOP/s", "frac": achieved / PEAK_INT8_MAC, "traffic": None,
+                "kernel": "k_update_mfma", "avg_launch_ms": dom_ms / dom_n, "launches": dom_n}
+    roof["kernel_ms_per_step"] = {k: round(v[0], 3) for k, v in prof.items() if v[1]}
+
+    out = {"metric": METRIC, "value": value, "unit": "limb-MAC/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "u32" if dom == "update_valu" else "i8", "data": "synthetic",
+           "config": {"workload": desc, "N": int(mats[0][1].exp.shape[0]), "bits": 32 * P,
+                      "matrices": len(mats), "path": path, "updates_per_step": upd,
+                      "limb_macs_per_step": macs},
+           "roofline": roof}
+    if not args.no_cpu_baseline:
+        gpu_D = Ds[0].row(0)
+        out["cpu_baseline"] = cpu_baseline(mats[0][1], gpu_D, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

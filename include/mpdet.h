@@ -119,6 +119,19 @@ int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c,
 int mp_to_f64(mpdet_handle *h, mpdet_mat x, double *mant_dev, int64_t *exp_dev,
               void *stream);
 
+/*
+ * Per-kernel timing with HIP events (tracing; off by default).
+ * mpdet_profile_begin clears the counters and brackets every later launch on
+ * this handle with two events on the launch stream; mpdet_profile_end waits
+ * for those events and adds their elapsed times to the totals;
+ * mpdet_profile_get returns the total milliseconds and launch count of one
+ * kernel: "pivot_divide", "update_valu", "update_mfma", "mfma_prep",
+ * "minors_sweep", "minors_final" or "other" (MPDET_EINVAL for other names).
+ */
+int mpdet_profile_begin(mpdet_handle *h);
+int mpdet_profile_end(mpdet_handle *h);
+int mpdet_profile_get(mpdet_handle *h, const char *kernel, double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

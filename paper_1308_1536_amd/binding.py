@@ -66,7 +66,12 @@ def lib() -> ctypes.CDLL:
         L.mp_det_factor.argtypes = [vp, MpdetMat, MpdetMat, vp, ctypes.c_int, vp]
         L.mp_det_minors.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, vp, vp]
         L.mp_to_f64.argtypes = [vp, MpdetMat, vp, vp, vp]
-        for name in ("mpdet_create", "mpdet_destroy", "mp_det_factor", "mp_det_minors", "mp_to_f64"):
+        L.mpdet_profile_begin.argtypes = [vp]
+        L.mpdet_profile_end.argtypes = [vp]
+        L.mpdet_profile_get.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_double),
+                                        ctypes.POINTER(ctypes.c_int64)]
+        for name in ("mpdet_create", "mpdet_destroy", "mp_det_factor", "mp_det_minors", "mp_to_f64",
+                     "mpdet_profile_begin", "mpdet_profile_end", "mpdet_profile_get"):
             getattr(L, name).restype = ctypes.c_int
         if hasattr(L, "mp_det_batched"):
             L.mp_det_batched.argtypes = [vp, i64, ctypes.POINTER(MpdetMat), ctypes.POINTER(MpdetMat),
@@ -228,6 +233,27 @@ def to_f64(x: DeviceMp, stream=None):
     h = handle(x.limbs.device.index or 0)
     _check("mp_to_f64", lib().mp_to_f64(h.ptr, x.mat(), mant.data_ptr(), e.data_ptr(), _stream(stream)))
     return mant, e
+
+
+KERNELS = ("pivot_divide", "update_valu", "update_mfma", "mfma_prep", "minors_sweep",
+           "minors_final", "other")
+
+
+def profile_begin(device: int = 0):
+    _check("mpdet_profile_begin", lib().mpdet_profile_begin(handle(device).ptr))
+
+
+def profile_end(device: int = 0) -> dict:
+    """Stop per-kernel event timing; returns {kernel: (total_ms, launches)}."""
+    h = handle(device)
+    _check("mpdet_profile_end", lib().mpdet_profile_end(h.ptr))
+    out = {}
+    for k in KERNELS:
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        _check("mpdet_profile_get", lib().mpdet_profile_get(h.ptr, k.encode(), ctypes.byref(ms),
+                                                            ctypes.byref(n)))
+        out[k] = (ms.value, n.value)
+    return out
 
 
 def det(A: DeviceMp, path: str = "auto", stream=None):

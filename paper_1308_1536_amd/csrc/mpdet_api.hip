@@ -12,8 +12,28 @@
 #include "mpdet.h"
 #include "kernels_valu.h"
 
+// Per-kernel timing (off by default): each launch is bracketed by two HIP
+// events recorded on the launch stream; mpdet_profile_end folds the elapsed
+// times into per-kernel totals.
+enum KernelId { K_PIVOT_DIVIDE = 0, K_UPDATE_VALU, K_UPDATE_MFMA, K_MFMA_PREP, K_MINORS_SWEEP,
+                K_MINORS_FINAL, K_OTHER, K_COUNT };
+static const char *kKernelNames[K_COUNT] = {"pivot_divide", "update_valu", "update_mfma", "mfma_prep",
+                                            "minors_sweep", "minors_final", "other"};
+
+struct ProfRec {
+    int kernel;
+    hipEvent_t start, stop;
+};
+
 struct mpdet_handle {
     int device;
+    bool profiling;
+    ProfRec *recs;
+    int64_t nrec, caprec;
+    hipEvent_t *pool;
+    int64_t npool, cappool;
+    double total_ms[K_COUNT];
+    int64_t launches[K_COUNT];
 };
 
 namespace {
@@ -39,6 +59,51 @@ dim3 grid_for(int64_t blocks) {
 
 int last_launch() { return check(hipGetLastError()); }
 
+hipEvent_t pool_event(mpdet_handle *h) {
+    if (h->npool == h->cappool) {
+        int64_t cap = h->cappool ? 2 * h->cappool : 256;
+        hipEvent_t *p = (hipEvent_t *)realloc(h->pool, sizeof(hipEvent_t) * (size_t)cap);
+        if (!p) return nullptr;
+        h->pool = p;
+        for (int64_t i = h->cappool; i < cap; ++i)
+            if (hipEventCreate(&h->pool[i]) != hipSuccess) h->pool[i] = nullptr;
+        h->cappool = cap;
+    }
+    return h->pool[h->npool++];
+}
+
+// Bracket one launch with events when profiling is on.
+struct Prof {
+    mpdet_handle *h;
+    hipStream_t s;
+    int kernel;
+    hipEvent_t stop = nullptr;
+    Prof(mpdet_handle *h_, hipStream_t s_, int k) : h(h_), s(s_), kernel(k) {
+        if (!h || !h->profiling) return;
+        hipEvent_t start = pool_event(h);
+        stop = pool_event(h);
+        if (!start || !stop) {
+            stop = nullptr;
+            return;
+        }
+        if (h->nrec == h->caprec) {
+            int64_t cap = h->caprec ? 2 * h->caprec : 256;
+            ProfRec *p = (ProfRec *)realloc(h->recs, sizeof(ProfRec) * (size_t)cap);
+            if (!p) {
+                stop = nullptr;
+                return;
+            }
+            h->recs = p;
+            h->caprec = cap;
+        }
+        h->recs[h->nrec++] = ProfRec{kernel, start, stop};
+        (void)hipEventRecord(start, s);
+    }
+    ~Prof() {
+        if (stop) (void)hipEventRecord(stop, s);
+    }
+};
+
 struct DeviceGuard {
     int prev = -1;
     bool ok = false;
@@ -50,19 +115,26 @@ struct DeviceGuard {
     }
 };
 
-int factor_valu(const mpdet_mat &A, const mpdet_mat &D, int32_t *info, hipStream_t s) {
+int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, hipStream_t s) {
     const int64_t n = A.rows;
     const int P = A.nlimbs;
     const size_t lds = mpk::lds_bytes(P);
     mpk::MatDev a = dev(A), d = dev(D);
     for (int64_t k = 0; k < n; ++k) {
-        hipLaunchKernelGGL(mpk::k_pivot_divide, dim3((unsigned)(n - k)), dim3(64), lds, s, a, d, info, k, n, P);
+        {
+            Prof pr(h, s, K_PIVOT_DIVIDE);
+            hipLaunchKernelGGL(mpk::k_pivot_divide, dim3((unsigned)(n - k)), dim3(64), lds, s, a, d, info, k, n,
+                               P);
+        }
         int rc = last_launch();
         if (rc) return rc;
         const int64_t m = n - k - 1;
         if (m > 0) {
-            hipLaunchKernelGGL(mpk::k_update_valu, grid_for(m * m), dim3(64), lds, s, a, (const int32_t *)info, k,
-                               n, P);
+            {
+                Prof pr(h, s, K_UPDATE_VALU);
+                hipLaunchKernelGGL(mpk::k_update_valu, grid_for(m * m), dim3(64), lds, s, a, (const int32_t *)info,
+                                   k, n, P);
+            }
             rc = last_launch();
             if (rc) return rc;
         }
@@ -101,8 +173,60 @@ int mpdet_destroy(mpdet_handle *h) {
     if (!h) return MPDET_EINVAL;
     DeviceGuard g(h->device);
     (void)hipDeviceSynchronize();
+    for (int64_t i = 0; i < h->cappool; ++i)
+        if (h->pool[i]) (void)hipEventDestroy(h->pool[i]);
+    free(h->pool);
+    free(h->recs);
     free(h);
     return MPDET_OK;
+}
+
+int mpdet_profile_begin(mpdet_handle *h) {
+    if (!h) return MPDET_EINVAL;
+    h->profiling = true;
+    h->nrec = 0;
+    h->npool = 0;
+    for (int k = 0; k < K_COUNT; ++k) {
+        h->total_ms[k] = 0.0;
+        h->launches[k] = 0;
+    }
+    return MPDET_OK;
+}
+
+int mpdet_profile_end(mpdet_handle *h) {
+    if (!h) return MPDET_EINVAL;
+    DeviceGuard g(h->device);
+    h->profiling = false;
+    int rc = MPDET_OK;
+    for (int64_t i = 0; i < h->nrec; ++i) {
+        const ProfRec &r = h->recs[i];
+        if (hipEventSynchronize(r.stop) != hipSuccess) {
+            rc = MPDET_EHIP;
+            continue;
+        }
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.start, r.stop) != hipSuccess) {
+            rc = MPDET_EHIP;
+            continue;
+        }
+        h->total_ms[r.kernel] += ms;
+        h->launches[r.kernel] += 1;
+    }
+    h->nrec = 0;
+    h->npool = 0;
+    return rc;
+}
+
+int mpdet_profile_get(mpdet_handle *h, const char *kernel, double *total_ms, int64_t *launches) {
+    if (!h || !kernel || !total_ms || !launches) return MPDET_EINVAL;
+    for (int k = 0; k < K_COUNT; ++k) {
+        if (strcmp(kernel, kKernelNames[k]) == 0) {
+            *total_ms = h->total_ms[k];
+            *launches = h->launches[k];
+            return MPDET_OK;
+        }
+    }
+    return MPDET_EINVAL;
 }
 
 int mp_det_factor(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, int path, void *stream) {
@@ -118,7 +242,7 @@ int mp_det_factor(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, 
     int rc = last_launch();
     if (rc) return rc;
     if (A.rows == 0) return MPDET_OK;
-    return factor_valu(A, D, info_dev, s);
+    return factor_valu(h, A, D, info_dev, s);
 }
 
 int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c, const int32_t *info_dev,
@@ -139,11 +263,18 @@ int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c, const
     int rc = last_launch();
     if (rc) return rc;
     for (int64_t j = n - 1; j >= 1; --j) {
-        hipLaunchKernelGGL(mpk::k_minors_sweep, dim3((unsigned)j), dim3(64), lds, s, lu, cv, info_dev, j, n, P);
+        {
+            Prof pr(h, s, K_MINORS_SWEEP);
+            hipLaunchKernelGGL(mpk::k_minors_sweep, dim3((unsigned)j), dim3(64), lds, s, lu, cv, info_dev, j, n,
+                               P);
+        }
         rc = last_launch();
         if (rc) return rc;
     }
-    hipLaunchKernelGGL(mpk::k_minors_final, dim3((unsigned)n), dim3(64), lds, s, d, cv, info_dev, n, P);
+    {
+        Prof pr(h, s, K_MINORS_FINAL);
+        hipLaunchKernelGGL(mpk::k_minors_final, dim3((unsigned)n), dim3(64), lds, s, d, cv, info_dev, n, P);
+    }
     return last_launch();
 }
 
