@@ -1,0 +1,261 @@
+// kernels_mfma.h -- the trailing update (Algorithm 1 step 2.2.2) with the limb
+// products on INT8 MFMA (v_mfma_i32_32x32x32_i8, gfx950).
+//
+// Exactness.  Each mantissa m (P8 = 4P little-endian bytes) is rewritten in
+// balanced base 256: m = sum_{c=0..P8} d_c 256^c with d_c in [-128, 127] for
+// c < P8 and d_P8 in {0, 1} (a carry-lookahead over the bytes: a byte >= 128
+// borrows 256 from itself and carries 1 up).  Signed int8 operands then hold
+// the digits exactly, and every column sum S_r = sum_c dl[r-c] du[c] obeys
+// |S_r| <= (P8+1) 2^14 < 2^31, so int32 accumulation is exact.
+//
+// Contraction.  For a fixed row i the products l_i u_j for all j are one
+// integer matrix product: S[r][j] = sum_c T_i[r][c] U[c][j] with the Toeplitz
+// matrix T_i[r][c] = dl_i[r-c] (M = byte position r, K = digit c) and
+// U[c][j] = du_j[c] (N = column j).  A 64-lane wave owns (row i, 32 columns)
+// and sweeps r in chunks of 8 output tiles of 32 rows; the A fragment of a tile
+// depends only on d = r0 - c0, so moving one K-step along the diagonal turns
+// tile t's fragment into tile t+1's and only one new fragment is read from LDS
+// per K-step (the row's digits are staged there reversed).  Tiles outside the
+// band 0 <= r - c <= P8 are skipped.
+//
+// Epilogue.  Column sums are biased, S'_r = S_r + 2^27 - 2^19 [r >= 1], which
+// makes them positive (< 2^28) and adds sum_r bias_r 256^r = 2^27 256^R -- a
+// multiple of 2^(2p) -- to the total, invisible in the low 2p bits.  Four
+// consecutive S' form a 64-bit limb column V_q < 2^53, and one lane per column
+// runs the carry chain limb_q = (V_q + c) mod 2^32, c = (V_q + c) >> 32 from
+// the lowest limb up.  Limbs P-1 .. 2P-1 of each product go to a scratch
+// buffer; a wave-cooperative kernel then truncates the product to p bits and
+// forms RZ_p(a_ij - RZ_p(l_i u_j)).
+#pragma once
+
+#include "kernels_valu.h"
+
+namespace mpk {
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+typedef int v16i __attribute__((ext_vector_type(16)));
+
+struct MfmaGeom {
+    int P, P8;
+    int K8;       // bytes per pivot-row digit string (digits 0..P8, zero padded)
+    int LR;       // bytes per reversed multiplier digit string
+    int Q;        // reversal origin: Lr[x] = dl[Q - x]
+    int TP;       // limbs per product-top record in the scratch buffer
+    int nchunks;  // chunks of 256 product bytes covering r < 2 P8
+};
+
+__host__ __device__ inline MfmaGeom mfma_geom(int P) {
+    MfmaGeom g;
+    g.P = P;
+    g.P8 = 4 * P;
+    g.K8 = g.P8 + 32;
+    g.LR = g.P8 + 192;
+    g.Q = g.P8 + 67;  // Q = 3 mod 4: reversed limbs land on aligned words
+    g.TP = P + 4;
+    g.nchunks = (2 * g.P8 + 255) / 256;
+    return g;
+}
+
+__host__ __device__ inline bool mfma_supported(int P) { return P >= 8 && P % 8 == 0; }
+
+// LDS for k_update_mfma: the reversed digit row, then 32 columns x 65 uint64
+__host__ __device__ inline size_t mfma_lds_bytes(int P) {
+    MfmaGeom g = mfma_geom(P);
+    return (size_t)g.LR + 32u * 65u * 8u;
+}
+
+// ---------------------------------------------------------------------------
+// Balanced digits of one mantissa (all lanes of the wave): dw[0..P] receive the
+// digit words (digit 4q+b in byte b of word q; word P holds d_P8 in byte 0).
+// ---------------------------------------------------------------------------
+__device__ void balanced_digit_words(uint32_t *dw, const uint32_t *m, int P) {
+    uint32_t carry = 0;
+    for (int base = 0; base < P; base += MP_WAVE) {
+        const int q = base + mpw::lane();
+        const int cnt = min(MP_WAVE, P - base);
+        const uint32_t w = q < P ? m[q] : 0u;
+        // carry out of the limb's four bytes for carry-in 0 and 1
+        uint32_t co0 = 0, co1 = 1;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            uint32_t by = (w >> (8 * b)) & 0xFFu;
+            co0 = (by + co0) >= 128u;
+            co1 = (by + co1) >= 128u;
+        }
+        const uint64_t valid = cnt == 64 ? ~0ull : ((1ull << cnt) - 1ull);
+        const uint64_t G = __ballot(co0 != 0u) & valid;
+        const uint64_t Pm = __ballot(co1 != 0u && co0 == 0u) & valid;
+        const uint64_t C = mpw::lookahead(G, Pm, carry);
+        uint32_t c = (uint32_t)((C >> mpw::lane()) & 1ull);
+        uint32_t out = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            uint32_t t = ((w >> (8 * b)) & 0xFFu) + c;
+            c = t >= 128u;
+            out |= ((t - 256u * c) & 0xFFu) << (8 * b);
+        }
+        if (q < P) dw[q] = out;
+        carry = mpw::block_carry_out(G, Pm, C, cnt);
+    }
+    if (mpw::lane() == 0) dw[P] = carry;
+    mpw::wsync();
+}
+
+// Per step: block b < m -> reversed multiplier digits of row k+1+b (Lr),
+// block b >= m -> digits of pivot-row element k+1+(b-m) (Ub).
+__global__ void __launch_bounds__(64) k_mfma_prep(MatDev A, uint8_t *Lr, uint8_t *Ub, const int32_t *info,
+                                                  int64_t k, int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    const MfmaGeom g = mfma_geom(P);
+    const int64_t m = n - k - 1;
+    const int64_t b = blockIdx.x;
+    const bool is_row = b < m;
+    const uint32_t *src = is_row ? el(A, k + 1 + b, k, P) : el(A, k, k + 1 + (b - m), P);
+    if (src[P - 1] == 0u && is_row) return;  // zero multiplier: its row is skipped
+    uint32_t *dw = lds_raw;                  // P + 1 words
+    balanced_digit_words(dw, src, P);
+    if (is_row) {
+        // word w of the reversed row holds digit word P + 16 - w, bytes reversed
+        uint32_t *out = (uint32_t *)(Lr + b * (int64_t)g.LR);
+        for (int w = mpw::lane(); w < g.LR / 4; w += MP_WAVE) {
+            int qd = P + 16 - w;
+            uint32_t v = 0;
+            if (qd >= 0 && qd <= P) v = __builtin_bswap32(dw[qd]);
+            out[w] = v;
+        }
+    } else {
+        uint32_t *out = (uint32_t *)(Ub + (b - m) * (int64_t)g.K8);
+        for (int w = mpw::lane(); w < g.K8 / 4; w += MP_WAVE) out[w] = w <= P ? dw[w] : 0u;
+    }
+}
+
+// A fragment of the Toeplitz block with diagonal offset d = r0 - c0: lane
+// (r = lane % 32, h = lane / 32) holds T[r0 + r][c0 + 16h + b], b = 0..15.
+__device__ __forceinline__ v4i load_a(const uint8_t *lr, int d, int P8, int Q) {
+    v4i v = {0, 0, 0, 0};
+    if (d >= -31 && d <= P8 + 31) {
+        const int r = mpw::lane() & 31, h = mpw::lane() >> 5;
+        __builtin_memcpy(&v, lr + (Q - d - r + 16 * h), 16);
+    }
+    return v;
+}
+
+// Product top limbs: for every row i' (multiplier l = a_{k+1+i', k}) and
+// column block of 32, T[(i' m + j') TP + x] = limb P-1+x of l * u_{j'}, x <= P.
+__global__ void __launch_bounds__(64) k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T,
+                                                    const int32_t *info, int64_t k, int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    const MfmaGeom g = mfma_geom(P);
+    const int64_t m = n - k - 1;
+    const int64_t njb = (m + 31) / 32;
+    const int64_t wu = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
+    if (wu >= m * njb) return;
+    const int64_t ip = wu / njb, jb = wu % njb;
+    if (el(A, k + 1 + ip, k, P)[P - 1] == 0u) return;
+
+    uint8_t *lr = (uint8_t *)lds_raw;
+    uint64_t *vbuf = (uint64_t *)(lds_raw + g.LR / 4);
+    {
+        const uint4 *src = (const uint4 *)(Lr + ip * (int64_t)g.LR);
+        uint4 *dst = (uint4 *)lr;
+        for (int w = mpw::lane(); w < g.LR / 16; w += MP_WAVE) dst[w] = src[w];
+    }
+    mpw::wsync();
+
+    const int lane = mpw::lane();
+    const int j = lane & 31, h = lane >> 5;
+    const int64_t jp = jb * 32 + j;
+    const bool jvalid = jp < m;
+    const uint8_t *ub = Ub + (jvalid ? jp : 0) * (int64_t)g.K8 + 16 * h;
+    uint32_t *trow = T + (ip * m + (jvalid ? jp : 0)) * (int64_t)g.TP;
+    const int P8 = g.P8, Q = g.Q;
+    uint64_t carry = 0;
+
+    for (int chunk = 0; chunk < g.nchunks; ++chunk) {
+        const int r0 = chunk * 256;
+        v16i acc[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) acc[t] = (v16i){0};
+        int c_lo = r0 - 31 - P8;
+        c_lo = c_lo <= 0 ? 0 : ((c_lo + 31) & ~31);
+        const int c_hi = min(P8, r0 + 224);
+        v4i fr[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) fr[t] = load_a(lr, r0 + 32 * t - c_lo, P8, Q);
+        for (int c0 = c_lo; c0 <= c_hi; c0 += 32) {
+            v4i bv = {0, 0, 0, 0};
+            if (jvalid) bv = *(const v4i *)(ub + c0);
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const int d = r0 + 32 * t - c0;
+                if (d >= -31 && d <= P8 + 31 && r0 + 32 * t < 2 * P8)
+                    acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fr[t], bv, acc[t], 0, 0, 0);
+            }
+#pragma unroll
+            for (int t = 7; t > 0; --t) fr[t] = fr[t - 1];
+            fr[0] = load_a(lr, r0 - c0 - 32, P8, Q);
+        }
+        // biased 64-bit limb columns: lane (j, h), tile t, group gq holds r =
+        // r0 + 32t + 8gq + 4h + {0..3}, i.e. limb q = r0/4 + 8t + 2gq + h
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+#pragma unroll
+            for (int gq = 0; gq < 4; ++gq) {
+                const int rb = r0 + 32 * t + 8 * gq + 4 * h;
+                uint64_t V = 0;
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    const int r = rb + b;
+                    const uint32_t bias = r == 0 ? (1u << 27) : ((1u << 27) - (1u << 19));
+                    const uint32_t s = (uint32_t)acc[t][4 * gq + b] + bias;
+                    V += (uint64_t)s << (8 * b);
+                }
+                vbuf[j * 65 + 8 * t + 2 * gq + h] = V;
+            }
+        }
+        mpw::wsync();
+        if (h == 0) {
+            const int qbase = r0 / 4;
+            for (int ql = 0; ql < 64; ++ql) {
+                const int q = qbase + ql;
+                if (q >= 2 * P) break;
+                const uint64_t x = vbuf[j * 65 + ql] + carry;
+                carry = x >> 32;
+                if (q >= P - 1 && jvalid) trow[q - (P - 1)] = (uint32_t)x;
+            }
+        }
+        mpw::wsync();
+    }
+}
+
+// a_ij = RZ_p(a_ij - t), t = RZ_p(l_i u_j) rebuilt from the product's top limbs.
+__global__ void __launch_bounds__(64) k_sub_mfma(MatDev A, const uint32_t *T, const int32_t *info, int64_t k,
+                                                 int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    const MfmaGeom g = mfma_geom(P);
+    const int64_t m = n - k - 1;
+    const int64_t bx = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
+    if (bx >= m * m) return;
+    const int64_t ip = bx / m, jp = bx % m;
+    const int64_t i = k + 1 + ip, j = k + 1 + jp;
+    const uint32_t *lm = el(A, i, k, P);
+    const uint32_t *um = el(A, k, j, P);
+    if (lm[P - 1] == 0u || um[P - 1] == 0u) return;
+    Lds L(lds_raw, P);
+    const uint32_t *raw = T + (ip * m + jp) * (int64_t)g.TP;
+    for (int q = mpw::lane(); q < P + 1; q += MP_WAVE) L.sc.prod[q] = raw[q];
+    mpw::wsync();
+    const int top = (int)(L.sc.prod[P] >> 31);
+    mpw::shift(L.sc.t3, P, L.sc.prod, P + 1, -(31 + top));
+    mpw::wsync();
+    mpw::Hdr ht{ex(A, i, k) + ex(A, k, j) - 1 + top, sg(A, i, k) ^ sg(A, k, j) ^ 1, false};
+    uint32_t *am = el(A, i, j, P);
+    mpw::Hdr ha = mpw::load(L.sc.x, am, ex(A, i, j), sg(A, i, j), P);
+    mpw::Hdr hr = mpw::addsub(L.sc.t2, L.sc.x, ha, L.sc.t3, ht, L.sc.t0, L.sc.t1, P);
+    mpw::store(am, &ex(A, i, j), &sg(A, i, j), L.sc.t2, hr, P);
+}
+
+}  // namespace mpk

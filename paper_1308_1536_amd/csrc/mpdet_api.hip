@@ -11,6 +11,7 @@
 
 #include "mpdet.h"
 #include "kernels_valu.h"
+#include "kernels_mfma.h"
 
 // Per-kernel timing (off by default): each launch is bracketed by two HIP
 // events recorded on the launch stream; mpdet_profile_end folds the elapsed
@@ -34,6 +35,9 @@ struct mpdet_handle {
     int64_t npool, cappool;
     double total_ms[K_COUNT];
     int64_t launches[K_COUNT];
+    // MFMA-path workspace (grown on demand, freed by mpdet_destroy)
+    void *ws;
+    size_t ws_bytes;
 };
 
 namespace {
@@ -142,6 +146,77 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     return MPDET_OK;
 }
 
+// Workspace of the MFMA path for trailing blocks up to m x m: reversed
+// multiplier digits, pivot-row digits and product-top records.
+struct MfmaWs {
+    uint8_t *Lr, *Ub;
+    uint32_t *T;
+};
+
+int mfma_workspace(mpdet_handle *h, int64_t m, int P, MfmaWs *w) {
+    const mpk::MfmaGeom g = mpk::mfma_geom(P);
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t lr = up((size_t)m * g.LR), ub = up((size_t)m * g.K8);
+    const size_t t = up((size_t)m * (size_t)m * (size_t)g.TP * 4u);
+    const size_t need = lr + ub + t;
+    if (need > h->ws_bytes) {
+        if (h->ws) (void)hipFree(h->ws);
+        h->ws = nullptr;
+        h->ws_bytes = 0;
+        if (hipMalloc(&h->ws, need) != hipSuccess) {
+            h->ws = nullptr;
+            (void)hipGetLastError();
+            return MPDET_ENOMEM;
+        }
+        h->ws_bytes = need;
+    }
+    uint8_t *base = (uint8_t *)h->ws;
+    w->Lr = base;
+    w->Ub = base + lr;
+    w->T = (uint32_t *)(base + lr + ub);
+    return MPDET_OK;
+}
+
+int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, hipStream_t s) {
+    const int64_t n = A.rows;
+    const int P = A.nlimbs;
+    MfmaWs w;
+    int rc = mfma_workspace(h, n > 1 ? n - 1 : 1, P, &w);
+    if (rc) return rc;
+    const size_t lds = mpk::lds_bytes(P), lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
+    mpk::MatDev a = dev(A), d = dev(D);
+    const int32_t *cinfo = info;
+    for (int64_t k = 0; k < n; ++k) {
+        {
+            Prof pr(h, s, K_PIVOT_DIVIDE);
+            hipLaunchKernelGGL(mpk::k_pivot_divide, dim3((unsigned)(n - k)), dim3(64), lds, s, a, d, info, k, n,
+                               P);
+        }
+        if ((rc = last_launch())) return rc;
+        const int64_t m = n - k - 1;
+        if (m <= 0) continue;
+        {
+            Prof pr(h, s, K_MFMA_PREP);
+            hipLaunchKernelGGL(mpk::k_mfma_prep, grid_for(2 * m), dim3(64), lds_prep, s, a, w.Lr, w.Ub, cinfo, k,
+                               n, P);
+        }
+        if ((rc = last_launch())) return rc;
+        {
+            Prof pr(h, s, K_UPDATE_MFMA);
+            hipLaunchKernelGGL(mpk::k_update_mfma, grid_for(m * ((m + 31) / 32)), dim3(64), lds_mfma, s, a,
+                               (const uint8_t *)w.Lr, (const uint8_t *)w.Ub, w.T, cinfo, k, n, P);
+        }
+        if ((rc = last_launch())) return rc;
+        {
+            Prof pr(h, s, K_OTHER);
+            hipLaunchKernelGGL(mpk::k_sub_mfma, grid_for(m * m), dim3(64), lds, s, a, (const uint32_t *)w.T, cinfo,
+                               k, n, P);
+        }
+        if ((rc = last_launch())) return rc;
+    }
+    return MPDET_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -177,6 +252,7 @@ int mpdet_destroy(mpdet_handle *h) {
         if (h->pool[i]) (void)hipEventDestroy(h->pool[i]);
     free(h->pool);
     free(h->recs);
+    if (h->ws) (void)hipFree(h->ws);
     free(h);
     return MPDET_OK;
 }
@@ -234,7 +310,9 @@ int mp_det_factor(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, 
     if (!mat_ok(A, A.rows > 0) || !mat_ok(D, A.rows > 0)) return MPDET_EINVAL;
     if (A.rows != A.cols || D.nlimbs != A.nlimbs || D.rows < 1 || D.cols < A.rows) return MPDET_EINVAL;
     if (path != MPDET_PATH_AUTO && path != MPDET_PATH_VALU && path != MPDET_PATH_MFMA) return MPDET_EINVAL;
-    if (path == MPDET_PATH_MFMA) return MPDET_ENOTSUP;
+    const bool mfma_ok = mpk::mfma_supported(A.nlimbs);
+    if (path == MPDET_PATH_MFMA && !mfma_ok) return MPDET_ENOTSUP;
+    const bool use_mfma = path == MPDET_PATH_MFMA || (path == MPDET_PATH_AUTO && mfma_ok);
     DeviceGuard g(h->device);
     if (!g.ok) return MPDET_EHIP;
     hipStream_t s = (hipStream_t)stream;
@@ -242,7 +320,7 @@ int mp_det_factor(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, 
     int rc = last_launch();
     if (rc) return rc;
     if (A.rows == 0) return MPDET_OK;
-    return factor_valu(h, A, D, info_dev, s);
+    return use_mfma ? factor_mfma(h, A, D, info_dev, s) : factor_valu(h, A, D, info_dev, s);
 }
 
 int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c, const int32_t *info_dev,

@@ -11,11 +11,18 @@ from paper_1308_1536_amd import inputs
 
 pytestmark = pytest.mark.gpu
 
-PATHS = ["valu"]
+PATHS = ["valu", "mfma"]
 
 
 def check_against_oracle(A, path, what, ld=None):
-    say(f"[parity] {what} path={path} N={A.exp.shape[0]} P={A.limbs.shape[-1]}")
+    from paper_1308_1536_amd import binding
+    P = A.limbs.shape[-1]
+    say(f"[parity] {what} path={path} N={A.exp.shape[0]} P={P}")
+    if path == "mfma" and (P % 8 != 0 or P < 8):
+        with pytest.raises(binding.MpdetError) as e:
+            gpu_det(A, path, ld=ld)
+        assert e.value.status == binding.MPDET_ENOTSUP
+        return None, None, None, None
     LU, D, c, info = gpu_det(A, path, ld=ld)
     f, cw = oracle.det_pipeline(A)
     assert info == f.info, (what, info, f.info)
@@ -37,14 +44,14 @@ def test_random_mantissas(path, N, P):
 @pytest.mark.parametrize("path", PATHS)
 def test_wide_exponent_range(path):
     """Exponent gaps far beyond p exercise the sticky/clamp paths."""
-    A = inputs.random_mantissas((24, 24), 4, 77, emin=-3000, emax=3000)
+    A = inputs.random_mantissas((24, 24), 8, 77, emin=-3000, emax=3000)
     check_against_oracle(A, path, "wide exponents")
 
 
 @pytest.mark.parametrize("path", PATHS)
 def test_cancellation_heavy(path):
     """Nearly equal rows: the updates cancel to a few bits and renormalise."""
-    P = 4
+    P = 8
     base = inputs.random_mantissas((1, 20), P, 5)
     A = inputs.random_mantissas((20, 20), P, 6)
     for i in range(20):
@@ -67,13 +74,13 @@ def test_config1(path):
 @pytest.mark.parametrize("path", PATHS)
 def test_cauchy_hilbert_exact(path):
     check_against_oracle(inputs.cauchy_dyadic(48, 8, 3)[0], path, "dyadic cauchy")
-    check_against_oracle(inputs.hilbert(30, 4), path, "hilbert")
-    check_against_oracle(inputs.triangular_product(40, 2, 9)[0], path, "exact L*U")
+    check_against_oracle(inputs.hilbert(30, 8), path, "hilbert")
+    check_against_oracle(inputs.triangular_product(40, 8, 9)[0], path, "exact L*U")
 
 
 @pytest.mark.parametrize("path", PATHS)
 def test_padded_leading_dimension(path):
-    A = inputs.random_mantissas((19, 19), 5, 31)
+    A = inputs.random_mantissas((19, 19), 16, 31)
     check_against_oracle(A, path, "ld=27", ld=27)
 
 
@@ -81,6 +88,7 @@ def test_padded_leading_dimension(path):
 def test_zero_pivots(path):
     P = 2
     # a_11 = 0
+    P = 8 if path == "mfma" else 2
     A = inputs.from_values([[0, 1, 2], [3, 4, 5], [6, 7, 9]], P)
     _, D, _, info = check_against_oracle(A, path, "zero pivot 1")
     assert info == 1 and not D.limbs.any()
@@ -94,7 +102,7 @@ def test_zero_pivots(path):
 
 @pytest.mark.parametrize("path", PATHS)
 def test_exponent_overflow(path):
-    P = 2
+    P = 8 if path == "mfma" else 2
     A = inputs.from_values([[1, 0, 0], [0, 1, 0], [0, 0, 1]], P)
     A.exp[0, 0] = 2 ** 61
     A.exp[1, 1] = 2 ** 61 + 5
@@ -128,3 +136,38 @@ def test_to_f64_matches_oracle():
     wm, we = oracle.to_f64(x)
     assert np.array_equal(mant.cpu().numpy(), wm)
     assert np.array_equal(e.cpu().numpy(), we)
+
+
+@pytest.mark.parametrize("N,P", [(3, 8), (33, 8), (40, 16), (37, 24), (66, 32), (20, 40), (70, 64),
+                                 (35, 128), (9, 256)])
+def test_mfma_shapes(N, P):
+    """MFMA path: ragged column blocks (N-k-1 not a multiple of 32), partial
+    product chunks (2*P8 not a multiple of 256) and several chunk counts."""
+    A = inputs.random_mantissas((N, N), P, 4000 + 13 * N + P)
+    check_against_oracle(A, "mfma", f"mfma shape N={N} P={P}")
+
+
+def test_mfma_digit_carry_extremes():
+    """Bytes 0x7F/0x80/0xFF patterns drive every balanced-digit carry case."""
+    P = 16
+    N = 20
+    A = inputs.random_mantissas((N, N), P, 55)
+    pats = [0x7F7F7F7F, 0x80808080, 0xFFFFFFFF, 0x7F80FF7F, 0x00000000, 0x807F0080]
+    for i in range(N):
+        for j in range(N):
+            if (i + j) % 3 == 0:
+                A.limbs[i, j, :] = np.uint32(pats[(i * N + j) % len(pats)])
+                A.limbs[i, j, -1] |= np.uint32(0x80000000)
+    check_against_oracle(A, "mfma", "digit extremes")
+
+
+def test_mfma_equals_valu_config2_sized():
+    """Both paths on the same config-2-sized numbers (4096-bit), N=100."""
+    c = inputs.config_c2(N=100)
+    for name in ("cauchy", "randmant"):
+        A = c[name][0] if name == "cauchy" else c[name]
+        check_against_oracle(A, "mfma", f"C2-sized {name}")
+        a = gpu_det(A, "valu")
+        b = gpu_det(A, "mfma")
+        for x, y, w in ((a[0], b[0], "LU"), (a[1], b[1], "D"), (a[2], b[2], "c")):
+            assert_same(x, y, f"valu vs mfma {name} {w}")
