@@ -125,7 +125,8 @@ int mp_to_f64(mpdet_handle *h, mpdet_mat x, double *mant_dev, int64_t *exp_dev,
  * this handle with two events on the launch stream; mpdet_profile_end waits
  * for those events and adds their elapsed times to the totals;
  * mpdet_profile_get returns the total milliseconds and launch count of one
- * kernel: "pivot_divide", "update_valu", "update_mfma", "mfma_prep",
+ * kernel: "pivot_divide" (leading determinant and the pivot's reciprocal),
+ * "divide" (multipliers), "update_valu", "update_mfma", "mfma_prep",
  * "minors_sweep", "minors_final" or "other" (MPDET_EINVAL for other names).
  */
 int mpdet_profile_begin(mpdet_handle *h);

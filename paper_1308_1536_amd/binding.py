@@ -235,7 +235,7 @@ def to_f64(x: DeviceMp, stream=None):
     return mant, e
 
 
-KERNELS = ("pivot_divide", "update_valu", "update_mfma", "mfma_prep", "minors_sweep",
+KERNELS = ("pivot_divide", "divide", "update_valu", "update_mfma", "mfma_prep", "minors_sweep",
            "minors_final", "other")
 
 

@@ -181,21 +181,34 @@ __global__ void __launch_bounds__(64) k_update_mfma(MatDev A, const uint8_t *Lr,
         int c_lo = r0 - 31 - P8;
         c_lo = c_lo <= 0 ? 0 : ((c_lo + 31) & ~31);
         const int c_hi = min(P8, r0 + 224);
-        v4i fr[8];
+        const int nsteps = (c_hi - c_lo) / 32 + 1;
+        // Step n, tile t uses the A fragment with d = r0 + 32(t - n) - c_lo,
+        // kept in window slot (t - n) mod 8; the slot of tile 7 is refilled with
+        // the next step's tile-0 fragment, so slots rotate by renaming inside
+        // the 8-way unrolled loop.  B fragments sit in an 8-deep register ring
+        // (prefetch distance 8 steps).  All 8 MFMAs run every step: a fragment
+        // outside the band is zero.
+        v4i W[8], BR[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) fr[t] = load_a(lr, r0 + 32 * t - c_lo, P8, Q);
-        for (int c0 = c_lo; c0 <= c_hi; c0 += 32) {
-            v4i bv = {0, 0, 0, 0};
-            if (jvalid) bv = *(const v4i *)(ub + c0);
+        for (int t = 0; t < 8; ++t) W[t] = load_a(lr, r0 + 32 * t - c_lo, P8, Q);
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const int d = r0 + 32 * t - c0;
-                if (d >= -31 && d <= P8 + 31 && r0 + 32 * t < 2 * P8)
-                    acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fr[t], bv, acc[t], 0, 0, 0);
+        for (int u = 0; u < 8; ++u) {
+            BR[u] = (v4i){0, 0, 0, 0};
+            if (jvalid && u < nsteps) BR[u] = *(const v4i *)(ub + c_lo + 32 * u);
+        }
+        for (int n8 = 0; n8 < nsteps; n8 += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int n = n8 + u;
+                const int c0 = c_lo + 32 * n;
+                const v4i bv = BR[u];
+                BR[u] = (v4i){0, 0, 0, 0};
+                if (jvalid && n + 8 < nsteps) BR[u] = *(const v4i *)(ub + c0 + 256);
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(W[(t - u) & 7], bv, acc[t], 0, 0, 0);
+                W[(7 - u) & 7] = load_a(lr, r0 - c0 - 32, P8, Q);
             }
-#pragma unroll
-            for (int t = 7; t > 0; --t) fr[t] = fr[t - 1];
-            fr[0] = load_a(lr, r0 - c0 - 32, P8, Q);
         }
         // biased 64-bit limb columns: lane (j, h), tile t, group gq holds r =
         // r0 + 32t + 8gq + 4h + {0..3}, i.e. limb q = r0/4 + 8t + 2gq + h
@@ -218,12 +231,18 @@ __global__ void __launch_bounds__(64) k_update_mfma(MatDev A, const uint8_t *Lr,
         mpw::wsync();
         if (h == 0) {
             const int qbase = r0 / 4;
-            for (int ql = 0; ql < 64; ++ql) {
-                const int q = qbase + ql;
-                if (q >= 2 * P) break;
-                const uint64_t x = vbuf[j * 65 + ql] + carry;
-                carry = x >> 32;
-                if (q >= P - 1 && jvalid) trow[q - (P - 1)] = (uint32_t)x;
+            const int qend = min(64, 2 * P - qbase);  // limbs of this chunk below 2P
+            for (int q8 = 0; q8 < qend; q8 += 8) {
+                uint64_t v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) v[u] = vbuf[j * 65 + q8 + u];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int q = qbase + q8 + u;
+                    const uint64_t x = v[u] + carry;
+                    carry = x >> 32;
+                    if (q8 + u < qend && q >= P - 1 && jvalid) trow[q - (P - 1)] = (uint32_t)x;
+                }
             }
         }
         mpw::wsync();
@@ -256,6 +275,140 @@ __global__ void __launch_bounds__(64) k_sub_mfma(MatDev A, const uint32_t *T, co
     mpw::Hdr ha = mpw::load(L.sc.x, am, ex(A, i, j), sg(A, i, j), P);
     mpw::Hdr hr = mpw::addsub(L.sc.t2, L.sc.x, ha, L.sc.t3, ht, L.sc.t0, L.sc.t1, P);
     mpw::store(am, &ex(A, i, j), &sg(A, i, j), L.sc.t2, hr, P);
+}
+
+// ---------------------------------------------------------------------------
+// Lane-per-element finish: a_ij = RZ_p(a_ij - t), t = RZ_p(l_i u_j) rebuilt
+// from the product's top limbs (raw[x] = product limb P-1+x, x = 0..P).
+// Same case analysis as mpw::addsub, run sequentially by one lane over the
+// limbs (low to high with one-limb register windows): G, the exact p+2-bit
+// intermediate, overwrites the lane's own raw record in place (every read of
+// the record is at or ahead of the limb being written), and the normalised
+// result goes to a_ij.
+// ---------------------------------------------------------------------------
+
+// sequential reader of mantissa limbs 0..P-1 of a or t (0 outside)
+struct LimbSrc {
+    const uint32_t *p;  // raw words
+    int off;            // limb q uses words q+off and q+off-1
+    int sh;             // 0: limb = p[q+off]; 1: limb = (p[q+off] << 1) | (p[q+off-1] >> 31)
+    int P;
+    __device__ __forceinline__ uint32_t word(int64_t idx) const {
+        return (idx >= 0 && idx < (int64_t)P + off) ? p[idx] : 0u;
+    }
+    __device__ __forceinline__ uint32_t limb(int64_t q) const {
+        if (q < 0 || q >= P) return 0u;
+        uint32_t hi = word(q + off);
+        if (!sh) return hi;
+        return (hi << 1) | (word(q + off - 1) >> 31);
+    }
+};
+
+__global__ void __launch_bounds__(256) k_sub_lane(MatDev A, uint32_t *T, const int32_t *info, int64_t k,
+                                                  int64_t n, int P) {
+    if (*info != 0) return;
+    const MfmaGeom g = mfma_geom(P);
+    const int64_t m = n - k - 1;
+    const int64_t id = ((int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x) * blockDim.x + threadIdx.x;
+    if (id >= m * m) return;
+    const int64_t ip = id / m, jp = id % m;
+    const int64_t i = k + 1 + ip, j = k + 1 + jp;
+    if (el(A, i, k, P)[P - 1] == 0u || el(A, k, j, P)[P - 1] == 0u) return;
+    uint32_t *raw = T + (ip * m + jp) * (int64_t)g.TP;
+    uint32_t *am = el(A, i, j, P);
+    const int64_t p = 32LL * P;
+    const int top = (int)(raw[P] >> 31);
+    const LimbSrc ts{raw, 1, 1 - top, P};
+    const LimbSrc as{am, 0, 0, P};
+    const int64_t et = ex(A, i, k) + ex(A, k, j) - 1 + top;
+    const int32_t sy = sg(A, i, k) ^ sg(A, k, j) ^ 1;  // sign of -t
+    const int64_t ea = ex(A, i, j);
+    const int32_t sa = sg(A, i, j);
+    int64_t *eo = &ex(A, i, j);
+    int32_t *so = &sg(A, i, j);
+    if (am[P - 1] == 0u) {  // 0 - t
+        for (int q = 0; q < P; ++q) am[q] = ts.limb(q);
+        *eo = et;
+        *so = sy;
+        return;
+    }
+    const bool subtract = sa != sy;
+    bool a_is_x = ea > et || (ea == et && !subtract);
+    if (ea == et && subtract) {
+        int c = 0;
+        for (int q = P - 1; q >= 0 && c == 0; --q) {
+            uint32_t x = as.limb(q), y = ts.limb(q);
+            c = x > y ? 1 : (x < y ? -1 : 0);
+        }
+        if (c == 0) {
+            for (int q = 0; q < P; ++q) am[q] = 0u;
+            *eo = 0;
+            *so = 0;
+            return;
+        }
+        a_is_x = c > 0;
+    }
+    const LimbSrc X = a_is_x ? as : ts, Y = a_is_x ? ts : as;
+    const int64_t eX = a_is_x ? ea : et, eY = a_is_x ? et : ea;
+    const int32_t sX = a_is_x ? sa : sy;
+    const uint64_t d = (uint64_t)eX - (uint64_t)eY;
+    const int gsh = subtract ? (int)(d < 2 ? d : 2) : 0;  // left shift of X
+    const uint64_t rsu = subtract ? (d < 2 ? 0 : d - 2) : d;  // right shift of Y
+    const int64_t rs = (int64_t)(rsu > (uint64_t)(p + 64) ? (uint64_t)(p + 64) : rsu);
+    const int64_t w = rs / 32;
+    const int b = (int)(rs % 32);
+    uint32_t borrow_or_carry = 0;
+    if (subtract && rs > 0) {  // sticky: any bit of Y below bit rs
+        bool st = false;
+        for (int64_t q = 0; q < P && q <= w && !st; ++q) {
+            uint32_t v = Y.limb(q);
+            if (q < w) st = v != 0u;
+            else if (b) st = (v & ((1u << b) - 1u)) != 0u;
+        }
+        borrow_or_carry = st ? 1u : 0u;
+    }
+    uint32_t xprev = 0;
+    uint32_t ylo = Y.limb(w);
+    for (int q = 0; q <= P; ++q) {
+        const uint32_t xq = X.limb(q);
+        const uint32_t yhi = Y.limb(w + q + 1);
+        const uint32_t xg = gsh ? ((xq << gsh) | (xprev >> (32 - gsh))) : xq;
+        const uint32_t ysh = b ? ((ylo >> b) | (yhi << (32 - b))) : ylo;
+        uint32_t gq;
+        if (!subtract) {
+            uint64_t sum = (uint64_t)xg + ysh + borrow_or_carry;
+            gq = (uint32_t)sum;
+            borrow_or_carry = (uint32_t)(sum >> 32);
+        } else {
+            int64_t df = (int64_t)xg - (int64_t)ysh - (int64_t)borrow_or_carry;
+            gq = (uint32_t)df;
+            borrow_or_carry = df < 0 ? 1u : 0u;
+        }
+        raw[q] = gq;
+        xprev = xq;
+        ylo = yhi;
+    }
+    // normalise G (P+1 limbs in raw) to p bits
+    int qt = P;
+    while (qt >= 0 && raw[qt] == 0u) --qt;
+    if (qt < 0) {
+        for (int q = 0; q < P; ++q) am[q] = 0u;
+        *eo = 0;
+        *so = 0;
+        return;
+    }
+    const int64_t L = 32LL * qt + 32 - __clz(raw[qt]);
+    const int64_t sr = L - p;  // bits to drop (may be negative: shift left)
+    const int64_t w0 = sr >= 0 ? sr / 32 : -((-sr + 31) / 32);
+    const int bb = (int)(sr - 32 * w0);
+    for (int q = 0; q < P; ++q) {
+        const int64_t lo_i = q + w0, hi_i = q + w0 + 1;
+        const uint32_t lo = (lo_i >= 0 && lo_i <= P) ? raw[lo_i] : 0u;
+        const uint32_t hi = (hi_i >= 0 && hi_i <= P) ? raw[hi_i] : 0u;
+        am[q] = bb ? ((lo >> bb) | (hi << (32 - bb))) : lo;
+    }
+    *eo = eX - gsh - p + L;
+    *so = sX;
 }
 
 }  // namespace mpk

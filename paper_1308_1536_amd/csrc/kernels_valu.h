@@ -24,13 +24,13 @@ __device__ __forceinline__ int32_t &sg(const MatDev &A, int64_t i, int64_t j) { 
 
 constexpr int64_t kExpLimit = 1LL << 62;
 
-// LDS carve-up shared by all VALU kernels (12P + 138 limbs in total).
+// LDS carve-up shared by all VALU kernels (12P + 2*MP_YPAD + 10 limbs).
 struct Lds {
     mpw::Scratch sc;  // x, ypad, prod, t0..t3
     __device__ Lds(uint32_t *base, int P) {
         sc.x = base;
         sc.ypad = sc.x + P;
-        sc.prod = sc.ypad + P + 2 * MP_WAVE;
+        sc.prod = sc.ypad + P + 2 * MP_YPAD;
         sc.t0 = sc.prod + 2 * P + 2;
         sc.t1 = sc.t0 + 2 * P + 2;
         sc.t2 = sc.t1 + 2 * P + 2;
@@ -38,17 +38,18 @@ struct Lds {
     }
 };
 
-__host__ __device__ constexpr size_t lds_bytes(int P) { return (size_t)(12 * P + 138) * 4u; }
+__host__ __device__ constexpr size_t lds_bytes(int P) { return (size_t)(12 * P + 2 * MP_YPAD + 10) * 4u; }
 
-// y operand of a product: value at ypad + 64, zero limbs around it
+// y operand of a product: value at ypad + MP_YPAD, zero limbs around it
 __device__ __forceinline__ mpw::Hdr load_y(uint32_t *ypad, const uint32_t *src, int64_t e, int32_t s,
                                            int P) {
-    for (int q = mpw::lane(); q < P + 2 * MP_WAVE; q += MP_WAVE) {
-        int k = q - MP_WAVE;
-        ypad[q] = (k >= 0 && k < P) ? src[k] : 0u;
+    for (int q = mpw::lane(); q < MP_YPAD; q += MP_WAVE) {
+        ypad[q] = 0u;
+        ypad[MP_YPAD + P + q] = 0u;
     }
+    mpw::gload(ypad + MP_YPAD, src, P);
     mpw::wsync();
-    bool z = ypad[MP_WAVE + P - 1] == 0u;
+    bool z = ypad[MP_YPAD + P - 1] == 0u;
     return z ? mpw::zero_hdr() : mpw::Hdr{e, s, false};
 }
 
@@ -61,20 +62,27 @@ __device__ void store_zero(uint32_t *l, int64_t *e, int32_t *s, int P) {
 }
 
 // ---------------------------------------------------------------------------
-// Step k, part 1 (Algorithm 1 steps 2.1 and 2.2.1).
-// Block 0: D_k = D_{k-1} * pivot (D_1 = pivot), zero / overflow checks, info.
-// Block b >= 1: multiplier of row i = k + b: l_ik = RZ_p(a_ik / a_kk), in place.
+// Step k, part 1 (Algorithm 1 steps 2.1 and 2.2.1), with one shared reciprocal.
+// k_pivot_recip: block 0 = D_k = RZ_p(D_{k-1} a_kk) (D_1 = a_11) and the zero /
+// overflow checks that set info; block 1 = R = floor(2^(2p) / m_pivot) into rw[0..P], with
+// rw[P+1] = 1 when the reciprocal is exact (0: callers use long division).
+// k_divide: block b -> l_ik = RZ_p(a_ik / a_kk) for i = k+1+b.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_pivot_divide(MatDev A, MatDev D, int32_t *info, int64_t k,
-                                                     int64_t n, int P) {
+__host__ __device__ inline size_t pivot_lds_bytes(int P) {
+    size_t a = lds_bytes(P), b = mpw::div_lds_limbs(P) * 4u;
+    return a > b ? a : b;
+}
+
+__global__ void __launch_bounds__(64) k_pivot_recip(MatDev A, MatDev D, int32_t *info, uint32_t *rw, int64_t k,
+                                                    int64_t n, int P) {
     extern __shared__ uint32_t lds_raw[];
     if (*info != 0) return;
-    Lds L(lds_raw, P);
     const uint32_t *pm = el(A, k, k, P);
     const bool piv_zero = pm[P - 1] == 0u;
     const int64_t pe = ex(A, k, k);
     const int32_t ps = sg(A, k, k);
     if (blockIdx.x == 0) {
+        Lds L(lds_raw, P);
         bool bad = false;
         int32_t code = 0;
         mpw::Hdr hd{0, 0, true};
@@ -84,7 +92,7 @@ __global__ void __launch_bounds__(64) k_pivot_divide(MatDev A, MatDev D, int32_t
         } else {
             mpw::Hdr hp = load_y(L.sc.ypad, pm, pe, ps, P);
             if (k == 0) {
-                mpw::copy(L.sc.t3, L.sc.ypad + MP_WAVE, P);
+                mpw::copy(L.sc.t3, L.sc.ypad + MP_YPAD, P);
                 mpw::wsync();
                 hd = hp;
             } else {
@@ -104,14 +112,34 @@ __global__ void __launch_bounds__(64) k_pivot_divide(MatDev A, MatDev D, int32_t
         }
         return;
     }
-    if (piv_zero) return;
-    const int64_t i = k + (int64_t)blockIdx.x;
+    if (piv_zero || n - k - 1 <= 0) return;
+    mpw::DivBufs B = mpw::div_bufs(lds_raw, P);
+    mpw::gload(B.v, pm, P);
+    mpw::wsync();
+    const bool ok = mpw::recip(B, P);
+    for (int q = mpw::lane(); q < P + 1; q += MP_WAVE) rw[q] = B.x[q];
+    if (mpw::lane() == 0) rw[P + 1] = ok ? 1u : 0u;
+}
+
+__global__ void __launch_bounds__(64) k_divide(MatDev A, const uint32_t *rw, const int32_t *info, int64_t k,
+                                               int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    const uint32_t *pm = el(A, k, k, P);
+    if (pm[P - 1] == 0u) return;
+    const int64_t i = k + 1 + (int64_t)blockIdx.x;
     uint32_t *am = el(A, i, k, P);
-    mpw::Hdr ha = mpw::load(L.sc.x, am, ex(A, i, k), sg(A, i, k), P);
-    mpw::Hdr hp = mpw::load(L.sc.ypad, pm, pe, ps, P);
-    // U = prod (2P+2), LO = t0, HI = t1, Q = t2, out = t3
-    mpw::Hdr hq = mpw::div(L.sc.t3, L.sc.x, ha, L.sc.ypad, hp, L.sc.prod, L.sc.t0, L.sc.t1, L.sc.t2, P);
-    mpw::store(am, &ex(A, i, k), &sg(A, i, k), L.sc.t3, hq, P);
+    mpw::DivBufs B = mpw::div_bufs(lds_raw, P);
+    mpw::Hdr ha = mpw::load(B.a, am, ex(A, i, k), sg(A, i, k), P);
+    mpw::Hdr hp = mpw::load(B.v, pm, ex(A, k, k), sg(A, k, k), P);
+    mpw::Hdr hq;
+    bool done = false;
+    if (rw[P + 1] != 0u) done = mpw::div_by_recip(B.t3, hq, ha, hp, rw, B, P);
+    if (!done) {
+        // long division: U = prod (2P+2), LO = t0, HI = t1, Q = t2, out = t3
+        hq = mpw::div(B.t3, B.a, ha, B.v, hp, B.prod, B.t0, B.t1, B.t2, P);
+    }
+    mpw::store(am, &ex(A, i, k), &sg(A, i, k), B.t3, hq, P);
 }
 
 // ---------------------------------------------------------------------------

@@ -16,9 +16,9 @@
 // Per-kernel timing (off by default): each launch is bracketed by two HIP
 // events recorded on the launch stream; mpdet_profile_end folds the elapsed
 // times into per-kernel totals.
-enum KernelId { K_PIVOT_DIVIDE = 0, K_UPDATE_VALU, K_UPDATE_MFMA, K_MFMA_PREP, K_MINORS_SWEEP,
+enum KernelId { K_PIVOT_DIVIDE = 0, K_DIVIDE, K_UPDATE_VALU, K_UPDATE_MFMA, K_MFMA_PREP, K_MINORS_SWEEP,
                 K_MINORS_FINAL, K_OTHER, K_COUNT };
-static const char *kKernelNames[K_COUNT] = {"pivot_divide", "update_valu", "update_mfma", "mfma_prep",
+static const char *kKernelNames[K_COUNT] = {"pivot_divide", "divide", "update_valu", "update_mfma", "mfma_prep",
                                             "minors_sweep", "minors_final", "other"};
 
 struct ProfRec {
@@ -38,6 +38,9 @@ struct mpdet_handle {
     // MFMA-path workspace (grown on demand, freed by mpdet_destroy)
     void *ws;
     size_t ws_bytes;
+    // the pivot's reciprocal
+    void *rw;
+    size_t rw_bytes;
 };
 
 namespace {
@@ -119,18 +122,54 @@ struct DeviceGuard {
     }
 };
 
+// Scratch for the pivot's reciprocal: P + 2 limbs (R and its exactness flag).
+int recip_ws(mpdet_handle *h, int P, uint32_t **rw) {
+    const size_t need = ((size_t)(P + 2) * 4u + 255) & ~(size_t)255;
+    if (need > h->rw_bytes) {
+        if (h->rw) (void)hipFree(h->rw);
+        h->rw = nullptr;
+        h->rw_bytes = 0;
+        if (hipMalloc(&h->rw, need) != hipSuccess) {
+            h->rw = nullptr;
+            (void)hipGetLastError();
+            return MPDET_ENOMEM;
+        }
+        h->rw_bytes = need;
+    }
+    *rw = (uint32_t *)h->rw;
+    return MPDET_OK;
+}
+
+// Algorithm 1 steps 2.1 and 2.2.1 for step k: D_k and the pivot's reciprocal,
+// then the multipliers of rows k+1..n-1.
+int pivot_step(mpdet_handle *h, const mpk::MatDev &a, const mpk::MatDev &d, int32_t *info, int64_t k, int64_t n,
+               int P, hipStream_t s) {
+    uint32_t *rw = nullptr;
+    int rc = recip_ws(h, P, &rw);
+    if (rc) return rc;
+    const size_t lds = mpk::pivot_lds_bytes(P);
+    {
+        Prof pr(h, s, K_PIVOT_DIVIDE);
+        hipLaunchKernelGGL(mpk::k_pivot_recip, dim3(2), dim3(64), lds, s, a, d, info, rw, k, n, P);
+    }
+    if ((rc = last_launch())) return rc;
+    const int64_t m = n - k - 1;
+    if (m <= 0) return MPDET_OK;
+    {
+        Prof pr(h, s, K_DIVIDE);
+        hipLaunchKernelGGL(mpk::k_divide, dim3((unsigned)m), dim3(64), lds, s, a, (const uint32_t *)rw,
+                           (const int32_t *)info, k, n, P);
+    }
+    return last_launch();
+}
+
 int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, hipStream_t s) {
     const int64_t n = A.rows;
     const int P = A.nlimbs;
     const size_t lds = mpk::lds_bytes(P);
     mpk::MatDev a = dev(A), d = dev(D);
     for (int64_t k = 0; k < n; ++k) {
-        {
-            Prof pr(h, s, K_PIVOT_DIVIDE);
-            hipLaunchKernelGGL(mpk::k_pivot_divide, dim3((unsigned)(n - k)), dim3(64), lds, s, a, d, info, k, n,
-                               P);
-        }
-        int rc = last_launch();
+        int rc = pivot_step(h, a, d, info, k, n, P, s);
         if (rc) return rc;
         const int64_t m = n - k - 1;
         if (m > 0) {
@@ -183,16 +222,11 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     MfmaWs w;
     int rc = mfma_workspace(h, n > 1 ? n - 1 : 1, P, &w);
     if (rc) return rc;
-    const size_t lds = mpk::lds_bytes(P), lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
+    const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
     mpk::MatDev a = dev(A), d = dev(D);
     const int32_t *cinfo = info;
     for (int64_t k = 0; k < n; ++k) {
-        {
-            Prof pr(h, s, K_PIVOT_DIVIDE);
-            hipLaunchKernelGGL(mpk::k_pivot_divide, dim3((unsigned)(n - k)), dim3(64), lds, s, a, d, info, k, n,
-                               P);
-        }
-        if ((rc = last_launch())) return rc;
+        if ((rc = pivot_step(h, a, d, info, k, n, P, s))) return rc;
         const int64_t m = n - k - 1;
         if (m <= 0) continue;
         {
@@ -209,8 +243,8 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
         if ((rc = last_launch())) return rc;
         {
             Prof pr(h, s, K_OTHER);
-            hipLaunchKernelGGL(mpk::k_sub_mfma, grid_for(m * m), dim3(64), lds, s, a, (const uint32_t *)w.T, cinfo,
-                               k, n, P);
+            hipLaunchKernelGGL(mpk::k_sub_mfma, grid_for(m * m), dim3(64), mpk::lds_bytes(P), s, a,
+                               (const uint32_t *)w.T, cinfo, k, n, P);
         }
         if ((rc = last_launch())) return rc;
     }
@@ -253,6 +287,7 @@ int mpdet_destroy(mpdet_handle *h) {
     free(h->pool);
     free(h->recs);
     if (h->ws) (void)hipFree(h->ws);
+    if (h->rw) (void)hipFree(h->rw);
     free(h);
     return MPDET_OK;
 }

@@ -18,6 +18,8 @@
 #include <stdint.h>
 
 #define MP_WAVE 64
+// zero limbs on each side of the y operand of a product (covers r - a - 3 >= -66)
+#define MP_YPAD 72
 
 namespace mpw {
 
@@ -158,26 +160,48 @@ __device__ __forceinline__ int cmp(const uint32_t *a, const uint32_t *b, int n) 
 
 // ---------------------------------------------------------------------------
 // full product of two P-limb integers: prod[0..2P) = x * y
-//   x: LDS, P limbs;  ypad: LDS, P + 128 limbs with y at ypad + 64 and 64 zero
-//   limbs on each side;  t0..t3: LDS scratch of 2P limbs each.
+//   x: LDS, P limbs;  ypad: LDS, P + 2*MP_YPAD limbs with y at ypad + MP_YPAD
+//   and zero limbs on each side;  t0..t3: LDS scratch of 2P limbs each.
 // Lane t accumulates the product columns r = t, t+64, ... (96-bit sums of
 // x[a] * y[r-a]); the columns are then folded into limbs by carry passes that
 // never write a buffer they read.
 // ---------------------------------------------------------------------------
-__device__ void mul_full(uint32_t *prod, const uint32_t *x, const uint32_t *ypad, int P,
-                         uint32_t *t0, uint32_t *t1, uint32_t *t2, uint32_t *t3) {
-    const int R = 2 * P;
-    const uint32_t *y = ypad + MP_WAVE;
+// prod[0..ncols) = (x * y) mod 2^(32 ncols) for x of nx limbs and y of ny
+// limbs (ncols <= nx + ny).  x: LDS; ypad: LDS, y at ypad + MP_YPAD with
+// MP_YPAD zero limbs on each side; t0..t3: LDS scratch of ncols limbs each.
+__device__ void mul_gen(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *ypad, int ny,
+                        uint32_t *t0, uint32_t *t1, uint32_t *t2, uint32_t *t3) {
+    const int R = ncols;
+    const uint32_t *y = ypad + MP_YPAD;
     for (int base = 0; base < R; base += MP_WAVE) {
-        int r = base + lane();
-        int a0 = max(0, base - P + 1), a1 = min(base + MP_WAVE - 1, P - 1);
-        uint64_t acc = 0;
-        uint32_t acc_hi = 0;
-        for (int a = a0; a <= a1; ++a) {
-            uint64_t pr = (uint64_t)x[a] * (uint64_t)y[r - a];
-            acc += pr;
-            acc_hi += (acc < pr) ? 1u : 0u;
+        const int r = base + lane();
+        const int a0 = max(0, base - ny + 1), a1 = min(base + MP_WAVE - 1, nx - 1);
+        // two independent 96-bit accumulators break the add dependency chain
+        uint64_t acc0 = 0, acc1 = 0;
+        uint32_t hi0 = 0, hi1 = 0;
+        int a = a0;
+        for (; a + 3 <= a1; a += 4) {
+            uint4 xv, yv;  // x[a..a+3] (same for all lanes), y[r-a-3 .. r-a]
+            __builtin_memcpy(&xv, x + a, 16);
+            __builtin_memcpy(&yv, y + (r - a - 3), 16);
+            uint64_t p0 = (uint64_t)xv.x * yv.w, p1 = (uint64_t)xv.y * yv.z;
+            uint64_t p2 = (uint64_t)xv.z * yv.y, p3 = (uint64_t)xv.w * yv.x;
+            acc0 += p0;
+            hi0 += acc0 < p0;
+            acc1 += p1;
+            hi1 += acc1 < p1;
+            acc0 += p2;
+            hi0 += acc0 < p2;
+            acc1 += p3;
+            hi1 += acc1 < p3;
         }
+        for (; a <= a1; ++a) {
+            uint64_t pr = (uint64_t)x[a] * (uint64_t)y[r - a];
+            acc0 += pr;
+            hi0 += acc0 < pr;
+        }
+        uint64_t acc = acc0 + acc1;
+        uint32_t acc_hi = hi0 + hi1 + (acc < acc0 ? 1u : 0u);
         if (r < R) {
             t0[r] = (uint32_t)acc;
             t1[r] = (uint32_t)(acc >> 32);
@@ -205,17 +229,64 @@ __device__ void mul_full(uint32_t *prod, const uint32_t *x, const uint32_t *ypad
     wsync();
 }
 
+// prod[0..2P) = x * y for two P-limb integers
+__device__ __forceinline__ void mul_full(uint32_t *prod, const uint32_t *x, const uint32_t *ypad, int P,
+                                         uint32_t *t0, uint32_t *t1, uint32_t *t2, uint32_t *t3) {
+    mul_gen(prod, 2 * P, x, P, ypad, P, t0, t1, t2, t3);
+}
+
+// place n limbs of src as the y operand of mul_gen (zero pads around)
+__device__ __forceinline__ void set_y(uint32_t *ypad, const uint32_t *src, int n, int cap) {
+    for (int q = lane(); q < cap + 2 * MP_YPAD; q += MP_WAVE) {
+        int k = q - MP_YPAD;
+        ypad[q] = (k >= 0 && k < n) ? src[k] : 0u;
+    }
+}
+
 // Scratch for the number routines: every buffer is in LDS.
 struct Scratch {
     uint32_t *x;     // P
-    uint32_t *ypad;  // P + 128
+    uint32_t *ypad;  // P + 2*MP_YPAD
     uint32_t *prod;  // 2P + 2
     uint32_t *t0, *t1, *t2, *t3;  // 2P + 2 each
 };
 
+// Copy n limbs global -> LDS.  Lanes move 16-byte chunks when both sides
+// allow it (n % 4 == 0 and 16-byte aligned addresses); all of a lane's loads
+// are issued before its LDS stores.
+__device__ __forceinline__ void gload(uint32_t *dst, const uint32_t *src, int n) {
+    if ((n & 3) == 0 && (((uintptr_t)src | (uintptr_t)dst) & 15u) == 0) {
+        const int nc = n >> 2;
+        const uint4 *s4 = (const uint4 *)src;
+        uint4 *d4 = (uint4 *)dst;
+        int c = lane();
+        for (; c + 3 * MP_WAVE < nc; c += 4 * MP_WAVE) {
+            uint4 v0 = s4[c], v1 = s4[c + MP_WAVE], v2 = s4[c + 2 * MP_WAVE], v3 = s4[c + 3 * MP_WAVE];
+            d4[c] = v0;
+            d4[c + MP_WAVE] = v1;
+            d4[c + 2 * MP_WAVE] = v2;
+            d4[c + 3 * MP_WAVE] = v3;
+        }
+        for (; c < nc; c += MP_WAVE) d4[c] = s4[c];
+    } else {
+        for (int q = lane(); q < n; q += MP_WAVE) dst[q] = src[q];
+    }
+}
+
+__device__ __forceinline__ void gstore(uint32_t *dst, const uint32_t *src, int n) {
+    if ((n & 3) == 0 && (((uintptr_t)src | (uintptr_t)dst) & 15u) == 0) {
+        const int nc = n >> 2;
+        const uint4 *s4 = (const uint4 *)src;
+        uint4 *d4 = (uint4 *)dst;
+        for (int c = lane(); c < nc; c += MP_WAVE) d4[c] = s4[c];
+    } else {
+        for (int q = lane(); q < n; q += MP_WAVE) dst[q] = src[q];
+    }
+}
+
 // load a number from global memory into LDS (P limbs); returns its header
 __device__ __forceinline__ Hdr load(uint32_t *dst, const uint32_t *src, int64_t e, int32_t s, int P) {
-    for (int q = lane(); q < P; q += MP_WAVE) dst[q] = src[q];
+    gload(dst, src, P);
     wsync();
     bool z = dst[P - 1] == 0u;
     return z ? zero_hdr() : Hdr{e, s, false};
@@ -223,14 +294,18 @@ __device__ __forceinline__ Hdr load(uint32_t *dst, const uint32_t *src, int64_t 
 
 __device__ __forceinline__ void store(uint32_t *dst_limbs, int64_t *dst_e, int32_t *dst_s,
                                       const uint32_t *src, Hdr h, int P) {
-    for (int q = lane(); q < P; q += MP_WAVE) dst_limbs[q] = h.zero ? 0u : src[q];
+    if (h.zero) {
+        for (int q = lane(); q < P; q += MP_WAVE) dst_limbs[q] = 0u;
+    } else {
+        gstore(dst_limbs, src, P);
+    }
     if (lane() == 0) {
         *dst_e = h.zero ? 0 : h.e;
         *dst_s = h.zero ? 0 : h.s;
     }
 }
 
-// out = RZ_p(x * y).  x in sc.x, y in sc.ypad + 64 (pads must be zero).
+// out = RZ_p(x * y).  x in sc.x, y in sc.ypad + MP_YPAD (pads must be zero).
 __device__ Hdr mul(uint32_t *out, Hdr hx, Hdr hy, int P, const Scratch &sc) {
     if (hx.zero || hy.zero) return zero_hdr();
     mul_full(sc.prod, sc.x, sc.ypad, P, sc.t0, sc.t1, sc.t2, sc.t3);
@@ -309,53 +384,320 @@ __device__ Hdr addsub(uint32_t *out, const uint32_t *xm, Hdr hx, const uint32_t 
     return normalise(out, G, n, hX.e - g - 32LL * P, hX.s, P);
 }
 
+// floor(num / v1) for v1 >= 2^31 and num < v1 * 2^32: a float64 estimate
+// (error below one unit) fixed up with exact 64-bit remainders.
+__device__ __forceinline__ uint64_t udiv_2by1(uint64_t num, uint32_t v1) {
+    uint64_t q = (uint64_t)((double)num / (double)v1);
+    if (q > 0xFFFFFFFFull) q = 0xFFFFFFFFull;
+    int64_t r = (int64_t)(num - q * (uint64_t)v1);
+    while (r < 0) {
+        q--;
+        r += v1;
+    }
+    while (r >= (int64_t)v1) {
+        q++;
+        r -= v1;
+    }
+    return q;
+}
+
+constexpr int kMaxDivBlocks = 17;  // ceil((1024 + 1) / 64)
+
 // out = RZ_p(a / b), b != 0 with its top bit set.
 // Knuth's Algorithm D in base 2^32 on U = m_a * 2^(p+1) (2P+1 limbs, plus a
 // zero limb on top) and V = m_b (already normalised); the quotient Q has
-// p+1 or p+2 bits and is truncated to p bits.
-//   U: LDS 2P+2 limbs; LO, HI: LDS P+1 limbs; Q: LDS P+2 limbs.
+// p+1 or p+2 bits and is truncated to p bits.  Per quotient digit the
+// remainder window U[j..j+P] -= qhat * V runs in registers: lane t owns
+// window limbs t, t+64, ...; the product's high words and the first-stage
+// borrows (0..2) move one limb up by lane shuffles, and the remaining 1-bit
+// borrows are resolved by the ballot lookahead.  One LDS barrier per digit.
+//   U: LDS 2P+2 limbs; LO, HI: unused (kept for the layout); Q: LDS P+2 limbs.
 __device__ Hdr div(uint32_t *out, const uint32_t *am, Hdr ha, const uint32_t *bm, Hdr hb,
                    uint32_t *U, uint32_t *LO, uint32_t *HI, uint32_t *Q, int P) {
+    (void)LO;
+    (void)HI;
     if (ha.zero) return zero_hdr();
     const int m = 2 * P + 1;
+    const int n1 = P + 1;  // window limbs
+    const int S = (n1 + MP_WAVE - 1) / MP_WAVE;
     shift(U, m + 1, am, P, 32LL * P + 1);
     fill(Q, P + 2, 0u);
+    uint32_t vreg[kMaxDivBlocks];
+#pragma unroll
+    for (int s = 0; s < kMaxDivBlocks; ++s) {
+        const int q = s * MP_WAVE + lane();
+        vreg[s] = (s < S && q < P) ? bm[q] : 0u;
+    }
     wsync();
     const uint64_t B = 1ull << 32;
-    const uint64_t v1 = bm[P - 1], v2 = bm[P - 2];
+    const uint32_t v1 = bm[P - 1], v2 = bm[P - 2];
     for (int j = m - P; j >= 0; --j) {
-        uint64_t num = ((uint64_t)U[j + P] << 32) | U[j + P - 1];
-        uint64_t qhat = num / v1;
-        uint64_t rhat = num - qhat * v1;
-        while (qhat >= B || qhat * v2 > ((rhat << 32) | U[j + P - 2])) {
+        const uint32_t u2 = U[j + P], u1 = U[j + P - 1], u0 = U[j + P - 2];
+        const uint64_t num = ((uint64_t)u2 << 32) | u1;
+        uint64_t qhat, rhat;
+        if (u2 >= v1) {
+            qhat = B - 1;
+            rhat = num - qhat * v1;
+        } else {
+            qhat = udiv_2by1(num, v1);
+            rhat = num - qhat * v1;
+        }
+        while (rhat < B && qhat * v2 > ((rhat << 32) | u0)) {
             qhat--;
             rhat += v1;
-            if (rhat >= B) break;
         }
         if (qhat) {
-            for (int q = lane(); q < P + 1; q += MP_WAVE) {
-                uint64_t pr = q < P ? qhat * (uint64_t)bm[q] : 0ull;
-                LO[q] = (uint32_t)pr;
-                if (q < P) HI[q + 1] = (uint32_t)(pr >> 32);
+            uint32_t hi_in = 0, b1_in = 0, b2_in = 0;  // entering lane 0 of a block
+            uint32_t neg = 0;
+#pragma unroll
+            for (int s = 0; s < kMaxDivBlocks; ++s) {
+                if (s < S) {
+                    const int q = s * MP_WAVE + lane();
+                    const int cnt = min(MP_WAVE, n1 - s * MP_WAVE);
+                    const uint64_t pr = qhat * (uint64_t)vreg[s];
+                    const uint32_t lo = (uint32_t)pr, hi = (uint32_t)(pr >> 32);
+                    uint32_t hi_prev = __shfl_up(hi, 1);
+                    if (lane() == 0) hi_prev = hi_in;
+                    const uint32_t u = q < n1 ? U[j + q] : 0u;
+                    const int64_t diff = (int64_t)u - (int64_t)lo - (int64_t)hi_prev;
+                    const uint32_t limb = (uint32_t)diff;
+                    const uint32_t b1 = (uint32_t)(-(diff >> 32));  // 0, 1 or 2
+                    uint32_t b1_prev = __shfl_up(b1, 1);
+                    if (lane() == 0) b1_prev = b1_in;
+                    const int64_t t = (int64_t)limb - (int64_t)b1_prev;
+                    const uint32_t limb2 = (uint32_t)t;
+                    const bool gb = t < 0;
+                    const uint64_t valid = cnt == 64 ? ~0ull : ((1ull << cnt) - 1ull);
+                    const uint64_t G = __ballot(gb) & valid;
+                    const uint64_t Pm = __ballot(!gb && limb2 == 0u) & valid;
+                    const uint64_t C = lookahead(G, Pm, b2_in);
+                    const uint32_t cin = (uint32_t)((C >> lane()) & 1ull);
+                    if (q < n1) U[j + q] = limb2 - cin;
+                    b2_in = block_carry_out(G, Pm, C, cnt);
+                    hi_in = __shfl(hi, cnt - 1);
+                    b1_in = __shfl(b1, cnt - 1);
+                }
             }
-            if (lane() == 0) HI[0] = 0u;
+            // the top window limb's first-stage borrow and the chain's borrow
+            // leave the window: the difference is negative
+            neg = b1_in + b2_in;
             wsync();
-            uint32_t b1 = sub(U + j, U + j, LO, P + 1, 0u);
-            wsync();
-            uint32_t b2 = sub(U + j, U + j, HI, P + 1, 0u);
-            wsync();
-            if (b1 + b2) {
+            if (neg) {
                 qhat--;
-                for (int q = lane(); q < P + 1; q += MP_WAVE) LO[q] = q < P ? bm[q] : 0u;
-                wsync();
-                add(U + j, U + j, LO, P + 1, 0u);
+                uint32_t carry = 0;
+#pragma unroll
+                for (int s = 0; s < kMaxDivBlocks; ++s) {
+                    if (s < S) {
+                        const int q = s * MP_WAVE + lane();
+                        const int cnt = min(MP_WAVE, n1 - s * MP_WAVE);
+                        const uint32_t x = q < n1 ? U[j + q] : 0u, y = vreg[s];
+                        const uint32_t sm = x + y;
+                        const uint64_t valid = cnt == 64 ? ~0ull : ((1ull << cnt) - 1ull);
+                        const uint64_t G = __ballot(sm < x) & valid;
+                        const uint64_t Pm = __ballot(sm == 0xFFFFFFFFu) & valid;
+                        const uint64_t C = lookahead(G, Pm, carry);
+                        if (q < n1) U[j + q] = sm + (uint32_t)((C >> lane()) & 1ull);
+                        carry = block_carry_out(G, Pm, C, cnt);
+                    }
+                }
                 wsync();
             }
         }
         if (lane() == 0) Q[j] = (uint32_t)qhat;
+    }
+    wsync();
+    return normalise(out, Q, P + 2, ha.e - hb.e - 32LL * P - 1, ha.s ^ hb.s, P);
+}
+
+// ---------------------------------------------------------------------------
+// Division through one shared reciprocal.
+//
+// recip(): R = floor(2^(2p) / v) for v of P limbs with its top bit set.
+// Newton's iteration X <- X + X (1 - V X) on scaled integers: X_f ~ 2^(p+f)/v
+// carries f bits; one step goes from f to f' = min(2f - 8, p) using the top
+// g = f' + 16 bits of v:  T = V_g X_f ~ 2^(f+g)(1 - eps),  e = 2^(f+g) - T,
+// X_f' = X_f 2^(f'-f) + floor(X_f e / 2^(2f+g-f')).  The seed (f = 48) comes
+// from a float64 quotient of the top 64 bits of v.  The result is then made
+// exact by the remainder E = 2^(2p) - v R (R moves by one while E < 0 or
+// E >= v).  Correctness rests only on this final exact check; the error
+// analysis (about 8 units left) only bounds its trip count.  Returns false
+// when the correction did not settle within the bound (callers then fall back
+// to long division).
+// ---------------------------------------------------------------------------
+struct DivBufs {
+    uint32_t *x;     // P + 4
+    uint32_t *ypad;  // P + 4 + 2*MP_YPAD
+    uint32_t *prod;  // 2P + 4
+    uint32_t *t0, *t1, *t2, *t3;  // 2P + 4 each
+    uint32_t *a;     // P + 4
+    uint32_t *v;     // P + 4
+};
+
+__host__ __device__ constexpr size_t div_lds_limbs(int P) { return (size_t)(14 * P + 2 * MP_YPAD + 36); }
+
+__device__ __forceinline__ DivBufs div_bufs(uint32_t *base, int P) {
+    DivBufs b;
+    b.x = base;
+    b.ypad = b.x + P + 4;
+    b.prod = b.ypad + P + 4 + 2 * MP_YPAD;
+    b.t0 = b.prod + 2 * P + 4;
+    b.t1 = b.t0 + 2 * P + 4;
+    b.t2 = b.t1 + 2 * P + 4;
+    b.t3 = b.t2 + 2 * P + 4;
+    b.a = b.t3 + 2 * P + 4;
+    b.v = b.a + P + 4;
+    return b;
+}
+
+__device__ __forceinline__ int limbs_for_bits(int64_t bits) { return (int)((bits + 31) / 32); }
+
+// v must be in B.v (P limbs, top bit set); R (P + 1 limbs) is written to B.x.
+__device__ bool recip(const DivBufs &B, int P) {
+    const int64_t p = 32LL * P;
+    // seed: X_48 ~ 2^(p+48) / v = 2^112 / (top 64 bits of v)
+    if (lane() == 0) {
+        const uint64_t vt = ((uint64_t)B.v[P - 1] << 32) | B.v[P - 2];
+        const double q = 5192296858534827628530496329220096.0 / (double)vt;  // 2^112 / vt
+        const uint64_t X0 = (uint64_t)q;
+        B.x[0] = (uint32_t)X0;
+        B.x[1] = (uint32_t)(X0 >> 32);
+    }
+    wsync();
+    int64_t f = 48;
+    int nX = 2;
+    while (f < p) {
+        const int64_t f2 = min(2 * f - 8, p);
+        const int64_t gb = f2 + 16;
+        const int nV = limbs_for_bits(gb) + 1;
+        // V_g = floor(v * 2^(g - p)) into ypad (as the y operand)
+        shift(B.ypad + MP_YPAD, nV, B.v, P, gb - p);
+        for (int q = lane(); q < MP_YPAD; q += MP_WAVE) {
+            B.ypad[q] = 0u;
+            B.ypad[MP_YPAD + nV + q] = 0u;
+        }
+        wsync();
+        const int nT = nV + nX;
+        mul_gen(B.prod, nT, B.x, nX, B.ypad, nV, B.t0, B.t1, B.t2, B.t3);
+        // e = 2^(f+g) - T modulo 2^(32 nT): power of two minus the product
+        fill(B.t0, nT, 0u);
+        wsync();
+        if (lane() == 0) B.t0[(f + gb) / 32] = 1u << ((f + gb) % 32);
+        wsync();
+        sub(B.prod, B.t0, B.prod, nT, 0u);
+        wsync();
+        const bool eneg = (B.prod[nT - 1] >> 31) != 0u;
+        if (eneg) {  // |e| = -e
+            fill(B.t0, nT, 0u);
+            wsync();
+            sub(B.prod, B.t0, B.prod, nT, 0u);
+            wsync();
+        }
+        // |e| ~ 2^(g+8): keep its limbs as the y operand
+        const int ne = min(nT, limbs_for_bits(gb + 12) + 1);
+        if (top_nonzero(B.prod, nT) >= ne) return false;
+        set_y(B.ypad, B.prod, ne, max(nV, ne));
+        wsync();
+        const int nD = nX + ne;
+        mul_gen(B.prod, nD, B.x, nX, B.ypad, ne, B.t0, B.t1, B.t2, B.t3);
+        // X' = X 2^(f'-f) +- (X |e|) >> (2f + g - f')
+        const int nX2 = limbs_for_bits(f2 + 2) + 1;
+        shift(B.t0, nX2, B.x, nX, f2 - f);
+        shift(B.t1, nX2, B.prod, nD, -(2 * f + gb - f2));
+        wsync();
+        if (eneg) sub(B.x, B.t0, B.t1, nX2, 0u);
+        else add(B.x, B.t0, B.t1, nX2, 0u);
+        wsync();
+        f = f2;
+        nX = nX2;
+    }
+    // exact correction with E = 2^(2p) - v X over 2P + 2 limbs
+    const int nE = 2 * P + 2;
+    fill(B.x + nX, P + 4 - nX, 0u);
+    set_y(B.ypad, B.v, P, P + 4);
+    wsync();
+    mul_gen(B.prod, nE, B.x, P + 2, B.ypad, P, B.t0, B.t1, B.t2, B.t3);
+    fill(B.t0, nE, 0u);
+    wsync();
+    if (lane() == 0) B.t0[2 * P] = 1u;
+    wsync();
+    sub(B.prod, B.t0, B.prod, nE, 0u);  // E (two's complement over nE limbs)
+    wsync();
+    // v padded to nE limbs in t1, one in t2 (for X -+ 1)
+    fill(B.t1, nE, 0u);
+    fill(B.t2, nE, 0u);
+    wsync();
+    copy(B.t1, B.v, P);
+    if (lane() == 0) B.t2[0] = 1u;
+    wsync();
+    for (int it = 0; it < 24; ++it) {
+        const bool neg = (B.prod[nE - 1] >> 31) != 0u;
+        if (neg) {  // X -= 1, E += v
+            sub(B.x, B.x, B.t2, P + 2, 0u);
+            add(B.prod, B.prod, B.t1, nE, 0u);
+            wsync();
+            continue;
+        }
+        if (cmp(B.prod, B.t1, nE) >= 0) {  // X += 1, E -= v
+            add(B.x, B.x, B.t2, P + 2, 0u);
+            sub(B.prod, B.prod, B.t1, nE, 0u);
+            wsync();
+            continue;
+        }
+        return true;  // 0 <= E < v
+    }
+    return false;
+}
+
+// out = RZ_p(a / b) given R = floor(2^(2p) / m_b) (P + 1 limbs, in global
+// memory).  Q = floor(m_a 2^(p+1) / m_b) lies in [Q0, Q0 + 2] for
+// Q0 = floor(m_a R / 2^(p-1)); the remainder m_a 2^(p+1) - Q0 m_b, formed
+// modulo 2^(32(P+2)) from the low half of Q0 m_b, moves Q0 up to Q.  a (P
+// limbs) must be in B.a, b in B.v.  Returns false if the remainder check did
+// not settle (callers then fall back to long division).
+__device__ bool div_by_recip(uint32_t *out, Hdr &hq, Hdr ha, Hdr hb, const uint32_t *R, const DivBufs &B,
+                             int P) {
+    const int64_t p = 32LL * P;
+    if (ha.zero) {
+        hq = zero_hdr();
+        return true;
+    }
+    const int n2 = P + 2;
+    // Q0 = (m_a R) >> (p - 1)
+    copy(B.x, B.a, P);
+    for (int q = lane(); q < P + 1 + 2 * MP_YPAD; q += MP_WAVE) {
+        int kq = q - MP_YPAD;
+        B.ypad[q] = (kq >= 0 && kq < P + 1) ? R[kq] : 0u;
+    }
+    wsync();
+    mul_gen(B.prod, 2 * P + 1, B.x, P, B.ypad, P + 1, B.t0, B.t1, B.t2, B.t3);
+    shift(B.x, n2, B.prod, 2 * P + 1, -(p - 1));  // Q0 (P + 2 limbs)
+    set_y(B.ypad, B.v, P, P + 4);
+    wsync();
+    // low half of Q0 m_b
+    mul_gen(B.prod, n2, B.x, n2, B.ypad, P, B.t0, B.t1, B.t2, B.t3);
+    // rem = (m_a 2^(p+1) - Q0 m_b) mod 2^(32 n2)
+    shift(B.t0, n2, B.a, P, p + 1);
+    fill(B.t1, n2, 0u);
+    fill(B.t2, n2, 0u);
+    wsync();
+    sub(B.t0, B.t0, B.prod, n2, 0u);
+    copy(B.t1, B.v, P);  // v padded to n2 limbs
+    if (lane() == 0) B.t2[0] = 1u;
+    wsync();
+    bool ok = false;
+    for (int it = 0; it < 4; ++it) {
+        if ((B.t0[n2 - 1] >> 31) != 0u) break;  // negative: R was not exact
+        if (cmp(B.t0, B.t1, n2) < 0) {
+            ok = true;
+            break;
+        }
+        add(B.x, B.x, B.t2, n2, 0u);
+        sub(B.t0, B.t0, B.t1, n2, 0u);
         wsync();
     }
-    return normalise(out, Q, P + 2, ha.e - hb.e - 32LL * P - 1, ha.s ^ hb.s, P);
+    if (!ok) return false;
+    hq = normalise(out, B.x, n2, ha.e - hb.e - p - 1, ha.s ^ hb.s, P);
+    return true;
 }
 
 }  // namespace mpw
