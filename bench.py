@@ -53,6 +53,9 @@ def workload(cfg: int):
         c = inputs.config_c3()
         return ("config 3: N=2048, 32768-bit: interlaced dyadic Cauchy on [0,1000]",
                 [("cauchy", c["cauchy"][0])])
+    if cfg == 4:
+        return ("config 4: 256 matrices, N uniform in [16,384], 2048-bit, half random mantissas / half "
+                "dyadic Cauchy, one batched elimination", inputs.config_c4())
     raise SystemExit(f"bench.py: config {cfg} is not a single-GPU bench workload")
 
 
@@ -101,6 +104,9 @@ def main():
     ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma"])
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="before the timed region, copy MIB MiB device-to-device once (a kernel of known "
+                         "traffic for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -123,13 +129,30 @@ def main():
     infos = [torch.zeros(1, dtype=torch.int32, device=dev) for _ in pristine]
     path = args.path
 
+    batched = args.config == 4
+    if batched:
+        binfo = torch.zeros(len(pristine), dtype=torch.int32, device=dev)
+
     def step():
-        for p, w, D, c, info in zip(pristine, work, Ds, cs, infos):
+        for p, w in zip(pristine, work):
             w.limbs.copy_(p.limbs)
             w.exp.copy_(p.exp)
             w.sign.copy_(p.sign)
+        if batched:
+            binding.batched(work, path, minors=True, Ds=Ds, cs=cs, info=binfo)
+            return
+        for w, D, c, info in zip(work, Ds, cs, infos):
             binding.factor(w, path, D=D, info=info)
             binding.minors(w, D, info, c=c)
+
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.empty(nbytes // 4, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     for _ in range(args.warmup):
         step()
@@ -141,7 +164,8 @@ def main():
         print(f"[bench] step {s + 1}/{args.steps} done", file=sys.stderr, flush=True)
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
-    bad = [int(i.item()) for i in infos if int(i.item()) != 0]
+    bad = ([int(v) for v in binfo.cpu().tolist() if v] if batched else
+           [int(i.item()) for i in infos if int(i.item()) != 0])
     if bad:
         raise SystemExit(f"bench.py: factorisation reported info {bad}")
     macs, upd = unit_work(mats)
@@ -154,6 +178,8 @@ def main():
     dom = max(("update_valu", "update_mfma"), key=lambda k: prof[k][0])
     dom_ms, dom_n = prof[dom]
     P = mats[0][1].limbs.shape[-1]
+    if dom_n == 0:
+        raise SystemExit("bench.py: no trailing-update launches were timed")
     if dom == "update_valu":
         work_units = sum((m.exp.shape[0] - 1) * m.exp.shape[0] * (2 * m.exp.shape[0] - 1) // 6
                          for _, m in mats) * P * P  # 32x32->64 MACs
@@ -171,13 +197,14 @@ def main():
     out = {"metric": METRIC, "value": value, "unit": "limb-MAC/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "u32" if dom == "update_valu" else "i8", "data": "synthetic",
-           "config": {"workload": desc, "N": int(mats[0][1].exp.shape[0]), "bits": 32 * P,
+           "config": {"workload": desc, "N": int(max(m.exp.shape[0] for _, m in mats)), "bits": 32 * P,
                       "matrices": len(mats), "path": path, "updates_per_step": upd,
                       "limb_macs_per_step": macs},
            "roofline": roof}
     if not args.no_cpu_baseline:
-        gpu_D = Ds[0].row(0)
-        out["cpu_baseline"] = cpu_baseline(mats[0][1], gpu_D, args.cpu_budget)
+        first = max(range(len(mats)), key=lambda b: mats[b][1].exp.shape[0]) if batched else 0
+        gpu_D = Ds[first].row(0)
+        out["cpu_baseline"] = cpu_baseline(mats[first][1], gpu_D, args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 

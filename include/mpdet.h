@@ -112,12 +112,61 @@ int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c,
                   const int32_t *info_dev, void *stream);
 
 /*
+ * mp_det_batched -- mp_det_factor (and, with MPDET_WANT_MINORS, mp_det_minors)
+ * on `batch` matrices of uneven n in lockstep: the batch is ordered by n
+ * (largest first) and every phase of every elimination step is one launch
+ * covering all matrices still active at that step.  Results are bit-identical
+ * to calling mp_det_factor / mp_det_minors on each matrix.
+ *   A_arr, D_arr, c_arr  host arrays of `batch` descriptors (device buffers),
+ *                        shapes as for mp_det_factor / mp_det_minors; all
+ *                        matrices share one nlimbs;  c_arr may be NULL
+ *                        without MPDET_WANT_MINORS.
+ *   info_dev             device int32[batch], one info per matrix (a failing
+ *                        matrix does not affect the others).
+ *   flags                0 or MPDET_WANT_MINORS.
+ * The descriptor tables are staged through pinned host memory owned by the
+ * handle; per-matrix scratch lives in the handle's device workspace.
+ */
+enum { MPDET_WANT_MINORS = 1 };
+int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const mpdet_mat *D_arr,
+                   const mpdet_mat *c_arr, int32_t *info_dev, int flags, int path, void *stream);
+
+/*
+ * mp_det_adjugate -- adjT = adj(A)^T, i.e. adjT[i][j] = C_ij = d det(A) / d a_ij
+ * (Sec. 3: by Baur-Strassen all (N-1)x(N-1) minors are partial derivatives of
+ * the determinant), from mp_det_factor's output.  With L the unit lower factor
+ * and W = L^-1, adj(A) = adj(U) W; the operations and their order are fixed
+ * (W by row sweeps, adj(U) by right-looking back substitution of
+ * U x = det(U) e_j, then adj(A) accumulated in ascending k), so column n of
+ * adjT equals mp_det_minors' c bit for bit.
+ *   LU    n x n factor output;  D  1 x n leading determinants;
+ *   adjT  n x n output (its own ld);  info_dev  the factorisation's info:
+ *         when it is not 0, adjT is written as all zeros.
+ * The library allocates a workspace of about 2 n^2 numbers in the handle.
+ */
+int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT,
+                    const int32_t *info_dev, void *stream);
+
+/*
  * mp_to_f64 -- (mantissa, exponent) pairs: mant = (-1)^s * RZ_53(m / 2^p) in
  * +-[0.5, 1) and exp_out = exp (zero -> 0.0, 0).  x is any rows x cols matrix;
  * outputs are dense [rows][cols] device arrays.
  */
 int mp_to_f64(mpdet_handle *h, mpdet_mat x, double *mant_dev, int64_t *exp_dev,
               void *stream);
+
+/*
+ * mp_to_f64_scaled -- val = (-1)^s * RZ_53(m / 2^p) * 2^(exp - *shift_dev) as
+ * one float64 per number (dense [rows][cols]); the only rounding after the
+ * 53-bit truncation is IEEE ldexp's (nearest even) in the subnormal range, and
+ * results beyond float64's range are +-inf or +-0.  shift_dev is a device
+ * int64 read by the kernel (for instance the det's exponent written by
+ * mp_to_f64), so no host synchronisation is needed.  This is the float64
+ * gradient of the det mantissa, adj(A)^T 2^-e_det, when x is adj(A)^T (Sec. 3:
+ * the cofactors are the partial derivatives of det).
+ */
+int mp_to_f64_scaled(mpdet_handle *h, mpdet_mat x, const int64_t *shift_dev, double *val_dev,
+                     void *stream);
 
 /*
  * Per-kernel timing with HIP events (tracing; off by default).
@@ -127,7 +176,9 @@ int mp_to_f64(mpdet_handle *h, mpdet_mat x, double *mant_dev, int64_t *exp_dev,
  * mpdet_profile_get returns the total milliseconds and launch count of one
  * kernel: "pivot_divide" (leading determinant and the pivot's reciprocal),
  * "divide" (multipliers), "update_valu", "update_mfma", "mfma_prep",
- * "minors_sweep", "minors_final" or "other" (MPDET_EINVAL for other names).
+ * "minors_sweep", "minors_final", "update_finish" (the MFMA path's per-element
+ * rounding and subtraction), "adjugate" or "other" (MPDET_EINVAL for other
+ * names).
  */
 int mpdet_profile_begin(mpdet_handle *h);
 int mpdet_profile_end(mpdet_handle *h);

@@ -506,8 +506,9 @@ int mpref_minors(int64_t n, int32_t P, const uint32_t *limbs, const int64_t *exp
  *   W row r: x^T L_std = e_r^T, solved exactly as in mpref_minors with r in
  *     place of n (so row n of W is the minors' x, bit for bit);
  *   adj(U)_ii = D_{i-1} * S_{i+1}, S_{n+1} = 1, S_i = u_ii * S_{i+1};
- *   adj(U)_ij (i < j) = t / u_ii, t = -sum_{k=i+1..j} u_ik adj(U)_kj,
- *     accumulated in ascending k (U adj(U) = det(U) I, row i, column j);
+ *   adj(U)_ij (i < j) = t / u_ii, t = -sum_{k=i+1..j} u_ik adj(U)_kj
+ *     (U adj(U) = det(U) I, row i, column j), accumulated in descending k:
+ *     the right-looking back substitution of each column;
  *   adj(A)_im = sum_{k >= max(i,m)} adj(U)_ik W_km, ascending k.
  * Row n of adj(A) is then D_{n-1} x_m = c_m, identical to mpref_minors.
  * Output: adjT[i][m] = adj(A)[m][i].
@@ -579,20 +580,22 @@ int mpref_adjugate_t(int64_t n, int32_t P, const uint32_t *limbs, const int64_t 
                    Se[i + 1], Ss[i + 1], J_(i, i), &JE(i, i), &JS(i, i));
         }
     }
-    /* adj(U) strictly upper part, column by column (columns are independent) */
+    /* adj(U) strictly upper part: back substitution in U x = det(U) e_j for
+     * every column j, right-looking: once x_k is final, t_i <- t_i - u_ik x_k
+     * for all i < k (k descending), then x_{k-1} = t_{k-1} / u_{k-1,k-1}.
+     * The accumulators t_i live in J(i, j), which starts at zero (calloc). */
+    for (int64_t k = n - 1; k >= 1; k--) {
 #pragma omp parallel for num_threads(threads) schedule(dynamic, 1)
-    for (int64_t j = 1; j < n; j++) {
-        uint32_t acc[P], tm[P];
-        int64_t ae, tE;
-        int32_t as, tS;
-        for (int64_t i = j - 1; i >= 0; i--) {
-            set_zero(acc, &ae, &as, P);
-            for (int64_t k = i + 1; k <= j; k++) {
-                rz_mul(P, EL(i, k), EE(i, k), ES(i, k), J_(k, j), JE(k, j), JS(k, j),
-                       tm, &tE, &tS);
-                rz_addsub(P, acc, ae, as, tm, tE, tS, 1, acc, &ae, &as);
+        for (int64_t j = k; j < n; j++) {
+            uint32_t tm[P];
+            int64_t tE;
+            int32_t tS;
+            for (int64_t i = 0; i < k; i++) {
+                rz_mul(P, EL(i, k), EE(i, k), ES(i, k), J_(k, j), JE(k, j), JS(k, j), tm, &tE, &tS);
+                rz_addsub(P, J_(i, j), JE(i, j), JS(i, j), tm, tE, tS, 1, J_(i, j), &JE(i, j), &JS(i, j));
             }
-            rz_div(P, acc, ae, as, EL(i, i), EE(i, i), ES(i, i), J_(i, j), &JE(i, j), &JS(i, j));
+            rz_div(P, J_(k - 1, j), JE(k - 1, j), JS(k - 1, j), EL(k - 1, k - 1), EE(k - 1, k - 1),
+                   ES(k - 1, k - 1), J_(k - 1, j), &JE(k - 1, j), &JS(k - 1, j));
         }
     }
     /* adj(A)_im = sum_{k >= max(i,m)} adj(U)_ik W_km; stored transposed */

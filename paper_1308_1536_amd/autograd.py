@@ -1,0 +1,65 @@
+"""torch.autograd integration of the multiprecision determinant.
+
+det(A) is affine in every entry, and d det / d a_ij is the cofactor C_ij
+(Sec. 3: by Baur-Strassen all (N-1)x(N-1) minors are partial derivatives of
+the determinant), so the gradient is adj(A)^T.  Multiprecision integers cannot
+carry autograd state and float64 determinants overflow (2^1024) long before
+N = 384, so the Function works on a float64 *proxy* leaf of shape (n, n):
+
+    mant, e = MpDet.apply(proxy, A, "auto", holder)    # det(A) = mant * 2^e
+    mant.backward()                                    # proxy.grad = adj(A)^T * 2^-e
+
+`mant` is the determinant's mantissa in +-[0.5, 1) (differentiable), `e` its
+exponent (not differentiable).  The backward runs mp_det_adjugate on the
+stored factors; the exact multiprecision adj(A)^T is kept on `holder.adjT`
+(a DeviceMp) when a holder is given.  Everything runs in libmpdet.so.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import binding
+
+
+class GradHolder:
+    """Receives the exact multiprecision adj(A)^T from the backward pass."""
+
+    def __init__(self):
+        self.adjT = None
+        self.D = None
+        self.info = None
+
+
+class MpDet(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, proxy, A, path="auto", holder=None):
+        n = A.rows
+        LU = binding.DeviceMp(A.limbs.clone(), A.exp.clone(), A.sign.clone(), A.rows, A.cols)
+        D, info = binding.factor(LU, path)
+        mant, e = binding.to_f64(D)
+        dm = mant[0, n - 1].clone()
+        de = e[0, n - 1].clone()
+        ctx.LU, ctx.D, ctx.info, ctx.holder = LU, D, info, holder
+        ctx.save_for_backward(de)
+        if holder is not None:
+            holder.D, holder.info = D, info
+        ctx.mark_non_differentiable(de)
+        return dm, de
+
+    @staticmethod
+    def backward(ctx, g_mant, g_e):
+        (de,) = ctx.saved_tensors
+        adjT = binding.adjugate(ctx.LU, ctx.D, ctx.info)
+        if ctx.holder is not None:
+            ctx.holder.adjT = adjT
+        # d mant / d a_ij = C_ij 2^-e_det, converted in one kernel
+        grad = binding.to_f64_scaled(adjT, de)
+        return g_mant * grad, None, None, None
+
+
+def mp_det(A, proxy=None, path: str = "auto", holder: GradHolder | None = None):
+    """Differentiable determinant of a DeviceMp A: returns (mantissa, exponent)."""
+    if proxy is None:
+        proxy = torch.zeros((A.rows, A.cols), dtype=torch.float64, device=A.limbs.device,
+                            requires_grad=True)
+    return MpDet.apply(proxy, A, path, holder)

@@ -73,13 +73,13 @@ def lib() -> ctypes.CDLL:
         for name in ("mpdet_create", "mpdet_destroy", "mp_det_factor", "mp_det_minors", "mp_to_f64",
                      "mpdet_profile_begin", "mpdet_profile_end", "mpdet_profile_get"):
             getattr(L, name).restype = ctypes.c_int
-        if hasattr(L, "mp_det_batched"):
-            L.mp_det_batched.argtypes = [vp, i64, ctypes.POINTER(MpdetMat), ctypes.POINTER(MpdetMat),
-                                         ctypes.POINTER(MpdetMat), vp, ctypes.c_int, ctypes.c_int, vp]
-            L.mp_det_batched.restype = ctypes.c_int
-        if hasattr(L, "mp_det_adjugate"):
-            L.mp_det_adjugate.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, vp, vp]
-            L.mp_det_adjugate.restype = ctypes.c_int
+        L.mp_det_batched.argtypes = [vp, i64, ctypes.POINTER(MpdetMat), ctypes.POINTER(MpdetMat),
+                                     ctypes.POINTER(MpdetMat), vp, ctypes.c_int, ctypes.c_int, vp]
+        L.mp_det_batched.restype = ctypes.c_int
+        L.mp_det_adjugate.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, vp, vp]
+        L.mp_det_adjugate.restype = ctypes.c_int
+        L.mp_to_f64_scaled.argtypes = [vp, MpdetMat, vp, vp, vp]
+        L.mp_to_f64_scaled.restype = ctypes.c_int
         _ = (i32,)
         _lib = L
     return _lib
@@ -200,8 +200,19 @@ class HostMp:
         return int(self.limbs.shape[-1])
 
 
+def _resolve(path: str, n: int, P: int) -> int:
+    """Path name -> MPDET_PATH_*; "tuned" asks the autotuner (measured, cached)."""
+    if path == "tuned":
+        from . import autotune
+        path = autotune.choose_path(n, P)
+    if path not in PATHS:
+        raise ValueError(f"unknown path {path!r}: one of {sorted(PATHS) + ['tuned']}")
+    return PATHS[path]
+
+
 def factor(A: DeviceMp, path: str = "auto", D: DeviceMp | None = None, info=None, stream=None):
-    """mp_det_factor in place on A.  Returns (D, info) device tensors."""
+    """mp_det_factor in place on A.  Returns (D, info) device tensors.
+    path: "auto" (MFMA where the limb count allows), "valu", "mfma" or "tuned"."""
     import torch
     n = A.rows
     if D is None:
@@ -209,8 +220,8 @@ def factor(A: DeviceMp, path: str = "auto", D: DeviceMp | None = None, info=None
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.limbs.device)
     h = handle(A.limbs.device.index or 0)
-    _check("mp_det_factor", lib().mp_det_factor(h.ptr, A.mat(), D.mat(), info.data_ptr(), PATHS[path],
-                                                _stream(stream)))
+    _check("mp_det_factor", lib().mp_det_factor(h.ptr, A.mat(), D.mat(), info.data_ptr(),
+                                                _resolve(path, n, A.P), _stream(stream)))
     return D, info
 
 
@@ -225,6 +236,44 @@ def minors(LU: DeviceMp, D: DeviceMp, info, c: DeviceMp | None = None, stream=No
     return c
 
 
+def adjugate(LU: DeviceMp, D: DeviceMp, info, adjT: DeviceMp | None = None, stream=None) -> DeviceMp:
+    """mp_det_adjugate: adj(A)^T = d det / d A from the factored matrix."""
+    n = LU.rows
+    if adjT is None:
+        adjT = DeviceMp.empty(n, n, LU.P, LU.limbs.device)
+    h = handle(LU.limbs.device.index or 0)
+    _check("mp_det_adjugate", lib().mp_det_adjugate(h.ptr, LU.mat(), D.mat(), adjT.mat(), info.data_ptr(),
+                                                    _stream(stream)))
+    return adjT
+
+
+MPDET_WANT_MINORS = 1
+
+
+def batched(mats: list, path: str = "auto", minors: bool = True, Ds=None, cs=None, info=None,
+            stream=None):
+    """mp_det_batched on a list of square DeviceMp matrices (factored in place).
+    Returns (Ds, cs or None, info[batch])."""
+    import torch
+    B = len(mats)
+    dev = mats[0].limbs.device
+    if Ds is None:
+        Ds = [DeviceMp.empty(1, m.rows, m.P, dev) for m in mats]
+    if minors and cs is None:
+        cs = [DeviceMp.empty(1, m.rows, m.P, dev) for m in mats]
+    if info is None:
+        info = torch.zeros(B, dtype=torch.int32, device=dev)
+    Aa = (MpdetMat * B)(*[m.mat() for m in mats])
+    Da = (MpdetMat * B)(*[d.mat() for d in Ds])
+    Ca = (MpdetMat * B)(*[c.mat() for c in cs]) if minors else None
+    h = handle(dev.index or 0)
+    _check("mp_det_batched", lib().mp_det_batched(h.ptr, B, Aa, Da, Ca, info.data_ptr(),
+                                                  MPDET_WANT_MINORS if minors else 0,
+                                                  _resolve(path, max(m.rows for m in mats), mats[0].P),
+                                                  _stream(stream)))
+    return Ds, (cs if minors else None), info
+
+
 def to_f64(x: DeviceMp, stream=None):
     """mp_to_f64: (mantissa float64 [rows, cols], exponent int64 [rows, cols]) device tensors."""
     import torch
@@ -235,8 +284,23 @@ def to_f64(x: DeviceMp, stream=None):
     return mant, e
 
 
+def to_f64_scaled(x: DeviceMp, shift, stream=None):
+    """mp_to_f64_scaled: float64 [rows, cols] = RZ_53 value of x * 2^-shift
+    (shift: a one-element int64 device tensor)."""
+    import torch
+    val = torch.zeros((x.rows, x.cols), dtype=torch.float64, device=x.limbs.device)
+    shift = shift.reshape(1)
+    if shift.dtype != torch.int64 or shift.device != x.limbs.device:
+        raise ValueError("shift must be an int64 tensor on the device of x")
+    shift = shift.contiguous()
+    h = handle(x.limbs.device.index or 0)
+    _check("mp_to_f64_scaled",
+           lib().mp_to_f64_scaled(h.ptr, x.mat(), shift.data_ptr(), val.data_ptr(), _stream(stream)))
+    return val
+
+
 KERNELS = ("pivot_divide", "divide", "update_valu", "update_mfma", "mfma_prep", "minors_sweep",
-           "minors_final", "other")
+           "minors_final", "update_finish", "adjugate", "other")
 
 
 def profile_begin(device: int = 0):

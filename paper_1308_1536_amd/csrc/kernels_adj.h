@@ -1,0 +1,170 @@
+// kernels_adj.h -- adj(A)^T = d det / d A from the stored factors (the
+// backward of the determinant; Sec. 3: by Baur-Strassen every (N-1)x(N-1)
+// minor is a partial derivative of det, d det / d a_ij = C_ij).
+//
+// With A = L U (L unit lower, holding the multipliers), adj(A) = adj(U) W,
+// W = L^-1, in this fixed order (the oracle follows the same one):
+//   W:      row r solves x^T L = e_r^T; sweeps j = n-1..1 (all rows r >= j in
+//           one launch): W_ri <- RZ(W_ri - RZ(W_rj l_ji)), i < j;
+//   adj(U): S_n = 1, S_i = RZ(u_ii S_{i+1}); adj(U)_ii = RZ(D_{i-1} S_{i+1});
+//           strictly upper part by right-looking back substitution of
+//           U x = det(U) e_j: for k = n-1..1, t_i <- RZ(t_i - RZ(u_ik x_k))
+//           (i < k, all columns j >= k in one launch), then
+//           x_{k-1} = RZ(t_{k-1} / u_{k-1,k-1});
+//   adj(A): for k = 0..n-1, acc_im <- RZ(acc_im + RZ(adj(U)_ik W_km)) for
+//           i, m <= k (each entry sums its terms in ascending k).
+// Every launch is one wave per number operation (wave-cooperative limbs).
+// Row n-1 of adj(A) is RZ(D_{n-2} W_{n-1,m}), the last-column minors.
+#pragma once
+
+#include "kernels_valu.h"
+
+namespace mpk {
+
+// zero a matrix block of n x n numbers; diag_one puts 1 on the diagonal
+__global__ void k_adj_init(MatDev X, int64_t n, int P, int diag_one) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = n * n;
+    if (t >= total) return;
+    const int64_t i = t / n, j = t % n;
+    uint32_t *m = el(X, i, j, P);
+    const bool one = diag_one && i == j;
+    for (int q = 0; q < P; ++q) m[q] = (one && q == P - 1) ? 0x80000000u : 0u;
+    ex(X, i, j) = one ? 1 : 0;
+    sg(X, i, j) = 0;
+}
+
+// c = RZ(c + s * RZ(x * y)), s = -1 (subtract) or +1, all through LDS
+__device__ __forceinline__ void fma_like(uint32_t *cm, int64_t *ce, int32_t *cs, const uint32_t *xm,
+                                         int64_t xe, int32_t xs, const uint32_t *ym, int64_t ye, int32_t ys,
+                                         bool subtract, Lds &L, int P) {
+    mpw::Hdr hx = mpw::load(L.sc.x, xm, xe, xs, P);
+    mpw::Hdr hy = load_y(L.sc.ypad, ym, ye, ys, P);
+    if (hx.zero || hy.zero) return;  // c +- 0 = c
+    mpw::Hdr ht = mpw::mul(L.sc.t3, hx, hy, P, L.sc);
+    if (subtract) ht.s ^= 1;
+    mpw::Hdr hc = mpw::load(L.sc.x, cm, *ce, *cs, P);
+    mpw::Hdr hr = mpw::addsub(L.sc.t2, L.sc.x, hc, L.sc.t3, ht, L.sc.t0, L.sc.t1, P);
+    mpw::store(cm, ce, cs, L.sc.t2, hr, P);
+}
+
+// W sweep j: block b -> (r, i) = (j + b / j, b % j)
+__global__ void __launch_bounds__(64) k_adj_w(MatDev LU, MatDev W, const int32_t *info, int64_t j, int64_t n,
+                                              int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    const int64_t b = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
+    if (b >= (n - j) * j) return;
+    const int64_t r = j + b / j, i = b % j;
+    Lds L(lds_raw, P);
+    fma_like(el(W, r, i, P), &ex(W, r, i), &sg(W, r, i), el(W, r, j, P), ex(W, r, j), sg(W, r, j),
+             el(LU, j, i, P), ex(LU, j, i), sg(LU, j, i), true, L, P);
+}
+
+// S_n = 1, S_i = RZ(u_ii S_{i+1}) (one wave, sequential), then the diagonal
+// of adj(U) is written by k_adj_diag
+__global__ void __launch_bounds__(64) k_adj_s(MatDev LU, MatDev S, const int32_t *info, int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    Lds L(lds_raw, P);
+    // the running product stays in LDS as the y operand (S_n = 1)
+    for (int q = mpw::lane(); q < P + 2 * MP_YPAD; q += MP_WAVE)
+        L.sc.ypad[q] = (q == MP_YPAD + P - 1) ? 0x80000000u : 0u;
+    for (int q = mpw::lane(); q < P; q += MP_WAVE) el(S, 0, n, P)[q] = (q == P - 1) ? 0x80000000u : 0u;
+    if (mpw::lane() == 0) {
+        ex(S, 0, n) = 1;
+        sg(S, 0, n) = 0;
+    }
+    mpw::wsync();
+    mpw::Hdr hs{1, 0, false};
+    for (int64_t i = n - 1; i >= 0; --i) {
+        mpw::Hdr hu = mpw::load(L.sc.x, el(LU, i, i, P), ex(LU, i, i), sg(LU, i, i), P);
+        mpw::Hdr hr = mpw::mul(L.sc.t3, hu, hs, P, L.sc);
+        mpw::store(el(S, 0, i, P), &ex(S, 0, i), &sg(S, 0, i), L.sc.t3, hr, P);
+        mpw::copy(L.sc.ypad + MP_YPAD, L.sc.t3, P);
+        mpw::wsync();
+        hs = hr;
+    }
+}
+
+// adj(U)_ii = RZ(D_{i-1} S_{i+1}), D_0 = 1 (so adj(U)_00 = S_1)
+__global__ void __launch_bounds__(64) k_adj_diag(MatDev D, MatDev S, MatDev J, const int32_t *info, int64_t n,
+                                                 int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    const int64_t i = blockIdx.x;
+    Lds L(lds_raw, P);
+    mpw::Hdr hs = mpw::load(L.sc.t3, el(S, 0, i + 1, P), ex(S, 0, i + 1), sg(S, 0, i + 1), P);
+    mpw::Hdr hr = hs;
+    if (i > 0) {
+        mpw::Hdr hd = mpw::load(L.sc.x, el(D, 0, i - 1, P), ex(D, 0, i - 1), sg(D, 0, i - 1), P);
+        mpw::Hdr hs2 = load_y(L.sc.ypad, el(S, 0, i + 1, P), ex(S, 0, i + 1), sg(S, 0, i + 1), P);
+        hr = mpw::mul(L.sc.t3, hd, hs2, P, L.sc);
+    }
+    mpw::store(el(J, i, i, P), &ex(J, i, i), &sg(J, i, i), L.sc.t3, hr, P);
+}
+
+// reciprocals of the pivots u_ii (block i), as k_pivot_recip's block 1
+__global__ void __launch_bounds__(64) k_adj_recips(MatDev LU, uint32_t *rw, const int32_t *info, int64_t n,
+                                                   int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    const int64_t i = blockIdx.x;
+    mpw::DivBufs B = mpw::div_bufs(lds_raw, P);
+    mpw::gload(B.v, el(LU, i, i, P), P);
+    mpw::wsync();
+    const bool ok = mpw::recip(B, P);
+    uint32_t *r = rw + i * (int64_t)(P + 2);
+    for (int q = mpw::lane(); q < P + 1; q += MP_WAVE) r[q] = B.x[q];
+    if (mpw::lane() == 0) r[P + 1] = ok ? 1u : 0u;
+}
+
+// back substitution step k, part 1: block b -> (i, j) = (b % k, k + b / k):
+// J_ij <- RZ(J_ij - RZ(u_ik J_kj))
+__global__ void __launch_bounds__(64) k_adj_u_upd(MatDev LU, MatDev J, const int32_t *info, int64_t k, int64_t n,
+                                                  int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    const int64_t b = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
+    if (b >= k * (n - k)) return;
+    const int64_t i = b % k, j = k + b / k;
+    Lds L(lds_raw, P);
+    fma_like(el(J, i, j, P), &ex(J, i, j), &sg(J, i, j), el(LU, i, k, P), ex(LU, i, k), sg(LU, i, k),
+             el(J, k, j, P), ex(J, k, j), sg(J, k, j), true, L, P);
+}
+
+// part 2: block b -> j = k + b: J_{k-1,j} <- RZ(J_{k-1,j} / u_{k-1,k-1})
+__global__ void __launch_bounds__(64) k_adj_u_div(MatDev LU, MatDev J, const uint32_t *rw, const int32_t *info,
+                                                  int64_t k, int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    const int64_t j = k + (int64_t)blockIdx.x;
+    const int64_t i = k - 1;
+    mpw::DivBufs B = mpw::div_bufs(lds_raw, P);
+    uint32_t *tm = el(J, i, j, P);
+    mpw::Hdr ht = mpw::load(B.a, tm, ex(J, i, j), sg(J, i, j), P);
+    mpw::Hdr hu = mpw::load(B.v, el(LU, i, i, P), ex(LU, i, i), sg(LU, i, i), P);
+    const uint32_t *R = rw + i * (int64_t)(P + 2);
+    mpw::Hdr hq;
+    bool done = false;
+    if (R[P + 1] != 0u) done = mpw::div_by_recip(B.t3, hq, ht, hu, R, B, P);
+    if (!done) hq = mpw::div(B.t3, B.a, ht, B.v, hu, B.prod, B.t0, B.t1, B.t2, P);
+    mpw::store(tm, &ex(J, i, j), &sg(J, i, j), B.t3, hq, P);
+}
+
+// adj(A) accumulation step k: block b -> (i, m) = (b / (k+1), b % (k+1)):
+// adjT_mi <- RZ(adjT_mi + RZ(J_ik W_km))
+__global__ void __launch_bounds__(64) k_adj_prod(MatDev J, MatDev W, MatDev T, const int32_t *info, int64_t k,
+                                                 int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    const int64_t b = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
+    const int64_t k1 = k + 1;
+    if (b >= k1 * k1) return;
+    const int64_t i = b / k1, m = b % k1;
+    Lds L(lds_raw, P);
+    fma_like(el(T, m, i, P), &ex(T, m, i), &sg(T, m, i), el(J, i, k, P), ex(J, i, k), sg(J, i, k),
+             el(W, k, m, P), ex(W, k, m), sg(W, k, m), false, L, P);
+}
+
+}  // namespace mpk

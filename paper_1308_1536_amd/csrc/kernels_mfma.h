@@ -58,6 +58,14 @@ __host__ __device__ inline MfmaGeom mfma_geom(int P) {
 
 __host__ __device__ inline bool mfma_supported(int P) { return P >= 8 && P % 8 == 0; }
 
+constexpr int64_t kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
+
+// workgroups of k_update_mfma for an m x m trailing block
+__host__ __device__ inline int64_t mfma_update_blocks(int64_t m) {
+    const int64_t njb = (m + 31) / 32;
+    return njb >= kXcds ? kXcds * m * ((njb + kXcds - 1) / kXcds) : m * njb;
+}
+
 // LDS for k_update_mfma: the reversed digit row, then 32 columns x 65 uint64
 __host__ __device__ inline size_t mfma_lds_bytes(int P) {
     MfmaGeom g = mfma_geom(P);
@@ -103,13 +111,11 @@ __device__ void balanced_digit_words(uint32_t *dw, const uint32_t *m, int P) {
 
 // Per step: block b < m -> reversed multiplier digits of row k+1+b (Lr),
 // block b >= m -> digits of pivot-row element k+1+(b-m) (Ub).
-__global__ void __launch_bounds__(64) k_mfma_prep(MatDev A, uint8_t *Lr, uint8_t *Ub, const int32_t *info,
-                                                  int64_t k, int64_t n, int P) {
-    extern __shared__ uint32_t lds_raw[];
+__device__ __forceinline__ void mfma_prep_body(uint32_t *lds_raw, MatDev A, uint8_t *Lr, uint8_t *Ub, const int32_t *info,
+                               int64_t k, int64_t n, int P, int64_t b) {
     if (*info != 0) return;
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
-    const int64_t b = blockIdx.x;
     const bool is_row = b < m;
     const uint32_t *src = is_row ? el(A, k + 1 + b, k, P) : el(A, k, k + 1 + (b - m), P);
     if (src[P - 1] == 0u && is_row) return;  // zero multiplier: its row is skipped
@@ -142,17 +148,30 @@ __device__ __forceinline__ v4i load_a(const uint8_t *lr, int d, int P8, int Q) {
 }
 
 // Product top limbs: for every row i' (multiplier l = a_{k+1+i', k}) and
-// column block of 32, T[(i' m + j') TP + x] = limb P-1+x of l * u_{j'}, x <= P.
-__global__ void __launch_bounds__(64) k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T,
-                                                    const int32_t *info, int64_t k, int64_t n, int P) {
-    extern __shared__ uint32_t lds_raw[];
+// column block jb of 32, word x <= P of the record of column j' = 32 jb + j is
+// limb P-1+x of l * u_{j'}, stored limb-major across the block's 32 columns:
+// T[((i' njb + jb) TP + x) 32 + j].
+__device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T,
+                                 const int32_t *info, int64_t k, int64_t n, int P, int64_t bx, bool xcd_aware) {
     if (*info != 0) return;
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
     const int64_t njb = (m + 31) / 32;
-    const int64_t wu = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
-    if (wu >= m * njb) return;
-    const int64_t ip = wu / njb, jb = wu % njb;
+    int64_t ip, jb;
+    if (xcd_aware && njb >= kXcds) {
+        // workgroups go to the 8 XCDs round-robin: XCD x takes the column
+        // blocks jb = x (mod 8), so each XCD's L2 holds only its share of the
+        // pivot-row digits
+        const int64_t xcd = bx % kXcds, loc = bx / kXcds;
+        const int64_t cnt = (njb - xcd + kXcds - 1) / kXcds;
+        if (loc >= m * cnt) return;
+        ip = loc / cnt;
+        jb = xcd + kXcds * (loc % cnt);
+    } else {
+        if (bx >= m * njb) return;
+        ip = bx / njb;
+        jb = bx % njb;
+    }
     if (el(A, k + 1 + ip, k, P)[P - 1] == 0u) return;
 
     uint8_t *lr = (uint8_t *)lds_raw;
@@ -169,7 +188,7 @@ __global__ void __launch_bounds__(64) k_update_mfma(MatDev A, const uint8_t *Lr,
     const int64_t jp = jb * 32 + j;
     const bool jvalid = jp < m;
     const uint8_t *ub = Ub + (jvalid ? jp : 0) * (int64_t)g.K8 + 16 * h;
-    uint32_t *trow = T + (ip * m + (jvalid ? jp : 0)) * (int64_t)g.TP;
+    uint32_t *tcol = T + (ip * njb + jb) * (int64_t)g.TP * 32 + j;
     const int P8 = g.P8, Q = g.Q;
     uint64_t carry = 0;
 
@@ -241,7 +260,7 @@ __global__ void __launch_bounds__(64) k_update_mfma(MatDev A, const uint8_t *Lr,
                     const int q = qbase + q8 + u;
                     const uint64_t x = v[u] + carry;
                     carry = x >> 32;
-                    if (q8 + u < qend && q >= P - 1 && jvalid) trow[q - (P - 1)] = (uint32_t)x;
+                    if (q8 + u < qend && q >= P - 1 && jvalid) tcol[(int64_t)(q - (P - 1)) * 32] = (uint32_t)x;
                 }
             }
         }
@@ -249,77 +268,53 @@ __global__ void __launch_bounds__(64) k_update_mfma(MatDev A, const uint8_t *Lr,
     }
 }
 
-// a_ij = RZ_p(a_ij - t), t = RZ_p(l_i u_j) rebuilt from the product's top limbs.
-__global__ void __launch_bounds__(64) k_sub_mfma(MatDev A, const uint32_t *T, const int32_t *info, int64_t k,
-                                                 int64_t n, int P) {
-    extern __shared__ uint32_t lds_raw[];
-    if (*info != 0) return;
-    const MfmaGeom g = mfma_geom(P);
-    const int64_t m = n - k - 1;
-    const int64_t bx = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
-    if (bx >= m * m) return;
-    const int64_t ip = bx / m, jp = bx % m;
-    const int64_t i = k + 1 + ip, j = k + 1 + jp;
-    const uint32_t *lm = el(A, i, k, P);
-    const uint32_t *um = el(A, k, j, P);
-    if (lm[P - 1] == 0u || um[P - 1] == 0u) return;
-    Lds L(lds_raw, P);
-    const uint32_t *raw = T + (ip * m + jp) * (int64_t)g.TP;
-    for (int q = mpw::lane(); q < P + 1; q += MP_WAVE) L.sc.prod[q] = raw[q];
-    mpw::wsync();
-    const int top = (int)(L.sc.prod[P] >> 31);
-    mpw::shift(L.sc.t3, P, L.sc.prod, P + 1, -(31 + top));
-    mpw::wsync();
-    mpw::Hdr ht{ex(A, i, k) + ex(A, k, j) - 1 + top, sg(A, i, k) ^ sg(A, k, j) ^ 1, false};
-    uint32_t *am = el(A, i, j, P);
-    mpw::Hdr ha = mpw::load(L.sc.x, am, ex(A, i, j), sg(A, i, j), P);
-    mpw::Hdr hr = mpw::addsub(L.sc.t2, L.sc.x, ha, L.sc.t3, ht, L.sc.t0, L.sc.t1, P);
-    mpw::store(am, &ex(A, i, j), &sg(A, i, j), L.sc.t2, hr, P);
-}
-
 // ---------------------------------------------------------------------------
-// Lane-per-element finish: a_ij = RZ_p(a_ij - t), t = RZ_p(l_i u_j) rebuilt
-// from the product's top limbs (raw[x] = product limb P-1+x, x = 0..P).
-// Same case analysis as mpw::addsub, run sequentially by one lane over the
-// limbs (low to high with one-limb register windows): G, the exact p+2-bit
-// intermediate, overwrites the lane's own raw record in place (every read of
-// the record is at or ahead of the limb being written), and the normalised
-// result goes to a_ij.
+// Finish of the update, one lane per element: a_ij = RZ_p(a_ij - t) with
+// t = RZ_p(l_i u_j) rebuilt from the product's top limbs (raw word x = product
+// limb P-1+x, x = 0..P, in the limb-major record above).  Same case analysis
+// as mpw::addsub, run by one lane over the limbs from low to high with
+// one-limb register windows: pass 1 writes G, the exact p+2-bit intermediate,
+// to its own limb-major buffer (no location is read after it is written), and
+// pass 2 normalises G into a_ij.  Lanes of a wave take consecutive columns, so
+// the record and G accesses are coalesced.
 // ---------------------------------------------------------------------------
 
-// sequential reader of mantissa limbs 0..P-1 of a or t (0 outside)
+// limb q (0..P-1) of a or t through a strided word view (0 outside)
 struct LimbSrc {
-    const uint32_t *p;  // raw words
+    const uint32_t *p;  // raw words, word idx at p[idx * stride]
+    int64_t stride;
     int off;            // limb q uses words q+off and q+off-1
-    int sh;             // 0: limb = p[q+off]; 1: limb = (p[q+off] << 1) | (p[q+off-1] >> 31)
+    int sh;             // 0: limb = w[q+off]; 1: limb = (w[q+off] << 1) | (w[q+off-1] >> 31)
     int P;
     __device__ __forceinline__ uint32_t word(int64_t idx) const {
-        return (idx >= 0 && idx < (int64_t)P + off) ? p[idx] : 0u;
+        return (idx >= 0 && idx < (int64_t)P + off) ? p[idx * stride] : 0u;
     }
     __device__ __forceinline__ uint32_t limb(int64_t q) const {
         if (q < 0 || q >= P) return 0u;
-        uint32_t hi = word(q + off);
+        const uint32_t hi = word(q + off);
         if (!sh) return hi;
         return (hi << 1) | (word(q + off - 1) >> 31);
     }
 };
 
-__global__ void __launch_bounds__(256) k_sub_lane(MatDev A, uint32_t *T, const int32_t *info, int64_t k,
-                                                  int64_t n, int P) {
+__device__ __forceinline__ void sub_lane_body(MatDev A, const uint32_t *__restrict__ T, uint32_t *__restrict__ Gb,
+                              const int32_t *info, int64_t k, int64_t n, int P, int64_t slot) {
     if (*info != 0) return;
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
-    const int64_t id = ((int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x) * blockDim.x + threadIdx.x;
-    if (id >= m * m) return;
-    const int64_t ip = id / m, jp = id % m;
+    const int64_t njb = (m + 31) / 32;
+    const int64_t ip = slot / (njb * 32), jp = slot % (njb * 32);
+    if (ip >= m || jp >= m) return;
     const int64_t i = k + 1 + ip, j = k + 1 + jp;
     if (el(A, i, k, P)[P - 1] == 0u || el(A, k, j, P)[P - 1] == 0u) return;
-    uint32_t *raw = T + (ip * m + jp) * (int64_t)g.TP;
-    uint32_t *am = el(A, i, j, P);
+    const int64_t rec = (ip * njb + jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
+    const uint32_t *__restrict__ raw = T + rec;
+    uint32_t *__restrict__ G = Gb + rec;
+    uint32_t *__restrict__ am = el(A, i, j, P);
     const int64_t p = 32LL * P;
-    const int top = (int)(raw[P] >> 31);
-    const LimbSrc ts{raw, 1, 1 - top, P};
-    const LimbSrc as{am, 0, 0, P};
+    const int top = (int)(raw[(int64_t)P * 32] >> 31);
+    const LimbSrc ts{raw, 32, 1, 1 - top, P};
+    const LimbSrc as{am, 1, 0, 0, P};
     const int64_t et = ex(A, i, k) + ex(A, k, j) - 1 + top;
     const int32_t sy = sg(A, i, k) ^ sg(A, k, j) ^ 1;  // sign of -t
     const int64_t ea = ex(A, i, j);
@@ -337,7 +332,7 @@ __global__ void __launch_bounds__(256) k_sub_lane(MatDev A, uint32_t *T, const i
     if (ea == et && subtract) {
         int c = 0;
         for (int q = P - 1; q >= 0 && c == 0; --q) {
-            uint32_t x = as.limb(q), y = ts.limb(q);
+            const uint32_t x = as.limb(q), y = ts.limb(q);
             c = x > y ? 1 : (x < y ? -1 : 0);
         }
         if (c == 0) {
@@ -352,21 +347,22 @@ __global__ void __launch_bounds__(256) k_sub_lane(MatDev A, uint32_t *T, const i
     const int64_t eX = a_is_x ? ea : et, eY = a_is_x ? et : ea;
     const int32_t sX = a_is_x ? sa : sy;
     const uint64_t d = (uint64_t)eX - (uint64_t)eY;
-    const int gsh = subtract ? (int)(d < 2 ? d : 2) : 0;  // left shift of X
-    const uint64_t rsu = subtract ? (d < 2 ? 0 : d - 2) : d;  // right shift of Y
+    const int gsh = subtract ? (int)(d < 2 ? d : 2) : 0;       // left shift of X
+    const uint64_t rsu = subtract ? (d < 2 ? 0 : d - 2) : d;   // right shift of Y
     const int64_t rs = (int64_t)(rsu > (uint64_t)(p + 64) ? (uint64_t)(p + 64) : rsu);
     const int64_t w = rs / 32;
     const int b = (int)(rs % 32);
-    uint32_t borrow_or_carry = 0;
+    uint32_t cb = 0;  // carry (sum) or borrow (difference)
     if (subtract && rs > 0) {  // sticky: any bit of Y below bit rs
         bool st = false;
         for (int64_t q = 0; q < P && q <= w && !st; ++q) {
-            uint32_t v = Y.limb(q);
+            const uint32_t v = Y.limb(q);
             if (q < w) st = v != 0u;
             else if (b) st = (v & ((1u << b) - 1u)) != 0u;
         }
-        borrow_or_carry = st ? 1u : 0u;
+        cb = st ? 1u : 0u;
     }
+    // pass 1: G = X 2^gsh +- (Y >> rs) -+ sticky, P + 1 limbs
     uint32_t xprev = 0;
     uint32_t ylo = Y.limb(w);
     for (int q = 0; q <= P; ++q) {
@@ -376,39 +372,59 @@ __global__ void __launch_bounds__(256) k_sub_lane(MatDev A, uint32_t *T, const i
         const uint32_t ysh = b ? ((ylo >> b) | (yhi << (32 - b))) : ylo;
         uint32_t gq;
         if (!subtract) {
-            uint64_t sum = (uint64_t)xg + ysh + borrow_or_carry;
+            const uint64_t sum = (uint64_t)xg + ysh + cb;
             gq = (uint32_t)sum;
-            borrow_or_carry = (uint32_t)(sum >> 32);
+            cb = (uint32_t)(sum >> 32);
         } else {
-            int64_t df = (int64_t)xg - (int64_t)ysh - (int64_t)borrow_or_carry;
+            const int64_t df = (int64_t)xg - (int64_t)ysh - (int64_t)cb;
             gq = (uint32_t)df;
-            borrow_or_carry = df < 0 ? 1u : 0u;
+            cb = df < 0 ? 1u : 0u;
         }
-        raw[q] = gq;
+        G[(int64_t)q * 32] = gq;
         xprev = xq;
         ylo = yhi;
     }
-    // normalise G (P+1 limbs in raw) to p bits
+    // pass 2: normalise G to p bits into a_ij
     int qt = P;
-    while (qt >= 0 && raw[qt] == 0u) --qt;
+    while (qt >= 0 && G[(int64_t)qt * 32] == 0u) --qt;
     if (qt < 0) {
         for (int q = 0; q < P; ++q) am[q] = 0u;
         *eo = 0;
         *so = 0;
         return;
     }
-    const int64_t L = 32LL * qt + 32 - __clz(raw[qt]);
-    const int64_t sr = L - p;  // bits to drop (may be negative: shift left)
+    const int64_t L = 32LL * qt + 32 - __clz(G[(int64_t)qt * 32]);
+    const int64_t sr = L - p;  // bits to drop (negative: shift left)
     const int64_t w0 = sr >= 0 ? sr / 32 : -((-sr + 31) / 32);
     const int bb = (int)(sr - 32 * w0);
     for (int q = 0; q < P; ++q) {
         const int64_t lo_i = q + w0, hi_i = q + w0 + 1;
-        const uint32_t lo = (lo_i >= 0 && lo_i <= P) ? raw[lo_i] : 0u;
-        const uint32_t hi = (hi_i >= 0 && hi_i <= P) ? raw[hi_i] : 0u;
+        const uint32_t lo = (lo_i >= 0 && lo_i <= P) ? G[lo_i * 32] : 0u;
+        const uint32_t hi = (hi_i >= 0 && hi_i <= P) ? G[hi_i * 32] : 0u;
         am[q] = bb ? ((lo >> bb) | (hi << (32 - bb))) : lo;
     }
     *eo = eX - gsh - p + L;
     *so = sX;
+}
+
+// elements of the m x m trailing block in lane slots (m rows x njb*32 columns)
+__host__ __device__ inline int64_t sub_lane_slots(int64_t m) { return m * ((m + 31) / 32) * 32; }
+
+__global__ void __launch_bounds__(64) k_mfma_prep(MatDev A, uint8_t *Lr, uint8_t *Ub, const int32_t *info,
+                                                  int64_t k, int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    mfma_prep_body(lds_raw, A, Lr, Ub, info, k, n, P, flat_block());
+}
+
+__global__ void __launch_bounds__(64) k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T,
+                                                    const int32_t *info, int64_t k, int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    update_mfma_body(lds_raw, A, Lr, Ub, T, info, k, n, P, flat_block(), true);
+}
+
+__global__ void __launch_bounds__(64) k_sub_lane(MatDev A, const uint32_t *T, uint32_t *G, const int32_t *info,
+                                                 int64_t k, int64_t n, int P) {
+    sub_lane_body(A, T, G, info, k, n, P, flat_block() * 64 + threadIdx.x);
 }
 
 }  // namespace mpk

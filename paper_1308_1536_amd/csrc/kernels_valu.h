@@ -73,15 +73,14 @@ __host__ __device__ inline size_t pivot_lds_bytes(int P) {
     return a > b ? a : b;
 }
 
-__global__ void __launch_bounds__(64) k_pivot_recip(MatDev A, MatDev D, int32_t *info, uint32_t *rw, int64_t k,
-                                                    int64_t n, int P) {
-    extern __shared__ uint32_t lds_raw[];
+__device__ __forceinline__ void pivot_recip_body(uint32_t *lds_raw, MatDev A, MatDev D, int32_t *info, uint32_t *rw, int64_t k,
+                                 int64_t n, int P, int role) {
     if (*info != 0) return;
     const uint32_t *pm = el(A, k, k, P);
     const bool piv_zero = pm[P - 1] == 0u;
     const int64_t pe = ex(A, k, k);
     const int32_t ps = sg(A, k, k);
-    if (blockIdx.x == 0) {
+    if (role == 0) {
         Lds L(lds_raw, P);
         bool bad = false;
         int32_t code = 0;
@@ -121,13 +120,12 @@ __global__ void __launch_bounds__(64) k_pivot_recip(MatDev A, MatDev D, int32_t 
     if (mpw::lane() == 0) rw[P + 1] = ok ? 1u : 0u;
 }
 
-__global__ void __launch_bounds__(64) k_divide(MatDev A, const uint32_t *rw, const int32_t *info, int64_t k,
-                                               int64_t n, int P) {
-    extern __shared__ uint32_t lds_raw[];
+__device__ __forceinline__ void divide_body(uint32_t *lds_raw, MatDev A, const uint32_t *rw, const int32_t *info, int64_t k,
+                            int64_t n, int P, int64_t blk) {
     if (*info != 0) return;
     const uint32_t *pm = el(A, k, k, P);
     if (pm[P - 1] == 0u) return;
-    const int64_t i = k + 1 + (int64_t)blockIdx.x;
+    const int64_t i = k + 1 + blk;
     uint32_t *am = el(A, i, k, P);
     mpw::DivBufs B = mpw::div_bufs(lds_raw, P);
     mpw::Hdr ha = mpw::load(B.a, am, ex(A, i, k), sg(A, i, k), P);
@@ -146,12 +144,10 @@ __global__ void __launch_bounds__(64) k_divide(MatDev A, const uint32_t *rw, con
 // Step k, part 2 (Algorithm 1 step 2.2.2): a_ij = RZ_p(a_ij - RZ_p(l_ik u_kj))
 // for k < i, j < n; block (bx) -> i = k+1 + bx / m, j = k+1 + bx % m.
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(64) k_update_valu(MatDev A, const int32_t *info, int64_t k, int64_t n,
-                                                    int P) {
-    extern __shared__ uint32_t lds_raw[];
+__device__ __forceinline__ void update_valu_body(uint32_t *lds_raw, MatDev A, const int32_t *info, int64_t k, int64_t n, int P,
+                                 int64_t bx) {
     if (*info != 0) return;
     const int64_t m = n - k - 1;
-    const int64_t bx = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
     if (bx >= m * m) return;
     const int64_t i = k + 1 + bx / m, j = k + 1 + bx % m;
     const uint32_t *lm = el(A, i, k, P);
@@ -182,11 +178,9 @@ __global__ void k_minors_init(MatDev c, int64_t n, int P) {
 }
 
 // sweep j: s_i = RZ_p(s_i - RZ_p(x_j l_ji)), i < j; x_{n-1} = 1, x_j = s_j otherwise
-__global__ void __launch_bounds__(64) k_minors_sweep(MatDev LU, MatDev c, const int32_t *info, int64_t j,
-                                                     int64_t n, int P) {
-    extern __shared__ uint32_t lds_raw[];
+__device__ __forceinline__ void minors_sweep_body(uint32_t *lds_raw, MatDev LU, MatDev c, const int32_t *info, int64_t j,
+                                  int64_t n, int P, int64_t i) {
     if (*info != 0) return;
-    const int64_t i = blockIdx.x;
     Lds L(lds_raw, P);
     const uint32_t *lm = el(LU, j, i, P);
     if (lm[P - 1] == 0u) return;
@@ -207,11 +201,9 @@ __global__ void __launch_bounds__(64) k_minors_sweep(MatDev LU, MatDev c, const 
 }
 
 // c_i = RZ_p(D_{n-1} x_i) for i < n-1 (block i), c_{n-1} = D_{n-1}; n == 1: c = 1
-__global__ void __launch_bounds__(64) k_minors_final(MatDev D, MatDev c, const int32_t *info, int64_t n,
-                                                     int P) {
-    extern __shared__ uint32_t lds_raw[];
+__device__ __forceinline__ void minors_final_body(uint32_t *lds_raw, MatDev D, MatDev c, const int32_t *info, int64_t n, int P,
+                                  int64_t i) {
     if (*info != 0) return;
-    const int64_t i = blockIdx.x;
     uint32_t *cm = el(c, 0, i, P);
     if (n == 1) {
         for (int q = mpw::lane(); q < P; q += MP_WAVE) cm[q] = (q == P - 1) ? 0x80000000u : 0u;
@@ -238,6 +230,41 @@ __global__ void __launch_bounds__(64) k_minors_final(MatDev D, MatDev c, const i
 }
 
 // ---------------------------------------------------------------------------
+// single-matrix launches (one block per unit of work)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int64_t flat_block() {
+    return (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
+}
+
+__global__ void __launch_bounds__(64) k_pivot_recip(MatDev A, MatDev D, int32_t *info, uint32_t *rw, int64_t k,
+                                                    int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    pivot_recip_body(lds_raw, A, D, info, rw, k, n, P, (int)blockIdx.x);
+}
+
+__global__ void __launch_bounds__(64) k_divide(MatDev A, const uint32_t *rw, const int32_t *info, int64_t k,
+                                               int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    divide_body(lds_raw, A, rw, info, k, n, P, flat_block());
+}
+
+__global__ void __launch_bounds__(64) k_update_valu(MatDev A, const int32_t *info, int64_t k, int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    update_valu_body(lds_raw, A, info, k, n, P, flat_block());
+}
+
+__global__ void __launch_bounds__(64) k_minors_sweep(MatDev LU, MatDev c, const int32_t *info, int64_t j,
+                                                     int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    minors_sweep_body(lds_raw, LU, c, info, j, n, P, flat_block());
+}
+
+__global__ void __launch_bounds__(64) k_minors_final(MatDev D, MatDev c, const int32_t *info, int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    minors_final_body(lds_raw, D, c, info, n, P, flat_block());
+}
+
+// ---------------------------------------------------------------------------
 // Output conversion: (-1)^s RZ_53(m / 2^p) and the exponent.
 // ---------------------------------------------------------------------------
 __global__ void k_to_f64(MatDev x, int64_t rows, int64_t cols, int P, double *mant, int64_t *eo) {
@@ -256,6 +283,27 @@ __global__ void k_to_f64(MatDev x, int64_t rows, int64_t cols, int P, double *ma
     double d = ldexp((double)v, -53);
     mant[t] = sg(x, i, j) ? -d : d;
     eo[t] = ex(x, i, j);
+}
+
+// val = RZ_53 mantissa * 2^(exp - *shift), one IEEE rounding (ldexp: nearest
+// even) where the result lands in float64's subnormal range; the exponent
+// difference is clamped to +-2200, beyond which the result is 0 or inf anyway.
+__global__ void k_to_f64_scaled(MatDev x, int64_t rows, int64_t cols, int P, const int64_t *shift, double *val) {
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= rows * cols) return;
+    int64_t i = t / cols, j = t % cols;
+    const uint32_t *m = el(x, i, j, P);
+    uint32_t top = m[P - 1];
+    if (top == 0u) {
+        val[t] = 0.0;
+        return;
+    }
+    uint64_t v = ((uint64_t)top << 21) | (uint64_t)(m[P - 2] >> 11);
+    int64_t s = ex(x, i, j) - *shift;
+    s = s < -2200 ? -2200 : (s > 2200 ? 2200 : s);
+    // v 2^(s-53) in two exact-or-once-rounded steps: v 2^-53 is exact
+    double d = ldexp(ldexp((double)v, -53), (int)s);
+    val[t] = sg(x, i, j) ? -d : d;
 }
 
 __global__ void k_set_info(int32_t *info, int32_t v) {

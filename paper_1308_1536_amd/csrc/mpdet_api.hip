@@ -12,14 +12,20 @@
 #include "mpdet.h"
 #include "kernels_valu.h"
 #include "kernels_mfma.h"
+#include "kernels_adj.h"
+#include "kernels_batch.h"
+#include <algorithm>
+#include <numeric>
+#include <vector>
 
 // Per-kernel timing (off by default): each launch is bracketed by two HIP
 // events recorded on the launch stream; mpdet_profile_end folds the elapsed
 // times into per-kernel totals.
 enum KernelId { K_PIVOT_DIVIDE = 0, K_DIVIDE, K_UPDATE_VALU, K_UPDATE_MFMA, K_MFMA_PREP, K_MINORS_SWEEP,
-                K_MINORS_FINAL, K_OTHER, K_COUNT };
-static const char *kKernelNames[K_COUNT] = {"pivot_divide", "divide", "update_valu", "update_mfma", "mfma_prep",
-                                            "minors_sweep", "minors_final", "other"};
+                K_MINORS_FINAL, K_UPDATE_FINISH, K_ADJUGATE, K_OTHER, K_COUNT };
+static const char *kKernelNames[K_COUNT] = {"pivot_divide", "divide",       "update_valu",   "update_mfma",
+                                            "mfma_prep",    "minors_sweep", "minors_final",  "update_finish",
+                                            "adjugate",     "other"};
 
 struct ProfRec {
     int kernel;
@@ -41,6 +47,17 @@ struct mpdet_handle {
     // the pivot's reciprocal
     void *rw;
     size_t rw_bytes;
+    // adjugate workspace
+    void *aw;
+    size_t aw_bytes;
+    // batched launches: device workspace, pinned staging of the tables, and
+    // the event of the last staging copy
+    void *bw;
+    size_t bw_bytes;
+    void *bh;
+    size_t bh_bytes;
+    hipEvent_t bh_done;
+    bool bh_pending;
 };
 
 namespace {
@@ -56,6 +73,7 @@ bool mat_ok(const mpdet_mat &m, bool need_ptrs) {
 }
 
 mpk::MatDev dev(const mpdet_mat &m) { return mpk::MatDev{m.limbs, m.exp, m.sign, m.ld}; }
+mpk::MatDev dev_mat(const mpdet_mat &m) { return dev(m); }
 
 dim3 grid_for(int64_t blocks) {
     // gridDim.x <= 2^31-1; fold into y beyond that
@@ -189,15 +207,20 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
 // multiplier digits, pivot-row digits and product-top records.
 struct MfmaWs {
     uint8_t *Lr, *Ub;
-    uint32_t *T;
+    uint32_t *T, *G;
 };
+
+// bytes of one product-top buffer (T or G) for an m x m trailing block
+size_t mfma_rec_bytes(int64_t m, int P) {
+    return (size_t)mpk::sub_lane_slots(m) * (size_t)mpk::mfma_geom(P).TP * 4u;
+}
 
 int mfma_workspace(mpdet_handle *h, int64_t m, int P, MfmaWs *w) {
     const mpk::MfmaGeom g = mpk::mfma_geom(P);
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t lr = up((size_t)m * g.LR), ub = up((size_t)m * g.K8);
-    const size_t t = up((size_t)m * (size_t)m * (size_t)g.TP * 4u);
-    const size_t need = lr + ub + t;
+    const size_t t = up(mfma_rec_bytes(m, P));
+    const size_t need = lr + ub + 2 * t;
     if (need > h->ws_bytes) {
         if (h->ws) (void)hipFree(h->ws);
         h->ws = nullptr;
@@ -213,6 +236,7 @@ int mfma_workspace(mpdet_handle *h, int64_t m, int P, MfmaWs *w) {
     w->Lr = base;
     w->Ub = base + lr;
     w->T = (uint32_t *)(base + lr + ub);
+    w->G = (uint32_t *)(base + lr + ub + t);
     return MPDET_OK;
 }
 
@@ -237,14 +261,14 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
         if ((rc = last_launch())) return rc;
         {
             Prof pr(h, s, K_UPDATE_MFMA);
-            hipLaunchKernelGGL(mpk::k_update_mfma, grid_for(m * ((m + 31) / 32)), dim3(64), lds_mfma, s, a,
+            hipLaunchKernelGGL(mpk::k_update_mfma, grid_for(mpk::mfma_update_blocks(m)), dim3(64), lds_mfma, s, a,
                                (const uint8_t *)w.Lr, (const uint8_t *)w.Ub, w.T, cinfo, k, n, P);
         }
         if ((rc = last_launch())) return rc;
         {
-            Prof pr(h, s, K_OTHER);
-            hipLaunchKernelGGL(mpk::k_sub_mfma, grid_for(m * m), dim3(64), mpk::lds_bytes(P), s, a,
-                               (const uint32_t *)w.T, cinfo, k, n, P);
+            Prof pr(h, s, K_UPDATE_FINISH);
+            hipLaunchKernelGGL(mpk::k_sub_lane, grid_for((mpk::sub_lane_slots(m) + 63) / 64), dim3(64), 0, s, a,
+                               (const uint32_t *)w.T, w.G, cinfo, k, n, P);
         }
         if ((rc = last_launch())) return rc;
     }
@@ -288,6 +312,10 @@ int mpdet_destroy(mpdet_handle *h) {
     free(h->recs);
     if (h->ws) (void)hipFree(h->ws);
     if (h->rw) (void)hipFree(h->rw);
+    if (h->aw) (void)hipFree(h->aw);
+    if (h->bw) (void)hipFree(h->bw);
+    if (h->bh) (void)hipHostFree(h->bh);
+    if (h->bh_done) (void)hipEventDestroy(h->bh_done);
     free(h);
     return MPDET_OK;
 }
@@ -391,6 +419,305 @@ int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c, const
     return last_launch();
 }
 
+namespace {
+
+enum BatchPhase { BP_PIVOT = 0, BP_DIVIDE, BP_UPD, BP_PREP, BP_SUB, BP_COUNT };
+
+int grow_device(void **p, size_t *have, size_t need) {
+    if (need <= *have) return MPDET_OK;
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+    *have = 0;
+    if (hipMalloc(p, need) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return MPDET_ENOMEM;
+    }
+    *have = need;
+    return MPDET_OK;
+}
+
+}  // namespace
+
+int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const mpdet_mat *D_arr,
+                   const mpdet_mat *c_arr, int32_t *info_dev, int flags, int path, void *stream) {
+    if (!h || batch < 0) return MPDET_EINVAL;
+    if (batch == 0) return MPDET_OK;
+    if (!A_arr || !D_arr || !info_dev) return MPDET_EINVAL;
+    if (flags & ~MPDET_WANT_MINORS) return MPDET_EINVAL;
+    const bool minors = (flags & MPDET_WANT_MINORS) != 0;
+    if (minors && !c_arr) return MPDET_EINVAL;
+    if (path != MPDET_PATH_AUTO && path != MPDET_PATH_VALU && path != MPDET_PATH_MFMA) return MPDET_EINVAL;
+    const int P = A_arr[0].nlimbs;
+    int64_t nmax = 0;
+    for (int64_t b = 0; b < batch; ++b) {
+        const mpdet_mat &A = A_arr[b], &D = D_arr[b];
+        const int64_t n = A.rows;
+        if (n < 1 || A.cols != n || !mat_ok(A, true) || !mat_ok(D, true) || A.nlimbs != P || D.nlimbs != P ||
+            D.cols < n)
+            return MPDET_EINVAL;
+        if (minors && (!mat_ok(c_arr[b], true) || c_arr[b].nlimbs != P || c_arr[b].cols < n))
+            return MPDET_EINVAL;
+        nmax = n > nmax ? n : nmax;
+    }
+    const bool mfma_ok = mpk::mfma_supported(P);
+    if (path == MPDET_PATH_MFMA && !mfma_ok) return MPDET_ENOTSUP;
+    const bool use_mfma = path == MPDET_PATH_MFMA || (path == MPDET_PATH_AUTO && mfma_ok);
+    DeviceGuard g(h->device);
+    if (!g.ok) return MPDET_EHIP;
+    hipStream_t s = (hipStream_t)stream;
+
+    // largest first: the matrices active at step k are a prefix of `order`
+    std::vector<int32_t> order((size_t)batch);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return A_arr[a].rows > A_arr[b].rows; });
+    auto nof = [&](int t) { return A_arr[order[(size_t)t]].rows; };
+
+    // block counts per (step, phase) -> prefix offsets, all in one table
+    auto blocks = [&](int phase, int64_t n, int64_t k) -> int64_t {
+        const int64_t m = n - k - 1;
+        switch (phase) {
+            case BP_PIVOT: return 2;
+            case BP_DIVIDE: return m;
+            case BP_UPD: return use_mfma ? m * ((m + 31) / 32) : m * m;
+            case BP_PREP: return 2 * m;
+            case BP_SUB: return (mpk::sub_lane_slots(m) + 63) / 64;
+        }
+        return 0;
+    };
+    std::vector<int64_t> table;
+    std::vector<int64_t> start((size_t)(nmax * BP_COUNT + nmax + 2), -1);
+    std::vector<int32_t> count((size_t)(nmax * BP_COUNT + nmax + 2), 0);
+    int cnt = (int)batch;
+    for (int64_t k = 0; k < nmax; ++k) {
+        while (cnt > 0 && nof(cnt - 1) <= k) --cnt;
+        for (int ph = 0; ph < BP_COUNT; ++ph) {
+            const size_t slot = (size_t)(k * BP_COUNT + ph);
+            start[slot] = (int64_t)table.size();
+            count[slot] = cnt;
+            int64_t acc = 0;
+            table.push_back(0);
+            for (int t = 0; t < cnt; ++t) {
+                acc += blocks(ph, nof(t), k);
+                table.push_back(acc);
+            }
+        }
+    }
+    // minors: sweep s (active: n >= s + 2), then final and init (all)
+    const size_t mbase = (size_t)(nmax * BP_COUNT);
+    if (minors) {
+        for (int64_t sw = 0; sw + 2 <= nmax; ++sw) {
+            int c2 = 0;
+            while (c2 < (int)batch && nof(c2) >= sw + 2) ++c2;
+            start[mbase + (size_t)sw] = (int64_t)table.size();
+            count[mbase + (size_t)sw] = c2;
+            int64_t acc = 0;
+            table.push_back(0);
+            for (int t = 0; t < c2; ++t) {
+                acc += nof(t) - 1 - sw;
+                table.push_back(acc);
+            }
+        }
+        for (int which = 0; which < 2; ++which) {  // 0: final (n blocks), 1: init
+            const size_t slot = mbase + (size_t)nmax + (size_t)which;
+            start[slot] = (int64_t)table.size();
+            count[slot] = (int)batch;
+            int64_t acc = 0;
+            table.push_back(0);
+            for (int t = 0; t < (int)batch; ++t) {
+                acc += which == 0 ? nof(t) : (nof(t) * P + 255) / 256;
+                table.push_back(acc);
+            }
+        }
+    }
+
+    // device workspace: descriptors, order, table, then per-matrix scratch
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const mpk::MfmaGeom geo = mpk::mfma_geom(P);
+    std::vector<size_t> scratch((size_t)batch);
+    size_t total_scratch = 0;
+    for (int64_t b = 0; b < batch; ++b) {
+        const int64_t n = A_arr[b].rows, m = n > 1 ? n - 1 : 1;
+        size_t need = up((size_t)(P + 2) * 4u);
+        if (use_mfma)
+            need += up((size_t)m * geo.LR) + up((size_t)m * geo.K8) + 2 * up(mfma_rec_bytes(m, P));
+        scratch[(size_t)b] = need;
+        total_scratch += need;
+    }
+    const size_t desc_bytes = up(sizeof(mpk::BatchMat) * (size_t)batch);
+    const size_t order_bytes = up(sizeof(int32_t) * (size_t)batch);
+    const size_t table_bytes = up(sizeof(int64_t) * table.size());
+    const size_t host_bytes = desc_bytes + order_bytes + table_bytes;
+    int rc = grow_device(&h->bw, &h->bw_bytes, host_bytes + total_scratch);
+    if (rc) return rc;
+    if (h->bh_pending) {
+        (void)hipEventSynchronize(h->bh_done);
+        h->bh_pending = false;
+    }
+    if (host_bytes > h->bh_bytes) {
+        if (h->bh) (void)hipHostFree(h->bh);
+        h->bh = nullptr;
+        h->bh_bytes = 0;
+        if (hipHostMalloc(&h->bh, host_bytes, hipHostMallocDefault) != hipSuccess) {
+            h->bh = nullptr;
+            (void)hipGetLastError();
+            return MPDET_ENOMEM;
+        }
+        h->bh_bytes = host_bytes;
+    }
+    if (!h->bh_done && hipEventCreateWithFlags(&h->bh_done, hipEventDisableTiming) != hipSuccess) return MPDET_EHIP;
+    uint8_t *dev = (uint8_t *)h->bw;
+    uint8_t *hst = (uint8_t *)h->bh;
+    mpk::BatchMat *hm = (mpk::BatchMat *)hst;
+    uint8_t *sp = dev + host_bytes;
+    for (int64_t b = 0; b < batch; ++b) {
+        const int64_t n = A_arr[b].rows, m = n > 1 ? n - 1 : 1;
+        mpk::BatchMat &M = hm[b];
+        M.A = dev_mat(A_arr[b]);
+        M.D = dev_mat(D_arr[b]);
+        M.c = minors ? dev_mat(c_arr[b]) : mpk::MatDev{nullptr, nullptr, nullptr, 0};
+        M.info = info_dev + b;
+        M.n = n;
+        uint8_t *q = sp;
+        M.rw = (uint32_t *)q;
+        q += up((size_t)(P + 2) * 4u);
+        M.Lr = M.Ub = nullptr;
+        M.T = M.G = nullptr;
+        if (use_mfma) {
+            M.Lr = q;
+            q += up((size_t)m * geo.LR);
+            M.Ub = q;
+            q += up((size_t)m * geo.K8);
+            M.T = (uint32_t *)q;
+            q += up(mfma_rec_bytes(m, P));
+            M.G = (uint32_t *)q;
+        }
+        sp += scratch[(size_t)b];
+    }
+    memcpy(hst + desc_bytes, order.data(), sizeof(int32_t) * order.size());
+    memcpy(hst + desc_bytes + order_bytes, table.data(), sizeof(int64_t) * table.size());
+    if (hipMemcpyAsync(dev, hst, host_bytes, hipMemcpyHostToDevice, s) != hipSuccess) return MPDET_EHIP;
+    if (hipEventRecord(h->bh_done, s) != hipSuccess) return MPDET_EHIP;
+    h->bh_pending = true;
+    const mpk::BatchMat *dmats = (const mpk::BatchMat *)dev;
+    const int32_t *dorder = (const int32_t *)(dev + desc_bytes);
+    const int64_t *dtable = (const int64_t *)(dev + desc_bytes + order_bytes);
+
+    hipLaunchKernelGGL(mpk::k_batch_zero_info, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, info_dev,
+                       batch);
+    if ((rc = last_launch())) return rc;
+    const size_t lds_piv = mpk::pivot_lds_bytes(P), lds = mpk::lds_bytes(P);
+    const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
+    auto launch = [&](int kernel_id, auto kern, size_t slot, size_t shmem, int64_t arg) -> int {
+        const int c = count[slot];
+        if (c <= 0) return MPDET_OK;
+        const int64_t total = table[(size_t)start[slot] + (size_t)c];
+        if (total <= 0) return MPDET_OK;
+        Prof pr(h, s, kernel_id);
+        hipLaunchKernelGGL(kern, grid_for(total), dim3(64), shmem, s, dmats, dorder, dtable + start[slot], c, arg,
+                           P);
+        return last_launch();
+    };
+    for (int64_t k = 0; k < nmax; ++k) {
+        const size_t base = (size_t)(k * BP_COUNT);
+        if ((rc = launch(K_PIVOT_DIVIDE, mpk::k_batch_pivot, base + BP_PIVOT, lds_piv, k))) return rc;
+        if ((rc = launch(K_DIVIDE, mpk::k_batch_divide, base + BP_DIVIDE, lds_piv, k))) return rc;
+        if (use_mfma) {
+            if ((rc = launch(K_MFMA_PREP, mpk::k_batch_prep, base + BP_PREP, lds_prep, k))) return rc;
+            if ((rc = launch(K_UPDATE_MFMA, mpk::k_batch_update_mfma, base + BP_UPD, lds_mfma, k))) return rc;
+            if ((rc = launch(K_UPDATE_FINISH, mpk::k_batch_sub, base + BP_SUB, 0, k))) return rc;
+        } else {
+            if ((rc = launch(K_UPDATE_VALU, mpk::k_batch_update_valu, base + BP_UPD, lds, k))) return rc;
+        }
+    }
+    if (minors) {
+        const size_t islot = mbase + (size_t)nmax + 1;
+        const int64_t itotal = table[(size_t)start[islot] + (size_t)count[islot]];
+        hipLaunchKernelGGL(mpk::k_batch_minit, grid_for(itotal), dim3(256), 0, s, dmats, dorder,
+                           dtable + start[islot], count[islot], P);
+        if ((rc = last_launch())) return rc;
+        for (int64_t sw = 0; sw + 2 <= nmax; ++sw)
+            if ((rc = launch(K_MINORS_SWEEP, mpk::k_batch_msweep, mbase + (size_t)sw, lds, sw))) return rc;
+        if ((rc = launch(K_MINORS_FINAL, mpk::k_batch_mfinal, mbase + (size_t)nmax, lds, 0))) return rc;
+    }
+    return MPDET_OK;
+}
+
+int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT, const int32_t *info_dev,
+                    void *stream) {
+    if (!h || !info_dev) return MPDET_EINVAL;
+    const int64_t n = LU.rows;
+    if (n < 1 || !mat_ok(LU, true) || !mat_ok(D, true) || !mat_ok(adjT, true)) return MPDET_EINVAL;
+    if (LU.cols != n || D.cols < n || adjT.rows != n || adjT.cols != n || D.nlimbs != LU.nlimbs ||
+        adjT.nlimbs != LU.nlimbs)
+        return MPDET_EINVAL;
+    DeviceGuard g(h->device);
+    if (!g.ok) return MPDET_EHIP;
+    hipStream_t s = (hipStream_t)stream;
+    const int P = LU.nlimbs;
+    // workspace: W, adj(U) (n x n each), S (n + 1), reciprocals (n x (P + 2))
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t nn = (size_t)n * (size_t)n;
+    const size_t ml = up(nn * (size_t)P * 4u), me = up(nn * 8u), ms = up(nn * 4u);
+    const size_t sl = up((size_t)(n + 1) * P * 4u), se = up((size_t)(n + 1) * 8u), ss = up((size_t)(n + 1) * 4u);
+    const size_t rb = up((size_t)n * (P + 2) * 4u);
+    const size_t need = 2 * (ml + me + ms) + sl + se + ss + rb;
+    if (need > h->aw_bytes) {
+        if (h->aw) (void)hipFree(h->aw);
+        h->aw = nullptr;
+        h->aw_bytes = 0;
+        if (hipMalloc(&h->aw, need) != hipSuccess) {
+            h->aw = nullptr;
+            (void)hipGetLastError();
+            return MPDET_ENOMEM;
+        }
+        h->aw_bytes = need;
+    }
+    uint8_t *base = (uint8_t *)h->aw;
+    auto carve = [&](size_t bytes) {
+        uint8_t *p = base;
+        base += bytes;
+        return p;
+    };
+    mpk::MatDev W{(uint32_t *)carve(ml), (int64_t *)carve(me), (int32_t *)carve(ms), n};
+    mpk::MatDev J{(uint32_t *)carve(ml), (int64_t *)carve(me), (int32_t *)carve(ms), n};
+    mpk::MatDev S{(uint32_t *)carve(sl), (int64_t *)carve(se), (int32_t *)carve(ss), n + 1};
+    uint32_t *rw = (uint32_t *)carve(rb);
+    mpk::MatDev lu = dev(LU), d = dev(D), t = dev(adjT);
+    const size_t lds = mpk::pivot_lds_bytes(P);
+    int rc;
+    const int64_t cells = (int64_t)nn;
+    hipLaunchKernelGGL(mpk::k_adj_init, grid_for((cells + 255) / 256), dim3(256), 0, s, W, n, P, 1);
+    hipLaunchKernelGGL(mpk::k_adj_init, grid_for((cells + 255) / 256), dim3(256), 0, s, J, n, P, 0);
+    hipLaunchKernelGGL(mpk::k_adj_init, grid_for((cells + 255) / 256), dim3(256), 0, s, t, n, P, 0);
+    if ((rc = last_launch())) return rc;
+    {
+        Prof pr(h, s, K_ADJUGATE);
+        for (int64_t j = n - 1; j >= 1; --j) {
+            hipLaunchKernelGGL(mpk::k_adj_w, grid_for((n - j) * j), dim3(64), lds, s, lu, W, info_dev, j, n, P);
+            if ((rc = last_launch())) return rc;
+        }
+        hipLaunchKernelGGL(mpk::k_adj_s, dim3(1), dim3(64), lds, s, lu, S, info_dev, n, P);
+        hipLaunchKernelGGL(mpk::k_adj_diag, dim3((unsigned)n), dim3(64), lds, s, d, S, J, info_dev, n, P);
+        hipLaunchKernelGGL(mpk::k_adj_recips, dim3((unsigned)n), dim3(64), lds, s, lu, rw, info_dev, n, P);
+        if ((rc = last_launch())) return rc;
+        for (int64_t k = n - 1; k >= 1; --k) {
+            hipLaunchKernelGGL(mpk::k_adj_u_upd, grid_for(k * (n - k)), dim3(64), lds, s, lu, J, info_dev, k, n,
+                               P);
+            hipLaunchKernelGGL(mpk::k_adj_u_div, dim3((unsigned)(n - k)), dim3(64), lds, s, lu, J,
+                               (const uint32_t *)rw, info_dev, k, n, P);
+            if ((rc = last_launch())) return rc;
+        }
+        for (int64_t k = 0; k < n; ++k) {
+            hipLaunchKernelGGL(mpk::k_adj_prod, grid_for((k + 1) * (k + 1)), dim3(64), lds, s, J, W, t, info_dev,
+                               k, P);
+            if ((rc = last_launch())) return rc;
+        }
+    }
+    return MPDET_OK;
+}
+
 int mp_to_f64(mpdet_handle *h, mpdet_mat x, double *mant_dev, int64_t *exp_dev, void *stream) {
     if (!h || !mat_ok(x, x.rows * x.cols > 0)) return MPDET_EINVAL;
     const int64_t cnt = x.rows * x.cols;
@@ -400,6 +727,18 @@ int mp_to_f64(mpdet_handle *h, mpdet_mat x, double *mant_dev, int64_t *exp_dev, 
     if (!g.ok) return MPDET_EHIP;
     hipLaunchKernelGGL(mpk::k_to_f64, grid_for((cnt + 255) / 256), dim3(256), 0, (hipStream_t)stream, dev(x),
                        x.rows, x.cols, x.nlimbs, mant_dev, exp_dev);
+    return last_launch();
+}
+
+int mp_to_f64_scaled(mpdet_handle *h, mpdet_mat x, const int64_t *shift_dev, double *val_dev, void *stream) {
+    if (!h || !mat_ok(x, x.rows * x.cols > 0)) return MPDET_EINVAL;
+    const int64_t cnt = x.rows * x.cols;
+    if (cnt == 0) return MPDET_OK;
+    if (!shift_dev || !val_dev) return MPDET_EINVAL;
+    DeviceGuard g(h->device);
+    if (!g.ok) return MPDET_EHIP;
+    hipLaunchKernelGGL(mpk::k_to_f64_scaled, grid_for((cnt + 255) / 256), dim3(256), 0, (hipStream_t)stream,
+                       dev(x), x.rows, x.cols, x.nlimbs, shift_dev, val_dev);
     return last_launch();
 }
 

@@ -401,13 +401,11 @@ __device__ __forceinline__ uint64_t udiv_2by1(uint64_t num, uint32_t v1) {
     return q;
 }
 
-constexpr int kMaxDivBlocks = 17;  // ceil((1024 + 1) / 64)
-
 // out = RZ_p(a / b), b != 0 with its top bit set.
 // Knuth's Algorithm D in base 2^32 on U = m_a * 2^(p+1) (2P+1 limbs, plus a
 // zero limb on top) and V = m_b (already normalised); the quotient Q has
 // p+1 or p+2 bits and is truncated to p bits.  Per quotient digit the
-// remainder window U[j..j+P] -= qhat * V runs in registers: lane t owns
+// remainder window U[j..j+P] -= qhat * V runs block by block: lane t owns
 // window limbs t, t+64, ...; the product's high words and the first-stage
 // borrows (0..2) move one limb up by lane shuffles, and the remaining 1-bit
 // borrows are resolved by the ballot lookahead.  One LDS barrier per digit.
@@ -422,12 +420,6 @@ __device__ Hdr div(uint32_t *out, const uint32_t *am, Hdr ha, const uint32_t *bm
     const int S = (n1 + MP_WAVE - 1) / MP_WAVE;
     shift(U, m + 1, am, P, 32LL * P + 1);
     fill(Q, P + 2, 0u);
-    uint32_t vreg[kMaxDivBlocks];
-#pragma unroll
-    for (int s = 0; s < kMaxDivBlocks; ++s) {
-        const int q = s * MP_WAVE + lane();
-        vreg[s] = (s < S && q < P) ? bm[q] : 0u;
-    }
     wsync();
     const uint64_t B = 1ull << 32;
     const uint32_t v1 = bm[P - 1], v2 = bm[P - 2];
@@ -449,12 +441,12 @@ __device__ Hdr div(uint32_t *out, const uint32_t *am, Hdr ha, const uint32_t *bm
         if (qhat) {
             uint32_t hi_in = 0, b1_in = 0, b2_in = 0;  // entering lane 0 of a block
             uint32_t neg = 0;
-#pragma unroll
-            for (int s = 0; s < kMaxDivBlocks; ++s) {
-                if (s < S) {
+#pragma unroll 1
+            for (int s = 0; s < S; ++s) {
+                {
                     const int q = s * MP_WAVE + lane();
                     const int cnt = min(MP_WAVE, n1 - s * MP_WAVE);
-                    const uint64_t pr = qhat * (uint64_t)vreg[s];
+                    const uint64_t pr = qhat * (uint64_t)(q < P ? bm[q] : 0u);
                     const uint32_t lo = (uint32_t)pr, hi = (uint32_t)(pr >> 32);
                     uint32_t hi_prev = __shfl_up(hi, 1);
                     if (lane() == 0) hi_prev = hi_in;
@@ -485,12 +477,12 @@ __device__ Hdr div(uint32_t *out, const uint32_t *am, Hdr ha, const uint32_t *bm
             if (neg) {
                 qhat--;
                 uint32_t carry = 0;
-#pragma unroll
-                for (int s = 0; s < kMaxDivBlocks; ++s) {
-                    if (s < S) {
+#pragma unroll 1
+                for (int s = 0; s < S; ++s) {
+                    {
                         const int q = s * MP_WAVE + lane();
                         const int cnt = min(MP_WAVE, n1 - s * MP_WAVE);
-                        const uint32_t x = q < n1 ? U[j + q] : 0u, y = vreg[s];
+                        const uint32_t x = q < n1 ? U[j + q] : 0u, y = q < P ? bm[q] : 0u;
                         const uint32_t sm = x + y;
                         const uint64_t valid = cnt == 64 ? ~0ull : ((1ull << cnt) - 1ull);
                         const uint64_t G = __ballot(sm < x) & valid;

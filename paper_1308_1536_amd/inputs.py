@@ -115,16 +115,12 @@ def from_values(values, P: int) -> MpArray:
 # matrices
 # ---------------------------------------------------------------------------
 
-def _cauchy_rows(args):
-    rows, xs_num, ys_num, F, P = args
+def _cauchy_fill(rows, xs_num, ys_num, F, P, out_l, out_e, out_s):
+    """a_ij = 1 / (x_i - y_j) = 2^F / d, d = X_i - Y_j an integer, truncated to p bits."""
     p = 32 * P
-    out_l = np.zeros((len(rows), len(ys_num), P), np.uint32)
-    out_e = np.zeros((len(rows), len(ys_num)), np.int64)
-    out_s = np.zeros((len(rows), len(ys_num)), np.int32)
-    for r, i in enumerate(rows):
+    for i in rows:
         xi = xs_num[i]
         for j, yj in enumerate(ys_num):
-            # a_ij = 1 / (x_i - y_j) = 2^F / d with d = X_i - Y_j an integer
             d = xi - yj
             if d == 0:
                 raise ZeroDivisionError("Cauchy nodes collide")
@@ -134,16 +130,25 @@ def _cauchy_rows(args):
             e = F - d.bit_length() + 1
             if d & (d - 1) == 0:  # exact power of two
                 e += 1
-            sh = p - e + F
-            m = (1 << sh) // d
-            out_s[r, j] = s
-            out_e[r, j] = e
-            out_l[r, j] = np.frombuffer(m.to_bytes(4 * P, "little"), dtype="<u4")
-    return out_l, out_e, out_s
+            m = (1 << (p - e + F)) // d
+            out_s[i, j] = s
+            out_e[i, j] = e
+            out_l[i, j] = np.frombuffer(m.to_bytes(4 * P, "little"), dtype="<u4")
+
+
+_SHARED = {}
+
+
+def _cauchy_worker(rows):
+    a = _SHARED
+    _cauchy_fill(rows, a["xs"], a["ys"], a["F"], a["P"], a["l"], a["e"], a["s"])
+    return len(rows)
 
 
 def cauchy(x: Sequence, y: Sequence, P: int, workers: int | None = None) -> MpArray:
-    """a_ij = RZ_p(1 / (x_i - y_j)) for exact dyadic or integer nodes."""
+    """a_ij = RZ_p(1 / (x_i - y_j)) for exact dyadic or integer nodes.  Large
+    matrices are filled by forked workers writing into one shared mapping."""
+    import mmap
     xf = [Fraction(v) for v in x]
     yf = [Fraction(v) for v in y]
     dens = [f.denominator for f in xf + yf]
@@ -156,17 +161,26 @@ def cauchy(x: Sequence, y: Sequence, P: int, workers: int | None = None) -> MpAr
     n, m = len(xs), len(ys)
     if workers is None:
         workers = 1 if n * m * P < 4_000_000 else min(16, os.cpu_count() or 1)
+    if workers <= 1 or n < 2:
+        out = MpArray.zeros((n, m), P)
+        _cauchy_fill(range(n), xs, ys, F, P, out.limbs, out.exp, out.sign)
+        return out
+    nl, ne, ns = n * m * P * 4, n * m * 8, n * m * 4
+    buf = mmap.mmap(-1, nl + ne + ns)
+    limbs = np.frombuffer(buf, dtype=np.uint32, count=n * m * P, offset=0).reshape(n, m, P)
+    exp = np.frombuffer(buf, dtype=np.int64, count=n * m, offset=nl).reshape(n, m)
+    sign = np.frombuffer(buf, dtype=np.int32, count=n * m, offset=nl + ne).reshape(n, m)
+    _SHARED.update(xs=xs, ys=ys, F=F, P=P, l=limbs, e=exp, s=sign)
     step = max(1, -(-n // (4 * workers)))
     chunks = [list(range(i, min(n, i + step))) for i in range(0, n, step)]
-    args = [(c, xs, ys, F, P) for c in chunks]
-    if workers > 1 and len(chunks) > 1:
-        import multiprocessing as mp
-        with mp.get_context("fork").Pool(workers) as pool:
-            parts = pool.map(_cauchy_rows, args)
-    else:
-        parts = [_cauchy_rows(a) for a in args]
-    return MpArray(np.concatenate([p[0] for p in parts]), np.concatenate([p[1] for p in parts]),
-                   np.concatenate([p[2] for p in parts]))
+    import multiprocessing as mpc
+    try:
+        with mpc.get_context("fork").Pool(workers) as pool:
+            done = sum(pool.map(_cauchy_worker, chunks))
+    finally:
+        _SHARED.clear()
+    assert done == n
+    return MpArray(limbs, exp, sign)
 
 
 def cauchy_integer_nodes(N: int, P: int) -> tuple[MpArray, list, list]:

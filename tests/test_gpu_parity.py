@@ -138,6 +138,27 @@ def test_to_f64_matches_oracle():
     assert np.array_equal(e.cpu().numpy(), we)
 
 
+def test_to_f64_scaled_matches_ldexp():
+    """mp_to_f64_scaled against numpy's ldexp of the oracle's (mantissa,
+    exponent): normal, subnormal (one rounding), underflow to zero and
+    overflow to inf."""
+    import torch
+    from paper_1308_1536_amd import binding
+    x = inputs.random_mantissas((6, 11), 5, 77, emin=-1200, emax=1200)
+    x.limbs[1, 2] = 0
+    x.exp[1, 2] = 0
+    x.sign[1, 2] = 0
+    x.exp[0, :] = [-1021, -1022, -1030, -1060, -1073, -1074, -1075, -1076, 1023, 1024, 1025]
+    xd = binding.DeviceMp.from_host(x)
+    wm, we = oracle.to_f64(x)
+    for sh in (0, 5, -7, 3000, -3000):
+        got = binding.to_f64_scaled(xd, torch.tensor([sh], dtype=torch.int64, device="cuda"))
+        torch.cuda.synchronize()
+        want = np.ldexp(wm, np.clip(we - sh, -2200, 2200))
+        g = got.cpu().numpy()
+        assert np.array_equal(g, want), (sh, np.argwhere(g != want)[:4])
+
+
 @pytest.mark.parametrize("N,P", [(3, 8), (33, 8), (40, 16), (37, 24), (66, 32), (20, 40), (70, 64),
                                  (35, 128), (9, 256)])
 def test_mfma_shapes(N, P):
