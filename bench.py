@@ -34,6 +34,13 @@ PEAK_INT8_MAC = PEAK_INT8_MFMA_TOPS / 2
 # v_mad_u64_u32 (32x32->64 multiply-add) issues at quarter rate: 16 lanes per
 # clock per CU -> 256 CUs * 16 * 2.4 GHz.
 PEAK_VALU_MAC32 = 256 * 16 * 2.4e9
+PEAK_HBM = 8.0e12                      # bytes/s
+
+
+def FINISH_BYTES(P: int) -> int:
+    """HBM bytes the finish must move per element update: read a_ij (4P limb
+    bytes + 8 exponent + 4 sign) and the product record (4(P+1)), write a_ij."""
+    return 2 * (4 * P + 12) + 4 * (P + 1)
 
 METRIC = "time to det+all D_k+last-col minors at (N,bits); limb-MAC/s vs INT8 MFMA peak"
 
@@ -101,9 +108,11 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma"])
+    ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma", "tuned"])
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--per-matrix", action="store_true",
+                    help="factor the workload's matrices one after another instead of in one batched call")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy MIB MiB device-to-device once (a kernel of known "
                          "traffic for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)")
@@ -129,7 +138,9 @@ def main():
     infos = [torch.zeros(1, dtype=torch.int32, device=dev) for _ in pristine]
     path = args.path
 
-    batched = args.config == 4
+    # several matrices go through one batched call (the same kernels, every
+    # phase of a step launched once for all of them)
+    batched = len(pristine) > 1 and not args.per_matrix
     if batched:
         binfo = torch.zeros(len(pristine), dtype=torch.int32, device=dev)
 
@@ -175,30 +186,42 @@ def main():
     binding.profile_begin()
     step()
     prof = binding.profile_end()
-    dom = max(("update_valu", "update_mfma"), key=lambda k: prof[k][0])
-    dom_ms, dom_n = prof[dom]
     P = mats[0][1].limbs.shape[-1]
-    if dom_n == 0:
+
+    def roofline(kname):
+        """Algorithmic work of every launch of `kname` in one step over its
+        total event time: MFMA int8 MACs, VALU 32x32->64 MACs, or the finish's
+        HBM bytes (read a_ij and the product record, write a_ij)."""
+        kms, kn = prof[kname]
+        secs = kms / 1e3
+        if kname == "update_valu":
+            achieved = upd * P * P / secs
+            r = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_MAC32 / 1e12,
+                 "unit": "Tmac32/s", "frac": achieved / PEAK_VALU_MAC32, "kernel": "k_update_valu"}
+        elif kname == "update_mfma":
+            achieved = macs / secs
+            r = {"bound": "mfma", "achieved": 2 * achieved / 1e12, "peak": PEAK_INT8_MFMA_TOPS / 1e12,
+                 "unit": "TOP/s", "frac": achieved / PEAK_INT8_MAC, "kernel": "k_update_mfma"}
+        else:
+            achieved = upd * FINISH_BYTES(P) / secs
+            r = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                 "frac": achieved / PEAK_HBM, "kernel": "k_finish"}
+        r.update({"traffic": None, "avg_launch_ms": kms / kn, "launches": kn})
+        return r
+
+    cands = [k for k in ("update_valu", "update_mfma", "update_finish") if prof[k][1] > 0]
+    if not cands:
         raise SystemExit("bench.py: no trailing-update launches were timed")
-    if dom == "update_valu":
-        work_units = sum((m.exp.shape[0] - 1) * m.exp.shape[0] * (2 * m.exp.shape[0] - 1) // 6
-                         for _, m in mats) * P * P  # 32x32->64 MACs
-        achieved = work_units / dom_n / (dom_ms / dom_n / 1e3)
-        roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_MAC32 / 1e12,
-                "unit": "Tmac32/s", "frac": achieved / PEAK_VALU_MAC32, "traffic": None,
-                "kernel": "k_update_valu", "avg_launch_ms": dom_ms / dom_n, "launches": dom_n}
-    else:
-        achieved = macs / dom_n / (dom_ms / dom_n / 1e3)
-        roof = {"bound": "mfma", "achieved": 2 * achieved / 1e12, "peak": PEAK_INT8_MFMA_TOPS / 1e12,
-                "unit": "TOP/s", "frac": achieved / PEAK_INT8_MAC, "traffic": None,
-                "kernel": "k_update_mfma", "avg_launch_ms": dom_ms / dom_n, "launches": dom_n}
+    dom = max(cands, key=lambda k: prof[k][0])
+    roof = roofline(dom)
+    roof["other_update_kernels"] = {k: roofline(k) for k in cands if k != dom}
     roof["kernel_ms_per_step"] = {k: round(v[0], 3) for k, v in prof.items() if v[1]}
 
     out = {"metric": METRIC, "value": value, "unit": "limb-MAC/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "u32" if dom == "update_valu" else "i8", "data": "synthetic",
+           "vs_baseline": None, "dtype": "i8" if prof["update_mfma"][1] > 0 else "u32", "data": "synthetic",
            "config": {"workload": desc, "N": int(max(m.exp.shape[0] for _, m in mats)), "bits": 32 * P,
-                      "matrices": len(mats), "path": path, "updates_per_step": upd,
+                      "matrices": len(mats), "path": path, "batched": batched, "updates_per_step": upd,
                       "limb_macs_per_step": macs},
            "roofline": roof}
     if not args.no_cpu_baseline:

@@ -18,7 +18,6 @@ struct BatchMat {
     int64_t n;
     uint8_t *Lr, *Ub;  // MFMA digit strings (null on the VALU path)
     uint32_t *T;       // MFMA product-top records
-    uint32_t *G;       // MFMA exact differences (same layout as T)
     uint32_t *rw;      // the pivot's reciprocal (P + 2 limbs)
 };
 
@@ -65,17 +64,18 @@ __global__ void __launch_bounds__(64) k_batch_prep(const BatchMat *mats, const i
     mfma_prep_body(lds_raw, M.A, M.Lr, M.Ub, M.info, k, M.n, P, loc);
 }
 
-__global__ void __launch_bounds__(64) k_batch_update_mfma(const BatchMat *mats, const int32_t *order,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) k_batch_update_mfma(const BatchMat *mats, const int32_t *order,
                                                           const int64_t *off, int cnt, int64_t k, int P) {
     MPK_BATCH_PROLOGUE
-    update_mfma_body(lds_raw, M.A, M.Lr, M.Ub, M.T, M.info, k, M.n, P, loc, false);
+    // every matrix's block count is a multiple of 8, so loc and bx agree mod 8
+    // and the XCD-aware column mapping holds inside each matrix
+    update_mfma_body(lds_raw, M.A, M.Lr, M.Ub, M.T, M.info, k, M.n, P, loc, true);
 }
 
-__global__ void __launch_bounds__(64) k_batch_sub(const BatchMat *mats, const int32_t *order, const int64_t *off,
-                                                  int cnt, int64_t k, int P) {
+__global__ void __launch_bounds__(64) k_batch_finish(const BatchMat *mats, const int32_t *order,
+                                                     const int64_t *off, int cnt, int64_t k, int P) {
     MPK_BATCH_PROLOGUE
-    (void)lds_raw;
-    sub_lane_body(M.A, M.T, M.G, M.info, k, M.n, P, loc * 64 + threadIdx.x);
+    finish_body(lds_raw, M.A, M.T, M.info, k, M.n, P, loc);
 }
 
 // minors sweep number s: matrix of size n processes j = n - 1 - s (blocks i < j)

@@ -15,17 +15,17 @@
 // and sweeps r in chunks of 8 output tiles of 32 rows; the A fragment of a tile
 // depends only on d = r0 - c0, so moving one K-step along the diagonal turns
 // tile t's fragment into tile t+1's and only one new fragment is read from LDS
-// per K-step (the row's digits are staged there reversed).  Tiles outside the
-// band 0 <= r - c <= P8 are skipped.
+// per K-step (the row's digits are staged there reversed).  Fragments outside
+// the band 0 <= r - c <= P8 are zero; every MFMA of a K-step is issued.
 //
 // Epilogue.  Column sums are biased, S'_r = S_r + 2^27 - 2^19 [r >= 1], which
-// makes them positive (< 2^28) and adds sum_r bias_r 256^r = 2^27 256^R -- a
-// multiple of 2^(2p) -- to the total, invisible in the low 2p bits.  Four
-// consecutive S' form a 64-bit limb column V_q < 2^53, and one lane per column
-// runs the carry chain limb_q = (V_q + c) mod 2^32, c = (V_q + c) >> 32 from
-// the lowest limb up.  Limbs P-1 .. 2P-1 of each product go to a scratch
-// buffer; a wave-cooperative kernel then truncates the product to p bits and
-// forms RZ_p(a_ij - RZ_p(l_i u_j)).
+// makes them positive (< 2^28) and adds sum_r bias_r 256^r = 2^27 256^(R-1)
+// -- a multiple of 2^(2p) -- to the total, invisible in the low 2p bits.
+// Four consecutive S' form a 64-bit limb column V_q < 2^53.  The limbs follow
+// from the V_q by one carry-lookahead per chunk of 64 limbs, in registers
+// (see update_mfma_body).  Limbs P-1 .. 2P-1 of each product go to a record
+// buffer; the finish kernel truncates the product to p bits and forms
+// RZ_p(a_ij - RZ_p(l_i u_j)).
 #pragma once
 
 #include "kernels_valu.h"
@@ -49,8 +49,10 @@ __host__ __device__ inline MfmaGeom mfma_geom(int P) {
     g.P = P;
     g.P8 = 4 * P;
     g.K8 = g.P8 + 32;
-    g.LR = g.P8 + 192;
-    g.Q = g.P8 + 67;  // Q = 3 mod 4: reversed limbs land on aligned words
+    // the zero padding on both sides covers every diagonal offset d the
+    // K-loop reads (-256 <= d <= P8 + 255), so out-of-band fragments read zeros
+    g.LR = g.P8 + 608;
+    g.Q = g.P8 + 291;  // Q = 3 mod 4: reversed limbs land on aligned words
     g.TP = P + 4;
     g.nchunks = (2 * g.P8 + 255) / 256;
     return g;
@@ -66,10 +68,18 @@ __host__ __device__ inline int64_t mfma_update_blocks(int64_t m) {
     return njb >= kXcds ? kXcds * m * ((njb + kXcds - 1) / kXcds) : m * njb;
 }
 
-// LDS for k_update_mfma: the reversed digit row, then 32 columns x 65 uint64
-__host__ __device__ inline size_t mfma_lds_bytes(int P) {
-    MfmaGeom g = mfma_geom(P);
-    return (size_t)g.LR + 32u * 65u * 8u;
+// LDS for k_update_mfma: the reversed digit row
+__host__ __device__ inline size_t mfma_lds_bytes(int P) { return (size_t)mfma_geom(P).LR; }
+
+// bit k of v -> bit 2k
+__device__ __forceinline__ uint64_t spread_bits(uint32_t v) {
+    uint64_t x = v;
+    x = (x | (x << 16)) & 0x0000FFFF0000FFFFull;
+    x = (x | (x << 8)) & 0x00FF00FF00FF00FFull;
+    x = (x | (x << 4)) & 0x0F0F0F0F0F0F0F0Full;
+    x = (x | (x << 2)) & 0x3333333333333333ull;
+    x = (x | (x << 1)) & 0x5555555555555555ull;
+    return x;
 }
 
 // ---------------------------------------------------------------------------
@@ -122,10 +132,10 @@ __device__ __forceinline__ void mfma_prep_body(uint32_t *lds_raw, MatDev A, uint
     uint32_t *dw = lds_raw;                  // P + 1 words
     balanced_digit_words(dw, src, P);
     if (is_row) {
-        // word w of the reversed row holds digit word P + 16 - w, bytes reversed
+        // word w of the reversed row holds digit word (Q - 3) / 4 - w, bytes reversed
         uint32_t *out = (uint32_t *)(Lr + b * (int64_t)g.LR);
         for (int w = mpw::lane(); w < g.LR / 4; w += MP_WAVE) {
-            int qd = P + 16 - w;
+            int qd = (g.Q - 3) / 4 - w;
             uint32_t v = 0;
             if (qd >= 0 && qd <= P) v = __builtin_bswap32(dw[qd]);
             out[w] = v;
@@ -137,13 +147,12 @@ __device__ __forceinline__ void mfma_prep_body(uint32_t *lds_raw, MatDev A, uint
 }
 
 // A fragment of the Toeplitz block with diagonal offset d = r0 - c0: lane
-// (r = lane % 32, h = lane / 32) holds T[r0 + r][c0 + 16h + b], b = 0..15.
-__device__ __forceinline__ v4i load_a(const uint8_t *lr, int d, int P8, int Q) {
-    v4i v = {0, 0, 0, 0};
-    if (d >= -31 && d <= P8 + 31) {
-        const int r = mpw::lane() & 31, h = mpw::lane() >> 5;
-        __builtin_memcpy(&v, lr + (Q - d - r + 16 * h), 16);
-    }
+// (r = lane % 32, h = lane / 32) holds T[r0 + r][c0 + 16h + b], b = 0..15
+// (zero outside the band, from the padding; -256 <= d <= P8 + 255).
+__device__ __forceinline__ v4i load_a(const uint8_t *lr, int d, int Q) {
+    v4i v;
+    const int r = mpw::lane() & 31, h = mpw::lane() >> 5;
+    __builtin_memcpy(&v, lr + (Q - d - r + 16 * h), 16);
     return v;
 }
 
@@ -175,7 +184,6 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
     if (el(A, k + 1 + ip, k, P)[P - 1] == 0u) return;
 
     uint8_t *lr = (uint8_t *)lds_raw;
-    uint64_t *vbuf = (uint64_t *)(lds_raw + g.LR / 4);
     {
         const uint4 *src = (const uint4 *)(Lr + ip * (int64_t)g.LR);
         uint4 *dst = (uint4 *)lr;
@@ -190,7 +198,8 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
     const uint8_t *ub = Ub + (jvalid ? jp : 0) * (int64_t)g.K8 + 16 * h;
     uint32_t *tcol = T + (ip * njb + jb) * (int64_t)g.TP * 32 + j;
     const int P8 = g.P8, Q = g.Q;
-    uint64_t carry = 0;
+    const int bmax = g.K8 - 32;  // last 16-byte offset of a lane (ub includes 16h)
+    uint32_t hi_in = 0, c_in = 0;  // carry from the chunk below
 
     for (int chunk = 0; chunk < g.nchunks; ++chunk) {
         const int r0 = chunk * 256;
@@ -209,28 +218,49 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
         // outside the band is zero.
         v4i W[8], BR[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) W[t] = load_a(lr, r0 + 32 * t - c_lo, P8, Q);
+        for (int t = 0; t < 8; ++t) W[t] = load_a(lr, r0 + 32 * t - c_lo, Q);
+        // B loads are unconditional: offsets are clamped into the column's
+        // digit string, and a fragment fetched for a step >= nsteps is never used
+#pragma unroll
+        for (int u = 0; u < 8; ++u) BR[u] = *(const v4i *)(ub + min(c_lo + 32 * u, bmax));
+        // one K-step: tile 7's MFMA frees its window slot, which is refilled
+        // at once with the next step's tile-0 fragment (its LDS latency hides
+        // behind tiles 0..6); the slot's next B fragment is fetched after the
+        // step's MFMAs, so the ring keeps its registers and 7 loads stay in
+        // flight
+        auto kstep = [&](int n, int u) __attribute__((always_inline)) {
+            const int c0 = c_lo + 32 * n;
+            acc[7] = __builtin_amdgcn_mfma_i32_32x32x32_i8(W[(7 - u) & 7], BR[u], acc[7], 0, 0, 0);
+            W[(7 - u) & 7] = load_a(lr, r0 - c0 - 32, Q);
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int t = 0; t < 7; ++t)
+                acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(W[(t - u) & 7], BR[u], acc[t], 0, 0, 0);
+            BR[u] = *(const v4i *)(ub + min(c0 + 256, bmax));
+            // keep each step's loads in their step: the scheduler would
+            // otherwise sink a block's 8 loads to its end
+            __builtin_amdgcn_sched_barrier(0);
+        };
+        // full blocks of 8 steps (no exit inside, so the load count at the loop
+        // edge is the same on every path), then the partial block
+        int n8 = 0;
+        for (; n8 + 8 <= nsteps; n8 += 8) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) kstep(n8 + u, u);
+        }
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            BR[u] = (v4i){0, 0, 0, 0};
-            if (jvalid && u < nsteps) BR[u] = *(const v4i *)(ub + c_lo + 32 * u);
+            if (n8 + u >= nsteps) break;
+            kstep(n8 + u, u);
         }
-        for (int n8 = 0; n8 < nsteps; n8 += 8) {
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int n = n8 + u;
-                const int c0 = c_lo + 32 * n;
-                const v4i bv = BR[u];
-                BR[u] = (v4i){0, 0, 0, 0};
-                if (jvalid && n + 8 < nsteps) BR[u] = *(const v4i *)(ub + c0 + 256);
-#pragma unroll
-                for (int t = 0; t < 8; ++t)
-                    acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(W[(t - u) & 7], bv, acc[t], 0, 0, 0);
-                W[(7 - u) & 7] = load_a(lr, r0 - c0 - 32, P8, Q);
-            }
-        }
-        // biased 64-bit limb columns: lane (j, h), tile t, group gq holds r =
-        // r0 + 32t + 8gq + 4h + {0..3}, i.e. limb q = r0/4 + 8t + 2gq + h
+        // Epilogue, in registers.  Lane (j, h) holds, for tile t and group gq,
+        // the 4 byte positions r = r0 + 32t + 8gq + 4h + {0..3} of column j,
+        // i.e. limb q = r0/4 + 2u + h with u = 4t + gq: its biased column sum
+        // is V = lo + hi 2^32, hi < 2^21.  Limb q's value is lo_q + hi_{q-1}
+        // plus a one-bit carry; the carries of the chunk's 64 limbs come from
+        // one 64-bit carry-lookahead, with the limbs of both parities
+        // exchanged between lanes j and j + 32.
+        uint32_t lo[32], hi[32];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
 #pragma unroll
@@ -244,171 +274,271 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
                     const uint32_t s = (uint32_t)acc[t][4 * gq + b] + bias;
                     V += (uint64_t)s << (8 * b);
                 }
-                vbuf[j * 65 + 8 * t + 2 * gq + h] = V;
+                lo[4 * t + gq] = (uint32_t)V;
+                hi[4 * t + gq] = (uint32_t)(V >> 32);
             }
         }
-        mpw::wsync();
-        if (h == 0) {
-            const int qbase = r0 / 4;
-            const int qend = min(64, 2 * P - qbase);  // limbs of this chunk below 2P
-            for (int q8 = 0; q8 < qend; q8 += 8) {
-                uint64_t v[8];
+        // hi of limb q - 1: the partner's u for h = 1, its u - 1 for h = 0
+        uint32_t ho[32];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) v[u] = vbuf[j * 65 + q8 + u];
+        for (int u = 0; u < 32; ++u) ho[u] = __shfl_xor(hi[u], 32);
+        uint32_t Gm = 0, Pm = 0;
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int q = qbase + q8 + u;
-                    const uint64_t x = v[u] + carry;
-                    carry = x >> 32;
-                    if (q8 + u < qend && q >= P - 1 && jvalid) tcol[(int64_t)(q - (P - 1)) * 32] = (uint32_t)x;
-                }
-            }
+        for (int u = 0; u < 32; ++u) {
+            const uint32_t hin = h ? ho[u] : (u ? ho[u - 1] : hi_in);
+            const uint64_t y = (uint64_t)lo[u] + hin + ((u == 0 && h == 0) ? c_in : 0u);
+            lo[u] = (uint32_t)y;
+            Gm |= (uint32_t)(y >> 32) << u;
+            Pm |= (lo[u] == 0xFFFFFFFFu ? 1u : 0u) << u;
         }
-        mpw::wsync();
+        const uint32_t Go = __shfl_xor(Gm, 32), Po = __shfl_xor(Pm, 32);
+        const uint64_t G64 = h ? (spread_bits(Go) | (spread_bits(Gm) << 1)) : (spread_bits(Gm) | (spread_bits(Go) << 1));
+        const uint64_t P64 = h ? (spread_bits(Po) | (spread_bits(Pm) << 1)) : (spread_bits(Pm) | (spread_bits(Po) << 1));
+        const uint64_t X = G64 | P64;
+        const uint64_t S = X + G64;
+        const uint64_t C = S ^ X ^ G64;  // carry into each limb of the chunk
+        // carry into the next chunk: hi of limb 63 and the lookahead's carry out
+        hi_in = h ? hi[31] : ho[31];
+        c_in = S < X ? 1u : 0u;
+        const int qbase = r0 / 4;
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int q = qbase + 2 * u + h;
+            const uint32_t limb = lo[u] + (uint32_t)((C >> (2 * u + h)) & 1ull);
+            if (q >= P - 1 && q < 2 * P && jvalid) tcol[(int64_t)(q - (P - 1)) * 32] = limb;
+        }
     }
 }
 
 // ---------------------------------------------------------------------------
-// Finish of the update, one lane per element: a_ij = RZ_p(a_ij - t) with
-// t = RZ_p(l_i u_j) rebuilt from the product's top limbs (raw word x = product
-// limb P-1+x, x = 0..P, in the limb-major record above).  Same case analysis
-// as mpw::addsub, run by one lane over the limbs from low to high with
-// one-limb register windows: pass 1 writes G, the exact p+2-bit intermediate,
-// to its own limb-major buffer (no location is read after it is written), and
-// pass 2 normalises G into a_ij.  Lanes of a wave take consecutive columns, so
-// the record and G accesses are coalesced.
+// Finish of the update: a_ij = RZ_p(a_ij - t), t = RZ_p(l_i u_j) rebuilt from
+// the record (word x = product limb P-1+x, x = 0..P).  One workgroup (one
+// wave) takes FT consecutive elements of a row, which are one contiguous run
+// in HBM: it copies their limbs into LDS limb-major (row q holds limb q of the
+// FT elements, rows padded to FT+1 words, so both the coalesced copy and the
+// per-lane walk are free of bank conflicts), each lane finishes one element
+// in place with the case analysis of mpw::addsub (pass 1 forms the exact
+// p+2-bit sum or difference G over the element's own LDS column, pass 2
+// normalises G to p bits), and the tile is copied back.  Every pass walks the
+// limbs in an order that never reads a location after writing it.
 // ---------------------------------------------------------------------------
+__host__ __device__ inline int finish_tile(int P) { return P <= 256 ? 64 : (P <= 512 ? 32 : 16); }
+__host__ __device__ inline size_t finish_lds_bytes(int P) {
+    return (size_t)(P + 1) * (size_t)(finish_tile(P) + 1) * 4u;
+}
+__host__ __device__ inline int64_t finish_blocks(int64_t m, int P) {
+    const int ft = finish_tile(P);
+    return m * ((m + ft - 1) / ft);
+}
+// record slots of an m x m trailing block: m rows x njb blocks of 32 columns
+__host__ __device__ inline int64_t rec_slots(int64_t m) { return m * ((m + 31) / 32) * 32; }
 
-// limb q (0..P-1) of a or t through a strided word view (0 outside)
-struct LimbSrc {
-    const uint32_t *p;  // raw words, word idx at p[idx * stride]
-    int64_t stride;
-    int off;            // limb q uses words q+off and q+off-1
-    int sh;             // 0: limb = w[q+off]; 1: limb = (w[q+off] << 1) | (w[q+off-1] >> 31)
-    int P;
-    __device__ __forceinline__ uint32_t word(int64_t idx) const {
-        return (idx >= 0 && idx < (int64_t)P + off) ? p[idx * stride] : 0u;
-    }
-    __device__ __forceinline__ uint32_t limb(int64_t q) const {
-        if (q < 0 || q >= P) return 0u;
-        const uint32_t hi = word(q + off);
-        if (!sh) return hi;
-        return (hi << 1) | (word(q + off - 1) >> 31);
-    }
-};
-
-__device__ __forceinline__ void sub_lane_body(MatDev A, const uint32_t *__restrict__ T, uint32_t *__restrict__ Gb,
-                              const int32_t *info, int64_t k, int64_t n, int P, int64_t slot) {
+__device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, const uint32_t *__restrict__ T,
+                                            const int32_t *info, int64_t k, int64_t n, int P, int64_t bx) {
     if (*info != 0) return;
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
     const int64_t njb = (m + 31) / 32;
-    const int64_t ip = slot / (njb * 32), jp = slot % (njb * 32);
-    if (ip >= m || jp >= m) return;
-    const int64_t i = k + 1 + ip, j = k + 1 + jp;
-    if (el(A, i, k, P)[P - 1] == 0u || el(A, k, j, P)[P - 1] == 0u) return;
-    const int64_t rec = (ip * njb + jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
-    const uint32_t *__restrict__ raw = T + rec;
-    uint32_t *__restrict__ G = Gb + rec;
-    uint32_t *__restrict__ am = el(A, i, j, P);
-    const int64_t p = 32LL * P;
-    const int top = (int)(raw[(int64_t)P * 32] >> 31);
-    const LimbSrc ts{raw, 32, 1, 1 - top, P};
-    const LimbSrc as{am, 1, 0, 0, P};
-    const int64_t et = ex(A, i, k) + ex(A, k, j) - 1 + top;
-    const int32_t sy = sg(A, i, k) ^ sg(A, k, j) ^ 1;  // sign of -t
-    const int64_t ea = ex(A, i, j);
-    const int32_t sa = sg(A, i, j);
-    int64_t *eo = &ex(A, i, j);
-    int32_t *so = &sg(A, i, j);
-    if (am[P - 1] == 0u) {  // 0 - t
-        for (int q = 0; q < P; ++q) am[q] = ts.limb(q);
-        *eo = et;
-        *so = sy;
-        return;
-    }
-    const bool subtract = sa != sy;
-    bool a_is_x = ea > et || (ea == et && !subtract);
-    if (ea == et && subtract) {
-        int c = 0;
-        for (int q = P - 1; q >= 0 && c == 0; --q) {
-            const uint32_t x = as.limb(q), y = ts.limb(q);
-            c = x > y ? 1 : (x < y ? -1 : 0);
-        }
-        if (c == 0) {
-            for (int q = 0; q < P; ++q) am[q] = 0u;
-            *eo = 0;
-            *so = 0;
-            return;
-        }
-        a_is_x = c > 0;
-    }
-    const LimbSrc X = a_is_x ? as : ts, Y = a_is_x ? ts : as;
-    const int64_t eX = a_is_x ? ea : et, eY = a_is_x ? et : ea;
-    const int32_t sX = a_is_x ? sa : sy;
-    const uint64_t d = (uint64_t)eX - (uint64_t)eY;
-    const int gsh = subtract ? (int)(d < 2 ? d : 2) : 0;       // left shift of X
-    const uint64_t rsu = subtract ? (d < 2 ? 0 : d - 2) : d;   // right shift of Y
-    const int64_t rs = (int64_t)(rsu > (uint64_t)(p + 64) ? (uint64_t)(p + 64) : rsu);
-    const int64_t w = rs / 32;
-    const int b = (int)(rs % 32);
-    uint32_t cb = 0;  // carry (sum) or borrow (difference)
-    if (subtract && rs > 0) {  // sticky: any bit of Y below bit rs
-        bool st = false;
-        for (int64_t q = 0; q < P && q <= w && !st; ++q) {
-            const uint32_t v = Y.limb(q);
-            if (q < w) st = v != 0u;
-            else if (b) st = (v & ((1u << b) - 1u)) != 0u;
-        }
-        cb = st ? 1u : 0u;
-    }
-    // pass 1: G = X 2^gsh +- (Y >> rs) -+ sticky, P + 1 limbs
-    uint32_t xprev = 0;
-    uint32_t ylo = Y.limb(w);
-    for (int q = 0; q <= P; ++q) {
-        const uint32_t xq = X.limb(q);
-        const uint32_t yhi = Y.limb(w + q + 1);
-        const uint32_t xg = gsh ? ((xq << gsh) | (xprev >> (32 - gsh))) : xq;
-        const uint32_t ysh = b ? ((ylo >> b) | (yhi << (32 - b))) : ylo;
-        uint32_t gq;
-        if (!subtract) {
-            const uint64_t sum = (uint64_t)xg + ysh + cb;
-            gq = (uint32_t)sum;
-            cb = (uint32_t)(sum >> 32);
-        } else {
-            const int64_t df = (int64_t)xg - (int64_t)ysh - (int64_t)cb;
-            gq = (uint32_t)df;
-            cb = df < 0 ? 1u : 0u;
-        }
-        G[(int64_t)q * 32] = gq;
-        xprev = xq;
-        ylo = yhi;
-    }
-    // pass 2: normalise G to p bits into a_ij
-    int qt = P;
-    while (qt >= 0 && G[(int64_t)qt * 32] == 0u) --qt;
-    if (qt < 0) {
-        for (int q = 0; q < P; ++q) am[q] = 0u;
-        *eo = 0;
-        *so = 0;
-        return;
-    }
-    const int64_t L = 32LL * qt + 32 - __clz(G[(int64_t)qt * 32]);
-    const int64_t sr = L - p;  // bits to drop (negative: shift left)
-    const int64_t w0 = sr >= 0 ? sr / 32 : -((-sr + 31) / 32);
-    const int bb = (int)(sr - 32 * w0);
-    for (int q = 0; q < P; ++q) {
-        const int64_t lo_i = q + w0, hi_i = q + w0 + 1;
-        const uint32_t lo = (lo_i >= 0 && lo_i <= P) ? G[lo_i * 32] : 0u;
-        const uint32_t hi = (hi_i >= 0 && hi_i <= P) ? G[hi_i * 32] : 0u;
-        am[q] = bb ? ((lo >> bb) | (hi << (32 - bb))) : lo;
-    }
-    *eo = eX - gsh - p + L;
-    *so = sX;
-}
+    const int FT = finish_tile(P), FTP = FT + 1;
+    const int64_t ntile = (m + FT - 1) / FT;
+    const int64_t ip = bx / ntile, j0 = (bx % ntile) * FT;
+    if (ip >= m) return;
+    const int64_t i = k + 1 + ip;
+    if (el(A, i, k, P)[P - 1] == 0u) return;  // zero multiplier: the row keeps its values
+    const int cnt = (int)min((int64_t)FT, m - j0);
+    uint32_t *arow = el(A, i, k + 1 + j0, P);  // cnt elements, cnt * P contiguous limbs
+    const int lane = mpw::lane();
+    const int e = lane;
+    const bool live = e < cnt;
+    const int64_t jp = j0 + (live ? e : 0), j = k + 1 + jp;
+    // per-lane scalars first, so their latency overlaps the tile copy
+    const uint32_t *raw = T + (ip * njb + jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
+    const uint32_t utop = el(A, k, j, P)[P - 1];
+    const uint32_t rtop = raw[(int64_t)P * 32];
+    const int64_t eik = ex(A, i, k), ekj = ex(A, k, j), ea = ex(A, i, j);
+    const int32_t sik = sg(A, i, k), skj = sg(A, k, j), sa = sg(A, i, j);
 
-// elements of the m x m trailing block in lane slots (m rows x njb*32 columns)
-__host__ __device__ inline int64_t sub_lane_slots(int64_t m) { return m * ((m + 31) / 32) * 32; }
+    // tile copy in 16-byte chunks, 16 per lane in flight: chunk c holds limbs
+    // 4(c mod cpe) .. +3 of element c / cpe, cpe = P / 4 (c < 4096, so the
+    // quotient is (c * magic) >> 24 exactly)
+    const int cpe = P / 4;
+    const uint32_t magic = (1u << 24) / (uint32_t)cpe + 1u;
+    const int nch = cnt * cpe;
+    {
+        const uint4 *src = (const uint4 *)arow;
+        for (int c0 = 0; c0 < nch; c0 += 16 * MP_WAVE) {
+            uint4 v[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int c = c0 + u * MP_WAVE + lane;
+                v[u] = c < nch ? src[c] : make_uint4(0u, 0u, 0u, 0u);
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const int c = c0 + u * MP_WAVE + lane;
+                if (c < nch) {
+                    const int ee = (int)(((uint64_t)c * magic) >> 24);
+                    uint32_t *d = lds + 4 * (c - ee * cpe) * FTP + ee;
+                    d[0] = v[u].x;
+                    d[FTP] = v[u].y;
+                    d[2 * FTP] = v[u].z;
+                    d[3 * FTP] = v[u].w;
+                }
+            }
+        }
+    }
+    mpw::wsync();
+
+    if (live && utop != 0u) {
+        uint32_t *col = lds + e;  // limb q at col[q * FTP], q = 0..P
+        const int64_t p = 32LL * P;
+        const int top = (int)(rtop >> 31);
+        const int sh = 1 - top;
+        // word x of the record (0 outside 0..P) and limb q of t (0 outside 0..P-1)
+        auto rw = [&](int64_t x) -> uint32_t { return (x >= 0 && x <= P) ? raw[x * 32] : 0u; };
+        auto tl = [&](int64_t q) -> uint32_t {
+            if (q < 0 || q >= P) return 0u;
+            const uint32_t hi = rw(q + 1);
+            return sh ? (hi << 1) | (rw(q) >> 31) : hi;
+        };
+        auto al = [&](int64_t q) -> uint32_t { return (q >= 0 && q < P) ? col[q * FTP] : 0u; };
+        const int64_t et = eik + ekj - 1 + top;
+        const int32_t sy = sik ^ skj ^ 1;  // sign of -t
+        int64_t *eo = &ex(A, i, j);
+        int32_t *so = &sg(A, i, j);
+        if (col[(P - 1) * FTP] == 0u) {  // 0 - t
+            for (int q = 0; q < P; ++q) col[q * FTP] = tl(q);
+            *eo = et;
+            *so = sy;
+        } else {
+            const bool subtract = sa != sy;
+            bool a_is_x = ea > et || (ea == et && !subtract);
+            bool zero = false;
+            if (ea == et && subtract) {
+                int c = 0;
+                for (int q = P - 1; q >= 0 && c == 0; --q) {
+                    const uint32_t x = al(q), y = tl(q);
+                    c = x > y ? 1 : (x < y ? -1 : 0);
+                }
+                zero = c == 0;
+                a_is_x = c > 0;
+            }
+            if (zero) {
+                for (int q = 0; q < P; ++q) col[q * FTP] = 0u;
+                *eo = 0;
+                *so = 0;
+            } else {
+                const int64_t eX = a_is_x ? ea : et, eY = a_is_x ? et : ea;
+                const int32_t sX = a_is_x ? sa : sy;
+                const uint64_t d = (uint64_t)eX - (uint64_t)eY;
+                const int gsh = subtract ? (int)(d < 2 ? d : 2) : 0;      // left shift of X
+                const uint64_t rsu = subtract ? (d < 2 ? 0 : d - 2) : d;  // right shift of Y
+                const int64_t rs = (int64_t)(rsu > (uint64_t)(p + 64) ? (uint64_t)(p + 64) : rsu);
+                const int64_t w = rs / 32;
+                const int b = (int)(rs % 32);
+                uint32_t cb = 0;  // carry (sum) or borrow (difference)
+                if (subtract && rs > 0) {  // sticky: any bit of Y below bit rs
+                    bool st = false;
+                    for (int64_t q = 0; q < P && q <= w && !st; ++q) {
+                        const uint32_t v = a_is_x ? tl(q) : al(q);
+                        if (q < w) st = v != 0u;
+                        else if (b) st = (v & ((1u << b) - 1u)) != 0u;
+                    }
+                    cb = st ? 1u : 0u;
+                }
+                // pass 1: G = X 2^gsh +- (Y >> rs) -+ sticky, P + 1 limbs, in place:
+                // step q reads X limb q and Y limb w+q+1 (both at or above q)
+                const int64_t oa = a_is_x ? 0 : w + 1, ot = a_is_x ? w + 1 : 0;
+                uint32_t xprev = 0;
+                uint32_t ylo = a_is_x ? tl(w) : al(w);
+                uint32_t wlo = rw(ot);  // record word of t limb q + ot, streamed upwards
+                // record words W(ot + 1 + q), q = 0..P, in a ring of PF registers
+                // fetched PF steps ahead, so the loads overlap the carry chain;
+                // the loads are unconditional (index clamped to P) and words
+                // past P are zeroed where they are used
+                constexpr int PF = 32;
+                uint32_t ring[PF];
+                const int64_t xlim = (int64_t)P - ot - 1;  // step q uses a real word iff q <= xlim
+#pragma unroll
+                for (int u = 0; u < PF; ++u) ring[u] = raw[min(ot + 1 + u, (int64_t)P) * 32];
+                auto step1 = [&](int q, int u) __attribute__((always_inline)) {
+                    const int64_t it = q + ot;
+                    const uint32_t whi = q <= xlim ? ring[u] : 0u;
+                    ring[u] = raw[min(it + 1 + PF, (int64_t)P) * 32];
+                    const uint32_t tv = (it < P) ? (sh ? (whi << 1) | (wlo >> 31) : whi) : 0u;
+                    wlo = whi;
+                    const int64_t ia = q + oa;
+                    const uint32_t ar = col[min(ia, (int64_t)P) * FTP];
+                    const uint32_t av = ia < P ? ar : 0u;
+                    const uint32_t xq = a_is_x ? av : tv;
+                    const uint32_t yhi = a_is_x ? tv : av;
+                    const uint32_t xg = gsh ? ((xq << gsh) | (xprev >> (32 - gsh))) : xq;
+                    const uint32_t ysh = b ? ((ylo >> b) | (yhi << (32 - b))) : ylo;
+                    uint32_t gq;
+                    if (!subtract) {
+                        const uint64_t sum = (uint64_t)xg + ysh + cb;
+                        gq = (uint32_t)sum;
+                        cb = (uint32_t)(sum >> 32);
+                    } else {
+                        const int64_t df = (int64_t)xg - (int64_t)ysh - (int64_t)cb;
+                        gq = (uint32_t)df;
+                        cb = df < 0 ? 1u : 0u;
+                    }
+                    col[q * FTP] = gq;
+                    xprev = xq;
+                    ylo = yhi;
+                };
+                // full blocks (one load per step on every path), then the rest
+                int q0 = 0;
+                for (; q0 + PF <= P + 1; q0 += PF) {
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) step1(q0 + u, u);
+                }
+#pragma unroll
+                for (int u = 0; u < PF; ++u) {
+                    if (q0 + u > P) break;
+                    step1(q0 + u, u);
+                }
+                // pass 2: normalise G (limbs 0..P) to p bits, in place
+                int qt = P;
+                while (qt >= 0 && col[qt * FTP] == 0u) --qt;
+                if (qt < 0) {
+                    for (int q = 0; q < P; ++q) col[q * FTP] = 0u;
+                    *eo = 0;
+                    *so = 0;
+                } else {
+                    const int64_t L = 32LL * qt + 32 - __clz(col[qt * FTP]);
+                    const int64_t sr = L - p;  // bits to drop (negative: shift left)
+                    const int w0 = (int)(sr >= 0 ? sr / 32 : -((-sr + 31) / 32));
+                    const int bb = (int)(sr - 32LL * w0);
+                    auto gl = [&](int idx) -> uint32_t { return (idx >= 0 && idx <= P) ? col[idx * FTP] : 0u; };
+                    if (w0 >= 0) {  // reads at or above the written limb: ascending
+                        for (int q = 0; q < P; ++q) {
+                            const uint32_t lo = gl(q + w0), hi = gl(q + w0 + 1);
+                            col[q * FTP] = bb ? ((lo >> bb) | (hi << (32 - bb))) : lo;
+                        }
+                    } else {  // reads at or below the written limb: descending
+                        for (int q = P - 1; q >= 0; --q) {
+                            const uint32_t lo = gl(q + w0), hi = gl(q + w0 + 1);
+                            col[q * FTP] = bb ? ((lo >> bb) | (hi << (32 - bb))) : lo;
+                        }
+                    }
+                    *eo = eX - gsh - p + L;
+                    *so = sX;
+                }
+            }
+        }
+    }
+    mpw::wsync();
+    {
+        uint4 *dst = (uint4 *)arow;
+        for (int c = lane; c < nch; c += MP_WAVE) {
+            const int ee = (int)(((uint64_t)c * magic) >> 24);
+            const uint32_t *d = lds + 4 * (c - ee * cpe) * FTP + ee;
+            dst[c] = make_uint4(d[0], d[FTP], d[2 * FTP], d[3 * FTP]);
+        }
+    }
+}
 
 __global__ void __launch_bounds__(64) k_mfma_prep(MatDev A, uint8_t *Lr, uint8_t *Ub, const int32_t *info,
                                                   int64_t k, int64_t n, int P) {
@@ -416,15 +546,16 @@ __global__ void __launch_bounds__(64) k_mfma_prep(MatDev A, uint8_t *Lr, uint8_t
     mfma_prep_body(lds_raw, A, Lr, Ub, info, k, n, P, flat_block());
 }
 
-__global__ void __launch_bounds__(64) k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T,
                                                     const int32_t *info, int64_t k, int64_t n, int P) {
     extern __shared__ uint32_t lds_raw[];
     update_mfma_body(lds_raw, A, Lr, Ub, T, info, k, n, P, flat_block(), true);
 }
 
-__global__ void __launch_bounds__(64) k_sub_lane(MatDev A, const uint32_t *T, uint32_t *G, const int32_t *info,
-                                                 int64_t k, int64_t n, int P) {
-    sub_lane_body(A, T, G, info, k, n, P, flat_block() * 64 + threadIdx.x);
+__global__ void __launch_bounds__(64) k_finish(MatDev A, const uint32_t *T, const int32_t *info, int64_t k,
+                                               int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    finish_body(lds_raw, A, T, info, k, n, P, flat_block());
 }
 
 }  // namespace mpk

@@ -207,12 +207,12 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
 // multiplier digits, pivot-row digits and product-top records.
 struct MfmaWs {
     uint8_t *Lr, *Ub;
-    uint32_t *T, *G;
+    uint32_t *T;
 };
 
-// bytes of one product-top buffer (T or G) for an m x m trailing block
+// bytes of the product-top records for an m x m trailing block
 size_t mfma_rec_bytes(int64_t m, int P) {
-    return (size_t)mpk::sub_lane_slots(m) * (size_t)mpk::mfma_geom(P).TP * 4u;
+    return (size_t)mpk::rec_slots(m) * (size_t)mpk::mfma_geom(P).TP * 4u;
 }
 
 int mfma_workspace(mpdet_handle *h, int64_t m, int P, MfmaWs *w) {
@@ -220,7 +220,7 @@ int mfma_workspace(mpdet_handle *h, int64_t m, int P, MfmaWs *w) {
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t lr = up((size_t)m * g.LR), ub = up((size_t)m * g.K8);
     const size_t t = up(mfma_rec_bytes(m, P));
-    const size_t need = lr + ub + 2 * t;
+    const size_t need = lr + ub + t;
     if (need > h->ws_bytes) {
         if (h->ws) (void)hipFree(h->ws);
         h->ws = nullptr;
@@ -236,7 +236,6 @@ int mfma_workspace(mpdet_handle *h, int64_t m, int P, MfmaWs *w) {
     w->Lr = base;
     w->Ub = base + lr;
     w->T = (uint32_t *)(base + lr + ub);
-    w->G = (uint32_t *)(base + lr + ub + t);
     return MPDET_OK;
 }
 
@@ -247,6 +246,7 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     int rc = mfma_workspace(h, n > 1 ? n - 1 : 1, P, &w);
     if (rc) return rc;
     const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
+    const size_t lds_fin = mpk::finish_lds_bytes(P);
     mpk::MatDev a = dev(A), d = dev(D);
     const int32_t *cinfo = info;
     for (int64_t k = 0; k < n; ++k) {
@@ -267,8 +267,8 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
         if ((rc = last_launch())) return rc;
         {
             Prof pr(h, s, K_UPDATE_FINISH);
-            hipLaunchKernelGGL(mpk::k_sub_lane, grid_for((mpk::sub_lane_slots(m) + 63) / 64), dim3(64), 0, s, a,
-                               (const uint32_t *)w.T, w.G, cinfo, k, n, P);
+            hipLaunchKernelGGL(mpk::k_finish, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a,
+                               (const uint32_t *)w.T, cinfo, k, n, P);
         }
         if ((rc = last_launch())) return rc;
     }
@@ -480,9 +480,9 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
         switch (phase) {
             case BP_PIVOT: return 2;
             case BP_DIVIDE: return m;
-            case BP_UPD: return use_mfma ? m * ((m + 31) / 32) : m * m;
+            case BP_UPD: return use_mfma ? (mpk::mfma_update_blocks(m) + 7) / 8 * 8 : m * m;
             case BP_PREP: return 2 * m;
-            case BP_SUB: return (mpk::sub_lane_slots(m) + 63) / 64;
+            case BP_SUB: return mpk::finish_blocks(m, P);
         }
         return 0;
     };
@@ -541,7 +541,7 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
         const int64_t n = A_arr[b].rows, m = n > 1 ? n - 1 : 1;
         size_t need = up((size_t)(P + 2) * 4u);
         if (use_mfma)
-            need += up((size_t)m * geo.LR) + up((size_t)m * geo.K8) + 2 * up(mfma_rec_bytes(m, P));
+            need += up((size_t)m * geo.LR) + up((size_t)m * geo.K8) + up(mfma_rec_bytes(m, P));
         scratch[(size_t)b] = need;
         total_scratch += need;
     }
@@ -583,15 +583,13 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
         M.rw = (uint32_t *)q;
         q += up((size_t)(P + 2) * 4u);
         M.Lr = M.Ub = nullptr;
-        M.T = M.G = nullptr;
+        M.T = nullptr;
         if (use_mfma) {
             M.Lr = q;
             q += up((size_t)m * geo.LR);
             M.Ub = q;
             q += up((size_t)m * geo.K8);
             M.T = (uint32_t *)q;
-            q += up(mfma_rec_bytes(m, P));
-            M.G = (uint32_t *)q;
         }
         sp += scratch[(size_t)b];
     }
@@ -609,6 +607,7 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
     if ((rc = last_launch())) return rc;
     const size_t lds_piv = mpk::pivot_lds_bytes(P), lds = mpk::lds_bytes(P);
     const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
+    const size_t lds_fin = mpk::finish_lds_bytes(P);
     auto launch = [&](int kernel_id, auto kern, size_t slot, size_t shmem, int64_t arg) -> int {
         const int c = count[slot];
         if (c <= 0) return MPDET_OK;
@@ -626,7 +625,7 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
         if (use_mfma) {
             if ((rc = launch(K_MFMA_PREP, mpk::k_batch_prep, base + BP_PREP, lds_prep, k))) return rc;
             if ((rc = launch(K_UPDATE_MFMA, mpk::k_batch_update_mfma, base + BP_UPD, lds_mfma, k))) return rc;
-            if ((rc = launch(K_UPDATE_FINISH, mpk::k_batch_sub, base + BP_SUB, 0, k))) return rc;
+            if ((rc = launch(K_UPDATE_FINISH, mpk::k_batch_finish, base + BP_SUB, lds_fin, k))) return rc;
         } else {
             if ((rc = launch(K_UPDATE_VALU, mpk::k_batch_update_valu, base + BP_UPD, lds, k))) return rc;
         }
