@@ -66,6 +66,35 @@ def workload(cfg: int):
     raise SystemExit(f"bench.py: config {cfg} is not a single-GPU bench workload")
 
 
+def cached_workload(cfg: int, cache: str | None):
+    """workload(cfg), with the generated matrices stored as .npy files under
+    `cache` (numpy's own format, loaded without pickle)."""
+    import numpy as np
+
+    from paper_1308_1536_amd.inputs import MpArray
+    if cache is None:
+        return workload(cfg)
+    root = os.path.join(cache, f"config{cfg}")
+    index = os.path.join(root, "index.json")
+    if os.path.exists(index):
+        with open(index) as fh:
+            meta = json.load(fh)
+        mats = []
+        for k, name in enumerate(meta["names"]):
+            parts = [np.load(os.path.join(root, f"{k}_{f}.npy"), allow_pickle=False)
+                     for f in ("limbs", "exp", "sign")]
+            mats.append((name, MpArray(*parts)))
+        return meta["desc"], mats
+    desc, mats = workload(cfg)
+    os.makedirs(root, exist_ok=True)
+    for k, (_, m) in enumerate(mats):
+        for f in ("limbs", "exp", "sign"):
+            np.save(os.path.join(root, f"{k}_{f}.npy"), getattr(m, f), allow_pickle=False)
+    with open(index, "w") as fh:
+        json.dump({"desc": desc, "names": [nm for nm, _ in mats]}, fh)
+    return desc, mats
+
+
 def unit_work(mats):
     from paper_1308_1536_amd.inputs import limb_macs_int8, u_count
     macs = sum(limb_macs_int8(m.exp.shape[0], m.limbs.shape[-1]) for _, m in mats)
@@ -111,6 +140,9 @@ def main():
     ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma", "tuned"])
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--input-cache", default=None, metavar="DIR",
+                    help="load the workload's generated matrices from DIR (.npy files), generating and "
+                         "saving them there first if absent")
     ap.add_argument("--per-matrix", action="store_true",
                     help="factor the workload's matrices one after another instead of in one batched call")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -129,7 +161,7 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
 
-    desc, mats = workload(args.config)
+    desc, mats = cached_workload(args.config, args.input_cache)
     print(f"[bench] {desc}", file=sys.stderr, flush=True)
     pristine = [binding.DeviceMp.from_host(m) for _, m in mats]
     work = [binding.DeviceMp.empty(p.rows, p.cols, p.P, dev) for p in pristine]

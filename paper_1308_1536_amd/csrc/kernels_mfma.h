@@ -391,17 +391,17 @@ __device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, const uint3
 
     if (live && utop != 0u) {
         uint32_t *col = lds + e;  // limb q at col[q * FTP], q = 0..P
-        const int64_t p = 32LL * P;
         const int top = (int)(rtop >> 31);
         const int sh = 1 - top;
-        // word x of the record (0 outside 0..P) and limb q of t (0 outside 0..P-1)
-        auto rw = [&](int64_t x) -> uint32_t { return (x >= 0 && x <= P) ? raw[x * 32] : 0u; };
-        auto tl = [&](int64_t q) -> uint32_t {
+        // word x of the record (0 outside 0..P) and limb q of t (0 outside 0..P-1);
+        // all indices here are below 2P + 40 and fit int
+        auto rw = [&](int x) -> uint32_t { return (x >= 0 && x <= P) ? raw[x * 32] : 0u; };
+        auto tl = [&](int q) -> uint32_t {
             if (q < 0 || q >= P) return 0u;
             const uint32_t hi = rw(q + 1);
             return sh ? (hi << 1) | (rw(q) >> 31) : hi;
         };
-        auto al = [&](int64_t q) -> uint32_t { return (q >= 0 && q < P) ? col[q * FTP] : 0u; };
+        auto al = [&](int q) -> uint32_t { return (q >= 0 && q < P) ? col[q * FTP] : 0u; };
         const int64_t et = eik + ekj - 1 + top;
         const int32_t sy = sik ^ skj ^ 1;  // sign of -t
         int64_t *eo = &ex(A, i, j);
@@ -428,69 +428,69 @@ __device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, const uint3
                 *eo = 0;
                 *so = 0;
             } else {
+                const int pbits = 32 * P;
                 const int64_t eX = a_is_x ? ea : et, eY = a_is_x ? et : ea;
                 const int32_t sX = a_is_x ? sa : sy;
                 const uint64_t d = (uint64_t)eX - (uint64_t)eY;
                 const int gsh = subtract ? (int)(d < 2 ? d : 2) : 0;      // left shift of X
                 const uint64_t rsu = subtract ? (d < 2 ? 0 : d - 2) : d;  // right shift of Y
-                const int64_t rs = (int64_t)(rsu > (uint64_t)(p + 64) ? (uint64_t)(p + 64) : rsu);
-                const int64_t w = rs / 32;
-                const int b = (int)(rs % 32);
-                uint32_t cb = 0;  // carry (sum) or borrow (difference)
-                if (subtract && rs > 0) {  // sticky: any bit of Y below bit rs
-                    bool st = false;
-                    for (int64_t q = 0; q < P && q <= w && !st; ++q) {
+                const int rs = (int)(rsu > (uint64_t)(pbits + 64) ? (uint64_t)(pbits + 64) : rsu);
+                const int w = rs / 32;
+                const int b = rs % 32;
+                uint32_t st = 0;  // sticky: any bit of Y below bit rs (subtraction only)
+                if (subtract && rs > 0) {
+                    bool any = false;
+                    for (int q = 0; q < P && q <= w && !any; ++q) {
                         const uint32_t v = a_is_x ? tl(q) : al(q);
-                        if (q < w) st = v != 0u;
-                        else if (b) st = (v & ((1u << b) - 1u)) != 0u;
+                        if (q < w) any = v != 0u;
+                        else if (b) any = (v & ((1u << b) - 1u)) != 0u;
                     }
-                    cb = st ? 1u : 0u;
+                    st = any ? 1u : 0u;
                 }
-                // pass 1: G = X 2^gsh +- (Y >> rs) -+ sticky, P + 1 limbs, in place:
-                // step q reads X limb q and Y limb w+q+1 (both at or above q)
-                const int64_t oa = a_is_x ? 0 : w + 1, ot = a_is_x ? w + 1 : 0;
+                // pass 1: G = X 2^gsh +- (Y >> rs) -+ sticky over P + 1 limbs, in
+                // place; a difference is X + ~Y' + (1 - sticky) in two's
+                // complement, so both cases are one carry chain.  Step q reads X
+                // limb q and Y limb w+q+1 (both at or above the limb it writes).
+                const int oa = a_is_x ? 0 : w + 1, ot = a_is_x ? w + 1 : 0;
+                const uint32_t ymask = subtract ? 0xFFFFFFFFu : 0u;
+                uint32_t c = subtract ? 1u - st : 0u;
                 uint32_t xprev = 0;
                 uint32_t ylo = a_is_x ? tl(w) : al(w);
                 uint32_t wlo = rw(ot);  // record word of t limb q + ot, streamed upwards
                 // record words W(ot + 1 + q), q = 0..P, in a ring of PF registers
-                // fetched PF steps ahead, so the loads overlap the carry chain;
-                // the loads are unconditional (index clamped to P) and words
-                // past P are zeroed where they are used
+                // fetched PF steps ahead, so the loads overlap the carry chain.
+                // The loads are unconditional (the record buffer is padded past
+                // its last record) and words past P are zeroed where they are used.
                 constexpr int PF = 32;
                 uint32_t ring[PF];
-                const int64_t xlim = (int64_t)P - ot - 1;  // step q uses a real word iff q <= xlim
+                const int xlim = P - ot - 1;  // step q uses a real word iff q <= xlim
+                const uint32_t *rp = raw + (ot + 1) * 32;
 #pragma unroll
-                for (int u = 0; u < PF; ++u) ring[u] = raw[min(ot + 1 + u, (int64_t)P) * 32];
+                for (int u = 0; u < PF; ++u) ring[u] = rp[u * 32];
+                const int na = P - oa;  // step q reads a real limb of a iff q < na
+                const int arow_max = P * FTP;  // LDS offset of row P (reads clamp there)
+                int abase = oa * FTP;           // LDS offset of a's limb q0 + oa
                 auto step1 = [&](int q, int u) __attribute__((always_inline)) {
-                    const int64_t it = q + ot;
                     const uint32_t whi = q <= xlim ? ring[u] : 0u;
-                    ring[u] = raw[min(it + 1 + PF, (int64_t)P) * 32];
-                    const uint32_t tv = (it < P) ? (sh ? (whi << 1) | (wlo >> 31) : whi) : 0u;
+                    ring[u] = rp[(q + PF) * 32];
+                    const uint32_t tsh = sh ? __builtin_amdgcn_alignbit(whi, wlo, 31) : whi;
+                    const uint32_t tv = q + ot < P ? tsh : 0u;
                     wlo = whi;
-                    const int64_t ia = q + oa;
-                    const uint32_t ar = col[min(ia, (int64_t)P) * FTP];
-                    const uint32_t av = ia < P ? ar : 0u;
+                    const uint32_t ar = col[min(abase + u * FTP, arow_max)];
+                    const uint32_t av = q < na ? ar : 0u;
                     const uint32_t xq = a_is_x ? av : tv;
                     const uint32_t yhi = a_is_x ? tv : av;
-                    const uint32_t xg = gsh ? ((xq << gsh) | (xprev >> (32 - gsh))) : xq;
-                    const uint32_t ysh = b ? ((ylo >> b) | (yhi << (32 - b))) : ylo;
-                    uint32_t gq;
-                    if (!subtract) {
-                        const uint64_t sum = (uint64_t)xg + ysh + cb;
-                        gq = (uint32_t)sum;
-                        cb = (uint32_t)(sum >> 32);
-                    } else {
-                        const int64_t df = (int64_t)xg - (int64_t)ysh - (int64_t)cb;
-                        gq = (uint32_t)df;
-                        cb = df < 0 ? 1u : 0u;
-                    }
-                    col[q * FTP] = gq;
+                    const uint32_t xg = gsh ? __builtin_amdgcn_alignbit(xq, xprev, 32 - gsh) : xq;
+                    const uint32_t ysh = __builtin_amdgcn_alignbit(yhi, ylo, b);
+                    const uint64_t t = (uint64_t)xg + (ysh ^ ymask) + c;
+                    col[q * FTP] = (uint32_t)t;
+                    c = (uint32_t)(t >> 32);
                     xprev = xq;
                     ylo = yhi;
                 };
                 // full blocks (one load per step on every path), then the rest
                 int q0 = 0;
-                for (; q0 + PF <= P + 1; q0 += PF) {
+                for (; q0 + PF <= P + 1; q0 += PF, abase += PF * FTP) {
 #pragma unroll
                     for (int u = 0; u < PF; ++u) step1(q0 + u, u);
                 }
@@ -499,7 +499,7 @@ __device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, const uint3
                     if (q0 + u > P) break;
                     step1(q0 + u, u);
                 }
-                // pass 2: normalise G (limbs 0..P) to p bits, in place
+                // pass 2: normalise G (limbs 0..P, G < 2^(p+2)) to p bits, in place
                 int qt = P;
                 while (qt >= 0 && col[qt * FTP] == 0u) --qt;
                 if (qt < 0) {
@@ -507,23 +507,26 @@ __device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, const uint3
                     *eo = 0;
                     *so = 0;
                 } else {
-                    const int64_t L = 32LL * qt + 32 - __clz(col[qt * FTP]);
-                    const int64_t sr = L - p;  // bits to drop (negative: shift left)
-                    const int w0 = (int)(sr >= 0 ? sr / 32 : -((-sr + 31) / 32));
-                    const int bb = (int)(sr - 32LL * w0);
-                    auto gl = [&](int idx) -> uint32_t { return (idx >= 0 && idx <= P) ? col[idx * FTP] : 0u; };
-                    if (w0 >= 0) {  // reads at or above the written limb: ascending
+                    const int L = 32 * qt + 32 - __clz(col[qt * FTP]);
+                    const int sr = L - pbits;  // bits to drop (negative: shift left)
+                    if (sr >= 0) {
+                        // sr <= 2: limb q = bits of G limbs q and q + 1, ascending
+                        uint32_t lo = col[0];
                         for (int q = 0; q < P; ++q) {
-                            const uint32_t lo = gl(q + w0), hi = gl(q + w0 + 1);
-                            col[q * FTP] = bb ? ((lo >> bb) | (hi << (32 - bb))) : lo;
+                            const uint32_t hi = col[(q + 1) * FTP];
+                            col[q * FTP] = __builtin_amdgcn_alignbit(hi, lo, sr);
+                            lo = hi;
                         }
-                    } else {  // reads at or below the written limb: descending
+                    } else {  // cancellation: shift left, reading at or below: descending
+                        const int w0 = -((-sr + 31) / 32);
+                        const int bb = sr - 32 * w0;
+                        auto gl = [&](int idx) -> uint32_t { return (idx >= 0 && idx <= P) ? col[idx * FTP] : 0u; };
                         for (int q = P - 1; q >= 0; --q) {
                             const uint32_t lo = gl(q + w0), hi = gl(q + w0 + 1);
-                            col[q * FTP] = bb ? ((lo >> bb) | (hi << (32 - bb))) : lo;
+                            col[q * FTP] = __builtin_amdgcn_alignbit(hi, lo, bb);
                         }
                     }
-                    *eo = eX - gsh - p + L;
+                    *eo = eX - gsh - pbits + L;
                     *so = sX;
                 }
             }

@@ -210,9 +210,11 @@ struct MfmaWs {
     uint32_t *T;
 };
 
-// bytes of the product-top records for an m x m trailing block
+// bytes of the product-top records for an m x m trailing block, plus the
+// padding the finish kernel's unconditional read-ahead may touch past the
+// last record ((P + 40) * 32 words)
 size_t mfma_rec_bytes(int64_t m, int P) {
-    return (size_t)mpk::rec_slots(m) * (size_t)mpk::mfma_geom(P).TP * 4u;
+    return ((size_t)mpk::rec_slots(m) * (size_t)mpk::mfma_geom(P).TP + (size_t)(P + 40) * 32u) * 4u;
 }
 
 int mfma_workspace(mpdet_handle *h, int64_t m, int P, MfmaWs *w) {

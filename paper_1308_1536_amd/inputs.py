@@ -160,7 +160,14 @@ def cauchy(x: Sequence, y: Sequence, P: int, workers: int | None = None) -> MpAr
     ys = [int(v * (1 << F)) for v in yf]
     n, m = len(xs), len(ys)
     if workers is None:
-        workers = 1 if n * m * P < 4_000_000 else min(16, os.cpu_count() or 1)
+        # forked workers only for the largest matrices (32K-bit, N = 2048);
+        # MPDET_GEN_WORKERS overrides (1: never fork, e.g. under a profiler
+        # whose signal handlers the children would inherit)
+        env = os.environ.get("MPDET_GEN_WORKERS")
+        if env is not None:
+            workers = max(1, int(env))
+        else:
+            workers = 1 if n * m * P < 1_000_000_000 else min(16, os.cpu_count() or 1)
     if workers <= 1 or n < 2:
         out = MpArray.zeros((n, m), P)
         _cauchy_fill(range(n), xs, ys, F, P, out.limbs, out.exp, out.sign)
