@@ -31,9 +31,10 @@ if ROOT not in sys.path:
 # Published MI355X peaks (dense) and the derived integer-VALU rate.
 PEAK_INT8_MFMA_TOPS = 5.0e15           # int8 ops/s; a MAC is 2 ops
 PEAK_INT8_MAC = PEAK_INT8_MFMA_TOPS / 2
-# v_mad_u64_u32 (32x32->64 multiply-add) issues at quarter rate: 16 lanes per
-# clock per CU -> 256 CUs * 16 * 2.4 GHz.
-PEAK_VALU_MAC32 = 256 * 16 * 2.4e9
+# v_mad_u64_u32 (32x32->64 multiply-add) issues at the rate of the float64
+# FMA (78.6 TFLOP/s = 39.3e12 FMA/s): 64 lanes per clock per CU -> 256 CUs * 64
+# * 2.4 GHz.  bench also reports the rate its probe kernel measures.
+PEAK_VALU_MAC32 = 256 * 64 * 2.4e9
 PEAK_HBM = 8.0e12                      # bytes/s
 
 
@@ -43,6 +44,7 @@ def FINISH_BYTES(P: int) -> int:
     return 2 * (4 * P + 12) + 4 * (P + 1)
 
 METRIC = "time to det+all D_k+last-col minors at (N,bits); limb-MAC/s vs INT8 MFMA peak"
+DEFAULT_PATH = {1: "valu", 2: "valu", 3: "mfma", 4: "auto"}
 
 
 def workload(cfg: int):
@@ -137,7 +139,12 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--path", default="auto", choices=["auto", "valu", "mfma", "tuned"])
+    ap.add_argument("--path", default=None, choices=["auto", "valu", "mfma", "tuned"],
+                    help="trailing-update path (default: the configuration's own -- VALU for the plain "
+                         "configurations 1 and 2, MFMA for 3, auto for the batched 4)")
+    ap.add_argument("--compare", default="default", choices=["default", "none", "valu", "mfma"],
+                    help="also time the other update path on the same workload and check that it gives the "
+                         "same bits (default: MFMA beside the VALU path of configuration 2)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--input-cache", default=None, metavar="DIR",
@@ -168,7 +175,10 @@ def main():
     Ds = [binding.DeviceMp.empty(1, p.rows, p.P, dev) for p in pristine]
     cs = [binding.DeviceMp.empty(1, p.rows, p.P, dev) for p in pristine]
     infos = [torch.zeros(1, dtype=torch.int32, device=dev) for _ in pristine]
-    path = args.path
+    path = args.path or DEFAULT_PATH[args.config]
+    compare = args.compare
+    if compare == "default":
+        compare = "mfma" if (args.config == 2 and path == "valu") else "none"
 
     # several matrices go through one batched call (the same kernels, every
     # phase of a step launched once for all of them)
@@ -176,7 +186,7 @@ def main():
     if batched:
         binfo = torch.zeros(len(pristine), dtype=torch.int32, device=dev)
 
-    def step():
+    def step(path=path):
         for p, w in zip(pristine, work):
             w.limbs.copy_(p.limbs)
             w.exp.copy_(p.exp)
@@ -220,6 +230,14 @@ def main():
     prof = binding.profile_end()
     P = mats[0][1].limbs.shape[-1]
 
+    peaks = {}
+
+    def measured_peak(kind):
+        """the unit's throughput measured on this GPU (probe kernel), multiply-adds/s"""
+        if kind not in peaks:
+            peaks[kind] = binding.measure_peak(kind)
+        return peaks[kind]
+
     def roofline(kname):
         """Algorithmic work of every launch of `kname` in one step over its
         total event time: MFMA int8 MACs, VALU 32x32->64 MACs, or the finish's
@@ -228,12 +246,17 @@ def main():
         secs = kms / 1e3
         if kname == "update_valu":
             achieved = upd * P * P / secs
+            mp = measured_peak("mad64")
             r = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_MAC32 / 1e12,
-                 "unit": "Tmac32/s", "frac": achieved / PEAK_VALU_MAC32, "kernel": "k_update_valu"}
+                 "unit": "Tmac32/s", "frac": achieved / PEAK_VALU_MAC32,
+                 "kernel": "k_update_lane" if P <= 128 else "k_update_valu",
+                 "measured_peak": mp / 1e12, "frac_of_measured_peak": achieved / mp}
         elif kname == "update_mfma":
             achieved = macs / secs
+            mp = measured_peak("mfma_i8")
             r = {"bound": "mfma", "achieved": 2 * achieved / 1e12, "peak": PEAK_INT8_MFMA_TOPS / 1e12,
-                 "unit": "TOP/s", "frac": achieved / PEAK_INT8_MAC, "kernel": "k_update_mfma"}
+                 "unit": "TOP/s", "frac": achieved / PEAK_INT8_MAC, "kernel": "k_update_mfma",
+                 "measured_peak": 2 * mp / 1e12, "frac_of_measured_peak": achieved / mp}
         else:
             achieved = upd * FINISH_BYTES(P) / secs
             r = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
@@ -260,6 +283,22 @@ def main():
         first = max(range(len(mats)), key=lambda b: mats[b][1].exp.shape[0]) if batched else 0
         gpu_D = Ds[first].row(0)
         out["cpu_baseline"] = cpu_baseline(mats[first][1], gpu_D, args.cpu_budget)
+    if compare != "none":
+        # the other update path on the same inputs: its time, and whether every
+        # D_k and minor it returns has the same bits
+        saved = [tuple(t.clone() for t in (D.limbs, D.exp, D.sign, c.limbs, c.exp, c.sign)) for D, c in zip(Ds, cs)]
+        step(compare)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            step(compare)
+            torch.cuda.synchronize()
+            print(f"[bench] {compare} step {s + 1}/{args.steps} done", file=sys.stderr, flush=True)
+        cms = (time.perf_counter() - t0) * 1e3 / args.steps
+        same = all(torch.equal(a, b) for sv, D, c in zip(saved, Ds, cs)
+                   for a, b in zip(sv, (D.limbs, D.exp, D.sign, c.limbs, c.exp, c.sign)))
+        out["comparison"] = {"path": compare, "ms_per_step": cms, "value": macs / (cms / 1e3),
+                             "measured_over_compared_time": ms / cms, "same_bits_D_and_minors": bool(same)}
     print(json.dumps(out), flush=True)
 
 

@@ -169,6 +169,19 @@ int mp_to_f64_scaled(mpdet_handle *h, mpdet_mat x, const int64_t *shift_dev, dou
                      void *stream);
 
 /*
+ * mpdet_measure_peak -- measured throughput of one arithmetic unit the
+ * trailing update runs on (a probe kernel over every compute unit, timed with
+ * HIP events after a warm-up launch; blocks the calling thread):
+ *   MPDET_PEAK_MAD64    32x32->64-bit multiply-adds per second (v_mad_u64_u32,
+ *                       the VALU path's limb product);
+ *   MPDET_PEAK_MFMA_I8  int8 multiply-adds per second (v_mfma_i32_32x32x32_i8,
+ *                       the MFMA path's limb product).
+ * The probe allocates and frees a small output buffer.
+ */
+enum { MPDET_PEAK_MAD64 = 0, MPDET_PEAK_MFMA_I8 = 1 };
+int mpdet_measure_peak(mpdet_handle *h, int kind, double *per_second);
+
+/*
  * Per-kernel timing with HIP events (tracing; off by default).
  * mpdet_profile_begin clears the counters and brackets every later launch on
  * this handle with two events on the launch stream; mpdet_profile_end waits

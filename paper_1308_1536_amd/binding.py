@@ -80,6 +80,8 @@ def lib() -> ctypes.CDLL:
         L.mp_det_adjugate.restype = ctypes.c_int
         L.mp_to_f64_scaled.argtypes = [vp, MpdetMat, vp, vp, vp]
         L.mp_to_f64_scaled.restype = ctypes.c_int
+        L.mpdet_measure_peak.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+        L.mpdet_measure_peak.restype = ctypes.c_int
         _ = (i32,)
         _lib = L
     return _lib
@@ -297,6 +299,17 @@ def to_f64_scaled(x: DeviceMp, shift, stream=None):
     _check("mp_to_f64_scaled",
            lib().mp_to_f64_scaled(h.ptr, x.mat(), shift.data_ptr(), val.data_ptr(), _stream(stream)))
     return val
+
+
+PEAK_KINDS = {"mad64": 0, "mfma_i8": 1}
+
+
+def measure_peak(kind: str, device: int = 0) -> float:
+    """mpdet_measure_peak: measured multiply-adds per second of one unit
+    ("mad64": 32x32->64 VALU, "mfma_i8": int8 MFMA)."""
+    out = ctypes.c_double()
+    _check("mpdet_measure_peak", lib().mpdet_measure_peak(handle(device).ptr, PEAK_KINDS[kind], ctypes.byref(out)))
+    return out.value
 
 
 KERNELS = ("pivot_divide", "divide", "update_valu", "update_mfma", "mfma_prep", "minors_sweep",

@@ -8,6 +8,7 @@
 // body as the single-matrix kernels with that matrix's descriptor.
 #pragma once
 
+#include "kernels_lane.h"
 #include "kernels_mfma.h"
 
 namespace mpk {
@@ -17,7 +18,7 @@ struct BatchMat {
     int32_t *info;
     int64_t n;
     uint8_t *Lr, *Ub;  // MFMA digit strings (null on the VALU path)
-    uint32_t *T;       // MFMA product-top records
+    uint32_t *T;       // product-top records (MFMA path, and the VALU path for P <= 128)
     uint32_t *rw;      // the pivot's reciprocal (P + 2 limbs)
 };
 
@@ -56,6 +57,12 @@ __global__ void __launch_bounds__(64) k_batch_update_valu(const BatchMat *mats, 
                                                           const int64_t *off, int cnt, int64_t k, int P) {
     MPK_BATCH_PROLOGUE
     update_valu_body(lds_raw, M.A, M.info, k, M.n, P, loc);
+}
+
+__global__ void __launch_bounds__(64 * kLaneRows) k_batch_prod_lane(const BatchMat *mats, const int32_t *order,
+                                                                    const int64_t *off, int cnt, int64_t k, int P) {
+    MPK_BATCH_PROLOGUE
+    prod_lane_body(lds_raw, M.A, M.T, M.info, k, M.n, P, loc);
 }
 
 __global__ void __launch_bounds__(64) k_batch_prep(const BatchMat *mats, const int32_t *order, const int64_t *off,

@@ -14,6 +14,8 @@
 #include "kernels_mfma.h"
 #include "kernels_adj.h"
 #include "kernels_batch.h"
+#include "kernels_lane.h"
+#include "peaks.h"
 #include <algorithm>
 #include <numeric>
 #include <vector>
@@ -181,27 +183,6 @@ int pivot_step(mpdet_handle *h, const mpk::MatDev &a, const mpk::MatDev &d, int3
     return last_launch();
 }
 
-int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, hipStream_t s) {
-    const int64_t n = A.rows;
-    const int P = A.nlimbs;
-    const size_t lds = mpk::lds_bytes(P);
-    mpk::MatDev a = dev(A), d = dev(D);
-    for (int64_t k = 0; k < n; ++k) {
-        int rc = pivot_step(h, a, d, info, k, n, P, s);
-        if (rc) return rc;
-        const int64_t m = n - k - 1;
-        if (m > 0) {
-            {
-                Prof pr(h, s, K_UPDATE_VALU);
-                hipLaunchKernelGGL(mpk::k_update_valu, grid_for(m * m), dim3(64), lds, s, a, (const int32_t *)info,
-                                   k, n, P);
-            }
-            rc = last_launch();
-            if (rc) return rc;
-        }
-    }
-    return MPDET_OK;
-}
 
 // Workspace of the MFMA path for trailing blocks up to m x m: reversed
 // multiplier digits, pivot-row digits and product-top records.
@@ -238,6 +219,48 @@ int mfma_workspace(mpdet_handle *h, int64_t m, int P, MfmaWs *w) {
     w->Lr = base;
     w->Ub = base + lr;
     w->T = (uint32_t *)(base + lr + ub);
+    return MPDET_OK;
+}
+
+// VALU path.  For P <= 128 (P a multiple of 4) each step runs the
+// lane-per-element product kernel into the record buffer, then the finish
+// kernel the MFMA path uses; otherwise one wave per element update.
+int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, hipStream_t s) {
+    const int64_t n = A.rows;
+    const int P = A.nlimbs;
+    const size_t lds = mpk::lds_bytes(P);
+    const bool lane = mpk::lane_update_ok(P);
+    MfmaWs w{};
+    if (lane) {
+        int rc = mfma_workspace(h, n > 1 ? n - 1 : 1, P, &w);
+        if (rc) return rc;
+    }
+    const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_lds_bytes(P);
+    mpk::MatDev a = dev(A), d = dev(D);
+    const int32_t *cinfo = info;
+    for (int64_t k = 0; k < n; ++k) {
+        int rc = pivot_step(h, a, d, info, k, n, P, s);
+        if (rc) return rc;
+        const int64_t m = n - k - 1;
+        if (m <= 0) continue;
+        if (lane) {
+            {
+                Prof pr(h, s, K_UPDATE_VALU);
+                hipLaunchKernelGGL(mpk::k_prod_lane, grid_for(mpk::lane_update_blocks(m)), dim3(64 * mpk::kLaneRows),
+                                   lds_prod, s, a, w.T, cinfo, k, n, P);
+            }
+            if ((rc = last_launch())) return rc;
+            {
+                Prof pr(h, s, K_UPDATE_FINISH);
+                hipLaunchKernelGGL(mpk::k_finish, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a,
+                                   (const uint32_t *)w.T, cinfo, k, n, P);
+            }
+        } else {
+            Prof pr(h, s, K_UPDATE_VALU);
+            hipLaunchKernelGGL(mpk::k_update_valu, grid_for(m * m), dim3(64), lds, s, a, cinfo, k, n, P);
+        }
+        if ((rc = last_launch())) return rc;
+    }
     return MPDET_OK;
 }
 
@@ -320,6 +343,47 @@ int mpdet_destroy(mpdet_handle *h) {
     if (h->bh_done) (void)hipEventDestroy(h->bh_done);
     free(h);
     return MPDET_OK;
+}
+
+int mpdet_measure_peak(mpdet_handle *h, int kind, double *per_second) {
+    if (!h || !per_second || (kind != MPDET_PEAK_MAD64 && kind != MPDET_PEAK_MFMA_I8)) return MPDET_EINVAL;
+    DeviceGuard g(h->device);
+    if (!g.ok) return MPDET_EHIP;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess || cus <= 0)
+        return MPDET_EHIP;
+    const unsigned blocks = (unsigned)cus * 8u, threads = 256u;
+    uint32_t *out = nullptr;
+    if (hipMalloc(&out, (size_t)blocks * threads * 4u) != hipSuccess) {
+        (void)hipGetLastError();
+        return MPDET_ENOMEM;
+    }
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    int rc = MPDET_OK;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = MPDET_EHIP;
+    const uint32_t iters = kind == MPDET_PEAK_MAD64 ? 8192u : 512u;
+    float ms = 0.f;
+    for (int pass = 0; pass < 2 && rc == MPDET_OK; ++pass) {  // pass 0 warms up
+        if (hipEventRecord(e0, nullptr) != hipSuccess) rc = MPDET_EHIP;
+        if (kind == MPDET_PEAK_MAD64)
+            hipLaunchKernelGGL(mpk::k_peak_mad64, dim3(blocks), dim3(threads), 0, nullptr, iters, 12345u, out);
+        else
+            hipLaunchKernelGGL(mpk::k_peak_mfma_i8, dim3(blocks), dim3(threads), 0, nullptr, iters, 12345u, out);
+        if (rc == MPDET_OK) rc = last_launch();
+        if (rc == MPDET_OK && hipEventRecord(e1, nullptr) != hipSuccess) rc = MPDET_EHIP;
+        if (rc == MPDET_OK && hipEventSynchronize(e1) != hipSuccess) rc = MPDET_EHIP;
+        if (rc == MPDET_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = MPDET_EHIP;
+    }
+    if (rc == MPDET_OK) {
+        const double threads_total = (double)blocks * threads;
+        const double ops = kind == MPDET_PEAK_MAD64 ? threads_total * 8.0 * iters
+                                                    : threads_total / 64.0 * 4.0 * iters * 32768.0;
+        *per_second = ms > 0.f ? ops / (ms * 1e-3) : 0.0;
+    }
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(out);
+    return rc;
 }
 
 int mpdet_profile_begin(mpdet_handle *h) {
@@ -465,6 +529,7 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
     const bool mfma_ok = mpk::mfma_supported(P);
     if (path == MPDET_PATH_MFMA && !mfma_ok) return MPDET_ENOTSUP;
     const bool use_mfma = path == MPDET_PATH_MFMA || (path == MPDET_PATH_AUTO && mfma_ok);
+    const bool lane_valu = !use_mfma && mpk::lane_update_ok(P);
     DeviceGuard g(h->device);
     if (!g.ok) return MPDET_EHIP;
     hipStream_t s = (hipStream_t)stream;
@@ -482,7 +547,9 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
         switch (phase) {
             case BP_PIVOT: return 2;
             case BP_DIVIDE: return m;
-            case BP_UPD: return use_mfma ? (mpk::mfma_update_blocks(m) + 7) / 8 * 8 : m * m;
+            case BP_UPD:
+                if (use_mfma) return (mpk::mfma_update_blocks(m) + 7) / 8 * 8;
+                return lane_valu ? mpk::lane_update_blocks(m) : m * m;
             case BP_PREP: return 2 * m;
             case BP_SUB: return mpk::finish_blocks(m, P);
         }
@@ -544,6 +611,8 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
         size_t need = up((size_t)(P + 2) * 4u);
         if (use_mfma)
             need += up((size_t)m * geo.LR) + up((size_t)m * geo.K8) + up(mfma_rec_bytes(m, P));
+        else if (lane_valu)
+            need += up(mfma_rec_bytes(m, P));
         scratch[(size_t)b] = need;
         total_scratch += need;
     }
@@ -592,6 +661,8 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
             M.Ub = q;
             q += up((size_t)m * geo.K8);
             M.T = (uint32_t *)q;
+        } else if (lane_valu) {
+            M.T = (uint32_t *)q;
         }
         sp += scratch[(size_t)b];
     }
@@ -610,14 +681,14 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
     const size_t lds_piv = mpk::pivot_lds_bytes(P), lds = mpk::lds_bytes(P);
     const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
     const size_t lds_fin = mpk::finish_lds_bytes(P);
-    auto launch = [&](int kernel_id, auto kern, size_t slot, size_t shmem, int64_t arg) -> int {
+    auto launch = [&](int kernel_id, auto kern, size_t slot, size_t shmem, int64_t arg, int threads = 64) -> int {
         const int c = count[slot];
         if (c <= 0) return MPDET_OK;
         const int64_t total = table[(size_t)start[slot] + (size_t)c];
         if (total <= 0) return MPDET_OK;
         Prof pr(h, s, kernel_id);
-        hipLaunchKernelGGL(kern, grid_for(total), dim3(64), shmem, s, dmats, dorder, dtable + start[slot], c, arg,
-                           P);
+        hipLaunchKernelGGL(kern, grid_for(total), dim3(threads), shmem, s, dmats, dorder, dtable + start[slot], c,
+                           arg, P);
         return last_launch();
     };
     for (int64_t k = 0; k < nmax; ++k) {
@@ -629,7 +700,14 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
             if ((rc = launch(K_UPDATE_MFMA, mpk::k_batch_update_mfma, base + BP_UPD, lds_mfma, k))) return rc;
             if ((rc = launch(K_UPDATE_FINISH, mpk::k_batch_finish, base + BP_SUB, lds_fin, k))) return rc;
         } else {
-            if ((rc = launch(K_UPDATE_VALU, mpk::k_batch_update_valu, base + BP_UPD, lds, k))) return rc;
+            if (lane_valu) {
+                if ((rc = launch(K_UPDATE_VALU, mpk::k_batch_prod_lane, base + BP_UPD, mpk::lane_lds_bytes(P), k,
+                                 64 * mpk::kLaneRows)))
+                    return rc;
+                if ((rc = launch(K_UPDATE_FINISH, mpk::k_batch_finish, base + BP_SUB, lds_fin, k))) return rc;
+            } else if ((rc = launch(K_UPDATE_VALU, mpk::k_batch_update_valu, base + BP_UPD, lds, k))) {
+                return rc;
+            }
         }
     }
     if (minors) {
