@@ -8,11 +8,12 @@
 // limb-major (row x holds limb x of the 64 elements, rows padded to 65 words
 // so the per-lane reads are free of bank conflicts), and each wave copies its
 // multiplier l_i into a broadcast buffer.  Each lane then forms l_i u_j by
-// column (Comba) accumulation: output columns r are taken four at a time,
-// every multiplier limb l[a] is multiplied into a window of four pivot-row
+// column (Comba) accumulation: output columns r are taken eight at a time,
+// every multiplier limb l[a] is multiplied into a window of eight pivot-row
 // limbs u[r+c-a] that slides by one limb per step, and each column keeps a
 // 96-bit sum of 32x32->64 products (v_mad_u64_u32 with its carry out, folded
-// by v_addc_co_u32).  Only the band 0 <= r-a < P is multiplied.
+// by v_addc_co_u32).  Zero rows below limb 0 and above limb P-1 let the
+// window run over the band's edges without bounds checks.
 //
 // The product's top limbs P-1 .. 2P-1 go to the same record buffer, in the
 // same limb-major layout, as the MFMA path's epilogue writes, and the same
@@ -26,10 +27,13 @@ namespace mpk {
 constexpr int kLaneMaxP = 128;
 constexpr int kLaneFT = 64;    // columns per workgroup (one per lane)
 constexpr int kLaneRows = 4;   // rows per workgroup (one per wave)
+constexpr int kLaneW = 8;      // product columns per Comba block
+constexpr int kPadLo = 8;      // zero tile rows below limb 0 ...
+constexpr int kPadHi = 8;      // ... and above limb P-1, read instead of clamping
 
 __host__ __device__ inline bool lane_update_ok(int P) { return P <= kLaneMaxP && P % 4 == 0; }
 __host__ __device__ inline size_t lane_lds_bytes(int P) {
-    return ((size_t)P * (kLaneFT + 1) + (size_t)kLaneRows * P) * 4u;
+    return ((size_t)(P + kPadLo + kPadHi) * (kLaneFT + 1) + (size_t)kLaneRows * P) * 4u;
 }
 // workgroups for an m x m trailing block
 __host__ __device__ inline int64_t lane_update_blocks(int64_t m) {
@@ -69,19 +73,23 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, MatDev A, uint32_t
     const int lane = mpw::lane();
     const int64_t ip = rg * kLaneRows + wave;
     const int cnt = (int)min((int64_t)FT, m - j0);
-    uint32_t *tile = lds;                               // P rows of FTP words
-    uint32_t *lsh = lds + (size_t)P * FTP + wave * P;  // this wave's multiplier
+    // tile rows -kPadLo .. P+kPadHi-1 of FTP words (limb x of element e at
+    // row x, column e; rows outside 0..P-1 hold zeros)
+    uint32_t *tile = lds + kPadLo * FTP;
+    uint32_t *lsh = lds + (size_t)(P + kPadLo + kPadHi) * FTP + wave * P;  // this wave's multiplier
     const bool row_ok = ip < m;
     const uint32_t *lm = el(A, k + 1 + (row_ok ? ip : 0), k, P);
     for (int q = lane; q < P; q += MP_WAVE) lsh[q] = lm[q];
     {
+        const int nt = (int)blockDim.x, tid = (int)threadIdx.x;
+        for (int z = tid; z < kPadLo * FTP; z += nt) lds[z] = 0u;
+        for (int z = tid; z < kPadHi * FTP; z += nt) tile[P * FTP + z] = 0u;
         // pivot-row limbs of the tile (cnt * P contiguous words) by the whole
         // workgroup, 8 loads per thread in flight; word w is limb w mod P of
         // element w / P, and for w < 2^13, P <= 128 the quotient is
-        // (w * magic) >> 24 exactly
+        // (w * magic) >> 24 exactly.  Columns cnt..63 are never read.
         const uint32_t *urow = el(A, k, k + 1 + j0, P);
         const int nw = cnt * P;
-        const int nt = (int)blockDim.x, tid = (int)threadIdx.x;
         const uint32_t magic = (1u << 24) / (uint32_t)P + 1u;
         for (int w0 = 0; w0 < nw; w0 += 8 * nt) {
             uint32_t v[8];
@@ -106,33 +114,38 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, MatDev A, uint32_t
     const int TP = mfma_geom(P).TP;
     uint32_t *rec = T + (ip * njb + jp / 32) * (int64_t)TP * 32 + (jp % 32);
 
-    const uint32_t *col = tile + e;  // row x at col[x * FTP]
+    const uint32_t *col = tile + e;  // limb x at col[x * FTP], -kPadLo <= x < P + kPadHi
     uint64_t carry = 0;              // carry into the next column (< 2^40)
-    for (int r0 = 0; r0 < 2 * P; r0 += 4) {
-        const int alo = max(0, r0 - P + 1), ahi = min(r0 + 3, P - 1);
-        // window w_c = u[r0 + c - a] at a = alo (zero outside 0..P-1)
-        uint32_t wv[4];
+    constexpr int W = kLaneW;
+    for (int r0 = 0; r0 < 2 * P; r0 += W) {
+        const int alo = max(0, r0 - P + 1), ahi = min(r0 + W - 1, P - 1);
+        // window w_c = u[r0 + c - a] at a = alo; r0 + c - alo <= P - 1 + c
+        uint32_t wv[W];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-            const int x = r0 + c - alo;
-            const uint32_t v = col[min(x, P - 1) * FTP];
-            wv[c] = x < P ? v : 0u;
+        for (int c = 0; c < W; ++c) wv[c] = col[(r0 + c - alo) * FTP];
+        uint64_t s[W];
+        uint32_t h[W];
+#pragma unroll
+        for (int c = 0; c < W; ++c) {
+            s[c] = 0;
+            h[c] = 0;
         }
-        uint64_t s[4] = {0, 0, 0, 0};
-        uint32_t h[4] = {0, 0, 0, 0};
         // one step at a: multiply l[a] into the window, then slide it down by
-        // one limb, u[r0 - a - 1] entering (zero below limb 0)
+        // one limb, u[r0 - a - 1] entering (>= -W: a zero pad row below limb 0)
         auto step = [&](uint32_t la, uint32_t vn) __attribute__((always_inline)) {
-            mac96x4(s, h, la, wv);
-            wv[3] = wv[2];
-            wv[2] = wv[1];
-            wv[1] = wv[0];
+            uint64_t(&s0)[4] = *reinterpret_cast<uint64_t(*)[4]>(&s[0]);
+            uint64_t(&s1)[4] = *reinterpret_cast<uint64_t(*)[4]>(&s[4]);
+            uint32_t(&h0)[4] = *reinterpret_cast<uint32_t(*)[4]>(&h[0]);
+            uint32_t(&h1)[4] = *reinterpret_cast<uint32_t(*)[4]>(&h[4]);
+            const uint32_t(&w0)[4] = *reinterpret_cast<const uint32_t(*)[4]>(&wv[0]);
+            const uint32_t(&w1)[4] = *reinterpret_cast<const uint32_t(*)[4]>(&wv[4]);
+            mac96x4(s0, h0, la, w0);
+            mac96x4(s1, h1, la, w1);
+#pragma unroll
+            for (int c = W - 1; c > 0; --c) wv[c] = wv[c - 1];
             wv[0] = vn;
         };
-        // raw LDS read of the limb entering at step a; the zero below limb 0
-        // is applied when it enters, so a prefetched value is not waited for early
-        auto fetch_u = [&](int a) -> uint32_t { return col[max(r0 - a - 1, 0) * FTP]; };
-        auto enter = [&](int a, uint32_t raw) -> uint32_t { return r0 - a - 1 >= 0 ? raw : 0u; };
+        const uint32_t *urd = col + (r0 - alo - 1) * FTP;  // row of the limb entering at step alo
         // groups of four steps, ping-pong buffered: a group's LDS reads are
         // issued while the previous group computes
         int a = alo;
@@ -141,12 +154,12 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, MatDev A, uint32_t
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 l[t] = lsh[a0 + t];
-                u[t] = fetch_u(a0 + t);
+                u[t] = urd[-(a0 - alo + t) * FTP];
             }
         };
-        auto run4 = [&](const uint32_t (&l)[4], const uint32_t (&u)[4], int a0) __attribute__((always_inline)) {
+        auto run4 = [&](const uint32_t (&l)[4], const uint32_t (&u)[4]) __attribute__((always_inline)) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) step(l[t], enter(a0 + t, u[t]));
+            for (int t = 0; t < 4; ++t) step(l[t], u[t]);
         };
         const int nfull = (ahi + 1 - alo) / 4;  // full groups
         int g = 0;
@@ -154,30 +167,30 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, MatDev A, uint32_t
             load4(la, ua, a);
             for (; g + 2 < nfull; g += 2, a += 8) {
                 load4(lb, ubf, a + 4);
-                run4(la, ua, a);
+                run4(la, ua);
                 load4(la, ua, a + 8);
-                run4(lb, ubf, a + 4);
+                run4(lb, ubf);
             }
             if (g + 1 < nfull) {
                 load4(lb, ubf, a + 4);
-                run4(la, ua, a);
-                run4(lb, ubf, a + 4);
+                run4(la, ua);
+                run4(lb, ubf);
                 a += 8;
             } else {
-                run4(la, ua, a);
+                run4(la, ua);
                 a += 4;
             }
         }
-        for (; a <= ahi; ++a) step(lsh[a], enter(a, fetch_u(a)));
-        // resolve the four columns; the record keeps limbs P-1 .. 2P-1
+        for (; a <= ahi; ++a) step(lsh[a], urd[-(a - alo) * FTP]);
+        // resolve the W columns; the record keeps limbs P-1 .. 2P-1
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
+        for (int c = 0; c < W; ++c) {
             const int r = r0 + c;
             const uint64_t lo = s[c] + carry;
             const uint32_t hi = h[c] + (lo < s[c] ? 1u : 0u);
             carry = (lo >> 32) | ((uint64_t)hi << 32);
             const int x = r - (P - 1);
-            if (x >= 0) rec[(int64_t)x * 32] = (uint32_t)lo;
+            if (x >= 0 && r < 2 * P) rec[(int64_t)x * 32] = (uint32_t)lo;
         }
     }
 }
