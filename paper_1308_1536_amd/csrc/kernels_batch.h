@@ -19,7 +19,7 @@ struct BatchMat {
     int64_t n;
     uint8_t *Lr, *Ub;  // MFMA digit strings (null on the VALU path)
     uint32_t *T;       // product-top records (MFMA path, and the VALU path for P <= 128)
-    uint32_t *rw;      // the pivot's reciprocal (P + 2 limbs)
+    uint32_t *rw;      // the pivot's reciprocal (P + 2 limbs) and the pending pivot code
 };
 
 // largest t in [0, cnt) with off[t] <= bx
@@ -44,7 +44,7 @@ __device__ __forceinline__ int locate(const int64_t *off, int cnt, int64_t bx) {
 __global__ void __launch_bounds__(64) k_batch_pivot(const BatchMat *mats, const int32_t *order, const int64_t *off,
                                                     int cnt, int64_t k, int P) {
     MPK_BATCH_PROLOGUE
-    pivot_recip_body(lds_raw, M.A, M.D, M.info, M.rw, k, M.n, P, (int)loc);
+    pivot_recip_body(lds_raw, M.A, M.D, M.info, M.info, M.rw, k, M.n, P, (int)loc);
 }
 
 __global__ void __launch_bounds__(64) k_batch_divide(const BatchMat *mats, const int32_t *order, const int64_t *off,
@@ -82,7 +82,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
 __global__ void __launch_bounds__(64) k_batch_finish(const BatchMat *mats, const int32_t *order,
                                                      const int64_t *off, int cnt, int64_t k, int P) {
     MPK_BATCH_PROLOGUE
-    finish_body(lds_raw, M.A, M.T, M.info, k, M.n, P, loc);
+    finish_body(lds_raw, M.A, M.T, M.info, k, M.n, P, loc, M.D, M.rw);
 }
 
 // minors sweep number s: matrix of size n processes j = n - 1 - s (blocks i < j)
@@ -117,6 +117,16 @@ __global__ void k_batch_minit(const BatchMat *mats, const int32_t *order, const 
 __global__ void k_batch_zero_info(int32_t *info, int64_t batch) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < batch) info[i] = 0;
+}
+
+// clear (promote = 0) or move into info (promote = 1) every matrix's pending
+// pivot code
+__global__ void k_batch_pend(const BatchMat *mats, int64_t batch, int P, int promote) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const BatchMat M = mats[b];
+    if (!promote) M.rw[P + 2] = 0u;
+    else if (*M.info == 0) *M.info = (int32_t)M.rw[P + 2];
 }
 
 #undef MPK_BATCH_PROLOGUE

@@ -333,9 +333,8 @@ __host__ __device__ inline int64_t finish_blocks(int64_t m, int P) {
 // record slots of an m x m trailing block: m rows x njb blocks of 32 columns
 __host__ __device__ inline int64_t rec_slots(int64_t m) { return m * ((m + 31) / 32) * 32; }
 
-__device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, const uint32_t *__restrict__ T,
-                                            const int32_t *info, int64_t k, int64_t n, int P, int64_t bx) {
-    if (*info != 0) return;
+__device__ __forceinline__ void finish_tile_body(uint32_t *lds, MatDev A, const uint32_t *__restrict__ T, int64_t k,
+                                                 int64_t n, int P, int64_t bx) {
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
     const int64_t njb = (m + 31) / 32;
@@ -555,10 +554,38 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
     update_mfma_body(lds_raw, A, Lr, Ub, T, info, k, n, P, flat_block(), true);
 }
 
+// The finish of step k, and the first part of step k+1: the workgroup that
+// holds a_{k+1,k+1} (block 0) goes on, once its tile is stored, to the next
+// pivot's reciprocal and D_{k+1} (pivot_recip_body), while the other
+// workgroups of the launch are still finishing -- the reciprocal leaves the
+// chain of dependent launches.  Its zero / overflow code goes to the pending
+// word rw[P + 2] rather than to info, which the launch's other workgroups are
+// reading; step k+1's divide kernel moves it into info.  rw == nullptr: no
+// look-ahead.
+__device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, const uint32_t *__restrict__ T,
+                                            const int32_t *info, int64_t k, int64_t n, int P, int64_t bx, MatDev D,
+                                            uint32_t *rw) {
+    if (*info != 0) return;
+    finish_tile_body(lds, A, T, k, n, P, bx);
+    if (rw != nullptr && bx == 0 && k + 1 < n) {
+        __syncthreads();  // the tile's stores are visible to the workgroup, its LDS is free
+        int32_t *pend = (int32_t *)(rw + P + 2);
+        pivot_recip_body(lds, A, D, info, pend, rw, k + 1, n, P, 1);
+        __syncthreads();
+        pivot_recip_body(lds, A, D, info, pend, rw, k + 1, n, P, 0);
+    }
+}
+
+// LDS of the finish launch: the tile, or the pivot's scratch if larger
+__host__ __device__ inline size_t finish_launch_lds(int P) {
+    const size_t a = finish_lds_bytes(P), b = pivot_lds_bytes(P);
+    return a > b ? a : b;
+}
+
 __global__ void __launch_bounds__(64) k_finish(MatDev A, const uint32_t *T, const int32_t *info, int64_t k,
-                                               int64_t n, int P) {
+                                               int64_t n, int P, MatDev D, uint32_t *rw) {
     extern __shared__ uint32_t lds_raw[];
-    finish_body(lds_raw, A, T, info, k, n, P, flat_block());
+    finish_body(lds_raw, A, T, info, k, n, P, flat_block(), D, rw);
 }
 
 }  // namespace mpk

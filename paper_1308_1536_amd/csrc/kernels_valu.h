@@ -73,8 +73,11 @@ __host__ __device__ inline size_t pivot_lds_bytes(int P) {
     return a > b ? a : b;
 }
 
-__device__ __forceinline__ void pivot_recip_body(uint32_t *lds_raw, MatDev A, MatDev D, int32_t *info, uint32_t *rw, int64_t k,
-                                 int64_t n, int P, int role) {
+// info_out receives the zero-pivot / overflow code (info itself, or a pending
+// word when this runs inside the previous step's launch, see finish_body)
+__device__ __forceinline__ void pivot_recip_body(uint32_t *lds_raw, MatDev A, MatDev D, const int32_t *info,
+                                                 int32_t *info_out, uint32_t *rw, int64_t k, int64_t n, int P,
+                                                 int role) {
     if (*info != 0) return;
     const uint32_t *pm = el(A, k, k, P);
     const bool piv_zero = pm[P - 1] == 0u;
@@ -104,7 +107,7 @@ __device__ __forceinline__ void pivot_recip_body(uint32_t *lds_raw, MatDev A, Ma
             }
         }
         if (bad) {
-            if (mpw::lane() == 0) *info = code;
+            if (mpw::lane() == 0) *info_out = code;
             for (int64_t t = k; t < n; ++t) store_zero(el(D, 0, t, P), &ex(D, 0, t), &sg(D, 0, t), P);
         } else {
             mpw::store(el(D, 0, k, P), &ex(D, 0, k), &sg(D, 0, k), L.sc.t3, hd, P);
@@ -120,9 +123,16 @@ __device__ __forceinline__ void pivot_recip_body(uint32_t *lds_raw, MatDev A, Ma
     if (mpw::lane() == 0) rw[P + 1] = ok ? 1u : 0u;
 }
 
-__device__ __forceinline__ void divide_body(uint32_t *lds_raw, MatDev A, const uint32_t *rw, const int32_t *info, int64_t k,
-                            int64_t n, int P, int64_t blk) {
-    if (*info != 0) return;
+// rw[P + 2] is the pending code of step k's pivot when that pivot was
+// examined inside the previous step's launch: a nonzero code stops the step,
+// and block 0 moves it into info for the launches that follow.
+__device__ __forceinline__ void divide_body(uint32_t *lds_raw, MatDev A, const uint32_t *rw, int32_t *info, int64_t k,
+                                            int64_t n, int P, int64_t blk) {
+    const int32_t pend = (int32_t)rw[P + 2];
+    if (*info != 0 || pend != 0) {
+        if (blk == 0 && mpw::lane() == 0 && *info == 0) *info = pend;
+        return;
+    }
     const uint32_t *pm = el(A, k, k, P);
     if (pm[P - 1] == 0u) return;
     const int64_t i = k + 1 + blk;
@@ -239,10 +249,19 @@ __device__ __forceinline__ int64_t flat_block() {
 __global__ void __launch_bounds__(64) k_pivot_recip(MatDev A, MatDev D, int32_t *info, uint32_t *rw, int64_t k,
                                                     int64_t n, int P) {
     extern __shared__ uint32_t lds_raw[];
-    pivot_recip_body(lds_raw, A, D, info, rw, k, n, P, (int)blockIdx.x);
+    pivot_recip_body(lds_raw, A, D, info, info, rw, k, n, P, (int)blockIdx.x);
 }
 
-__global__ void __launch_bounds__(64) k_divide(MatDev A, const uint32_t *rw, const int32_t *info, int64_t k,
+// clear the pending pivot code (rw[P + 2]) before a factorisation, and move a
+// code still pending after the last step into info
+__global__ void k_pend_clear(uint32_t *rw, int P) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) rw[P + 2] = 0u;
+}
+__global__ void k_pend_promote(int32_t *info, const uint32_t *rw, int P) {
+    if (threadIdx.x == 0 && blockIdx.x == 0 && *info == 0) *info = (int32_t)rw[P + 2];
+}
+
+__global__ void __launch_bounds__(64) k_divide(MatDev A, const uint32_t *rw, int32_t *info, int64_t k,
                                                int64_t n, int P) {
     extern __shared__ uint32_t lds_raw[];
     divide_body(lds_raw, A, rw, info, k, n, P, flat_block());

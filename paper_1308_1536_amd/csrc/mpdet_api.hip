@@ -142,9 +142,10 @@ struct DeviceGuard {
     }
 };
 
-// Scratch for the pivot's reciprocal: P + 2 limbs (R and its exactness flag).
+// Scratch for the pivot's reciprocal: P + 2 limbs (R and its exactness flag),
+// then the pending pivot code (see finish_body).
 int recip_ws(mpdet_handle *h, int P, uint32_t **rw) {
-    const size_t need = ((size_t)(P + 2) * 4u + 255) & ~(size_t)255;
+    const size_t need = ((size_t)(P + 3) * 4u + 255) & ~(size_t)255;
     if (need > h->rw_bytes) {
         if (h->rw) (void)hipFree(h->rw);
         h->rw = nullptr;
@@ -160,26 +161,37 @@ int recip_ws(mpdet_handle *h, int P, uint32_t **rw) {
     return MPDET_OK;
 }
 
-// Algorithm 1 steps 2.1 and 2.2.1 for step k: D_k and the pivot's reciprocal,
+// Algorithm 1 steps 2.1 and 2.2.1 for step k: D_k and the pivot's reciprocal
+// (unless the previous step's finish launch already examined this pivot),
 // then the multipliers of rows k+1..n-1.
-int pivot_step(mpdet_handle *h, const mpk::MatDev &a, const mpk::MatDev &d, int32_t *info, int64_t k, int64_t n,
-               int P, hipStream_t s) {
-    uint32_t *rw = nullptr;
-    int rc = recip_ws(h, P, &rw);
-    if (rc) return rc;
+int pivot_step(mpdet_handle *h, const mpk::MatDev &a, const mpk::MatDev &d, int32_t *info, uint32_t *rw, int64_t k,
+               int64_t n, int P, bool pivot_done, hipStream_t s) {
+    int rc;
     const size_t lds = mpk::pivot_lds_bytes(P);
-    {
-        Prof pr(h, s, K_PIVOT_DIVIDE);
-        hipLaunchKernelGGL(mpk::k_pivot_recip, dim3(2), dim3(64), lds, s, a, d, info, rw, k, n, P);
+    if (!pivot_done) {
+        {
+            Prof pr(h, s, K_PIVOT_DIVIDE);
+            hipLaunchKernelGGL(mpk::k_pivot_recip, dim3(2), dim3(64), lds, s, a, d, info, rw, k, n, P);
+        }
+        if ((rc = last_launch())) return rc;
     }
-    if ((rc = last_launch())) return rc;
     const int64_t m = n - k - 1;
     if (m <= 0) return MPDET_OK;
     {
         Prof pr(h, s, K_DIVIDE);
-        hipLaunchKernelGGL(mpk::k_divide, dim3((unsigned)m), dim3(64), lds, s, a, (const uint32_t *)rw,
-                           (const int32_t *)info, k, n, P);
+        hipLaunchKernelGGL(mpk::k_divide, dim3((unsigned)m), dim3(64), lds, s, a, (const uint32_t *)rw, info, k, n,
+                           P);
     }
+    return last_launch();
+}
+
+// the pending pivot code: cleared before a factorisation, moved into info after it
+int pend_clear(uint32_t *rw, int P, hipStream_t s) {
+    hipLaunchKernelGGL(mpk::k_pend_clear, dim3(1), dim3(64), 0, s, rw, P);
+    return last_launch();
+}
+int pend_promote(int32_t *info, const uint32_t *rw, int P, hipStream_t s) {
+    hipLaunchKernelGGL(mpk::k_pend_promote, dim3(1), dim3(64), 0, s, info, rw, P);
     return last_launch();
 }
 
@@ -235,11 +247,15 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
         int rc = mfma_workspace(h, n > 1 ? n - 1 : 1, P, &w);
         if (rc) return rc;
     }
-    const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_lds_bytes(P);
+    const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_launch_lds(P);
     mpk::MatDev a = dev(A), d = dev(D);
     const int32_t *cinfo = info;
+    uint32_t *rw = nullptr;
+    int rc0 = recip_ws(h, P, &rw);
+    if (rc0 || (rc0 = pend_clear(rw, P, s))) return rc0;
     for (int64_t k = 0; k < n; ++k) {
-        int rc = pivot_step(h, a, d, info, k, n, P, s);
+        // with the finish kernel, step k's pivot was examined by step k-1's finish launch
+        int rc = pivot_step(h, a, d, info, rw, k, n, P, lane && k > 0, s);
         if (rc) return rc;
         const int64_t m = n - k - 1;
         if (m <= 0) continue;
@@ -253,7 +269,7 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
             {
                 Prof pr(h, s, K_UPDATE_FINISH);
                 hipLaunchKernelGGL(mpk::k_finish, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a,
-                                   (const uint32_t *)w.T, cinfo, k, n, P);
+                                   (const uint32_t *)w.T, cinfo, k, n, P, d, rw);
             }
         } else {
             Prof pr(h, s, K_UPDATE_VALU);
@@ -261,7 +277,7 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
         }
         if ((rc = last_launch())) return rc;
     }
-    return MPDET_OK;
+    return pend_promote(info, rw, P, s);
 }
 
 int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, hipStream_t s) {
@@ -271,11 +287,13 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     int rc = mfma_workspace(h, n > 1 ? n - 1 : 1, P, &w);
     if (rc) return rc;
     const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
-    const size_t lds_fin = mpk::finish_lds_bytes(P);
+    const size_t lds_fin = mpk::finish_launch_lds(P);
     mpk::MatDev a = dev(A), d = dev(D);
     const int32_t *cinfo = info;
+    uint32_t *rw = nullptr;
+    if ((rc = recip_ws(h, P, &rw)) || (rc = pend_clear(rw, P, s))) return rc;
     for (int64_t k = 0; k < n; ++k) {
-        if ((rc = pivot_step(h, a, d, info, k, n, P, s))) return rc;
+        if ((rc = pivot_step(h, a, d, info, rw, k, n, P, k > 0, s))) return rc;
         const int64_t m = n - k - 1;
         if (m <= 0) continue;
         {
@@ -293,11 +311,11 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
         {
             Prof pr(h, s, K_UPDATE_FINISH);
             hipLaunchKernelGGL(mpk::k_finish, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a,
-                               (const uint32_t *)w.T, cinfo, k, n, P);
+                               (const uint32_t *)w.T, cinfo, k, n, P, d, rw);
         }
         if ((rc = last_launch())) return rc;
     }
-    return MPDET_OK;
+    return pend_promote(info, rw, P, s);
 }
 
 }  // namespace
@@ -608,7 +626,7 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
     size_t total_scratch = 0;
     for (int64_t b = 0; b < batch; ++b) {
         const int64_t n = A_arr[b].rows, m = n > 1 ? n - 1 : 1;
-        size_t need = up((size_t)(P + 2) * 4u);
+        size_t need = up((size_t)(P + 3) * 4u);
         if (use_mfma)
             need += up((size_t)m * geo.LR) + up((size_t)m * geo.K8) + up(mfma_rec_bytes(m, P));
         else if (lane_valu)
@@ -652,7 +670,7 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
         M.n = n;
         uint8_t *q = sp;
         M.rw = (uint32_t *)q;
-        q += up((size_t)(P + 2) * 4u);
+        q += up((size_t)(P + 3) * 4u);
         M.Lr = M.Ub = nullptr;
         M.T = nullptr;
         if (use_mfma) {
@@ -680,7 +698,11 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
     if ((rc = last_launch())) return rc;
     const size_t lds_piv = mpk::pivot_lds_bytes(P), lds = mpk::lds_bytes(P);
     const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
-    const size_t lds_fin = mpk::finish_lds_bytes(P);
+    const size_t lds_fin = mpk::finish_launch_lds(P);
+    // with the finish kernel, step k's pivot is examined by step k-1's finish launch
+    const bool lookahead = use_mfma || lane_valu;
+    hipLaunchKernelGGL(mpk::k_batch_pend, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, dmats, batch, P, 0);
+    if ((rc = last_launch())) return rc;
     auto launch = [&](int kernel_id, auto kern, size_t slot, size_t shmem, int64_t arg, int threads = 64) -> int {
         const int c = count[slot];
         if (c <= 0) return MPDET_OK;
@@ -693,7 +715,8 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
     };
     for (int64_t k = 0; k < nmax; ++k) {
         const size_t base = (size_t)(k * BP_COUNT);
-        if ((rc = launch(K_PIVOT_DIVIDE, mpk::k_batch_pivot, base + BP_PIVOT, lds_piv, k))) return rc;
+        if (!(lookahead && k > 0) && (rc = launch(K_PIVOT_DIVIDE, mpk::k_batch_pivot, base + BP_PIVOT, lds_piv, k)))
+            return rc;
         if ((rc = launch(K_DIVIDE, mpk::k_batch_divide, base + BP_DIVIDE, lds_piv, k))) return rc;
         if (use_mfma) {
             if ((rc = launch(K_MFMA_PREP, mpk::k_batch_prep, base + BP_PREP, lds_prep, k))) return rc;
@@ -710,6 +733,8 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
             }
         }
     }
+    hipLaunchKernelGGL(mpk::k_batch_pend, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, dmats, batch, P, 1);
+    if ((rc = last_launch())) return rc;
     if (minors) {
         const size_t islot = mbase + (size_t)nmax + 1;
         const int64_t itotal = table[(size_t)start[islot] + (size_t)count[islot]];
