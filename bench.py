@@ -68,6 +68,33 @@ def workload(cfg: int):
     raise SystemExit(f"bench.py: config {cfg} is not a single-GPU bench workload")
 
 
+def kernel_source_sha256() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1308_1536_amd", "csrc", "*"))):
+        if f.endswith((".h", ".hip")):
+            h.update(os.path.basename(f).encode())
+            with open(f, "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
+
+
+def load_traffic(cfg: int) -> dict:
+    """profiles/traffic_config<cfg>.json (per-launch HBM bytes measured with
+    rocprofv3 counters), keyed by kernel -- empty when absent or when the
+    kernel sources have changed since the counters were taken"""
+    path = os.path.join(ROOT, "profiles", f"traffic_config{cfg}.json")
+    try:
+        with open(path) as fh:
+            db = json.load(fh)
+    except (OSError, ValueError):
+        return {}
+    if db.get("source_sha256") != kernel_source_sha256():
+        return {}
+    return db.get("kernels", {})
+
+
 def cached_workload(cfg: int, cache: str | None):
     """workload(cfg), with the generated matrices stored as .npy files under
     `cache` (numpy's own format, loaded without pickle)."""
@@ -231,6 +258,21 @@ def main():
     P = mats[0][1].limbs.shape[-1]
 
     peaks = {}
+    traffic_db = load_traffic(args.config)
+
+    def measured_traffic(kernel):
+        """HBM bytes per launch from the committed FETCH_SIZE/WRITE_SIZE counter
+        passes, if they were taken on the current kernel sources, else None"""
+        t = traffic_db.get(kernel)
+        if t is None:
+            return None
+        return {"bytes_per_launch": t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"],
+                "fetch_bytes_per_launch": t["fetch_bytes_per_launch"],
+                "write_bytes_per_launch": t["write_bytes_per_launch"]}
+
+    def kname_of(single):
+        """the kernel's symbol as launched: the batched variants carry k_batch_"""
+        return "k_batch_" + single[2:] if batched else single
 
     def measured_peak(kind):
         """the unit's throughput measured on this GPU (probe kernel), multiply-adds/s"""
@@ -249,19 +291,19 @@ def main():
             mp = measured_peak("mad64")
             r = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_MAC32 / 1e12,
                  "unit": "Tmac32/s", "frac": achieved / PEAK_VALU_MAC32,
-                 "kernel": "k_update_lane" if P <= 128 else "k_update_valu",
+                 "kernel": kname_of("k_prod_lane" if (P <= 128 and P % 4 == 0) else "k_update_valu"),
                  "measured_peak": mp / 1e12, "frac_of_measured_peak": achieved / mp}
         elif kname == "update_mfma":
             achieved = macs / secs
             mp = measured_peak("mfma_i8")
             r = {"bound": "mfma", "achieved": 2 * achieved / 1e12, "peak": PEAK_INT8_MFMA_TOPS / 1e12,
-                 "unit": "TOP/s", "frac": achieved / PEAK_INT8_MAC, "kernel": "k_update_mfma",
+                 "unit": "TOP/s", "frac": achieved / PEAK_INT8_MAC, "kernel": kname_of("k_update_mfma"),
                  "measured_peak": 2 * mp / 1e12, "frac_of_measured_peak": achieved / mp}
         else:
             achieved = upd * FINISH_BYTES(P) / secs
             r = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                 "frac": achieved / PEAK_HBM, "kernel": "k_finish"}
-        r.update({"traffic": None, "avg_launch_ms": kms / kn, "launches": kn})
+                 "frac": achieved / PEAK_HBM, "kernel": kname_of("k_finish")}
+        r.update({"traffic": measured_traffic(r["kernel"]), "avg_launch_ms": kms / kn, "launches": kn})
         return r
 
     cands = [k for k in ("update_valu", "update_mfma", "update_finish") if prof[k][1] > 0]
