@@ -177,6 +177,9 @@ def main():
     ap.add_argument("--input-cache", default=None, metavar="DIR",
                     help="load the workload's generated matrices from DIR (.npy files), generating and "
                          "saving them there first if absent")
+    ap.add_argument("--size", type=int, default=0, metavar="N",
+                    help="use the leading N x N block of every matrix (a scaling study, not the configuration's "
+                         "workload; the JSON line says so)")
     ap.add_argument("--per-matrix", action="store_true",
                     help="factor the workload's matrices one after another instead of in one batched call")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -189,14 +192,21 @@ def main():
               "--gpus must be 1", file=sys.stderr, flush=True)
         sys.exit(2)
 
+    # inputs first: the generator may fork worker processes, which must
+    # happen before this process touches the GPU
+    desc, mats = cached_workload(args.config, args.input_cache)
+    if args.size:
+        from paper_1308_1536_amd.inputs import MpArray
+        mats = [(nm, MpArray(m.limbs[:args.size, :args.size].copy(), m.exp[:args.size, :args.size].copy(),
+                             m.sign[:args.size, :args.size].copy())) for nm, m in mats]
+        desc += f" -- leading {args.size}x{args.size} blocks"
+    print(f"[bench] {desc}", file=sys.stderr, flush=True)
+
     import torch
 
     from paper_1308_1536_amd import binding
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
-
-    desc, mats = cached_workload(args.config, args.input_cache)
-    print(f"[bench] {desc}", file=sys.stderr, flush=True)
     pristine = [binding.DeviceMp.from_host(m) for _, m in mats]
     work = [binding.DeviceMp.empty(p.rows, p.cols, p.P, dev) for p in pristine]
     Ds = [binding.DeviceMp.empty(1, p.rows, p.P, dev) for p in pristine]

@@ -82,7 +82,8 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
 __global__ void __launch_bounds__(64) k_batch_finish(const BatchMat *mats, const int32_t *order,
                                                      const int64_t *off, int cnt, int64_t k, int P) {
     MPK_BATCH_PROLOGUE
-    finish_body(lds_raw, M.A, M.T, M.info, k, M.n, P, loc, M.D, M.rw);
+    // the look-ahead pivot runs only where the host launches no pivot phase
+    finish_body(lds_raw, M.A, M.T, M.info, k, M.n, P, loc, M.D, finish_lookahead_ok(P) ? M.rw : nullptr);
 }
 
 // minors sweep number s: matrix of size n processes j = n - 1 - s (blocks i < j)

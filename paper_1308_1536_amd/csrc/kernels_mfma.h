@@ -322,8 +322,18 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
 // normalises G to p bits), and the tile is copied back.  Every pass walks the
 // limbs in an order that never reads a location after writing it.
 // ---------------------------------------------------------------------------
-__host__ __device__ inline int finish_tile(int P) { return P <= 256 ? 64 : (P <= 512 ? 32 : 16); }
+// Streaming variant (finish_stream_body), for P above kFinStreamMinP: the tile
+// is always 64 elements and LDS holds only 32-limb chunks, so occupancy and
+// lane use no longer fall with P (measured: 2.1x faster than the LDS tile at
+// 32K bits, 1.3x slower at 4K bits, where the tile keeps all 64 lanes busy).
+constexpr int kFinStreamMinP = 256;
+constexpr int kFinC = 32;  // limbs per chunk of the streaming finish
+__host__ __device__ inline bool finish_streams(int P) { return P > kFinStreamMinP; }
+__host__ __device__ inline int finish_tile(int P) {
+    return finish_streams(P) ? 64 : (P <= 256 ? 64 : (P <= 512 ? 32 : 16));
+}
 __host__ __device__ inline size_t finish_lds_bytes(int P) {
+    if (finish_streams(P)) return (size_t)(2 * kFinC * 65 + 64) * 4u;
     return (size_t)(P + 1) * (size_t)(finish_tile(P) + 1) * 4u;
 }
 __host__ __device__ inline int64_t finish_blocks(int64_t m, int P) {
@@ -562,11 +572,218 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
 // word rw[P + 2] rather than to info, which the launch's other workgroups are
 // reading; step k+1's divide kernel moves it into info.  rw == nullptr: no
 // look-ahead.
-__device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, const uint32_t *__restrict__ T,
+// The same finish with 64 elements per wave for any P.  The elements' limbs
+// move between HBM and LDS in chunks of kFinC limbs (a chunk of one element is
+// one contiguous run, so 32 lanes load or store 128 bytes), the exact p+2-bit
+// intermediate G is kept in the element's own record words (word q is read
+// before G[q] overwrites it), and the normalised result goes back through an
+// LDS chunk.  LDS: two chunk buffers and the per-element offsets.
+__device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint32_t *__restrict__ T, int64_t k,
+                                                   int64_t n, int P, int64_t bx) {
+    const MfmaGeom g = mfma_geom(P);
+    const int64_t m = n - k - 1;
+    const int64_t njb = (m + 31) / 32;
+    constexpr int FT = 64, FTP = 65, C = kFinC;
+    static_assert(C == 32 && FT == 64, "the chunk copies map 64 elements x 32 limbs onto 32 lane passes");
+    const int64_t ntile = (m + FT - 1) / FT;
+    const int64_t ip = bx / ntile, j0 = (bx % ntile) * FT;
+    if (ip >= m) return;
+    const int64_t i = k + 1 + ip;
+    if (el(A, i, k, P)[P - 1] == 0u) return;  // zero multiplier: the row keeps its values
+    const int cnt = (int)min((int64_t)FT, m - j0);
+    uint32_t *arow = el(A, i, k + 1 + j0, P);  // element e2's limbs at arow + e2 * P
+    uint32_t *achunk = lds;                    // C rows x FTP: a's limbs of the current chunk
+    uint32_t *ochunk = lds + C * FTP;          // C rows x FTP: result limbs of the current chunk
+    int32_t *eoff = (int32_t *)(lds + 2 * C * FTP);  // per element: a's limb offset, or -1: not written
+    const int lane = mpw::lane(), e = lane;
+    const bool in = e < cnt;
+    const int64_t jp = j0 + (in ? e : 0), j = k + 1 + jp;
+    uint32_t *am = arow + (int64_t)(in ? e : 0) * P;
+    uint32_t *raw = T + (ip * njb + jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
+    const bool live = in && el(A, k, j, P)[P - 1] != 0u;  // u_j = 0: a_ij is left as it is
+    const int pbits = 32 * P;
+
+    // ---- per element: operands, alignment, sticky ----
+    int oa = 0, ot = 0, gsh = 0, b = 0, w = 0, sh = 0;
+    bool a_is_x = true;
+    uint32_t ymask = 0u, cy = 0u;
+    int64_t eX = 0;
+    int32_t sX = 0;
+    auto rw = [&](int x) -> uint32_t { return (x >= 0 && x <= P) ? raw[(int64_t)x * 32] : 0u; };
+    auto tl = [&](int q) -> uint32_t {
+        if (q < 0 || q >= P) return 0u;
+        const uint32_t hi = rw(q + 1);
+        return sh ? __builtin_amdgcn_alignbit(hi, rw(q), 31) : hi;
+    };
+    auto al = [&](int q) -> uint32_t { return (q >= 0 && q < P) ? am[q] : 0u; };
+    uint32_t ylo = 0u, wlo = 0u;
+    if (live) {
+        const int top = (int)(rw(P) >> 31);
+        sh = 1 - top;
+        const int64_t et = ex(A, i, k) + ex(A, k, j) - 1 + top;
+        const int32_t sy = sg(A, i, k) ^ sg(A, k, j) ^ 1;  // sign of -t
+        const int64_t ea = ex(A, i, j);
+        const int32_t sa = sg(A, i, j);
+        bool subtract = false;
+        uint32_t st = 0u;
+        if (am[P - 1] == 0u) {  // 0 - t: X = t, Y = a = 0 shifted out
+            a_is_x = false;
+            eX = et;
+            sX = sy;
+            w = P + 2;
+        } else {
+            subtract = sa != sy;
+            a_is_x = ea > et || (ea == et && !subtract);
+            bool zero = false;
+            if (ea == et && subtract) {
+                int c = 0;
+                for (int q = P - 1; q >= 0 && c == 0; --q) {
+                    const uint32_t x = al(q), y = tl(q);
+                    c = x > y ? 1 : (x < y ? -1 : 0);
+                }
+                zero = c == 0;
+                a_is_x = c > 0;
+            }
+            if (zero) {  // a = t exactly: X = a, Y = t, G = 0
+                a_is_x = true;
+            }
+            eX = a_is_x ? ea : et;
+            const int64_t eY = a_is_x ? et : ea;
+            sX = a_is_x ? sa : sy;
+            const uint64_t d = (uint64_t)eX - (uint64_t)eY;
+            gsh = subtract ? (int)(d < 2 ? d : 2) : 0;
+            const uint64_t rsu = subtract ? (d < 2 ? 0 : d - 2) : d;
+            const int rs = (int)(rsu > (uint64_t)(pbits + 64) ? (uint64_t)(pbits + 64) : rsu);
+            w = rs / 32;
+            b = rs % 32;
+            if (subtract && rs > 0) {
+                bool any = false;
+                for (int q = 0; q < P && q <= w && !any; ++q) {
+                    const uint32_t v = a_is_x ? tl(q) : al(q);
+                    if (q < w) any = v != 0u;
+                    else if (b) any = (v & ((1u << b) - 1u)) != 0u;
+                }
+                st = any ? 1u : 0u;
+            }
+        }
+        oa = a_is_x ? 0 : w + 1;
+        ot = a_is_x ? w + 1 : 0;
+        ymask = subtract ? 0xFFFFFFFFu : 0u;
+        cy = subtract ? 1u - st : 0u;
+        ylo = a_is_x ? tl(w) : al(w);
+        wlo = rw(ot);
+    }
+    eoff[e] = live ? oa : -1;
+
+    // ---- pass 1: G = X 2^gsh +- (Y >> rs) -+ sticky, limbs 0..P, into the record ----
+    constexpr int PF = 16;  // record words fetched PF steps ahead (C is a multiple of PF)
+    uint32_t ring[PF];
+    const uint32_t *rp = raw + (int64_t)(ot + 1) * 32;
+    const int xlim = P - ot - 1;  // step q uses a real record word iff q <= xlim
+#pragma unroll
+    for (int u = 0; u < PF; ++u) ring[u] = rp[(int64_t)min(u, max(xlim, 0)) * 32];
+    uint32_t xprev = 0u;
+    for (int c0 = 0; c0 <= P; c0 += C) {
+        mpw::wsync();  // the previous chunk is consumed; eoff is visible
+        // a's limbs [c0 + off, c0 + off + C) of every element, 8 loads per
+        // lane in flight: pass t covers element t >> 5, limb t & 31
+#pragma unroll
+        for (int h4 = 0; h4 < 4; ++h4) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = (h4 * 8 + u) * MP_WAVE + lane;
+                const int e2 = t >> 5, r = t & 31;
+                const int off = eoff[e2];
+                const int q = c0 + off + r;
+                v[u] = (off >= 0 && q < P) ? arow[(int64_t)e2 * P + q] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int t = (h4 * 8 + u) * MP_WAVE + lane;
+                achunk[(t & 31) * FTP + (t >> 5)] = v[u];
+            }
+        }
+        mpw::wsync();
+        if (live) {
+            auto step1 = [&](int q, int u) __attribute__((always_inline)) {
+                const uint32_t wr = ring[u % PF];
+                ring[u % PF] = rp[(int64_t)min(q + PF, max(xlim, 0)) * 32];
+                const uint32_t whi = q <= xlim ? wr : 0u;
+                const uint32_t tsh = sh ? __builtin_amdgcn_alignbit(whi, wlo, 31) : whi;
+                const uint32_t tv = q + ot < P ? tsh : 0u;
+                wlo = whi;
+                const uint32_t av = achunk[u * FTP + e];
+                const uint32_t xq = a_is_x ? av : tv;
+                const uint32_t yhi = a_is_x ? tv : av;
+                const uint32_t xg = gsh ? __builtin_amdgcn_alignbit(xq, xprev, 32 - gsh) : xq;
+                const uint32_t ysh = __builtin_amdgcn_alignbit(yhi, ylo, b);
+                const uint64_t t = (uint64_t)xg + (ysh ^ ymask) + cy;
+                raw[(int64_t)q * 32] = (uint32_t)t;  // record word q was read by an earlier step
+                cy = (uint32_t)(t >> 32);
+                xprev = xq;
+                ylo = yhi;
+            };
+            if (c0 + C <= P + 1) {
+#pragma unroll
+                for (int u = 0; u < C; ++u) step1(c0 + u, u);
+            } else {
+#pragma unroll
+                for (int u = 0; u < C; ++u) {
+                    if (c0 + u > P) break;
+                    step1(c0 + u, u);
+                }
+            }
+        }
+    }
+
+    // ---- pass 2: normalise G to p bits, chunk by chunk into a_ij ----
+    int w0 = 0, bb = 0;
+    bool gzero = true;
+    int64_t eout = 0;
+    if (live) {
+        auto gw = [&](int x) -> uint32_t { return (x >= 0 && x <= P) ? raw[(int64_t)x * 32] : 0u; };
+        int qt = P;
+        while (qt >= 0 && gw(qt) == 0u) --qt;
+        if (qt >= 0) {
+            gzero = false;
+            const int L = 32 * qt + 32 - __clz(gw(qt));
+            const int sr = L - pbits;  // bits to drop (negative: shift left)
+            w0 = sr >= 0 ? 0 : -((-sr + 31) / 32);
+            bb = sr - 32 * w0;
+            eout = eX - gsh - pbits + L;
+        }
+        ex(A, i, j) = gzero ? 0 : eout;
+        sg(A, i, j) = gzero ? 0 : sX;
+    }
+    for (int c0 = 0; c0 < P; c0 += C) {
+        if (live) {
+#pragma unroll 8
+            for (int u = 0; u < C; ++u) {
+                const int x = c0 + u + w0;  // result limb c0+u = bits of G limbs x, x+1
+                const uint32_t lo = (!gzero && x >= 0 && x <= P) ? raw[(int64_t)x * 32] : 0u;
+                const uint32_t hi = (!gzero && x + 1 >= 0 && x + 1 <= P) ? raw[(int64_t)(x + 1) * 32] : 0u;
+                ochunk[u * FTP + e] = __builtin_amdgcn_alignbit(hi, lo, bb);
+            }
+        }
+        mpw::wsync();
+#pragma unroll
+        for (int u = 0; u < 32; ++u) {
+            const int t = u * MP_WAVE + lane;
+            const int e2 = t >> 5, r = t & 31;
+            const int q = c0 + r;
+            if (eoff[e2] >= 0 && q < P) arow[(int64_t)e2 * P + q] = ochunk[r * FTP + e2];
+        }
+        mpw::wsync();
+    }
+}
+
+__device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, uint32_t *__restrict__ T,
                                             const int32_t *info, int64_t k, int64_t n, int P, int64_t bx, MatDev D,
                                             uint32_t *rw) {
     if (*info != 0) return;
-    finish_tile_body(lds, A, T, k, n, P, bx);
+    if (finish_streams(P)) finish_stream_body(lds, A, T, k, n, P, bx);
+    else finish_tile_body(lds, A, T, k, n, P, bx);
     if (rw != nullptr && bx == 0 && k + 1 < n) {
         __syncthreads();  // the tile's stores are visible to the workgroup, its LDS is free
         int32_t *pend = (int32_t *)(rw + P + 2);
@@ -576,13 +793,16 @@ __device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, const uint3
     }
 }
 
+// Look-ahead pays while the pivot's LDS scratch does not crowd the finish
+// launch (P <= 256 or so); beyond, the pivot keeps a launch of its own.
+__host__ __device__ inline bool finish_lookahead_ok(int P) { return pivot_lds_bytes(P) <= 36u * 1024u; }
 // LDS of the finish launch: the tile, or the pivot's scratch if larger
 __host__ __device__ inline size_t finish_launch_lds(int P) {
-    const size_t a = finish_lds_bytes(P), b = pivot_lds_bytes(P);
+    const size_t a = finish_lds_bytes(P), b = finish_lookahead_ok(P) ? pivot_lds_bytes(P) : 0;
     return a > b ? a : b;
 }
 
-__global__ void __launch_bounds__(64) k_finish(MatDev A, const uint32_t *T, const int32_t *info, int64_t k,
+__global__ void __launch_bounds__(64) k_finish(MatDev A, uint32_t *T, const int32_t *info, int64_t k,
                                                int64_t n, int P, MatDev D, uint32_t *rw) {
     extern __shared__ uint32_t lds_raw[];
     finish_body(lds_raw, A, T, info, k, n, P, flat_block(), D, rw);

@@ -251,11 +251,12 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     mpk::MatDev a = dev(A), d = dev(D);
     const int32_t *cinfo = info;
     uint32_t *rw = nullptr;
+    const bool ahead = lane && mpk::finish_lookahead_ok(P);  // the finish launch examines the next pivot
     int rc0 = recip_ws(h, P, &rw);
     if (rc0 || (rc0 = pend_clear(rw, P, s))) return rc0;
     for (int64_t k = 0; k < n; ++k) {
         // with the finish kernel, step k's pivot was examined by step k-1's finish launch
-        int rc = pivot_step(h, a, d, info, rw, k, n, P, lane && k > 0, s);
+        int rc = pivot_step(h, a, d, info, rw, k, n, P, ahead && k > 0, s);
         if (rc) return rc;
         const int64_t m = n - k - 1;
         if (m <= 0) continue;
@@ -268,8 +269,8 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
             if ((rc = last_launch())) return rc;
             {
                 Prof pr(h, s, K_UPDATE_FINISH);
-                hipLaunchKernelGGL(mpk::k_finish, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a,
-                                   (const uint32_t *)w.T, cinfo, k, n, P, d, rw);
+                hipLaunchKernelGGL(mpk::k_finish, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a, w.T,
+                                   cinfo, k, n, P, d, ahead ? rw : nullptr);
             }
         } else {
             Prof pr(h, s, K_UPDATE_VALU);
@@ -292,8 +293,9 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     const int32_t *cinfo = info;
     uint32_t *rw = nullptr;
     if ((rc = recip_ws(h, P, &rw)) || (rc = pend_clear(rw, P, s))) return rc;
+    const bool ahead = mpk::finish_lookahead_ok(P);  // the finish launch examines the next pivot
     for (int64_t k = 0; k < n; ++k) {
-        if ((rc = pivot_step(h, a, d, info, rw, k, n, P, k > 0, s))) return rc;
+        if ((rc = pivot_step(h, a, d, info, rw, k, n, P, ahead && k > 0, s))) return rc;
         const int64_t m = n - k - 1;
         if (m <= 0) continue;
         {
@@ -310,8 +312,8 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
         if ((rc = last_launch())) return rc;
         {
             Prof pr(h, s, K_UPDATE_FINISH);
-            hipLaunchKernelGGL(mpk::k_finish, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a,
-                               (const uint32_t *)w.T, cinfo, k, n, P, d, rw);
+            hipLaunchKernelGGL(mpk::k_finish, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a, w.T,
+                               cinfo, k, n, P, d, ahead ? rw : nullptr);
         }
         if ((rc = last_launch())) return rc;
     }
@@ -700,7 +702,7 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
     const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
     const size_t lds_fin = mpk::finish_launch_lds(P);
     // with the finish kernel, step k's pivot is examined by step k-1's finish launch
-    const bool lookahead = use_mfma || lane_valu;
+    const bool lookahead = (use_mfma || lane_valu) && mpk::finish_lookahead_ok(P);
     hipLaunchKernelGGL(mpk::k_batch_pend, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, dmats, batch, P, 0);
     if ((rc = last_launch())) return rc;
     auto launch = [&](int kernel_id, auto kern, size_t slot, size_t shmem, int64_t arg, int threads = 64) -> int {

@@ -160,12 +160,43 @@ def test_to_f64_scaled_matches_ldexp():
 
 
 @pytest.mark.parametrize("N,P", [(3, 8), (33, 8), (40, 16), (37, 24), (66, 32), (20, 40), (70, 64),
-                                 (35, 128), (9, 256)])
+                                 (35, 128), (9, 256), (70, 264), (20, 520), (10, 1024)])
 def test_mfma_shapes(N, P):
     """MFMA path: ragged column blocks (N-k-1 not a multiple of 32), partial
     product chunks (2*P8 not a multiple of 256) and several chunk counts."""
     A = inputs.random_mantissas((N, N), P, 4000 + 13 * N + P)
     check_against_oracle(A, "mfma", f"mfma shape N={N} P={P}")
+
+
+@pytest.mark.parametrize("case", ["wide_exponents", "cancellation", "zero_entries", "zero_pivot"])
+def test_streaming_finish_cases(case):
+    """P > 256 takes the streaming finish (chunked a_ij, intermediate kept in
+    the record buffer): the sticky, cancellation, 0 - t and zero-pivot cases."""
+    P, N = 264, 22
+    if case == "wide_exponents":
+        A = inputs.random_mantissas((N, N), P, 91, emin=-30000, emax=30000)
+    elif case == "cancellation":
+        base = inputs.random_mantissas((1, N), P, 92)
+        A = inputs.random_mantissas((N, N), P, 93)
+        for i in range(N):
+            A.limbs[i] = base.limbs[0]
+            A.exp[i] = base.exp[0]
+            A.sign[i] = base.sign[0]
+            A.limbs[i, :, 0] ^= np.uint32(i + 1)
+            A.limbs[i, i, 5 + i] ^= np.uint32(1 << (i % 31))
+    elif case == "zero_entries":
+        A = inputs.random_mantissas((N, N), P, 94)
+        for i in range(N):
+            for j in range(N):
+                if i != j and (i * 7 + j * 3) % 5 == 0:
+                    A.limbs[i, j] = 0
+                    A.exp[i, j] = 0
+                    A.sign[i, j] = 0
+    else:
+        A, L, U = inputs.triangular_product(12, P, 8)
+        U[6, 6] = 0
+        A = inputs.from_values((L.astype(object) @ U.astype(object)), P)
+    check_against_oracle(A, "mfma", f"streaming finish {case}")
 
 
 def test_mfma_digit_carry_extremes():
