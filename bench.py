@@ -312,7 +312,7 @@ def main():
         else:
             achieved = upd * FINISH_BYTES(P) / secs
             r = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                 "frac": achieved / PEAK_HBM, "kernel": kname_of("k_finish")}
+                 "frac": achieved / PEAK_HBM, "kernel": kname_of("k_finish") + ("<true>" if P > 256 else "<false>")}
         r.update({"traffic": measured_traffic(r["kernel"]), "avg_launch_ms": kms / kn, "launches": kn})
         return r
 

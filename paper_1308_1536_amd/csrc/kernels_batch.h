@@ -71,7 +71,7 @@ __global__ void __launch_bounds__(64) k_batch_prep(const BatchMat *mats, const i
     mfma_prep_body(lds_raw, M.A, M.Lr, M.Ub, M.info, k, M.n, P, loc);
 }
 
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) k_batch_update_mfma(const BatchMat *mats, const int32_t *order,
+__global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_per_eu(2, 2))) k_batch_update_mfma(const BatchMat *mats, const int32_t *order,
                                                           const int64_t *off, int cnt, int64_t k, int P) {
     MPK_BATCH_PROLOGUE
     // every matrix's block count is a multiple of 8, so loc and bx agree mod 8
@@ -79,11 +79,12 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2)))
     update_mfma_body(lds_raw, M.A, M.Lr, M.Ub, M.T, M.info, k, M.n, P, loc, true);
 }
 
+template <bool STREAM>
 __global__ void __launch_bounds__(64) k_batch_finish(const BatchMat *mats, const int32_t *order,
                                                      const int64_t *off, int cnt, int64_t k, int P) {
     MPK_BATCH_PROLOGUE
     // the look-ahead pivot runs only where the host launches no pivot phase
-    finish_body(lds_raw, M.A, M.T, M.info, k, M.n, P, loc, M.D, finish_lookahead_ok(P) ? M.rw : nullptr);
+    finish_body<STREAM>(lds_raw, M.A, M.T, M.info, k, M.n, P, loc, M.D, finish_lookahead_ok(P) ? M.rw : nullptr);
 }
 
 // minors sweep number s: matrix of size n processes j = n - 1 - s (blocks i < j)

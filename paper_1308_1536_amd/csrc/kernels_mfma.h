@@ -60,16 +60,30 @@ __host__ __device__ inline MfmaGeom mfma_geom(int P) {
 
 __host__ __device__ inline bool mfma_supported(int P) { return P >= 8 && P % 8 == 0; }
 
+// Pivot-row digits in fragment-major order: digit c of column j' = 32 jb + j
+// is byte c % 16 of the 16-byte fragment at ((jb NF + c / 16) 32 + j) 16,
+// NF = K8 / 16, so the B fragments of one K-step of a 32-column block (lane
+// (j, h) takes digits c0 + 16h .. c0 + 16h + 15) are one contiguous 1 KB run.
+// Sized for whole 32-column blocks.
+__host__ __device__ inline size_t ub_bytes(int64_t m, int P) {
+    return (size_t)((m + 31) / 32) * 32u * (size_t)mfma_geom(P).K8;
+}
+
 constexpr int64_t kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
+
+// Waves per workgroup of k_update_mfma: the waves take consecutive rows i of
+// the same 32-column block, so the pivot-row digit fragments they stream are
+// the same cache lines and are fetched into the CU's L1 once for all of them.
+constexpr int kMfmaWaves = 4;
 
 // workgroups of k_update_mfma for an m x m trailing block
 __host__ __device__ inline int64_t mfma_update_blocks(int64_t m) {
-    const int64_t njb = (m + 31) / 32;
-    return njb >= kXcds ? kXcds * m * ((njb + kXcds - 1) / kXcds) : m * njb;
+    const int64_t njb = (m + 31) / 32, nrg = (m + kMfmaWaves - 1) / kMfmaWaves;
+    return njb >= kXcds ? kXcds * nrg * ((njb + kXcds - 1) / kXcds) : nrg * njb;
 }
 
-// LDS for k_update_mfma: the reversed digit row
-__host__ __device__ inline size_t mfma_lds_bytes(int P) { return (size_t)mfma_geom(P).LR; }
+// LDS for k_update_mfma: one reversed digit row per wave
+__host__ __device__ inline size_t mfma_lds_bytes(int P) { return (size_t)mfma_geom(P).LR * kMfmaWaves; }
 
 // bit k of v -> bit 2k
 __device__ __forceinline__ uint64_t spread_bits(uint32_t v) {
@@ -141,18 +155,40 @@ __device__ __forceinline__ void mfma_prep_body(uint32_t *lds_raw, MatDev A, uint
             out[w] = v;
         }
     } else {
-        uint32_t *out = (uint32_t *)(Ub + (b - m) * (int64_t)g.K8);
-        for (int w = mpw::lane(); w < g.K8 / 4; w += MP_WAVE) out[w] = w <= P ? dw[w] : 0u;
+        const int64_t jp = b - m;
+        const int NF = g.K8 / 16;
+        uint8_t *col = Ub + ((jp / 32) * NF * 32 + jp % 32) * 16;
+        // word w holds digits 4w .. 4w+3: fragment w / 4, bytes 4 (w % 4) on
+        for (int w = mpw::lane(); w < g.K8 / 4; w += MP_WAVE)
+            *(uint32_t *)(col + (int64_t)(w >> 2) * 512 + (w & 3) * 4) = w <= P ? dw[w] : 0u;
     }
 }
 
 // A fragment of the Toeplitz block with diagonal offset d = r0 - c0: lane
 // (r = lane % 32, h = lane / 32) holds T[r0 + r][c0 + 16h + b], b = 0..15
-// (zero outside the band, from the padding; -256 <= d <= P8 + 255).
-__device__ __forceinline__ v4i load_a(const uint8_t *lr, int d, int Q) {
-    v4i v;
+// (zero outside the band, from the padding; -256 <= d <= P8 + 255), i.e. the
+// 16 bytes of the reversed row from byte Q - d - r + 16h on.  That start moves
+// by one byte from lane to lane, and a 16-byte LDS read at a byte offset
+// stalls the LDS pipeline, so a lane reads the five aligned words covering its
+// bytes (load_a_raw) and shifts them into place (align_a, v_alignbyte_b32)
+// once they have arrived.
+struct ARaw {
+    uint32_t w[5];
+};
+__device__ __forceinline__ ARaw load_a_raw(const uint8_t *lr, int d, int Q) {
     const int r = mpw::lane() & 31, h = mpw::lane() >> 5;
-    __builtin_memcpy(&v, lr + (Q - d - r + 16 * h), 16);
+    const int s = Q - d - r + 16 * h;
+    const uint32_t *p = (const uint32_t *)(lr + (s & ~3));
+    ARaw a;
+#pragma unroll
+    for (int t = 0; t < 5; ++t) a.w[t] = p[t];
+    return a;
+}
+// sh = start byte mod 4: the same for every d (d is a multiple of 4)
+__device__ __forceinline__ v4i align_a(const ARaw &a, uint32_t sh) {
+    v4i v;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) v[t] = (int)__builtin_amdgcn_alignbyte(a.w[t + 1], a.w[t], sh);
     return v;
 }
 
@@ -165,40 +201,48 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
     if (*info != 0) return;
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
-    const int64_t njb = (m + 31) / 32;
-    int64_t ip, jb;
+    const int64_t njb = (m + 31) / 32, nrg = (m + kMfmaWaves - 1) / kMfmaWaves;
+    int64_t rg, jb;
     if (xcd_aware && njb >= kXcds) {
         // workgroups go to the 8 XCDs round-robin: XCD x takes the column
         // blocks jb = x (mod 8), so each XCD's L2 holds only its share of the
         // pivot-row digits
         const int64_t xcd = bx % kXcds, loc = bx / kXcds;
         const int64_t cnt = (njb - xcd + kXcds - 1) / kXcds;
-        if (loc >= m * cnt) return;
-        ip = loc / cnt;
+        if (loc >= nrg * cnt) return;
+        rg = loc / cnt;
         jb = xcd + kXcds * (loc % cnt);
     } else {
-        if (bx >= m * njb) return;
-        ip = bx / njb;
+        if (bx >= nrg * njb) return;
+        rg = bx / njb;
         jb = bx % njb;
     }
-    if (el(A, k + 1 + ip, k, P)[P - 1] == 0u) return;
-
-    uint8_t *lr = (uint8_t *)lds_raw;
-    {
+    // wave w of the workgroup takes row i' = kMfmaWaves rg + w and copies its
+    // reversed digit row into its own part of LDS; after the one barrier, which
+    // every wave reaches, a wave without a row (or with a zero multiplier) leaves
+    const int wave = (int)(threadIdx.x >> 6);
+    const int64_t ip = rg * kMfmaWaves + wave;
+    const bool active = ip < m && el(A, k + 1 + (ip < m ? ip : 0), k, P)[P - 1] != 0u;
+    uint8_t *lr = (uint8_t *)lds_raw + (size_t)wave * g.LR;
+    if (active) {
         const uint4 *src = (const uint4 *)(Lr + ip * (int64_t)g.LR);
         uint4 *dst = (uint4 *)lr;
         for (int w = mpw::lane(); w < g.LR / 16; w += MP_WAVE) dst[w] = src[w];
     }
-    mpw::wsync();
+    __syncthreads();
+    if (!active) return;
 
     const int lane = mpw::lane();
     const int j = lane & 31, h = lane >> 5;
     const int64_t jp = jb * 32 + j;
     const bool jvalid = jp < m;
-    const uint8_t *ub = Ub + (jvalid ? jp : 0) * (int64_t)g.K8 + 16 * h;
+    // this lane's B fragment of the K-step at c0 is at ub + 32 c0 (a column
+    // past m reads its block's unused, allocated slot; its results are dropped)
+    const uint8_t *ub = Ub + ((jb * (g.K8 / 16) + h) * 32 + j) * 16;
     uint32_t *tcol = T + (ip * njb + jb) * (int64_t)g.TP * 32 + j;
     const int P8 = g.P8, Q = g.Q;
-    const int bmax = g.K8 - 32;  // last 16-byte offset of a lane (ub includes 16h)
+    const int bmax = g.K8 - 32;  // last K-step offset c0 inside the digit strings
+    const uint32_t ash = (uint32_t)(Q - j + 16 * h) & 3u;  // byte shift of this lane's A fragments
     uint32_t hi_in = 0, c_in = 0;  // carry from the chunk below
 
     for (int chunk = 0; chunk < g.nchunks; ++chunk) {
@@ -218,25 +262,28 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
         // outside the band is zero.
         v4i W[8], BR[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) W[t] = load_a(lr, r0 + 32 * t - c_lo, Q);
+        for (int t = 0; t < 8; ++t) W[t] = align_a(load_a_raw(lr, r0 + 32 * t - c_lo, Q), ash);
         // B loads are unconditional: offsets are clamped into the column's
         // digit string, and a fragment fetched for a step >= nsteps is never used
 #pragma unroll
-        for (int u = 0; u < 8; ++u) BR[u] = *(const v4i *)(ub + min(c_lo + 32 * u, bmax));
-        // one K-step: tile 7's MFMA frees its window slot, which is refilled
-        // at once with the next step's tile-0 fragment (its LDS latency hides
-        // behind tiles 0..6); the slot's next B fragment is fetched after the
-        // step's MFMAs, so the ring keeps its registers and 7 loads stay in
-        // flight
+        for (int u = 0; u < 8; ++u) BR[u] = *(const v4i *)(ub + 32 * min(c_lo + 32 * u, bmax));
+        // one K-step: tile 7's MFMA frees its window slot; the words of the
+        // next step's tile-0 fragment are read at once and shifted into the
+        // slot after tiles 0..6 (their LDS latency hides behind those MFMAs);
+        // the slot's next B fragment is fetched after the step's MFMAs, so the
+        // ring keeps its registers and 7 loads stay in flight
         auto kstep = [&](int n, int u) __attribute__((always_inline)) {
             const int c0 = c_lo + 32 * n;
             acc[7] = __builtin_amdgcn_mfma_i32_32x32x32_i8(W[(7 - u) & 7], BR[u], acc[7], 0, 0, 0);
-            W[(7 - u) & 7] = load_a(lr, r0 - c0 - 32, Q);
+            const ARaw nxt = load_a_raw(lr, r0 - c0 - 32, Q);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int t = 0; t < 7; ++t)
                 acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(W[(t - u) & 7], BR[u], acc[t], 0, 0, 0);
-            BR[u] = *(const v4i *)(ub + min(c0 + 256, bmax));
+            // the shifts stay behind the 7 MFMAs: moved up, they would wait on the LDS
+            __builtin_amdgcn_sched_barrier(0);
+            W[(7 - u) & 7] = align_a(nxt, ash);
+            BR[u] = *(const v4i *)(ub + 32 * min(c0 + 256, bmax));
             // keep each step's loads in their step: the scheduler would
             // otherwise sink a block's 8 loads to its end
             __builtin_amdgcn_sched_barrier(0);
@@ -558,7 +605,7 @@ __global__ void __launch_bounds__(64) k_mfma_prep(MatDev A, uint8_t *Lr, uint8_t
     mfma_prep_body(lds_raw, A, Lr, Ub, info, k, n, P, flat_block());
 }
 
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2, 2))) k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T,
+__global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_per_eu(2, 2))) k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T,
                                                     const int32_t *info, int64_t k, int64_t n, int P) {
     extern __shared__ uint32_t lds_raw[];
     update_mfma_body(lds_raw, A, Lr, Ub, T, info, k, n, P, flat_block(), true);
@@ -778,11 +825,14 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
     }
 }
 
+// STREAM must equal finish_streams(P); the two forms are separate kernels so
+// that each gets its own register allocation.
+template <bool STREAM>
 __device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, uint32_t *__restrict__ T,
                                             const int32_t *info, int64_t k, int64_t n, int P, int64_t bx, MatDev D,
                                             uint32_t *rw) {
     if (*info != 0) return;
-    if (finish_streams(P)) finish_stream_body(lds, A, T, k, n, P, bx);
+    if constexpr (STREAM) finish_stream_body(lds, A, T, k, n, P, bx);
     else finish_tile_body(lds, A, T, k, n, P, bx);
     if (rw != nullptr && bx == 0 && k + 1 < n) {
         __syncthreads();  // the tile's stores are visible to the workgroup, its LDS is free
@@ -802,10 +852,11 @@ __host__ __device__ inline size_t finish_launch_lds(int P) {
     return a > b ? a : b;
 }
 
+template <bool STREAM>
 __global__ void __launch_bounds__(64) k_finish(MatDev A, uint32_t *T, const int32_t *info, int64_t k,
                                                int64_t n, int P, MatDev D, uint32_t *rw) {
     extern __shared__ uint32_t lds_raw[];
-    finish_body(lds_raw, A, T, info, k, n, P, flat_block(), D, rw);
+    finish_body<STREAM>(lds_raw, A, T, info, k, n, P, flat_block(), D, rw);
 }
 
 }  // namespace mpk

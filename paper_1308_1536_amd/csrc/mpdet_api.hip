@@ -213,7 +213,7 @@ size_t mfma_rec_bytes(int64_t m, int P) {
 int mfma_workspace(mpdet_handle *h, int64_t m, int P, MfmaWs *w) {
     const mpk::MfmaGeom g = mpk::mfma_geom(P);
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t lr = up((size_t)m * g.LR), ub = up((size_t)m * g.K8);
+    const size_t lr = up((size_t)m * g.LR), ub = up(mpk::ub_bytes(m, P));
     const size_t t = up(mfma_rec_bytes(m, P));
     const size_t need = lr + ub + t;
     if (need > h->ws_bytes) {
@@ -248,6 +248,7 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
         if (rc) return rc;
     }
     const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_launch_lds(P);
+    auto fin_kernel = mpk::finish_streams(P) ? mpk::k_finish<true> : mpk::k_finish<false>;
     mpk::MatDev a = dev(A), d = dev(D);
     const int32_t *cinfo = info;
     uint32_t *rw = nullptr;
@@ -269,7 +270,7 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
             if ((rc = last_launch())) return rc;
             {
                 Prof pr(h, s, K_UPDATE_FINISH);
-                hipLaunchKernelGGL(mpk::k_finish, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a, w.T,
+                hipLaunchKernelGGL(fin_kernel, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a, w.T,
                                    cinfo, k, n, P, d, ahead ? rw : nullptr);
             }
         } else {
@@ -289,6 +290,7 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     if (rc) return rc;
     const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
     const size_t lds_fin = mpk::finish_launch_lds(P);
+    auto fin_kernel = mpk::finish_streams(P) ? mpk::k_finish<true> : mpk::k_finish<false>;
     mpk::MatDev a = dev(A), d = dev(D);
     const int32_t *cinfo = info;
     uint32_t *rw = nullptr;
@@ -306,13 +308,14 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
         if ((rc = last_launch())) return rc;
         {
             Prof pr(h, s, K_UPDATE_MFMA);
-            hipLaunchKernelGGL(mpk::k_update_mfma, grid_for(mpk::mfma_update_blocks(m)), dim3(64), lds_mfma, s, a,
+            hipLaunchKernelGGL(mpk::k_update_mfma, grid_for(mpk::mfma_update_blocks(m)), dim3(64 * mpk::kMfmaWaves),
+                               lds_mfma, s, a,
                                (const uint8_t *)w.Lr, (const uint8_t *)w.Ub, w.T, cinfo, k, n, P);
         }
         if ((rc = last_launch())) return rc;
         {
             Prof pr(h, s, K_UPDATE_FINISH);
-            hipLaunchKernelGGL(mpk::k_finish, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a, w.T,
+            hipLaunchKernelGGL(fin_kernel, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a, w.T,
                                cinfo, k, n, P, d, ahead ? rw : nullptr);
         }
         if ((rc = last_launch())) return rc;
@@ -630,7 +633,7 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
         const int64_t n = A_arr[b].rows, m = n > 1 ? n - 1 : 1;
         size_t need = up((size_t)(P + 3) * 4u);
         if (use_mfma)
-            need += up((size_t)m * geo.LR) + up((size_t)m * geo.K8) + up(mfma_rec_bytes(m, P));
+            need += up((size_t)m * geo.LR) + up(mpk::ub_bytes(m, P)) + up(mfma_rec_bytes(m, P));
         else if (lane_valu)
             need += up(mfma_rec_bytes(m, P));
         scratch[(size_t)b] = need;
@@ -679,7 +682,7 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
             M.Lr = q;
             q += up((size_t)m * geo.LR);
             M.Ub = q;
-            q += up((size_t)m * geo.K8);
+            q += up(mpk::ub_bytes(m, P));
             M.T = (uint32_t *)q;
         } else if (lane_valu) {
             M.T = (uint32_t *)q;
@@ -701,6 +704,7 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
     const size_t lds_piv = mpk::pivot_lds_bytes(P), lds = mpk::lds_bytes(P);
     const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
     const size_t lds_fin = mpk::finish_launch_lds(P);
+    auto bfin_kernel = mpk::finish_streams(P) ? mpk::k_batch_finish<true> : mpk::k_batch_finish<false>;
     // with the finish kernel, step k's pivot is examined by step k-1's finish launch
     const bool lookahead = (use_mfma || lane_valu) && mpk::finish_lookahead_ok(P);
     hipLaunchKernelGGL(mpk::k_batch_pend, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, dmats, batch, P, 0);
@@ -722,14 +726,16 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
         if ((rc = launch(K_DIVIDE, mpk::k_batch_divide, base + BP_DIVIDE, lds_piv, k))) return rc;
         if (use_mfma) {
             if ((rc = launch(K_MFMA_PREP, mpk::k_batch_prep, base + BP_PREP, lds_prep, k))) return rc;
-            if ((rc = launch(K_UPDATE_MFMA, mpk::k_batch_update_mfma, base + BP_UPD, lds_mfma, k))) return rc;
-            if ((rc = launch(K_UPDATE_FINISH, mpk::k_batch_finish, base + BP_SUB, lds_fin, k))) return rc;
+            if ((rc = launch(K_UPDATE_MFMA, mpk::k_batch_update_mfma, base + BP_UPD, lds_mfma, k,
+                             64 * mpk::kMfmaWaves)))
+                return rc;
+            if ((rc = launch(K_UPDATE_FINISH, bfin_kernel, base + BP_SUB, lds_fin, k))) return rc;
         } else {
             if (lane_valu) {
                 if ((rc = launch(K_UPDATE_VALU, mpk::k_batch_prod_lane, base + BP_UPD, mpk::lane_lds_bytes(P), k,
                                  64 * mpk::kLaneRows)))
                     return rc;
-                if ((rc = launch(K_UPDATE_FINISH, mpk::k_batch_finish, base + BP_SUB, lds_fin, k))) return rc;
+                if ((rc = launch(K_UPDATE_FINISH, bfin_kernel, base + BP_SUB, lds_fin, k))) return rc;
             } else if ((rc = launch(K_UPDATE_VALU, mpk::k_batch_update_valu, base + BP_UPD, lds, k))) {
                 return rc;
             }
