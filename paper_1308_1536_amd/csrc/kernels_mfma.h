@@ -58,7 +58,7 @@ __host__ __device__ inline MfmaGeom mfma_geom(int P) {
     return g;
 }
 
-__host__ __device__ inline bool mfma_supported(int P) { return P >= 8 && P % 8 == 0; }
+__host__ __device__ inline bool mfma_shape_ok(int P) { return P >= 8 && P % 8 == 0; }
 
 // Pivot-row digits in fragment-major order: digit c of column j' = 32 jb + j
 // is byte c % 16 of the 16-byte fragment at ((jb NF + c / 16) 32 + j) 16,
@@ -70,11 +70,15 @@ __host__ __device__ inline size_t ub_bytes(int64_t m, int P) {
 }
 
 constexpr int64_t kXcds = 8;  // MI355X: 8 accelerator complex dies, one L2 each
+// word 3 of a raw (untyped, unswizzled) buffer resource on gfx9-class GPUs
+constexpr int kBufferRsrcWord3 = 0x00020000;
 
 // Waves per workgroup of k_update_mfma: the waves take consecutive rows i of
 // the same 32-column block, so the pivot-row digit fragments they stream are
 // the same cache lines and are fetched into the CU's L1 once for all of them.
-constexpr int kMfmaWaves = 4;
+constexpr int kMfmaWaves = 2;
+// LDS one workgroup of k_update_mfma may take
+constexpr size_t kMfmaLdsMax = 64 * 1024;
 
 // workgroups of k_update_mfma for an m x m trailing block
 __host__ __device__ inline int64_t mfma_update_blocks(int64_t m) {
@@ -82,8 +86,6 @@ __host__ __device__ inline int64_t mfma_update_blocks(int64_t m) {
     return njb >= kXcds ? kXcds * nrg * ((njb + kXcds - 1) / kXcds) : nrg * njb;
 }
 
-// LDS for k_update_mfma: one reversed digit row per wave
-__host__ __device__ inline size_t mfma_lds_bytes(int P) { return (size_t)mfma_geom(P).LR * kMfmaWaves; }
 
 // bit k of v -> bit 2k
 __device__ __forceinline__ uint64_t spread_bits(uint32_t v) {
@@ -164,40 +166,87 @@ __device__ __forceinline__ void mfma_prep_body(uint32_t *lds_raw, MatDev A, uint
     }
 }
 
-// A fragment of the Toeplitz block with diagonal offset d = r0 - c0: lane
-// (r = lane % 32, h = lane / 32) holds T[r0 + r][c0 + 16h + b], b = 0..15
-// (zero outside the band, from the padding; -256 <= d <= P8 + 255), i.e. the
-// 16 bytes of the reversed row from byte Q - d - r + 16h on.  That start moves
-// by one byte from lane to lane, and a 16-byte LDS read at a byte offset
-// stalls the LDS pipeline, so a lane reads the five aligned words covering its
-// bytes (load_a_raw) and shifts them into place (align_a, v_alignbyte_b32)
-// once they have arrived.
-struct ARaw {
-    uint32_t w[5];
-};
-__device__ __forceinline__ ARaw load_a_raw(const uint8_t *lr, int d, int Q) {
-    const int r = mpw::lane() & 31, h = mpw::lane() >> 5;
-    const int s = Q - d - r + 16 * h;
-    const uint32_t *p = (const uint32_t *)(lr + (s & ~3));
-    ARaw a;
-#pragma unroll
-    for (int t = 0; t < 5; ++t) a.w[t] = p[t];
-    return a;
-}
-// sh = start byte mod 4: the same for every d (d is a multiple of 4)
-__device__ __forceinline__ v4i align_a(const ARaw &a, uint32_t sh) {
+// Row order inside a 32-row output tile.  The MFMA's C fragment gives lane
+// (j, h) the rows 8gq + 4h + b (gq, b = 0..3) of column j; the tile's A rows
+// are permuted so that row 8gq + 4h + b is byte position 16h + 4gq + b of the
+// tile, and a lane then holds four whole consecutive limbs (4h + gq) of each
+// tile.  A row r of the A fragment is byte position tile_pos(r).
+__device__ __forceinline__ int tile_pos(int r) { return 16 * ((r >> 2) & 1) + 4 * (r >> 3) + (r & 3); }
+
+// LDS of one wave: NC copies of its reversed digit row, copy a shifted down by
+// a bytes (copy_a[x] = Lr[x + a]).  A fragment (16 consecutive bytes of the
+// row, starting at a lane-dependent byte) is read as four aligned words from
+// the copy whose shift cancels the start's misalignment; with NC = 1 the lane
+// reads the five words around its bytes and shifts them into place
+// (v_alignbyte_b32).  Byte-misaligned 16-byte LDS reads stall the LDS pipeline.
+// p: the aligned word at or below the fragment's first byte, in the copy the
+// lane reads (a_word below)
+template <int NC>
+__device__ __forceinline__ v4i load_a(const uint32_t *p, uint32_t sh) {
     v4i v;
+    if constexpr (NC == 4) {
 #pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = (int)__builtin_amdgcn_alignbyte(a.w[t + 1], a.w[t], sh);
+        for (int t = 0; t < 4; ++t) v[t] = (int)p[t];
+    } else {
+        uint32_t w[5];
+#pragma unroll
+        for (int t = 0; t < 5; ++t) w[t] = p[t];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = (int)__builtin_amdgcn_alignbyte(w[t + 1], w[t], sh);
+    }
     return v;
+}
+// the aligned word of byte s - sh (s = first byte of a fragment, sh = s mod 4)
+template <int NC>
+__device__ __forceinline__ const uint32_t *a_word(const uint8_t *lr, int LR, int s, uint32_t sh) {
+    return (const uint32_t *)(lr + (NC == 4 ? (int)sh * LR : 0) + (s - (int)sh));
+}
+
+// LDS copies of the digit row that fit a workgroup (0: the MFMA update does not fit)
+__host__ __device__ inline int mfma_copies(int P) {
+    const size_t lr = (size_t)mfma_geom(P).LR * kMfmaWaves;
+    return 4 * lr <= kMfmaLdsMax ? 4 : (lr <= kMfmaLdsMax ? 1 : 0);
+}
+__host__ __device__ inline size_t mfma_lds_bytes(int P) {
+    return (size_t)mfma_geom(P).LR * kMfmaWaves * (size_t)mfma_copies(P);
+}
+__host__ __device__ inline bool mfma_supported(int P) { return mfma_shape_ok(P) && mfma_copies(P) > 0; }
+
+// Exchange word of a tile between the lanes of a column: bits 0..23 the
+// signed high part of the tile's top limb sum, bits 24..25 the signed carry
+// out of that limb's low word.
+__device__ __forceinline__ uint32_t xw_pack(int32_t hi, int32_t c) {
+    return ((uint32_t)hi & 0xFFFFFFu) | (((uint32_t)c & 3u) << 24);
+}
+__device__ __forceinline__ int32_t xw_hi(uint32_t w) { return (int32_t)(w << 8) >> 8; }
+__device__ __forceinline__ int32_t xw_c(uint32_t w) { return (int32_t)(w << 6) >> 30; }
+
+// sum_b s_b 256^b over the four signed byte-column sums of one limb, exactly
+// (three v_mad_i64_i32 onto the sign-extended s_0)
+__device__ __forceinline__ int64_t limb_sum(int32_t s0, int32_t s1, int32_t s2, int32_t s3) {
+    int64_t v = (int64_t)s0;
+    uint64_t cc;
+    asm volatile("v_mad_i64_i32 %0, %1, %2, %3, %0" : "+v"(v), "=s"(cc) : "v"(s1), "s"(256));
+    asm volatile("v_mad_i64_i32 %0, %1, %2, %3, %0" : "+v"(v), "=s"(cc) : "v"(s2), "s"(65536));
+    asm volatile("v_mad_i64_i32 %0, %1, %2, %3, %0" : "+v"(v), "=s"(cc) : "v"(s3), "s"(16777216));
+    return v;
+}
+
+// value of the partner lane (lane ^ 32): h = 1 lanes receive b of lane j,
+// h = 0 lanes receive a of lane j + 32 (v_permlane32_swap_b32)
+__device__ __forceinline__ uint32_t partner_of(uint32_t a, uint32_t b, int h) {
+    const auto r = __builtin_amdgcn_permlane32_swap(a, b, false, false);
+    return h ? r[0] : r[1];
 }
 
 // Product top limbs: for every row i' (multiplier l = a_{k+1+i', k}) and
 // column block jb of 32, word x <= P of the record of column j' = 32 jb + j is
 // limb P-1+x of l * u_{j'}, stored limb-major across the block's 32 columns:
 // T[((i' njb + jb) TP + x) 32 + j].
-__device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T,
-                                 const int32_t *info, int64_t k, int64_t n, int P, int64_t bx, bool xcd_aware) {
+template <int NC>
+__device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, const uint8_t *Lr, const uint8_t *Ub,
+                                                 uint32_t *T, const int32_t *info, int64_t k, int64_t n, int P,
+                                                 int64_t bx, bool xcd_aware) {
     if (*info != 0) return;
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
@@ -217,17 +266,22 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
         rg = bx / njb;
         jb = bx % njb;
     }
-    // wave w of the workgroup takes row i' = kMfmaWaves rg + w and copies its
-    // reversed digit row into its own part of LDS; after the one barrier, which
-    // every wave reaches, a wave without a row (or with a zero multiplier) leaves
+    // wave w of the workgroup takes row i' = kMfmaWaves rg + w and fills its
+    // own part of LDS; after the one barrier, which every wave reaches, a wave
+    // without a row (or with a zero multiplier) leaves
     const int wave = (int)(threadIdx.x >> 6);
     const int64_t ip = rg * kMfmaWaves + wave;
     const bool active = ip < m && el(A, k + 1 + (ip < m ? ip : 0), k, P)[P - 1] != 0u;
-    uint8_t *lr = (uint8_t *)lds_raw + (size_t)wave * g.LR;
+    const int LR = g.LR;
+    uint8_t *lr = (uint8_t *)lds_raw + (size_t)wave * NC * LR;
     if (active) {
-        const uint4 *src = (const uint4 *)(Lr + ip * (int64_t)g.LR);
-        uint4 *dst = (uint4 *)lr;
-        for (int w = mpw::lane(); w < g.LR / 16; w += MP_WAVE) dst[w] = src[w];
+        const uint32_t *src = (const uint32_t *)(Lr + ip * (int64_t)LR);
+        const int nw = LR / 4;
+        for (int w = mpw::lane(); w < nw; w += MP_WAVE) {
+            const uint32_t x0 = src[w], x1 = w + 1 < nw ? src[w + 1] : 0u;
+#pragma unroll
+            for (int a = 0; a < NC; ++a) ((uint32_t *)(lr + a * LR))[w] = __builtin_amdgcn_alignbyte(x1, x0, a);
+        }
     }
     __syncthreads();
     if (!active) return;
@@ -236,14 +290,27 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
     const int j = lane & 31, h = lane >> 5;
     const int64_t jp = jb * 32 + j;
     const bool jvalid = jp < m;
-    // this lane's B fragment of the K-step at c0 is at ub + 32 c0 (a column
-    // past m reads its block's unused, allocated slot; its results are dropped)
-    const uint8_t *ub = Ub + ((jb * (g.K8 / 16) + h) * 32 + j) * 16;
+    // this lane's B fragment of the K-step at c0 is at ubs + 32 c0 + boff (a
+    // column past m reads its block's unused, allocated slot; its results are
+    // dropped); ubs is the same for the whole wave
+    // (read through a buffer resource: per-lane offset in a VGPR, the step's
+    // offset in an SGPR, no 64-bit address arithmetic per step)
+    const uint8_t *ubs = Ub + jb * (int64_t)(g.K8 / 16) * 512;
+    const uint32_t boff = (uint32_t)(h * 32 + j) * 16u;
+    const __amdgpu_buffer_rsrc_t brs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)ubs, (short)0, 32 * g.K8, kBufferRsrcWord3);
+    auto load_b = [&](int c0) __attribute__((always_inline)) {
+        return __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(brs, boff, 32 * c0, 0));
+    };
     uint32_t *tcol = T + (ip * njb + jb) * (int64_t)g.TP * 32 + j;
-    const int P8 = g.P8, Q = g.Q;
+    const int P8 = g.P8;
     const int bmax = g.K8 - 32;  // last K-step offset c0 inside the digit strings
-    const uint32_t ash = (uint32_t)(Q - j + 16 * h) & 3u;  // byte shift of this lane's A fragments
-    uint32_t hi_in = 0, c_in = 0;  // carry from the chunk below
+    // A fragment of diagonal offset d = r0 - c0 for this lane (row r = j of the
+    // A operand, K half h): the 16 bytes of the reversed row from byte
+    // sa - d on, sa = Q - tile_pos(j) + 16h; ash = the start's byte offset mod 4
+    const int sa = g.Q - tile_pos(j) + 16 * h;
+    const uint32_t ash = (uint32_t)sa & 3u;
+    uint32_t xw_prev = 0;  // exchange word of tile 7 of the chunk below (carry into this chunk)
 
     for (int chunk = 0; chunk < g.nchunks; ++chunk) {
         const int r0 = chunk * 256;
@@ -262,28 +329,28 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
         // outside the band is zero.
         v4i W[8], BR[8];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) W[t] = align_a(load_a_raw(lr, r0 + 32 * t - c_lo, Q), ash);
+        for (int t = 0; t < 8; ++t) W[t] = load_a<NC>(a_word<NC>(lr, LR, sa - (r0 + 32 * t - c_lo), ash), ash);
         // B loads are unconditional: offsets are clamped into the column's
         // digit string, and a fragment fetched for a step >= nsteps is never used
 #pragma unroll
-        for (int u = 0; u < 8; ++u) BR[u] = *(const v4i *)(ub + 32 * min(c_lo + 32 * u, bmax));
-        // one K-step: tile 7's MFMA frees its window slot; the words of the
-        // next step's tile-0 fragment are read at once and shifted into the
-        // slot after tiles 0..6 (their LDS latency hides behind those MFMAs);
-        // the slot's next B fragment is fetched after the step's MFMAs, so the
-        // ring keeps its registers and 7 loads stay in flight
-        auto kstep = [&](int n, int u) __attribute__((always_inline)) {
+        for (int u = 0; u < 8; ++u) BR[u] = load_b(min(c_lo + 32 * u, bmax));
+        // word of the tile-0 fragment of step 1 (the first one the loop reads);
+        // step n's is 8 (n - 1) words further on
+        const uint32_t *a1 = a_word<NC>(lr, LR, sa - (r0 - c_lo - 32), ash);
+        // one K-step: tile 7's MFMA frees its window slot, which is refilled at
+        // once with the next step's tile-0 fragment (its LDS latency hides
+        // behind tiles 0..6); the slot's next B fragment is fetched after the
+        // step's MFMAs, so the ring keeps its registers and 7 loads stay in
+        // flight
+        auto kstep = [&](const uint32_t *ablk, int n, int u) __attribute__((always_inline)) {
             const int c0 = c_lo + 32 * n;
             acc[7] = __builtin_amdgcn_mfma_i32_32x32x32_i8(W[(7 - u) & 7], BR[u], acc[7], 0, 0, 0);
-            const ARaw nxt = load_a_raw(lr, r0 - c0 - 32, Q);
+            W[(7 - u) & 7] = load_a<NC>(ablk + 8 * u, ash);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int t = 0; t < 7; ++t)
                 acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(W[(t - u) & 7], BR[u], acc[t], 0, 0, 0);
-            // the shifts stay behind the 7 MFMAs: moved up, they would wait on the LDS
-            __builtin_amdgcn_sched_barrier(0);
-            W[(7 - u) & 7] = align_a(nxt, ash);
-            BR[u] = *(const v4i *)(ub + 32 * min(c0 + 256, bmax));
+            BR[u] = load_b(min(c0 + 256, bmax));
             // keep each step's loads in their step: the scheduler would
             // otherwise sink a block's 8 loads to its end
             __builtin_amdgcn_sched_barrier(0);
@@ -292,67 +359,123 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
         // edge is the same on every path), then the partial block
         int n8 = 0;
         for (; n8 + 8 <= nsteps; n8 += 8) {
+            const uint32_t *ablk = a1 + 8 * n8;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) kstep(n8 + u, u);
+            for (int u = 0; u < 8; ++u) kstep(ablk, n8 + u, u);
         }
+        {
+            const uint32_t *ablk = a1 + 8 * n8;
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (n8 + u >= nsteps) break;
-            kstep(n8 + u, u);
-        }
-        // Epilogue, in registers.  Lane (j, h) holds, for tile t and group gq,
-        // the 4 byte positions r = r0 + 32t + 8gq + 4h + {0..3} of column j,
-        // i.e. limb q = r0/4 + 2u + h with u = 4t + gq: its biased column sum
-        // is V = lo + hi 2^32, hi < 2^21.  Limb q's value is lo_q + hi_{q-1}
-        // plus a one-bit carry; the carries of the chunk's 64 limbs come from
-        // one 64-bit carry-lookahead, with the limbs of both parities
-        // exchanged between lanes j and j + 32.
-        uint32_t lo[32], hi[32];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-#pragma unroll
-            for (int gq = 0; gq < 4; ++gq) {
-                const int rb = r0 + 32 * t + 8 * gq + 4 * h;
-                uint64_t V = 0;
-#pragma unroll
-                for (int b = 0; b < 4; ++b) {
-                    const int r = rb + b;
-                    const uint32_t bias = r == 0 ? (1u << 27) : ((1u << 27) - (1u << 19));
-                    const uint32_t s = (uint32_t)acc[t][4 * gq + b] + bias;
-                    V += (uint64_t)s << (8 * b);
-                }
-                lo[4 * t + gq] = (uint32_t)V;
-                hi[4 * t + gq] = (uint32_t)(V >> 32);
+            for (int u = 0; u < 8; ++u) {
+                if (n8 + u >= nsteps) break;
+                kstep(ablk, n8 + u, u);
             }
         }
-        // hi of limb q - 1: the partner's u for h = 1, its u - 1 for h = 0
-        uint32_t ho[32];
+
+        // Epilogue, in registers.  Lane (j, h) holds, for tile t and gq = 0..3,
+        // the signed column sums S of the four bytes of chunk limb
+        // L = 8t + 4h + gq of column j; V = sum_b S_b 256^b = lo + hi 2^32
+        // (lo unsigned, hi signed) and y_L = lo_L + hi_{L-1} leave a carry
+        // c_L in {-1, 0, 1} into each limb: limb_L = (y_L + c_L) mod 2^32,
+        // c_{L+1} = floor((y_L + c_L) / 2^32).  Fast path: c_{L+1} is taken as
+        // floor(y_L / 2^32), which is exact unless some y_L + c_L leaves
+        // [0, 2^32) in its low word (all-ones plus 1, or zero minus 1); the
+        // wave checks that and, if it happened anywhere, redoes the chunk's
+        // carries one limb after another.  The limbs of tile t's top limb
+        // (gq = 3) reach the partner lane through one exchange word per tile.
+        uint32_t ylo[32];
+        int32_t yhi[32];
+        uint32_t xw[8];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) ho[u] = __shfl_xor(hi[u], 32);
-        uint32_t Gm = 0, Pm = 0;
+        for (int t = 0; t < 8; ++t) {
+            int32_t hi[4];
+            uint32_t lo[4];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) {
-            const uint32_t hin = h ? ho[u] : (u ? ho[u - 1] : hi_in);
-            const uint64_t y = (uint64_t)lo[u] + hin + ((u == 0 && h == 0) ? c_in : 0u);
-            lo[u] = (uint32_t)y;
-            Gm |= (uint32_t)(y >> 32) << u;
-            Pm |= (lo[u] == 0xFFFFFFFFu ? 1u : 0u) << u;
+            for (int gq = 0; gq < 4; ++gq) {
+                const int64_t V = limb_sum(acc[t][4 * gq], acc[t][4 * gq + 1], acc[t][4 * gq + 2], acc[t][4 * gq + 3]);
+                lo[gq] = (uint32_t)V;
+                hi[gq] = (int32_t)(V >> 32);
+            }
+            // limbs 1..3 of the group take the high part of the limb below
+#pragma unroll
+            for (int gq = 1; gq < 4; ++gq) {
+                const int64_t y = (int64_t)lo[gq] + hi[gq - 1];
+                ylo[4 * t + gq] = (uint32_t)y;
+                yhi[4 * t + gq] = (int32_t)(y >> 32);
+            }
+            ylo[4 * t] = lo[0];  // the high part from below arrives with the exchange
+            xw[t] = xw_pack(hi[3], yhi[4 * t + 3]);
         }
-        const uint32_t Go = __shfl_xor(Gm, 32), Po = __shfl_xor(Pm, 32);
-        const uint64_t G64 = h ? (spread_bits(Go) | (spread_bits(Gm) << 1)) : (spread_bits(Gm) | (spread_bits(Go) << 1));
-        const uint64_t P64 = h ? (spread_bits(Po) | (spread_bits(Pm) << 1)) : (spread_bits(Pm) | (spread_bits(Po) << 1));
-        const uint64_t X = G64 | P64;
-        const uint64_t S = X + G64;
-        const uint64_t C = S ^ X ^ G64;  // carry into each limb of the chunk
-        // carry into the next chunk: hi of limb 63 and the lookahead's carry out
-        hi_in = h ? hi[31] : ho[31];
-        c_in = S < X ? 1u : 0u;
-        const int qbase = r0 / 4;
+        // limb 4h of tile t: below it is limb 3 of the partner's tile t (h = 1)
+        // or of the partner's tile t - 1 (h = 0; for t = 0 the chunk below)
+        bool danger = false;
+        uint32_t limb[32];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) {
-            const int q = qbase + 2 * u + h;
-            const uint32_t limb = lo[u] + (uint32_t)((C >> (2 * u + h)) & 1ull);
-            if (q >= P - 1 && q < 2 * P && jvalid) tcol[(int64_t)(q - (P - 1)) * 32] = limb;
+        for (int t = 0; t < 8; ++t) {
+            const uint32_t in = partner_of(t ? xw[t - 1] : xw_prev, xw[t], h);
+            const int64_t y = (int64_t)ylo[4 * t] + xw_hi(in);
+            ylo[4 * t] = (uint32_t)y;
+            yhi[4 * t] = (int32_t)(y >> 32);
+            int32_t c = xw_c(in);
+#pragma unroll
+            for (int gq = 0; gq < 4; ++gq) {
+                const int64_t z = (int64_t)ylo[4 * t + gq] + c;
+                limb[4 * t + gq] = (uint32_t)z;
+                danger |= (z >> 32) != 0;
+                c = yhi[4 * t + gq];
+            }
+        }
+        // the top limb of the chunk (h = 1, tile 7, gq = 3) carries into the next
+        // chunk's first limb (h = 0, tile 0): the h = 1 lanes keep its word
+        uint32_t next_prev = xw[7];
+        if (__builtin_amdgcn_ballot_w64(danger) != 0ull) {
+            // exact carries, limb after limb: per tile, the h = 0 lanes take
+            // their four limbs, then hand the carry to the h = 1 lanes, which
+            // hand theirs to the h = 0 lanes' next tile
+            int32_t c0 = xw_c(partner_of(xw_prev, xw_prev, h));  // carry into limb 0 (h = 0 lanes)
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                int32_t cin = c0;
+                // h = 0 lanes: limbs 8t .. 8t+3
+#pragma unroll
+                for (int gq = 0; gq < 4; ++gq) {
+                    const int64_t z = (int64_t)ylo[4 * t + gq] + cin;
+                    if (h == 0) limb[4 * t + gq] = (uint32_t)z;
+                    cin = yhi[4 * t + gq] + (int32_t)(z >> 32);
+                }
+                // carry out of the h = 0 group to the h = 1 lanes
+                const int32_t c1 = (int32_t)partner_of(0u, (uint32_t)cin, h);
+                cin = c1;
+#pragma unroll
+                for (int gq = 0; gq < 4; ++gq) {
+                    const int64_t z = (int64_t)ylo[4 * t + gq] + cin;
+                    if (h == 1) limb[4 * t + gq] = (uint32_t)z;
+                    cin = yhi[4 * t + gq] + (int32_t)(z >> 32);
+                }
+                // carry out of the h = 1 group back to the h = 0 lanes
+                c0 = (int32_t)partner_of((uint32_t)cin, 0u, h);
+                if (t == 7 && h == 1) next_prev = xw_pack(xw_hi(xw[7]), cin);
+            }
+        }
+        xw_prev = next_prev;
+        // limb q = r0/4 + 8t + 4h + gq of the product; the record keeps P-1 .. 2P-1
+        const int qbase = r0 / 4;
+        if (qbase + 63 >= P - 1 && jvalid) {
+            if (qbase >= P - 1 && qbase + 63 < 2 * P) {
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int gq = 0; gq < 4; ++gq)
+                        tcol[(int64_t)(qbase + 8 * t + 4 * h + gq - (P - 1)) * 32] = limb[4 * t + gq];
+            } else {
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+#pragma unroll
+                    for (int gq = 0; gq < 4; ++gq) {
+                        const int q = qbase + 8 * t + 4 * h + gq;
+                        if (q >= P - 1 && q < 2 * P) tcol[(int64_t)(q - (P - 1)) * 32] = limb[4 * t + gq];
+                    }
+            }
         }
     }
 }
@@ -605,10 +728,12 @@ __global__ void __launch_bounds__(64) k_mfma_prep(MatDev A, uint8_t *Lr, uint8_t
     mfma_prep_body(lds_raw, A, Lr, Ub, info, k, n, P, flat_block());
 }
 
-__global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_per_eu(2, 2))) k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T,
-                                                    const int32_t *info, int64_t k, int64_t n, int P) {
+template <int NC>
+__global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T, const int32_t *info, int64_t k, int64_t n,
+              int P) {
     extern __shared__ uint32_t lds_raw[];
-    update_mfma_body(lds_raw, A, Lr, Ub, T, info, k, n, P, flat_block(), true);
+    update_mfma_body<NC>(lds_raw, A, Lr, Ub, T, info, k, n, P, flat_block(), true);
 }
 
 // The finish of step k, and the first part of step k+1: the workgroup that

@@ -291,6 +291,7 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
     const size_t lds_fin = mpk::finish_launch_lds(P);
     auto fin_kernel = mpk::finish_streams(P) ? mpk::k_finish<true> : mpk::k_finish<false>;
+    auto upd_kernel = mpk::mfma_copies(P) == 4 ? mpk::k_update_mfma<4> : mpk::k_update_mfma<1>;
     mpk::MatDev a = dev(A), d = dev(D);
     const int32_t *cinfo = info;
     uint32_t *rw = nullptr;
@@ -308,7 +309,7 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
         if ((rc = last_launch())) return rc;
         {
             Prof pr(h, s, K_UPDATE_MFMA);
-            hipLaunchKernelGGL(mpk::k_update_mfma, grid_for(mpk::mfma_update_blocks(m)), dim3(64 * mpk::kMfmaWaves),
+            hipLaunchKernelGGL(upd_kernel, grid_for(mpk::mfma_update_blocks(m)), dim3(64 * mpk::kMfmaWaves),
                                lds_mfma, s, a,
                                (const uint8_t *)w.Lr, (const uint8_t *)w.Ub, w.T, cinfo, k, n, P);
         }
@@ -705,6 +706,7 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
     const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
     const size_t lds_fin = mpk::finish_launch_lds(P);
     auto bfin_kernel = mpk::finish_streams(P) ? mpk::k_batch_finish<true> : mpk::k_batch_finish<false>;
+    auto bupd_kernel = mpk::mfma_copies(P) == 4 ? mpk::k_batch_update_mfma<4> : mpk::k_batch_update_mfma<1>;
     // with the finish kernel, step k's pivot is examined by step k-1's finish launch
     const bool lookahead = (use_mfma || lane_valu) && mpk::finish_lookahead_ok(P);
     hipLaunchKernelGGL(mpk::k_batch_pend, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, dmats, batch, P, 0);
@@ -726,7 +728,7 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
         if ((rc = launch(K_DIVIDE, mpk::k_batch_divide, base + BP_DIVIDE, lds_piv, k))) return rc;
         if (use_mfma) {
             if ((rc = launch(K_MFMA_PREP, mpk::k_batch_prep, base + BP_PREP, lds_prep, k))) return rc;
-            if ((rc = launch(K_UPDATE_MFMA, mpk::k_batch_update_mfma, base + BP_UPD, lds_mfma, k,
+            if ((rc = launch(K_UPDATE_MFMA, bupd_kernel, base + BP_UPD, lds_mfma, k,
                              64 * mpk::kMfmaWaves)))
                 return rc;
             if ((rc = launch(K_UPDATE_FINISH, bfin_kernel, base + BP_SUB, lds_fin, k))) return rc;

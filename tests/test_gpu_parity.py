@@ -213,6 +213,42 @@ def test_mfma_digit_carry_extremes():
     check_against_oracle(A, "mfma", "digit extremes")
 
 
+def test_mfma_carry_into_zero_limbs():
+    """Step 0 multiplies a_i0 (a_00 = 1, so l_i = a_i0 exactly; its low 12
+    bytes are 0xFF, balanced digits -1, 0, ..., 0) by a_0j (low limbs
+    1, 0, 0): the product's signed column sums are -1 then zeros, so a borrow
+    has to run into a zero limb -- the case the update's one-level carry
+    shortcut cannot take and hands to the limb-by-limb resolution."""
+    P, N = 64, 24
+    A = inputs.random_mantissas((N, N), P, 61)
+    A.limbs[0, 0, :] = 0
+    A.limbs[0, 0, P - 1] = np.uint32(0x80000000)
+    A.exp[0, 0] = 1
+    A.sign[0, 0] = 0
+    for i in range(1, N):
+        A.limbs[i, 0, :3] = np.uint32(0xFFFFFFFF)
+    for j in range(1, N):
+        A.limbs[0, j, 0] = np.uint32(1)
+        A.limbs[0, j, 1:3] = 0
+    check_against_oracle(A, "mfma", "borrow into zero limbs")
+
+
+@pytest.mark.parametrize("P", [32, 64])
+def test_mfma_sparse_bytes(P):
+    """Mantissas made mostly of 0x00 and 0xFF bytes: long zero runs, negative
+    column sums and all-ones limbs throughout the products."""
+    N = 28
+    rng = np.random.default_rng(62 + P)
+    A = inputs.random_mantissas((N, N), P, 63 + P)
+    choice = rng.choice(5, size=(N, N, 4 * P), p=[0.70, 0.15, 0.05, 0.05, 0.05])
+    vals = np.array([0x00, 0xFF, 0x01, 0x80, 0x00], dtype=np.uint8)[choice]
+    rnd = rng.integers(0, 256, size=(N, N, 4 * P), dtype=np.uint16).astype(np.uint8)
+    vals = np.where(choice == 4, rnd, vals)
+    A.limbs[...] = np.ascontiguousarray(vals).view(np.uint32).reshape(N, N, P)
+    A.limbs[..., P - 1] |= np.uint32(0x80000000)
+    check_against_oracle(A, "mfma", f"sparse bytes P={P}")
+
+
 def test_mfma_equals_valu_config2_sized():
     """Both paths on the same config-2-sized numbers (4096-bit), N=100."""
     c = inputs.config_c2(N=100)
