@@ -28,6 +28,8 @@
 // RZ_p(a_ij - RZ_p(l_i u_j)).
 #pragma once
 
+#include <type_traits>
+
 #include "kernels_valu.h"
 
 namespace mpk {
@@ -315,8 +317,6 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
     for (int chunk = 0; chunk < g.nchunks; ++chunk) {
         const int r0 = chunk * 256;
         v16i acc[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) acc[t] = (v16i){0};
         int c_lo = r0 - 31 - P8;
         c_lo = c_lo <= 0 ? 0 : ((c_lo + 31) & ~31);
         const int c_hi = min(P8, r0 + 224);
@@ -342,14 +342,16 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
         // behind tiles 0..6); the slot's next B fragment is fetched after the
         // step's MFMAs, so the ring keeps its registers and 7 loads stay in
         // flight
-        auto kstep = [&](const uint32_t *ablk, int n, int u) __attribute__((always_inline)) {
+        // (first: the chunk's first step, whose MFMAs start from zero)
+        auto kstep = [&](auto first, const uint32_t *ablk, int n, int u) __attribute__((always_inline)) {
             const int c0 = c_lo + 32 * n;
-            acc[7] = __builtin_amdgcn_mfma_i32_32x32x32_i8(W[(7 - u) & 7], BR[u], acc[7], 0, 0, 0);
+            acc[7] = __builtin_amdgcn_mfma_i32_32x32x32_i8(W[(7 - u) & 7], BR[u], first ? (v16i){0} : acc[7], 0, 0, 0);
             W[(7 - u) & 7] = load_a<NC>(ablk + 8 * u, ash);
             __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
             for (int t = 0; t < 7; ++t)
-                acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(W[(t - u) & 7], BR[u], acc[t], 0, 0, 0);
+                acc[t] = __builtin_amdgcn_mfma_i32_32x32x32_i8(W[(t - u) & 7], BR[u], first ? (v16i){0} : acc[t], 0,
+                                                               0, 0);
             BR[u] = load_b(min(c0 + 256, bmax));
             // keep each step's loads in their step: the scheduler would
             // otherwise sink a block's 8 loads to its end
@@ -357,18 +359,29 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
         };
         // full blocks of 8 steps (no exit inside, so the load count at the loop
         // edge is the same on every path), then the partial block
+        constexpr std::true_type kFirst{};
+        constexpr std::false_type kNext{};
         int n8 = 0;
+        if (nsteps >= 8) {
+            kstep(kFirst, a1, 0, 0);
+#pragma unroll
+            for (int u = 1; u < 8; ++u) kstep(kNext, a1, u, u);
+            n8 = 8;
+        } else {
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc[t] = (v16i){0};
+        }
         for (; n8 + 8 <= nsteps; n8 += 8) {
             const uint32_t *ablk = a1 + 8 * n8;
 #pragma unroll
-            for (int u = 0; u < 8; ++u) kstep(ablk, n8 + u, u);
+            for (int u = 0; u < 8; ++u) kstep(kNext, ablk, n8 + u, u);
         }
         {
             const uint32_t *ablk = a1 + 8 * n8;
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
                 if (n8 + u >= nsteps) break;
-                kstep(ablk, n8 + u, u);
+                kstep(kNext, ablk, n8 + u, u);
             }
         }
 
