@@ -516,7 +516,7 @@ __host__ __device__ inline int finish_tile(int P) {
     return finish_streams(P) ? 64 : (P <= 256 ? 64 : (P <= 512 ? 32 : 16));
 }
 __host__ __device__ inline size_t finish_lds_bytes(int P) {
-    if (finish_streams(P)) return (size_t)(2 * kFinC * 65 + 64) * 4u;
+    if (finish_streams(P)) return (size_t)(2 * kFinC * 65 + 128) * 4u;
     return (size_t)(P + 1) * (size_t)(finish_tile(P) + 1) * 4u;
 }
 __host__ __device__ inline int64_t finish_blocks(int64_t m, int P) {
@@ -780,6 +780,7 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
     uint32_t *achunk = lds;                    // C rows x FTP: a's limbs of the current chunk
     uint32_t *ochunk = lds + C * FTP;          // C rows x FTP: result limbs of the current chunk
     int32_t *eoff = (int32_t *)(lds + 2 * C * FTP);  // per element: a's limb offset, or -1: not written
+    int32_t *fwoff = eoff + FT;  // per element: the single pass's limb shift w0 (0 or -1), 2: none
     const int lane = mpw::lane(), e = lane;
     const bool in = e < cnt;
     const int64_t jp = j0 + (in ? e : 0), j = k + 1 + jp;
@@ -802,6 +803,9 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
     };
     auto al = [&](int q) -> uint32_t { return (q >= 0 && q < P) ? am[q] : 0u; };
     uint32_t ylo = 0u, wlo = 0u;
+    bool fast = false;  // single pass: the result is written while G is formed
+    int fw0 = 0, fbb = 0;
+    int64_t feout = 0;
     if (live) {
         const int top = (int)(rw(P) >> 31);
         sh = 1 - top;
@@ -857,8 +861,55 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
         cy = subtract ? 1u - st : 0u;
         ylo = a_is_x ? tl(w) : al(w);
         wlo = rw(ot);
+        // Length of G from its top three limbs (leading-zero anticipation).
+        // H = X' +- Y' over limbs P-2 .. P (X' = X 2^gsh, Y' = Y >> rs) differs
+        // from G's limbs P-2 .. P by the carry (+1) or borrow (-1, sticky
+        // included) out of the limbs below, which changes H's length only if
+        // H is all ones (addition) or a power of two (subtraction).  Outside
+        // those cases, and if G keeps at least 33 bits in its top three limbs
+        // (the normalised result then starts no more than one limb below G's
+        // limb order), the result can be written while G is formed.
+        {
+            auto xl = [&](int q) -> uint32_t { return a_is_x ? al(q) : tl(q); };
+            auto yl = [&](int q) -> uint32_t { return a_is_x ? tl(q) : al(q); };
+            uint32_t hx[3], hy[3];
+#pragma unroll
+            for (int z = 0; z < 3; ++z) {
+                const int q = P - 2 + z;
+                hx[z] = gsh ? __builtin_amdgcn_alignbit(xl(q), xl(q - 1), 32 - gsh) : xl(q);
+                hy[z] = __builtin_amdgcn_alignbit(yl(q + w + 1), yl(q + w), b);
+            }
+            // H as one 96-bit value: two 64-bit words
+            const uint64_t xlo = ((uint64_t)hx[1] << 32) | hx[0], ylo64 = ((uint64_t)hy[1] << 32) | hy[0];
+            uint64_t hlo, hhi;
+            if (subtract) {
+                hlo = xlo - ylo64;
+                hhi = (uint64_t)hx[2] - hy[2] - (xlo < ylo64 ? 1u : 0u);
+            } else {
+                hlo = xlo + ylo64;
+                hhi = (uint64_t)hx[2] + hy[2] + (hlo < xlo ? 1u : 0u);
+            }
+            const int hbits = hhi ? 64 + 64 - __clzll(hhi) : (hlo ? 64 - __clzll(hlo) : 0);
+            bool ambiguous;
+            if (subtract) {  // a power of two
+                const uint64_t mlo = hlo - 1, mhi = hhi - (hlo == 0 ? 1u : 0u);
+                ambiguous = (hlo & mlo) == 0 && (hhi & mhi) == 0;
+            } else {  // all ones below the top bit: H + 1 is a power of two
+                const uint64_t plo = hlo + 1, phi = hhi + (plo == 0 ? 1u : 0u);
+                ambiguous = (hlo & plo) == 0 && (hhi & phi) == 0;
+            }
+            fast = !ambiguous && hbits >= 32;
+            if (fast) {
+                const int L = 32 * (P - 2) + hbits;
+                const int sr = L - pbits;  // -32 .. 3
+                fw0 = sr >= 0 ? 0 : -1;
+                fbb = sr - 32 * fw0;
+                feout = eX - gsh - pbits + L;
+            }
+        }
     }
     eoff[e] = live ? oa : -1;
+    fwoff[e] = (live && fast) ? fw0 : 2;  // 2: not written in pass 1
 
     // ---- pass 1: G = X 2^gsh +- (Y >> rs) -+ sticky, limbs 0..P, into the record ----
     constexpr int PF = 16;  // record words fetched PF steps ahead (C is a multiple of PF)
@@ -867,7 +918,7 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
     const int xlim = P - ot - 1;  // step q uses a real record word iff q <= xlim
 #pragma unroll
     for (int u = 0; u < PF; ++u) ring[u] = rp[(int64_t)min(u, max(xlim, 0)) * 32];
-    uint32_t xprev = 0u;
+    uint32_t xprev = 0u, gprev = 0u;
     for (int c0 = 0; c0 <= P; c0 += C) {
         mpw::wsync();  // the previous chunk is consumed; eoff is visible
         // a's limbs [c0 + off, c0 + off + C) of every element, 8 loads per
@@ -904,7 +955,13 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
                 const uint32_t xg = gsh ? __builtin_amdgcn_alignbit(xq, xprev, 32 - gsh) : xq;
                 const uint32_t ysh = __builtin_amdgcn_alignbit(yhi, ylo, b);
                 const uint64_t t = (uint64_t)xg + (ysh ^ ymask) + cy;
-                raw[(int64_t)q * 32] = (uint32_t)t;  // record word q was read by an earlier step
+                const uint32_t gq = (uint32_t)t;
+                // single pass: result limb q - w0 - 1 from G limbs q, q - 1 (the
+                // row is stored only for single-pass elements); two passes: G
+                // into record word q, which an earlier step has read
+                ochunk[u * FTP + e] = __builtin_amdgcn_alignbit(gq, gprev, fbb);
+                if (!fast) raw[(int64_t)q * 32] = gq;
+                gprev = gq;
                 cy = (uint32_t)(t >> 32);
                 xprev = xq;
                 ylo = yhi;
@@ -920,13 +977,33 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
                 }
             }
         }
+        // the single pass's result limbs of this chunk: row r of element e2 is
+        // limb c0 + r - w0 - 1 (every a limb it overwrites has been read)
+        mpw::wsync();
+#pragma unroll 4
+        for (int u = 0; u < 32; ++u) {
+            const int t = u * MP_WAVE + lane;
+            const int e2 = t >> 5, r = t & 31;
+            const int wo = fwoff[e2];
+            const int q = c0 + r - wo - 1;
+            if (wo != 2 && q >= 0 && q < P) arow[(int64_t)e2 * P + q] = ochunk[r * FTP + e2];
+        }
     }
+    if (live && fast) {
+        ex(A, i, j) = feout;
+        sg(A, i, j) = sX;
+    }
+    // the two-pass elements only from here on
+    const bool slow = live && !fast;
+    if (__builtin_amdgcn_ballot_w64(slow) == 0ull) return;
+    mpw::wsync();
+    eoff[e] = slow ? 0 : -1;
 
     // ---- pass 2: normalise G to p bits, chunk by chunk into a_ij ----
     int w0 = 0, bb = 0;
     bool gzero = true;
     int64_t eout = 0;
-    if (live) {
+    if (slow) {
         auto gw = [&](int x) -> uint32_t { return (x >= 0 && x <= P) ? raw[(int64_t)x * 32] : 0u; };
         int qt = P;
         while (qt >= 0 && gw(qt) == 0u) --qt;
@@ -942,7 +1019,7 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
         sg(A, i, j) = gzero ? 0 : sX;
     }
     for (int c0 = 0; c0 < P; c0 += C) {
-        if (live) {
+        if (slow) {
 #pragma unroll 8
             for (int u = 0; u < C; ++u) {
                 const int x = c0 + u + w0;  // result limb c0+u = bits of G limbs x, x+1

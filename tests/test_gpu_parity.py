@@ -168,7 +168,7 @@ def test_mfma_shapes(N, P):
     check_against_oracle(A, "mfma", f"mfma shape N={N} P={P}")
 
 
-@pytest.mark.parametrize("case", ["wide_exponents", "cancellation", "zero_entries", "zero_pivot"])
+@pytest.mark.parametrize("case", ["wide_exponents", "cancellation", "zero_entries", "zero_pivot", "patterns"])
 def test_streaming_finish_cases(case):
     """P > 256 takes the streaming finish (chunked a_ij, intermediate kept in
     the record buffer): the sticky, cancellation, 0 - t and zero-pivot cases."""
@@ -192,6 +192,21 @@ def test_streaming_finish_cases(case):
                     A.limbs[i, j] = 0
                     A.exp[i, j] = 0
                     A.sign[i, j] = 0
+    elif case == "patterns":
+        # powers of two and all-ones mantissas with equal exponents: sums and
+        # differences whose top limbs are all ones or a single bit, where the
+        # length of the intermediate cannot be read off its top limbs
+        A = inputs.random_mantissas((N, N), P, 95, emin=0, emax=1)
+        pats = [np.full(P, 0xFFFFFFFF, np.uint32), np.zeros(P, np.uint32), np.zeros(P, np.uint32)]
+        pats[1][P - 1] = 0x80000000
+        pats[2][P - 1] = 0x80000000
+        pats[2][: P - 1] = 0xFFFFFFFF
+        rng = np.random.default_rng(96)
+        for i in range(N):
+            for j in range(N):
+                if (i * 5 + j) % 3:
+                    A.limbs[i, j] = pats[int(rng.integers(0, 3))]
+                    A.exp[i, j] = int(rng.integers(0, 2))
     else:
         A, L, U = inputs.triangular_product(12, P, 8)
         U[6, 6] = 0
