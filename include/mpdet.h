@@ -99,6 +99,33 @@ int mp_det_factor(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev,
                   int path, void *stream);
 
 /*
+ * mp_det_factor_steps -- elimination steps k_begin .. k_end-1 (0-based; step k
+ * eliminates column k) of mp_det_factor, in place: a factorisation can be
+ * split into several calls (e.g. to bound the time of one call, or to check
+ * the leading determinants D_1 .. D_{k_end} of a large run while it runs).
+ * Calling it with the ranges [0, k_1), [k_1, k_2), ..., [k_r, n) on the same
+ * A, D and info, with the same path, gives the bits of one mp_det_factor call
+ * (Algorithm 1 runs its steps in order and each step only reads the state the
+ * previous one left).  k_begin == 0 resets info; a later range continues from
+ * info as the previous range left it (a nonzero info makes it do nothing).
+ *   0 <= k_begin <= k_end <= n, else MPDET_EINVAL; other arguments as for
+ *   mp_det_factor.
+ */
+int mp_det_factor_steps(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev,
+                        int64_t k_begin, int64_t k_end, int path, void *stream);
+
+/*
+ * mpdet_set_panel_rows -- rows per panel of the MFMA path's trailing update
+ * (the product records of one panel of rows are formed and consumed before the
+ * next panel's; their buffer grows with the panel).  0 (the default) sizes
+ * panels to a 24 GiB record buffer, which keeps one panel per step up to
+ * 32768-bit numbers at n ~ 2800; a 6144 x 6144 matrix of 32768-bit numbers
+ * (155 GB) then needs a few panels per step.  Any value gives the same bits.
+ *   rows >= 0, else MPDET_EINVAL.
+ */
+int mpdet_set_panel_rows(mpdet_handle *h, int64_t rows);
+
+/*
  * mp_det_minors -- signed last-column cofactors c_i = (-1)^(i+n) M_{i,n}
  * (eq. (minorsdef); Sec. 3 [A I] derivation), from mp_det_factor's output.
  * With L the unit lower factor, x^T L = e_n^T is solved by sweeps j = n..2,

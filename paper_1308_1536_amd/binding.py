@@ -64,6 +64,8 @@ def lib() -> ctypes.CDLL:
         L.mpdet_strerror.argtypes = [ctypes.c_int]
         L.mpdet_strerror.restype = ctypes.c_char_p
         L.mp_det_factor.argtypes = [vp, MpdetMat, MpdetMat, vp, ctypes.c_int, vp]
+        L.mp_det_factor_steps.argtypes = [vp, MpdetMat, MpdetMat, vp, i64, i64, ctypes.c_int, vp]
+        L.mpdet_set_panel_rows.argtypes = [vp, i64]
         L.mp_det_minors.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, vp, vp]
         L.mp_to_f64.argtypes = [vp, MpdetMat, vp, vp, vp]
         L.mpdet_profile_begin.argtypes = [vp]
@@ -225,6 +227,21 @@ def factor(A: DeviceMp, path: str = "auto", D: DeviceMp | None = None, info=None
     _check("mp_det_factor", lib().mp_det_factor(h.ptr, A.mat(), D.mat(), info.data_ptr(),
                                                 _resolve(path, n, A.P), _stream(stream)))
     return D, info
+
+
+def factor_steps(A: DeviceMp, D: DeviceMp, info, k_begin: int, k_end: int, path: str = "auto", stream=None):
+    """mp_det_factor_steps: elimination steps k_begin .. k_end-1 in place (D, info
+    carried between calls; k_begin == 0 resets info)."""
+    h = handle(A.limbs.device.index or 0)
+    _check("mp_det_factor_steps", lib().mp_det_factor_steps(h.ptr, A.mat(), D.mat(), info.data_ptr(), int(k_begin),
+                                                            int(k_end), _resolve(path, A.rows, A.P),
+                                                            _stream(stream)))
+    return D, info
+
+
+def set_panel_rows(rows: int, device: int = 0):
+    """mpdet_set_panel_rows on the device's handle (0: automatic)."""
+    _check("mpdet_set_panel_rows", lib().mpdet_set_panel_rows(handle(device).ptr, int(rows)))
 
 
 def minors(LU: DeviceMp, D: DeviceMp, info, c: DeviceMp | None = None, stream=None) -> DeviceMp:

@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_p
     MPK_BATCH_PROLOGUE
     // every matrix's block count is a multiple of 8, so loc and bx agree mod 8
     // and the XCD-aware column mapping holds inside each matrix
-    update_mfma_body<NC>(lds_raw, M.A, M.Lr, M.Ub, M.T, M.info, k, M.n, P, loc, true);
+    update_mfma_body<NC>(lds_raw, M.A, M.Lr, M.Ub, M.T, M.info, k, M.n, P, 0, M.n - k - 1, loc, true);
 }
 
 template <bool STREAM>
@@ -85,7 +85,8 @@ __global__ void __launch_bounds__(64) k_batch_finish(const BatchMat *mats, const
                                                      const int64_t *off, int cnt, int64_t k, int P) {
     MPK_BATCH_PROLOGUE
     // the look-ahead pivot runs only where the host launches no pivot phase
-    finish_body<STREAM>(lds_raw, M.A, M.T, M.info, k, M.n, P, loc, M.D, finish_lookahead_ok(P) ? M.rw : nullptr);
+    finish_body<STREAM>(lds_raw, M.A, M.T, M.info, k, M.n, P, 0, M.n - k - 1, loc, M.D,
+                        finish_lookahead_ok(P) ? M.rw : nullptr);
 }
 
 // minors sweep number s: matrix of size n processes j = n - 1 - s (blocks i < j)

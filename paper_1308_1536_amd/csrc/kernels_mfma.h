@@ -82,9 +82,9 @@ constexpr int kMfmaWaves = 2;
 // LDS one workgroup of k_update_mfma may take
 constexpr size_t kMfmaLdsMax = 64 * 1024;
 
-// workgroups of k_update_mfma for an m x m trailing block
-__host__ __device__ inline int64_t mfma_update_blocks(int64_t m) {
-    const int64_t njb = (m + 31) / 32, nrg = (m + kMfmaWaves - 1) / kMfmaWaves;
+// workgroups of k_update_mfma for `rows` rows of an m x m trailing block
+__host__ __device__ inline int64_t mfma_update_blocks(int64_t rows, int64_t m) {
+    const int64_t njb = (m + 31) / 32, nrg = (rows + kMfmaWaves - 1) / kMfmaWaves;
     return njb >= kXcds ? kXcds * nrg * ((njb + kXcds - 1) / kXcds) : nrg * njb;
 }
 
@@ -248,11 +248,11 @@ __device__ __forceinline__ uint32_t partner_of(uint32_t a, uint32_t b, int h) {
 template <int NC>
 __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, const uint8_t *Lr, const uint8_t *Ub,
                                                  uint32_t *T, const int32_t *info, int64_t k, int64_t n, int P,
-                                                 int64_t bx, bool xcd_aware) {
+                                                 int64_t ip0, int64_t rows, int64_t bx, bool xcd_aware) {
     if (*info != 0) return;
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
-    const int64_t njb = (m + 31) / 32, nrg = (m + kMfmaWaves - 1) / kMfmaWaves;
+    const int64_t njb = (m + 31) / 32, nrg = (rows + kMfmaWaves - 1) / kMfmaWaves;
     int64_t rg, jb;
     if (xcd_aware && njb >= kXcds) {
         // workgroups go to the 8 XCDs round-robin: XCD x takes the column
@@ -268,12 +268,14 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
         rg = bx / njb;
         jb = bx % njb;
     }
-    // wave w of the workgroup takes row i' = kMfmaWaves rg + w and fills its
-    // own part of LDS; after the one barrier, which every wave reaches, a wave
-    // without a row (or with a zero multiplier) leaves
+    // wave w of the workgroup takes row i' = ip0 + kMfmaWaves rg + w of the
+    // panel [ip0, ip0 + rows) and fills its own part of LDS; after the one
+    // barrier, which every wave reaches, a wave without a row (or with a zero
+    // multiplier) leaves
     const int wave = (int)(threadIdx.x >> 6);
-    const int64_t ip = rg * kMfmaWaves + wave;
-    const bool active = ip < m && el(A, k + 1 + (ip < m ? ip : 0), k, P)[P - 1] != 0u;
+    const int64_t ip = ip0 + rg * kMfmaWaves + wave;
+    const bool inrow = ip < ip0 + rows && ip < m;
+    const bool active = inrow && el(A, k + 1 + (inrow ? ip : 0), k, P)[P - 1] != 0u;
     const int LR = g.LR;
     uint8_t *lr = (uint8_t *)lds_raw + (size_t)wave * NC * LR;
     if (active) {
@@ -304,7 +306,7 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
     auto load_b = [&](int c0) __attribute__((always_inline)) {
         return __builtin_bit_cast(v4i, __builtin_amdgcn_raw_buffer_load_b128(brs, boff, 32 * c0, 0));
     };
-    uint32_t *tcol = T + (ip * njb + jb) * (int64_t)g.TP * 32 + j;
+    uint32_t *tcol = T + ((ip - ip0) * njb + jb) * (int64_t)g.TP * 32 + j;
     const int P8 = g.P8;
     const int bmax = g.K8 - 32;  // last K-step offset c0 inside the digit strings
     // A fragment of diagonal offset d = r0 - c0 for this lane (row r = j of the
@@ -519,22 +521,23 @@ __host__ __device__ inline size_t finish_lds_bytes(int P) {
     if (finish_streams(P)) return (size_t)(2 * kFinC * 65 + 128) * 4u;
     return (size_t)(P + 1) * (size_t)(finish_tile(P) + 1) * 4u;
 }
-__host__ __device__ inline int64_t finish_blocks(int64_t m, int P) {
+// workgroups of the finish for `rows` rows of an m x m trailing block
+__host__ __device__ inline int64_t finish_blocks(int64_t rows, int64_t m, int P) {
     const int ft = finish_tile(P);
-    return m * ((m + ft - 1) / ft);
+    return rows * ((m + ft - 1) / ft);
 }
-// record slots of an m x m trailing block: m rows x njb blocks of 32 columns
-__host__ __device__ inline int64_t rec_slots(int64_t m) { return m * ((m + 31) / 32) * 32; }
+// record slots of `rows` rows of an m x m trailing block: rows x njb blocks of 32 columns
+__host__ __device__ inline int64_t rec_slots(int64_t rows, int64_t m) { return rows * ((m + 31) / 32) * 32; }
 
 __device__ __forceinline__ void finish_tile_body(uint32_t *lds, MatDev A, const uint32_t *__restrict__ T, int64_t k,
-                                                 int64_t n, int P, int64_t bx) {
+                                                 int64_t n, int P, int64_t ip0, int64_t rows, int64_t bx) {
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
     const int64_t njb = (m + 31) / 32;
     const int FT = finish_tile(P), FTP = FT + 1;
     const int64_t ntile = (m + FT - 1) / FT;
-    const int64_t ip = bx / ntile, j0 = (bx % ntile) * FT;
-    if (ip >= m) return;
+    const int64_t ip = ip0 + bx / ntile, j0 = (bx % ntile) * FT;
+    if (bx / ntile >= rows || ip >= m) return;
     const int64_t i = k + 1 + ip;
     if (el(A, i, k, P)[P - 1] == 0u) return;  // zero multiplier: the row keeps its values
     const int cnt = (int)min((int64_t)FT, m - j0);
@@ -544,7 +547,7 @@ __device__ __forceinline__ void finish_tile_body(uint32_t *lds, MatDev A, const 
     const bool live = e < cnt;
     const int64_t jp = j0 + (live ? e : 0), j = k + 1 + jp;
     // per-lane scalars first, so their latency overlaps the tile copy
-    const uint32_t *raw = T + (ip * njb + jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
+    const uint32_t *raw = T + ((ip - ip0) * njb + jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
     const uint32_t utop = el(A, k, j, P)[P - 1];
     const uint32_t rtop = raw[(int64_t)P * 32];
     const int64_t eik = ex(A, i, k), ekj = ex(A, k, j), ea = ex(A, i, j);
@@ -744,9 +747,9 @@ __global__ void __launch_bounds__(64) k_mfma_prep(MatDev A, uint8_t *Lr, uint8_t
 template <int NC>
 __global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T, const int32_t *info, int64_t k, int64_t n,
-              int P) {
+              int P, int64_t ip0, int64_t rows) {
     extern __shared__ uint32_t lds_raw[];
-    update_mfma_body<NC>(lds_raw, A, Lr, Ub, T, info, k, n, P, flat_block(), true);
+    update_mfma_body<NC>(lds_raw, A, Lr, Ub, T, info, k, n, P, ip0, rows, flat_block(), true);
 }
 
 // The finish of step k, and the first part of step k+1: the workgroup that
@@ -764,15 +767,15 @@ k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T, const
 // before G[q] overwrites it), and the normalised result goes back through an
 // LDS chunk.  LDS: two chunk buffers and the per-element offsets.
 __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint32_t *__restrict__ T, int64_t k,
-                                                   int64_t n, int P, int64_t bx) {
+                                                   int64_t n, int P, int64_t ip0, int64_t rows, int64_t bx) {
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
     const int64_t njb = (m + 31) / 32;
     constexpr int FT = 64, FTP = 65, C = kFinC;
     static_assert(C == 32 && FT == 64, "the chunk copies map 64 elements x 32 limbs onto 32 lane passes");
     const int64_t ntile = (m + FT - 1) / FT;
-    const int64_t ip = bx / ntile, j0 = (bx % ntile) * FT;
-    if (ip >= m) return;
+    const int64_t ip = ip0 + bx / ntile, j0 = (bx % ntile) * FT;
+    if (bx / ntile >= rows || ip >= m) return;
     const int64_t i = k + 1 + ip;
     if (el(A, i, k, P)[P - 1] == 0u) return;  // zero multiplier: the row keeps its values
     const int cnt = (int)min((int64_t)FT, m - j0);
@@ -785,7 +788,7 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
     const bool in = e < cnt;
     const int64_t jp = j0 + (in ? e : 0), j = k + 1 + jp;
     uint32_t *am = arow + (int64_t)(in ? e : 0) * P;
-    uint32_t *raw = T + (ip * njb + jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
+    uint32_t *raw = T + ((ip - ip0) * njb + jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
     const bool live = in && el(A, k, j, P)[P - 1] != 0u;  // u_j = 0: a_ij is left as it is
     const int pbits = 32 * P;
 
@@ -1044,12 +1047,13 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
 // that each gets its own register allocation.
 template <bool STREAM>
 __device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, uint32_t *__restrict__ T,
-                                            const int32_t *info, int64_t k, int64_t n, int P, int64_t bx, MatDev D,
-                                            uint32_t *rw) {
+                                            const int32_t *info, int64_t k, int64_t n, int P, int64_t ip0,
+                                            int64_t rows, int64_t bx, MatDev D, uint32_t *rw) {
     if (*info != 0) return;
-    if constexpr (STREAM) finish_stream_body(lds, A, T, k, n, P, bx);
-    else finish_tile_body(lds, A, T, k, n, P, bx);
-    if (rw != nullptr && bx == 0 && k + 1 < n) {
+    if constexpr (STREAM) finish_stream_body(lds, A, T, k, n, P, ip0, rows, bx);
+    else finish_tile_body(lds, A, T, k, n, P, ip0, rows, bx);
+    // (block 0 of the panel holding row k+1 holds a_{k+1,k+1})
+    if (rw != nullptr && ip0 == 0 && bx == 0 && k + 1 < n) {
         __syncthreads();  // the tile's stores are visible to the workgroup, its LDS is free
         int32_t *pend = (int32_t *)(rw + P + 2);
         pivot_recip_body(lds, A, D, info, pend, rw, k + 1, n, P, 1);
@@ -1069,9 +1073,9 @@ __host__ __device__ inline size_t finish_launch_lds(int P) {
 
 template <bool STREAM>
 __global__ void __launch_bounds__(64) k_finish(MatDev A, uint32_t *T, const int32_t *info, int64_t k,
-                                               int64_t n, int P, MatDev D, uint32_t *rw) {
+                                               int64_t n, int P, int64_t ip0, int64_t rows, MatDev D, uint32_t *rw) {
     extern __shared__ uint32_t lds_raw[];
-    finish_body<STREAM>(lds_raw, A, T, info, k, n, P, flat_block(), D, rw);
+    finish_body<STREAM>(lds_raw, A, T, info, k, n, P, ip0, rows, flat_block(), D, rw);
 }
 
 }  // namespace mpk

@@ -46,6 +46,8 @@ struct mpdet_handle {
     // MFMA-path workspace (grown on demand, freed by mpdet_destroy)
     void *ws;
     size_t ws_bytes;
+    // rows per panel of the trailing update (0: from kRecBudget)
+    int64_t panel_rows;
     // the pivot's reciprocal
     void *rw;
     size_t rw_bytes;
@@ -206,15 +208,28 @@ struct MfmaWs {
 // bytes of the product-top records for an m x m trailing block, plus the
 // padding the finish kernel's unconditional read-ahead may touch past the
 // last record ((P + 40) * 32 words)
-size_t mfma_rec_bytes(int64_t m, int P) {
-    return ((size_t)mpk::rec_slots(m) * (size_t)mpk::mfma_geom(P).TP + (size_t)(P + 40) * 32u) * 4u;
+size_t mfma_rec_bytes(int64_t rows, int64_t m, int P) {
+    return ((size_t)mpk::rec_slots(rows, m) * (size_t)mpk::mfma_geom(P).TP + (size_t)(P + 40) * 32u) * 4u;
 }
 
-int mfma_workspace(mpdet_handle *h, int64_t m, int P, MfmaWs *w) {
+// Bytes the product-top records of one panel may take: the trailing update
+// runs over row panels of at most this size, so the workspace stays bounded
+// (a 6144 x 6144 matrix of 32768-bit numbers alone takes 155 GB).
+constexpr size_t kRecBudget = (size_t)24 << 30;
+
+// rows per panel for trailing blocks up to m x m
+int64_t panel_rows(const mpdet_handle *h, int64_t m, int P) {
+    if (h->panel_rows > 0) return h->panel_rows < m ? h->panel_rows : m;
+    const size_t per_row = (size_t)((m + 31) / 32) * 32u * (size_t)mpk::mfma_geom(P).TP * 4u;
+    const int64_t r = (int64_t)(kRecBudget / per_row);
+    return r < 1 ? 1 : (r < m ? r : m);
+}
+
+int mfma_workspace(mpdet_handle *h, int64_t m, int P, int64_t rows, MfmaWs *w) {
     const mpk::MfmaGeom g = mpk::mfma_geom(P);
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t lr = up((size_t)m * g.LR), ub = up(mpk::ub_bytes(m, P));
-    const size_t t = up(mfma_rec_bytes(m, P));
+    const size_t t = up(mfma_rec_bytes(rows, m, P));
     const size_t need = lr + ub + t;
     if (need > h->ws_bytes) {
         if (h->ws) (void)hipFree(h->ws);
@@ -237,14 +252,16 @@ int mfma_workspace(mpdet_handle *h, int64_t m, int P, MfmaWs *w) {
 // VALU path.  For P <= 128 (P a multiple of 4) each step runs the
 // lane-per-element product kernel into the record buffer, then the finish
 // kernel the MFMA path uses; otherwise one wave per element update.
-int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, hipStream_t s) {
+int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, int64_t k_begin,
+                int64_t k_end, hipStream_t s) {
     const int64_t n = A.rows;
     const int P = A.nlimbs;
     const size_t lds = mpk::lds_bytes(P);
     const bool lane = mpk::lane_update_ok(P);
     MfmaWs w{};
     if (lane) {
-        int rc = mfma_workspace(h, n > 1 ? n - 1 : 1, P, &w);
+        const int64_t m0 = n > 1 ? n - 1 : 1;
+        int rc = mfma_workspace(h, m0, P, m0, &w);
         if (rc) return rc;
     }
     const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_launch_lds(P);
@@ -255,9 +272,9 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     const bool ahead = lane && mpk::finish_lookahead_ok(P);  // the finish launch examines the next pivot
     int rc0 = recip_ws(h, P, &rw);
     if (rc0 || (rc0 = pend_clear(rw, P, s))) return rc0;
-    for (int64_t k = 0; k < n; ++k) {
+    for (int64_t k = k_begin; k < k_end; ++k) {
         // with the finish kernel, step k's pivot was examined by step k-1's finish launch
-        int rc = pivot_step(h, a, d, info, rw, k, n, P, ahead && k > 0, s);
+        int rc = pivot_step(h, a, d, info, rw, k, n, P, ahead && k > k_begin, s);
         if (rc) return rc;
         const int64_t m = n - k - 1;
         if (m <= 0) continue;
@@ -270,8 +287,8 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
             if ((rc = last_launch())) return rc;
             {
                 Prof pr(h, s, K_UPDATE_FINISH);
-                hipLaunchKernelGGL(fin_kernel, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a, w.T,
-                                   cinfo, k, n, P, d, ahead ? rw : nullptr);
+                hipLaunchKernelGGL(fin_kernel, grid_for(mpk::finish_blocks(m, m, P)), dim3(64), lds_fin, s, a, w.T,
+                                   cinfo, k, n, P, (int64_t)0, m, d, ahead ? rw : nullptr);
             }
         } else {
             Prof pr(h, s, K_UPDATE_VALU);
@@ -282,11 +299,14 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     return pend_promote(info, rw, P, s);
 }
 
-int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, hipStream_t s) {
+int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, int64_t k_begin,
+                int64_t k_end, hipStream_t s) {
     const int64_t n = A.rows;
     const int P = A.nlimbs;
     MfmaWs w;
-    int rc = mfma_workspace(h, n > 1 ? n - 1 : 1, P, &w);
+    const int64_t m0 = n - k_begin - 1 > 1 ? n - k_begin - 1 : 1;
+    const int64_t R = panel_rows(h, m0, P);
+    int rc = mfma_workspace(h, m0, P, R, &w);
     if (rc) return rc;
     const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
     const size_t lds_fin = mpk::finish_launch_lds(P);
@@ -297,8 +317,8 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     uint32_t *rw = nullptr;
     if ((rc = recip_ws(h, P, &rw)) || (rc = pend_clear(rw, P, s))) return rc;
     const bool ahead = mpk::finish_lookahead_ok(P);  // the finish launch examines the next pivot
-    for (int64_t k = 0; k < n; ++k) {
-        if ((rc = pivot_step(h, a, d, info, rw, k, n, P, ahead && k > 0, s))) return rc;
+    for (int64_t k = k_begin; k < k_end; ++k) {
+        if ((rc = pivot_step(h, a, d, info, rw, k, n, P, ahead && k > k_begin, s))) return rc;
         const int64_t m = n - k - 1;
         if (m <= 0) continue;
         {
@@ -307,19 +327,23 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
                                n, P);
         }
         if ((rc = last_launch())) return rc;
-        {
-            Prof pr(h, s, K_UPDATE_MFMA);
-            hipLaunchKernelGGL(upd_kernel, grid_for(mpk::mfma_update_blocks(m)), dim3(64 * mpk::kMfmaWaves),
-                               lds_mfma, s, a,
-                               (const uint8_t *)w.Lr, (const uint8_t *)w.Ub, w.T, cinfo, k, n, P);
+        // row panels [ip0, ip0 + rows) share the record buffer, one after another
+        for (int64_t ip0 = 0; ip0 < m; ip0 += R) {
+            const int64_t rows = m - ip0 < R ? m - ip0 : R;
+            {
+                Prof pr(h, s, K_UPDATE_MFMA);
+                hipLaunchKernelGGL(upd_kernel, grid_for(mpk::mfma_update_blocks(rows, m)),
+                                   dim3(64 * mpk::kMfmaWaves), lds_mfma, s, a, (const uint8_t *)w.Lr,
+                                   (const uint8_t *)w.Ub, w.T, cinfo, k, n, P, ip0, rows);
+            }
+            if ((rc = last_launch())) return rc;
+            {
+                Prof pr(h, s, K_UPDATE_FINISH);
+                hipLaunchKernelGGL(fin_kernel, grid_for(mpk::finish_blocks(rows, m, P)), dim3(64), lds_fin, s, a,
+                                   w.T, cinfo, k, n, P, ip0, rows, d, ahead ? rw : nullptr);
+            }
+            if ((rc = last_launch())) return rc;
         }
-        if ((rc = last_launch())) return rc;
-        {
-            Prof pr(h, s, K_UPDATE_FINISH);
-            hipLaunchKernelGGL(fin_kernel, grid_for(mpk::finish_blocks(m, P)), dim3(64), lds_fin, s, a, w.T,
-                               cinfo, k, n, P, d, ahead ? rw : nullptr);
-        }
-        if ((rc = last_launch())) return rc;
     }
     return pend_promote(info, rw, P, s);
 }
@@ -458,10 +482,12 @@ int mpdet_profile_get(mpdet_handle *h, const char *kernel, double *total_ms, int
     return MPDET_EINVAL;
 }
 
-int mp_det_factor(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, int path, void *stream) {
+int mp_det_factor_steps(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, int64_t k_begin,
+                        int64_t k_end, int path, void *stream) {
     if (!h || !info_dev) return MPDET_EINVAL;
     if (!mat_ok(A, A.rows > 0) || !mat_ok(D, A.rows > 0)) return MPDET_EINVAL;
     if (A.rows != A.cols || D.nlimbs != A.nlimbs || D.rows < 1 || D.cols < A.rows) return MPDET_EINVAL;
+    if (k_begin < 0 || k_end < k_begin || k_end > A.rows) return MPDET_EINVAL;
     if (path != MPDET_PATH_AUTO && path != MPDET_PATH_VALU && path != MPDET_PATH_MFMA) return MPDET_EINVAL;
     const bool mfma_ok = mpk::mfma_supported(A.nlimbs);
     if (path == MPDET_PATH_MFMA && !mfma_ok) return MPDET_ENOTSUP;
@@ -469,11 +495,24 @@ int mp_det_factor(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, 
     DeviceGuard g(h->device);
     if (!g.ok) return MPDET_EHIP;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(mpk::k_set_info, dim3(1), dim3(64), 0, s, info_dev, 0);
-    int rc = last_launch();
-    if (rc) return rc;
-    if (A.rows == 0) return MPDET_OK;
-    return use_mfma ? factor_mfma(h, A, D, info_dev, s) : factor_valu(h, A, D, info_dev, s);
+    if (k_begin == 0) {
+        hipLaunchKernelGGL(mpk::k_set_info, dim3(1), dim3(64), 0, s, info_dev, 0);
+        int rc = last_launch();
+        if (rc) return rc;
+    }
+    if (k_end == k_begin) return MPDET_OK;
+    return use_mfma ? factor_mfma(h, A, D, info_dev, k_begin, k_end, s)
+                    : factor_valu(h, A, D, info_dev, k_begin, k_end, s);
+}
+
+int mp_det_factor(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, int path, void *stream) {
+    return mp_det_factor_steps(h, A, D, info_dev, 0, A.rows, path, stream);
+}
+
+int mpdet_set_panel_rows(mpdet_handle *h, int64_t rows) {
+    if (!h || rows < 0) return MPDET_EINVAL;
+    h->panel_rows = rows;
+    return MPDET_OK;
 }
 
 int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c, const int32_t *info_dev,
@@ -572,10 +611,10 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
             case BP_PIVOT: return 2;
             case BP_DIVIDE: return m;
             case BP_UPD:
-                if (use_mfma) return (mpk::mfma_update_blocks(m) + 7) / 8 * 8;
+                if (use_mfma) return (mpk::mfma_update_blocks(m, m) + 7) / 8 * 8;
                 return lane_valu ? mpk::lane_update_blocks(m) : m * m;
             case BP_PREP: return 2 * m;
-            case BP_SUB: return mpk::finish_blocks(m, P);
+            case BP_SUB: return mpk::finish_blocks(m, m, P);
         }
         return 0;
     };
@@ -634,9 +673,9 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
         const int64_t n = A_arr[b].rows, m = n > 1 ? n - 1 : 1;
         size_t need = up((size_t)(P + 3) * 4u);
         if (use_mfma)
-            need += up((size_t)m * geo.LR) + up(mpk::ub_bytes(m, P)) + up(mfma_rec_bytes(m, P));
+            need += up((size_t)m * geo.LR) + up(mpk::ub_bytes(m, P)) + up(mfma_rec_bytes(m, m, P));
         else if (lane_valu)
-            need += up(mfma_rec_bytes(m, P));
+            need += up(mfma_rec_bytes(m, m, P));
         scratch[(size_t)b] = need;
         total_scratch += need;
     }
