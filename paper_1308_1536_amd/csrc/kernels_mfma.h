@@ -529,6 +529,47 @@ __host__ __device__ inline int64_t finish_blocks(int64_t rows, int64_t m, int P)
 // record slots of `rows` rows of an m x m trailing block: rows x njb blocks of 32 columns
 __host__ __device__ inline int64_t rec_slots(int64_t rows, int64_t m) { return rows * ((m + 31) / 32) * 32; }
 
+// Length of G = X 2^gsh +- (Y >> (32w + b)) (-+ a sticky unit) from the top
+// three limbs of both terms (leading-zero anticipation); xl(q), yl(q) give
+// limb q of X and Y (0 outside 0..P-1).  H, the same combination of limbs
+// P-2 .. P alone, differs from G's limbs P-2 .. P by the carry (+1) or borrow
+// (-1, sticky included) out of the limbs below, which changes H's length only
+// if H is all ones (addition) or a power of two (subtraction).  Outside those
+// cases, and if H has at least 32 bits (the normalised result then starts no
+// more than one limb below G's limb order, so it can be written while G is
+// formed), *len = G's bit length and the result is true.
+template <typename XL, typename YL>
+__device__ __forceinline__ bool lza_length(int P, int gsh, int w, int b, bool subtract, XL xl, YL yl, int *len) {
+    uint32_t hx[3], hy[3];
+#pragma unroll
+    for (int z = 0; z < 3; ++z) {
+        const int q = P - 2 + z;
+        hx[z] = gsh ? __builtin_amdgcn_alignbit(xl(q), xl(q - 1), 32 - gsh) : xl(q);
+        hy[z] = __builtin_amdgcn_alignbit(yl(q + w + 1), yl(q + w), b);
+    }
+    // H as one 96-bit value: two 64-bit words
+    const uint64_t xlo = ((uint64_t)hx[1] << 32) | hx[0], ylo64 = ((uint64_t)hy[1] << 32) | hy[0];
+    uint64_t hlo, hhi;
+    if (subtract) {
+        hlo = xlo - ylo64;
+        hhi = (uint64_t)hx[2] - hy[2] - (xlo < ylo64 ? 1u : 0u);
+    } else {
+        hlo = xlo + ylo64;
+        hhi = (uint64_t)hx[2] + hy[2] + (hlo < xlo ? 1u : 0u);
+    }
+    const int hbits = hhi ? 64 + 64 - __clzll(hhi) : (hlo ? 64 - __clzll(hlo) : 0);
+    bool ambiguous;
+    if (subtract) {  // a power of two
+        const uint64_t mlo = hlo - 1, mhi = hhi - (hlo == 0 ? 1u : 0u);
+        ambiguous = (hlo & mlo) == 0 && (hhi & mhi) == 0;
+    } else {  // all ones below the top bit: H + 1 is a power of two
+        const uint64_t plo = hlo + 1, phi = hhi + (plo == 0 ? 1u : 0u);
+        ambiguous = (hlo & plo) == 0 && (hhi & phi) == 0;
+    }
+    *len = 32 * (P - 2) + hbits;
+    return !ambiguous && hbits >= 32;
+}
+
 __device__ __forceinline__ void finish_tile_body(uint32_t *lds, MatDev A, const uint32_t *__restrict__ T, int64_t k,
                                                  int64_t n, int P, int64_t ip0, int64_t rows, int64_t bx) {
     const MfmaGeom g = mfma_geom(P);
@@ -649,7 +690,14 @@ __device__ __forceinline__ void finish_tile_body(uint32_t *lds, MatDev A, const 
                 const int oa = a_is_x ? 0 : w + 1, ot = a_is_x ? w + 1 : 0;
                 const uint32_t ymask = subtract ? 0xFFFFFFFFu : 0u;
                 uint32_t c = subtract ? 1u - st : 0u;
-                uint32_t xprev = 0;
+                uint32_t xprev = 0, gprev = 0;
+                // single pass where G's length is known from its top limbs: step
+                // q writes result limb q - w0 - 1 (at or below the limb it reads)
+                // instead of G limb q; result limb -1 goes to the unused row P
+                int flen = 0;
+                const bool fast = lza_length(P, gsh, w, b, subtract, [&](int q) { return a_is_x ? al(q) : tl(q); },
+                                             [&](int q) { return a_is_x ? tl(q) : al(q); }, &flen);
+                const int fw0 = flen - pbits >= 0 ? 0 : -1, fbb = flen - pbits - 32 * fw0;
                 uint32_t ylo = a_is_x ? tl(w) : al(w);
                 uint32_t wlo = rw(ot);  // record word of t limb q + ot, streamed upwards
                 // record words W(ot + 1 + q), q = 0..P, in a ring of PF registers
@@ -678,7 +726,10 @@ __device__ __forceinline__ void finish_tile_body(uint32_t *lds, MatDev A, const 
                     const uint32_t xg = gsh ? __builtin_amdgcn_alignbit(xq, xprev, 32 - gsh) : xq;
                     const uint32_t ysh = __builtin_amdgcn_alignbit(yhi, ylo, b);
                     const uint64_t t = (uint64_t)xg + (ysh ^ ymask) + c;
-                    col[q * FTP] = (uint32_t)t;
+                    const uint32_t gq = (uint32_t)t;
+                    const int row = fast ? (q - fw0 - 1 >= 0 ? q - fw0 - 1 : P) : q;
+                    col[row * FTP] = fast ? __builtin_amdgcn_alignbit(gq, gprev, fbb) : gq;
+                    gprev = gq;
                     c = (uint32_t)(t >> 32);
                     xprev = xq;
                     ylo = yhi;
@@ -696,6 +747,10 @@ __device__ __forceinline__ void finish_tile_body(uint32_t *lds, MatDev A, const 
                 }
                 // pass 2: normalise G (limbs 0..P, G < 2^(p+2)) to p bits, in place
                 int qt = P;
+                if (fast) {
+                    *eo = eX - gsh - pbits + flen;
+                    *so = sX;
+                } else {
                 while (qt >= 0 && col[qt * FTP] == 0u) --qt;
                 if (qt < 0) {
                     for (int q = 0; q < P; ++q) col[q * FTP] = 0u;
@@ -723,6 +778,7 @@ __device__ __forceinline__ void finish_tile_body(uint32_t *lds, MatDev A, const 
                     }
                     *eo = eX - gsh - pbits + L;
                     *so = sX;
+                }
                 }
             }
         }
@@ -807,7 +863,7 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
     auto al = [&](int q) -> uint32_t { return (q >= 0 && q < P) ? am[q] : 0u; };
     uint32_t ylo = 0u, wlo = 0u;
     bool fast = false;  // single pass: the result is written while G is formed
-    int fw0 = 0, fbb = 0;
+    int fw0 = 0, fbb = 0, flen = 0;
     int64_t feout = 0;
     if (live) {
         const int top = (int)(rw(P) >> 31);
@@ -864,51 +920,13 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
         cy = subtract ? 1u - st : 0u;
         ylo = a_is_x ? tl(w) : al(w);
         wlo = rw(ot);
-        // Length of G from its top three limbs (leading-zero anticipation).
-        // H = X' +- Y' over limbs P-2 .. P (X' = X 2^gsh, Y' = Y >> rs) differs
-        // from G's limbs P-2 .. P by the carry (+1) or borrow (-1, sticky
-        // included) out of the limbs below, which changes H's length only if
-        // H is all ones (addition) or a power of two (subtraction).  Outside
-        // those cases, and if G keeps at least 33 bits in its top three limbs
-        // (the normalised result then starts no more than one limb below G's
-        // limb order), the result can be written while G is formed.
-        {
-            auto xl = [&](int q) -> uint32_t { return a_is_x ? al(q) : tl(q); };
-            auto yl = [&](int q) -> uint32_t { return a_is_x ? tl(q) : al(q); };
-            uint32_t hx[3], hy[3];
-#pragma unroll
-            for (int z = 0; z < 3; ++z) {
-                const int q = P - 2 + z;
-                hx[z] = gsh ? __builtin_amdgcn_alignbit(xl(q), xl(q - 1), 32 - gsh) : xl(q);
-                hy[z] = __builtin_amdgcn_alignbit(yl(q + w + 1), yl(q + w), b);
-            }
-            // H as one 96-bit value: two 64-bit words
-            const uint64_t xlo = ((uint64_t)hx[1] << 32) | hx[0], ylo64 = ((uint64_t)hy[1] << 32) | hy[0];
-            uint64_t hlo, hhi;
-            if (subtract) {
-                hlo = xlo - ylo64;
-                hhi = (uint64_t)hx[2] - hy[2] - (xlo < ylo64 ? 1u : 0u);
-            } else {
-                hlo = xlo + ylo64;
-                hhi = (uint64_t)hx[2] + hy[2] + (hlo < xlo ? 1u : 0u);
-            }
-            const int hbits = hhi ? 64 + 64 - __clzll(hhi) : (hlo ? 64 - __clzll(hlo) : 0);
-            bool ambiguous;
-            if (subtract) {  // a power of two
-                const uint64_t mlo = hlo - 1, mhi = hhi - (hlo == 0 ? 1u : 0u);
-                ambiguous = (hlo & mlo) == 0 && (hhi & mhi) == 0;
-            } else {  // all ones below the top bit: H + 1 is a power of two
-                const uint64_t plo = hlo + 1, phi = hhi + (plo == 0 ? 1u : 0u);
-                ambiguous = (hlo & plo) == 0 && (hhi & phi) == 0;
-            }
-            fast = !ambiguous && hbits >= 32;
-            if (fast) {
-                const int L = 32 * (P - 2) + hbits;
-                const int sr = L - pbits;  // -32 .. 3
-                fw0 = sr >= 0 ? 0 : -1;
-                fbb = sr - 32 * fw0;
-                feout = eX - gsh - pbits + L;
-            }
+        fast = lza_length(P, gsh, w, b, subtract, [&](int q) { return a_is_x ? al(q) : tl(q); },
+                          [&](int q) { return a_is_x ? tl(q) : al(q); }, &flen);
+        if (fast) {
+            const int sr = flen - pbits;  // -32 .. 3
+            fw0 = sr >= 0 ? 0 : -1;
+            fbb = sr - 32 * fw0;
+            feout = eX - gsh - pbits + flen;
         }
     }
     eoff[e] = live ? oa : -1;

@@ -214,6 +214,25 @@ def test_streaming_finish_cases(case):
     check_against_oracle(A, "mfma", f"streaming finish {case}")
 
 
+@pytest.mark.parametrize("path", ["valu", "mfma"])
+def test_tile_finish_patterns(path):
+    """The LDS-tile finish (P <= 256) on powers of two and all-ones mantissas
+    with equal exponents: intermediates whose length the top limbs leave open."""
+    P, N = 64, 30
+    A = inputs.random_mantissas((N, N), P, 97, emin=0, emax=1)
+    pats = [np.full(P, 0xFFFFFFFF, np.uint32), np.zeros(P, np.uint32), np.zeros(P, np.uint32)]
+    pats[1][P - 1] = 0x80000000
+    pats[2][P - 1] = 0x80000000
+    pats[2][: P - 1] = 0xFFFFFFFF
+    rng = np.random.default_rng(98)
+    for i in range(N):
+        for j in range(N):
+            if (i * 7 + j) % 3:
+                A.limbs[i, j] = pats[int(rng.integers(0, 3))]
+                A.exp[i, j] = int(rng.integers(0, 2))
+    check_against_oracle(A, path, "tile finish patterns")
+
+
 def test_mfma_digit_carry_extremes():
     """Bytes 0x7F/0x80/0xFF patterns drive every balanced-digit carry case."""
     P = 16
