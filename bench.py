@@ -44,7 +44,7 @@ def FINISH_BYTES(P: int) -> int:
     return 2 * (4 * P + 12) + 4 * (P + 1)
 
 METRIC = "time to det+all D_k+last-col minors at (N,bits); limb-MAC/s vs INT8 MFMA peak"
-DEFAULT_PATH = {1: "valu", 2: "valu", 3: "mfma", 4: "auto"}
+DEFAULT_PATH = {1: "valu", 2: "valu", 3: "mfma", 4: "auto", 5: "mfma"}
 
 
 def workload(cfg: int):
@@ -65,6 +65,10 @@ def workload(cfg: int):
     if cfg == 4:
         return ("config 4: 256 matrices, N uniform in [16,384], 2048-bit, half random mantissas / half "
                 "dyadic Cauchy, one batched elimination", inputs.config_c4())
+    if cfg == 5:
+        c = inputs.config_c5()
+        return ("config 5: N=6144, 32768-bit: dyadic Cauchy, sorted nodes on [0,10000] (155 GB)",
+                [("cauchy", c["cauchy"][0])])
     raise SystemExit(f"bench.py: config {cfg} is not a single-GPU bench workload")
 
 
@@ -160,6 +164,101 @@ def cpu_baseline(A, gpu_D, budget_s: float):
             "seconds": dt, "prefix_D_bit_exact": prefix_ok}
 
 
+def bench_elimination_steps(args):
+    """--factor-steps K: time elimination steps W .. W+K-1 of the workload's
+    first matrix in place (mp_det_factor_steps; the first W steps run untimed,
+    with the workspace allocation), for matrices too large to repeat whole
+    steps of the path on (configuration 5: 155 GB, about 23 minutes a
+    factorisation).  The JSON line is marked as a partial run: `value` is the
+    algorithmic limb-MACs of the K timed elimination steps over their time,
+    and `extrapolated_factor_s` scales each kernel's time to the whole
+    factorisation by its work (trailing-block kernels by the sum of m^2, the
+    multipliers by the sum of m, the pivot by the step count).  The oracle on a
+    leading block checks D_1..D_K' bit for bit (prefix property)."""
+    import numpy as np
+
+    from paper_1308_1536_amd.inputs import MpArray
+    desc, mats = cached_workload(args.config, args.input_cache)
+    name, Ah = mats[0]
+    N, P = Ah.exp.shape[0], Ah.limbs.shape[-1]
+    W = max(0, min(args.warmup, N))
+    K = max(1, min(args.factor_steps, N - W))
+    lead = min(N, 64)
+    Alead = MpArray(Ah.limbs[:lead, :lead].copy(), Ah.exp[:lead, :lead].copy(), Ah.sign[:lead, :lead].copy())
+    print(f"[bench] {desc}: uploading", file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_1308_1536_amd import binding
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    A = binding.DeviceMp.from_host(Ah)
+    del Ah, mats
+    D = binding.DeviceMp.empty(1, N, P)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    path = args.path or DEFAULT_PATH.get(args.config, "mfma")
+    torch.cuda.synchronize()
+    binding.factor_steps(A, D, info, 0, W, path)
+    torch.cuda.synchronize()
+    print(f"[bench] {W} untimed steps done", file=sys.stderr, flush=True)
+    binding.profile_begin()
+    t0 = time.perf_counter()
+    chunk = 8  # report progress every few steps (each is ~1 s at N = 6144, 32K bits)
+    for k0 in range(W, W + K, chunk):
+        binding.factor_steps(A, D, info, k0, min(W + K, k0 + chunk), path)
+        torch.cuda.synchronize()
+        print(f"[bench] elimination steps {k0}..{min(W + K, k0 + chunk) - 1} done", file=sys.stderr, flush=True)
+    secs = time.perf_counter() - t0
+    prof = binding.profile_end()
+    if int(info.item()) != 0:
+        raise SystemExit(f"bench.py: factorisation reported info {int(info.item())}")
+    ms_ = [N - k - 1 for k in range(W, W + K)]
+    all_m = [N - k - 1 for k in range(N)]
+    s2, s2all = sum(m * m for m in ms_), sum(m * m for m in all_m)
+    s1, s1all = sum(ms_), sum(all_m)
+    P8 = 4 * P
+    macs = s2 * P8 * P8
+    ext = 0.0
+    for kname, (kms, _) in prof.items():
+        if kname in ("update_mfma", "update_valu", "update_finish", "mfma_prep"):
+            ext += kms / 1e3 * s2all / s2
+        elif kname == "divide":
+            ext += kms / 1e3 * s1all / s1
+        elif kname == "pivot_divide":
+            ext += kms / 1e3 * N / K
+    roof = None
+    upd_key = "update_mfma" if prof.get("update_mfma", (0, 0))[1] else "update_valu"
+    if prof.get(upd_key, (0, 0))[1]:
+        kms, kn = prof[upd_key]
+        if upd_key == "update_mfma":
+            mp = binding.measure_peak("mfma_i8")
+            ach = macs / (kms / 1e3)
+            roof = {"bound": "mfma", "achieved": 2 * ach / 1e12, "peak": PEAK_INT8_MFMA_TOPS / 1e12,
+                    "unit": "TOP/s", "frac": ach / PEAK_INT8_MAC, "kernel": "k_update_mfma",
+                    "measured_peak": 2 * mp / 1e12, "frac_of_measured_peak": ach / mp, "traffic": None,
+                    "avg_launch_ms": kms / kn, "launches": kn}
+        else:
+            ach = s2 * P * P / (kms / 1e3)
+            roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_VALU_MAC32 / 1e12, "unit": "Tmac32/s",
+                    "frac": ach / PEAK_VALU_MAC32, "kernel": "k_update_valu", "traffic": None,
+                    "avg_launch_ms": kms / kn, "launches": kn}
+    out = {"metric": METRIC, "value": macs / secs, "unit": "limb-MAC/s", "n_gpus": 1, "steps": 1, "warmup": W,
+           "ms_per_step": secs * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "i8" if path == "mfma" else "u32", "data": "synthetic",
+           "config": {"workload": f"{desc} -- elimination steps {W}..{W + K - 1} of {N - 1} only (partial run)",
+                      "N": N, "bits": 32 * P, "matrices": 1, "path": path, "partial": True,
+                      "elimination_steps_timed": K, "limb_macs_timed": macs},
+           "extrapolated_factor_s": ext, "roofline": roof,
+           "kernel_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]}}
+    if not args.no_cpu_baseline:
+        Dh = D.row(0)
+        done = W + K
+        sub = MpArray(Alead.limbs[:min(lead, done), :min(lead, done)],
+                      Alead.exp[:min(lead, done), :min(lead, done)],
+                      Alead.sign[:min(lead, done), :min(lead, done)])
+        out["cpu_baseline"] = cpu_baseline(sub, Dh, args.cpu_budget)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -185,12 +284,20 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy MIB MiB device-to-device once (a kernel of known "
                          "traffic for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--factor-steps", type=int, default=0, metavar="K",
+                    help="time only K elimination steps of the first matrix, after --warmup untimed ones "
+                         "(a partial run for matrices too large to repeat the path on; default for config 5: 24)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build measures one GPU (the method's single-GPU share); "
               "--gpus must be 1", file=sys.stderr, flush=True)
         sys.exit(2)
+    if args.config == 5 and not args.factor_steps:
+        args.factor_steps = 24
+    if args.factor_steps:
+        bench_elimination_steps(args)
+        return
 
     # inputs first: the generator may fork worker processes, which must
     # happen before this process touches the GPU

@@ -181,9 +181,14 @@ def cauchy(x: Sequence, y: Sequence, P: int, workers: int | None = None) -> MpAr
     step = max(1, -(-n // (4 * workers)))
     chunks = [list(range(i, min(n, i + step))) for i in range(0, n, step)]
     import multiprocessing as mpc
+    import sys
     try:
         with mpc.get_context("fork").Pool(workers) as pool:
-            done = sum(pool.map(_cauchy_worker, chunks))
+            done = 0
+            for rows_done in pool.imap_unordered(_cauchy_worker, chunks):
+                done += rows_done
+                if n * m * P >= 4_000_000_000:  # minutes of work: say how far it is
+                    print(f"[inputs] cauchy {n}x{m}: {done}/{n} rows", file=sys.stderr, flush=True)
     finally:
         _SHARED.clear()
     assert done == n
@@ -299,6 +304,12 @@ def config_c2(P: int = 128, N: int = 512) -> dict:
 def config_c3(P: int = 1024, N: int = 2048) -> dict:
     """N=2048, 32768 bits: interlaced dyadic Cauchy on [0, 1000]."""
     cau, x, y = cauchy_dyadic(N, P, config_seed(3), 0.0, 1000.0)
+    return {"cauchy": (cau, x, y)}
+
+
+def config_c5(P: int = 1024, N: int = 6144) -> dict:
+    """N=6144, 32768 bits (155 GB): dyadic Cauchy with sorted nodes on [0, 10000]."""
+    cau, x, y = cauchy_dyadic(N, P, config_seed(5), 0.0, 10000.0)
     return {"cauchy": (cau, x, y)}
 
 
