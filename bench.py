@@ -72,6 +72,13 @@ def workload(cfg: int):
     raise SystemExit(f"bench.py: config {cfg} is not a single-GPU bench workload")
 
 
+def mfma_copies(P: int) -> int:
+    """shifted LDS copies of the digit row the MFMA update keeps per wave (its
+    template argument): 4 where two waves' copies fit 64 KB"""
+    lr = 4 * P + 608
+    return 4 if 4 * lr * 2 <= 64 * 1024 else 1
+
+
 def kernel_source_sha256() -> str:
     import glob
     import hashlib
@@ -233,7 +240,7 @@ def bench_elimination_steps(args):
             mp = binding.measure_peak("mfma_i8")
             ach = macs / (kms / 1e3)
             roof = {"bound": "mfma", "achieved": 2 * ach / 1e12, "peak": PEAK_INT8_MFMA_TOPS / 1e12,
-                    "unit": "TOP/s", "frac": ach / PEAK_INT8_MAC, "kernel": "k_update_mfma",
+                    "unit": "TOP/s", "frac": ach / PEAK_INT8_MAC, "kernel": f"k_update_mfma<{mfma_copies(P)}>",
                     "measured_peak": 2 * mp / 1e12, "frac_of_measured_peak": ach / mp, "traffic": None,
                     "avg_launch_ms": kms / kn, "launches": kn}
         else:
@@ -414,7 +421,8 @@ def main():
             achieved = macs / secs
             mp = measured_peak("mfma_i8")
             r = {"bound": "mfma", "achieved": 2 * achieved / 1e12, "peak": PEAK_INT8_MFMA_TOPS / 1e12,
-                 "unit": "TOP/s", "frac": achieved / PEAK_INT8_MAC, "kernel": kname_of("k_update_mfma"),
+                 "unit": "TOP/s", "frac": achieved / PEAK_INT8_MAC,
+                 "kernel": kname_of("k_update_mfma") + f"<{mfma_copies(P)}>",
                  "measured_peak": 2 * mp / 1e12, "frac_of_measured_peak": achieved / mp}
         else:
             achieved = upd * FINISH_BYTES(P) / secs
