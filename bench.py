@@ -142,6 +142,85 @@ def unit_work(mats):
     return macs, upd
 
 
+# Cauchy matrices of the workloads, by configuration and matrix name: the
+# generator's node parameters, for the closed-form checks
+CAUCHY_NODES = {2: {"cauchy": (512, 2, 0.0, 1000.0)}, 3: {"cauchy": (2048, 3, 0.0, 1000.0)},
+                5: {"cauchy": (6144, 5, 0.0, 10000.0)}}
+
+
+def _mp_int(limbs, e, s, P):
+    """(-1)^s m 2^(e - 32P) as (signed integer m, exponent e - 32P)"""
+    import numpy as np
+    m = int.from_bytes(np.ascontiguousarray(limbs, "<u4").tobytes(), "little")
+    return (-m if s else m), int(e) - 32 * P
+
+
+def _rel_err_bits(got, exact):
+    """log2(|got - exact| / |exact|) for Fractions (-inf when equal)"""
+    import math
+    d = abs(got - exact)
+    if d == 0:
+        return float("-inf")
+    return math.log2(d.numerator) - math.log2(d.denominator) - (math.log2(abs(exact.numerator))
+                                                                - math.log2(exact.denominator))
+
+
+def full_size_checks(cfg, name, A_host, LU_dev, D_host, c_host, size, steps_done=None):
+    """Exact checks at the workload's full size (no oracle run needed):
+    - Cauchy matrices: sampled pivots u_kk against the closed form
+      u_kk = prod_{i<k} (x_k - x_i)(y_i - y_k) / ((x_k - y_k) prod_{i<k} (x_i - y_k)(x_k - y_i)),
+      evaluated exactly; reported as the largest relative error in bits;
+    - after a whole factorisation: the minors' invariant sum_i c_i a_iN = det(A)
+      (exact products and sum), reported relative to sum_i |c_i a_iN| in bits."""
+    import math
+    from fractions import Fraction
+
+    from paper_1308_1536_amd import inputs
+    N, P = A_host.exp.shape[0], A_host.limbs.shape[-1]
+    out = {}
+    spec = CAUCHY_NODES.get(cfg, {}).get(name)
+    if spec is not None:
+        n0, sc, lo, hi = spec
+        x, y = inputs.dyadic_nodes(n0, inputs.config_seed(sc), lo, hi)
+        x, y = [Fraction(v) for v in x[:N]], [Fraction(v) for v in y[:N]]
+        F = max(max(v.denominator for v in x + y).bit_length() - 1, 0)
+        X = [int(v * (1 << F)) for v in x]
+        Y = [int(v * (1 << F)) for v in y]
+        last = N if steps_done is None else min(N, steps_done + 1)
+        ks = sorted(set([0, 1, 2, last - 1] + [int(round(t * (last - 1) / 40)) for t in range(41)]))
+        import torch
+        idx = torch.tensor(ks, device=LU_dev.limbs.device)
+        dl = LU_dev.limbs[idx, idx].cpu().numpy().view("uint32")
+        de = LU_dev.exp[idx, idx].cpu().numpy()
+        ds = LU_dev.sign[idx, idx].cpu().numpy()
+        worst = float("-inf")
+        for t, k in enumerate(ks):
+            num, den = 1, X[k] - Y[k]
+            for i in range(k):
+                num *= (X[k] - X[i]) * (Y[i] - Y[k])
+                den *= (X[i] - Y[k]) * (X[k] - Y[i])
+            exact = Fraction(num << F, den)
+            m, e = _mp_int(dl[t], de[t], ds[t], P)
+            got = Fraction(m) * (Fraction(2) ** e)
+            worst = max(worst, _rel_err_bits(got, exact))
+        out["cauchy_pivots_checked"] = len(ks)
+        out["cauchy_pivot_max_rel_err_bits"] = worst
+        out["cauchy_pivot_bits_lost"] = worst + 32 * P if worst != float("-inf") else 0.0
+    if c_host is not None and steps_done is None:
+        terms = []
+        for i in range(N):
+            mc, ec = _mp_int(c_host.limbs[i], c_host.exp[i], c_host.sign[i], P)
+            ma, ea = _mp_int(A_host.limbs[i, N - 1], A_host.exp[i, N - 1], A_host.sign[i, N - 1], P)
+            terms.append((mc * ma, ec + ea))
+        md, ed = _mp_int(D_host.limbs[N - 1], D_host.exp[N - 1], D_host.sign[N - 1], P)
+        emin = min([e for _, e in terms] + [ed])
+        S = sum(v << (e - emin) for v, e in terms)
+        absS = sum(abs(v) << (e - emin) for v, e in terms)
+        diff = abs(S - (md << (ed - emin)))
+        out["minors_invariant_rel_err_bits"] = (math.log2(diff) - math.log2(absS)) if diff else float("-inf")
+    return out
+
+
 def cpu_baseline(A, gpu_D, budget_s: float):
     """Time the oracle (factor + minors) on the leading K x K block of A, K
     grown until one run takes at least a third of the budget (or K = N)."""
@@ -199,6 +278,9 @@ def bench_elimination_steps(args):
     from paper_1308_1536_amd import binding
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     A = binding.DeviceMp.from_host(Ah)
+    # the pivot check needs only the shape and P of the host matrix
+    Alead_full = MpArray(np.zeros((N, 0, P), np.uint32), np.zeros((N, N), np.int64)[:, :0],
+                         np.zeros((N, 0), np.int32))
     del Ah, mats
     D = binding.DeviceMp.empty(1, N, P)
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
@@ -256,6 +338,9 @@ def bench_elimination_steps(args):
                       "elimination_steps_timed": K, "limb_macs_timed": macs},
            "extrapolated_factor_s": ext, "roofline": roof,
            "kernel_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]}}
+    if not args.no_checks:
+        out["full_size_checks"] = {name: full_size_checks(args.config, name, Alead_full, A, None, None, 0,
+                                                          steps_done=W + K)}
     if not args.no_cpu_baseline:
         Dh = D.row(0)
         done = W + K
@@ -291,6 +376,9 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="before the timed region, copy MIB MiB device-to-device once (a kernel of known "
                          "traffic for scaling rocprofv3 FETCH_SIZE/WRITE_SIZE)")
+    ap.add_argument("--no-checks", action="store_true",
+                    help="skip the exact full-size checks (Cauchy pivots against their closed form, the "
+                         "minors' invariant sum_i c_i a_iN = det)")
     ap.add_argument("--factor-steps", type=int, default=0, metavar="K",
                     help="time only K elimination steps of the first matrix, after --warmup untimed ones "
                          "(a partial run for matrices too large to repeat the path on; default for config 5: 24)")
@@ -450,6 +538,17 @@ def main():
         first = max(range(len(mats)), key=lambda b: mats[b][1].exp.shape[0]) if batched else 0
         gpu_D = Ds[first].row(0)
         out["cpu_baseline"] = cpu_baseline(mats[first][1], gpu_D, args.cpu_budget)
+    if not args.no_checks:
+        # exact checks of the whole run's outputs (the work buffers hold the
+        # last step's factorisation)
+        checks = {}
+        for b, (nm, m) in enumerate(mats):
+            if args.config in CAUCHY_NODES or m.exp.shape[0] <= 600:
+                r = full_size_checks(args.config, nm, m, work[b], Ds[b].row(0), cs[b].row(0), args.size)
+                if r:
+                    checks[nm] = r
+        print("[bench] full-size checks done", file=sys.stderr, flush=True)
+        out["full_size_checks"] = checks
     if compare != "none":
         # the other update path on the same inputs: its time, and whether every
         # D_k and minor it returns has the same bits
