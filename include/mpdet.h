@@ -175,6 +175,24 @@ int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT,
                     const int32_t *info_dev, void *stream);
 
 /*
+ * mp_det_all_minors -- the last-column cofactors of every leading block
+ * (eq. (minorsdef) applied to A_r, the leading r x r block, r = 1..n): row
+ * r-1 of C holds c^(r)_i = (-1)^(i+r) M^(r)_{i,r}, i = 1..r, and zeros above
+ * the diagonal, from mp_det_factor's output.  Elimination without pivoting
+ * factors every leading block with the leading part of the same L and U, so
+ * row r-1 of W = L^-1 is the x of mp_det_minors on A_r; the sweeps are the
+ * adjugate's (all rows at once) and C[r-1][i] = RZ(D_{r-1} W[r-1][i]),
+ * C[r-1][r-1] = D_{r-1} (D_0 = 1).  Row r-1 equals mp_det_minors' c on A_r
+ * bit for bit, and sum_i C[r-1][i] a_ir = D_r.
+ *   LU    n x n factor output;  D  1 x n leading determinants;
+ *   C     n x n output (its own ld);  info_dev  the factorisation's info:
+ *         when it is not 0, C is written as all zeros.
+ * The library allocates a workspace of about n^2 numbers in the handle.
+ */
+int mp_det_all_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat C,
+                      const int32_t *info_dev, void *stream);
+
+/*
  * mp_to_f64 -- (mantissa, exponent) pairs: mant = (-1)^s * RZ_53(m / 2^p) in
  * +-[0.5, 1) and exp_out = exp (zero -> 0.0, 0).  x is any rows x cols matrix;
  * outputs are dense [rows][cols] device arrays.

@@ -15,6 +15,8 @@ blocks), which is an independent, deliberately plain implementation of:
 * the leading determinants D_k (Algorithm 1 step 2.1);
 * the signed last-column minors from the [A I] derivation (Sec. 3);
 * the adjugate adj(A)^T = d det / d A (Sec. 3, Baur-Strassen remark);
+* the last-column minors of every leading block (the minors above applied to
+  each leading block, factored afresh);
 * conversion of a number to a (float64 mantissa, int64 exponent) pair.
 
 Arrays use the element-contiguous host layout: limbs [..., P] uint32,
@@ -230,6 +232,26 @@ def adjugate_t(f: Factorization, threads: int | None = None) -> Mp:
     if rc != 0:
         raise ValueError("mpref_adjugate_t: bad argument")
     return t
+
+
+def all_minors(A, threads: int | None = None) -> Mp:
+    """The last-column cofactors of every leading block: row r-1 is minors()
+    of the factorization of A_r, the leading r x r block, on its first r
+    entries (eq. (minorsdef) per block), zeros above the diagonal.  Each block
+    is factored afresh from A, so nothing is shared between rows."""
+    A = _as_mp(A)
+    n = int(A.exp.shape[0])
+    if A.exp.shape != (n, n):
+        raise ValueError("all_minors: A must be square")
+    C = _zeros((n, n), A.P)
+    for r in range(1, n + 1):
+        block = Mp(A.limbs[:r, :r].copy(), A.exp[:r, :r].copy(), A.sign[:r, :r].copy())
+        f = factor(block, threads)
+        if f.info != 0:
+            raise ValueError("all_minors: leading block %d did not factor (info=%d)" % (r, f.info))
+        c = minors(f, threads)
+        C.limbs[r - 1, :r], C.exp[r - 1, :r], C.sign[r - 1, :r] = c.limbs, c.exp, c.sign
+    return C
 
 
 def to_f64(x) -> tuple[np.ndarray, np.ndarray]:

@@ -80,6 +80,8 @@ def lib() -> ctypes.CDLL:
         L.mp_det_batched.restype = ctypes.c_int
         L.mp_det_adjugate.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, vp, vp]
         L.mp_det_adjugate.restype = ctypes.c_int
+        L.mp_det_all_minors.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, vp, vp]
+        L.mp_det_all_minors.restype = ctypes.c_int
         L.mp_to_f64_scaled.argtypes = [vp, MpdetMat, vp, vp, vp]
         L.mp_to_f64_scaled.restype = ctypes.c_int
         L.mpdet_measure_peak.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
@@ -266,6 +268,18 @@ def adjugate(LU: DeviceMp, D: DeviceMp, info, adjT: DeviceMp | None = None, stre
     return adjT
 
 
+def all_minors(LU: DeviceMp, D: DeviceMp, info, C: DeviceMp | None = None, stream=None) -> DeviceMp:
+    """mp_det_all_minors: row r of C holds the signed last-column cofactors of
+    the leading (r+1) x (r+1) block (zeros above the diagonal)."""
+    n = LU.rows
+    if C is None:
+        C = DeviceMp.empty(n, n, LU.P, LU.limbs.device)
+    h = handle(LU.limbs.device.index or 0)
+    _check("mp_det_all_minors", lib().mp_det_all_minors(h.ptr, LU.mat(), D.mat(), C.mat(), info.data_ptr(),
+                                                        _stream(stream)))
+    return C
+
+
 MPDET_WANT_MINORS = 1
 
 
@@ -330,7 +344,7 @@ def measure_peak(kind: str, device: int = 0) -> float:
 
 
 KERNELS = ("pivot_divide", "divide", "update_valu", "update_mfma", "mfma_prep", "minors_sweep",
-           "minors_final", "update_finish", "adjugate", "other")
+           "minors_final", "update_finish", "adjugate", "all_minors", "other")
 
 
 def profile_begin(device: int = 0):

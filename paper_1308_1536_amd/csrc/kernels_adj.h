@@ -167,4 +167,43 @@ __global__ void __launch_bounds__(64) k_adj_prod(MatDev J, MatDev W, MatDev T, c
              el(W, k, m, P), ex(W, k, m), sg(W, k, m), false, L, P);
 }
 
+// The last-column minors of every leading block (mp_det_all_minors): row r
+// of W, after the sweeps above, is the minors solve of the leading
+// (r+1) x (r+1) block (its multipliers are the leading block of L), so
+// C[r][i] = RZ(D_r W[r][i]) for i < r, C[r][r] = D_r (D_r the determinant of
+// the leading r x r block, D_0 = 1), and 0 above the diagonal -- the same
+// operations, in the same order, as the minors of that block alone.  Block b
+// -> element (b / n, b % n); info != 0 writes zeros.
+__global__ void __launch_bounds__(64) k_all_minors_final(MatDev D, MatDev W, MatDev C, const int32_t *info,
+                                                         int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    const int64_t b = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
+    if (b >= n * n) return;
+    const int64_t r = b / n, i = b % n;
+    uint32_t *cm = el(C, r, i, P);
+    const bool one = *info == 0 && r == 0 && i == 0;
+    if (*info != 0 || i > r || one) {
+        for (int q = mpw::lane(); q < P; q += MP_WAVE) cm[q] = (one && q == P - 1) ? 0x80000000u : 0u;
+        if (mpw::lane() == 0) {
+            ex(C, r, i) = one ? 1 : 0;
+            sg(C, r, i) = 0;
+        }
+        return;
+    }
+    const uint32_t *dm = el(D, 0, r - 1, P);
+    if (i == r) {
+        for (int q = mpw::lane(); q < P; q += MP_WAVE) cm[q] = dm[q];
+        if (mpw::lane() == 0) {
+            ex(C, r, i) = ex(D, 0, r - 1);
+            sg(C, r, i) = sg(D, 0, r - 1);
+        }
+        return;
+    }
+    Lds L(lds_raw, P);
+    mpw::Hdr hd = mpw::load(L.sc.x, dm, ex(D, 0, r - 1), sg(D, 0, r - 1), P);
+    mpw::Hdr hx = load_y(L.sc.ypad, el(W, r, i, P), ex(W, r, i), sg(W, r, i), P);
+    mpw::Hdr hr = mpw::mul(L.sc.t3, hd, hx, P, L.sc);
+    mpw::store(cm, &ex(C, r, i), &sg(C, r, i), L.sc.t3, hr, P);
+}
+
 }  // namespace mpk

@@ -24,10 +24,10 @@
 // events recorded on the launch stream; mpdet_profile_end folds the elapsed
 // times into per-kernel totals.
 enum KernelId { K_PIVOT_DIVIDE = 0, K_DIVIDE, K_UPDATE_VALU, K_UPDATE_MFMA, K_MFMA_PREP, K_MINORS_SWEEP,
-                K_MINORS_FINAL, K_UPDATE_FINISH, K_ADJUGATE, K_OTHER, K_COUNT };
+                K_MINORS_FINAL, K_UPDATE_FINISH, K_ADJUGATE, K_ALL_MINORS, K_OTHER, K_COUNT };
 static const char *kKernelNames[K_COUNT] = {"pivot_divide", "divide",       "update_valu",   "update_mfma",
                                             "mfma_prep",    "minors_sweep", "minors_final",  "update_finish",
-                                            "adjugate",     "other"};
+                                            "adjugate",     "all_minors",    "other"};
 
 struct ProfRec {
     int kernel;
@@ -795,6 +795,53 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
         if ((rc = launch(K_MINORS_FINAL, mpk::k_batch_mfinal, mbase + (size_t)nmax, lds, 0))) return rc;
     }
     return MPDET_OK;
+}
+
+int mp_det_all_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat C, const int32_t *info_dev,
+                      void *stream) {
+    if (!h || !info_dev) return MPDET_EINVAL;
+    const int64_t n = LU.rows;
+    if (n < 1 || !mat_ok(LU, true) || !mat_ok(D, true) || !mat_ok(C, true)) return MPDET_EINVAL;
+    if (LU.cols != n || D.cols < n || C.rows != n || C.cols != n || D.nlimbs != LU.nlimbs ||
+        C.nlimbs != LU.nlimbs)
+        return MPDET_EINVAL;
+    DeviceGuard g(h->device);
+    if (!g.ok) return MPDET_EHIP;
+    hipStream_t s = (hipStream_t)stream;
+    const int P = LU.nlimbs;
+    // workspace: W (n x n), in the adjugate's buffer
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t nn = (size_t)n * (size_t)n;
+    const size_t ml = up(nn * (size_t)P * 4u), me = up(nn * 8u), ms = up(nn * 4u);
+    const size_t need = ml + me + ms;
+    if (need > h->aw_bytes) {
+        if (h->aw) (void)hipFree(h->aw);
+        h->aw = nullptr;
+        h->aw_bytes = 0;
+        if (hipMalloc(&h->aw, need) != hipSuccess) {
+            h->aw = nullptr;
+            (void)hipGetLastError();
+            return MPDET_ENOMEM;
+        }
+        h->aw_bytes = need;
+    }
+    uint8_t *base = (uint8_t *)h->aw;
+    mpk::MatDev W{(uint32_t *)base, (int64_t *)(base + ml), (int32_t *)(base + ml + me), n};
+    mpk::MatDev lu = dev(LU), d = dev(D), cm = dev(C);
+    const size_t lds = mpk::pivot_lds_bytes(P);
+    int rc;
+    hipLaunchKernelGGL(mpk::k_adj_init, grid_for(((int64_t)nn + 255) / 256), dim3(256), 0, s, W, n, P, 1);
+    if ((rc = last_launch())) return rc;
+    {
+        Prof pr(h, s, K_ALL_MINORS);
+        for (int64_t j = n - 1; j >= 1; --j) {
+            hipLaunchKernelGGL(mpk::k_adj_w, grid_for((n - j) * j), dim3(64), lds, s, lu, W, info_dev, j, n, P);
+            if ((rc = last_launch())) return rc;
+        }
+        hipLaunchKernelGGL(mpk::k_all_minors_final, grid_for((int64_t)nn), dim3(64), lds, s, d, W, cm, info_dev,
+                           n, P);
+    }
+    return last_launch();
 }
 
 int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT, const int32_t *info_dev,

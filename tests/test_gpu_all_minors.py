@@ -1,0 +1,50 @@
+"""GPU last-column minors of every leading block against the oracle (each
+block factored afresh on the CPU), bit for bit, and row n against the GPU's
+own minors of the whole matrix."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import assert_same, say
+from paper_1308_1536_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def gpu_all(A_host, path):
+    import torch
+    from paper_1308_1536_amd import binding
+    A = binding.DeviceMp.from_host(A_host)
+    D, info = binding.factor(A, path)
+    C = binding.all_minors(A, D, info)
+    c = binding.minors(A, D, info)
+    torch.cuda.synchronize()
+    return C.to_host(), c.to_host(), int(info.item())
+
+
+@pytest.mark.parametrize("N,P,path", [(1, 2, "valu"), (2, 8, "mfma"), (9, 3, "valu"), (20, 8, "mfma"),
+                                      (33, 16, "auto"), (48, 64, "mfma"), (70, 4, "valu")])
+def test_all_minors_match_oracle(N, P, path):
+    say(f"[all_minors] N={N} P={P} {path}")
+    A = inputs.random_mantissas((N, N), P, 900 + N + P)
+    got, c, info = gpu_all(A, path)
+    assert info == 0
+    assert_same(got, oracle.all_minors(A), f"all_minors N={N} P={P}")
+    # row N-1 is the minors vector of the whole matrix
+    assert np.array_equal(got.limbs[-1], c.limbs[0]) and np.array_equal(got.exp[-1], c.exp[0])
+    assert np.array_equal(got.sign[-1], c.sign[0])
+
+
+def test_all_minors_cauchy():
+    say("[all_minors] cauchy N=40 P=64")
+    A, _, _ = inputs.cauchy_dyadic(40, 64, 78)
+    got, _, info = gpu_all(A, "auto")
+    assert info == 0
+    assert_same(got, oracle.all_minors(A), "all_minors cauchy")
+
+
+def test_all_minors_zero_pivot_gives_zeros():
+    say("[all_minors] zero pivot")
+    A = inputs.from_values([[1, 2, 3], [2, 4, 5], [1, 1, 1]], 8)
+    got, _, info = gpu_all(A, "auto")
+    assert info == 2 and not got.limbs.any() and not got.exp.any() and not got.sign.any()

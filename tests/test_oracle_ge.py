@@ -167,6 +167,51 @@ def test_prefix_property(oracle_lib):
         assert np.array_equal(part.LU.limbs, full.LU.limbs[:K, :K])
 
 
+def test_all_minors_exact_case_and_cofactors(oracle_lib):
+    """Every row of all_minors against the exact last-column cofactors of its
+    leading block: bit for bit in the exact case (integer L, power-of-two
+    pivots), to within rounding on small random integer matrices (Laplace)."""
+    A, L, U = inputs.triangular_product(7, 4, 9)
+    C = vals(oracle_lib.all_minors(A, threads=2))
+    M = (L.astype(object) @ U.astype(object)).tolist()
+    for r in range(1, 8):
+        block = [row[:r] for row in M[:r]]
+        assert list(C[r - 1, :r]) == exact.last_col_cofactors_exact(block), r
+        assert all(C[r - 1, i] == 0 for i in range(r, 7))
+    P = 8
+    rng = np.random.default_rng(17)
+    while True:
+        Mi = rng.integers(-20, 21, size=(6, 6))
+        if all(d != 0 for d in exact.bareiss_leading(Mi)):
+            break
+    C = vals(oracle_lib.all_minors(inputs.from_values(Mi.astype(object), P), threads=1))
+    for r in range(1, 7):
+        cex = exact.last_col_cofactors_exact(Mi[:r, :r].tolist())
+        for i in range(r):
+            if cex[i] == 0:
+                assert abs(C[r - 1, i]) < Fraction(1, 2 ** (32 * P - 40))
+            else:
+                assert exact.bits_agree(C[r - 1, i], cex[i]) > 32 * P - 24, (r, i)
+
+
+def test_all_minors_invariants(oracle_lib):
+    """sum_i C[r-1][i] a_ij = 0 for j < r and = D_r for j = r (Sec. 3, each
+    leading block), exactly evaluated on a random and a Cauchy matrix."""
+    for A in (inputs.random_mantissas((24, 24), 8, 31), inputs.cauchy_dyadic(20, 8, 12)[0]):
+        N = int(A.exp.shape[0])
+        C = vals(oracle_lib.all_minors(A))
+        a = vals(A)
+        D = vals(oracle_lib.factor(A).D)
+        for r in range(1, N + 1):
+            for j in range(r):
+                s = sum(C[r - 1, i] * a[i, j] for i in range(r))
+                scale = sum(abs(C[r - 1, i] * a[i, j]) for i in range(r))
+                if j < r - 1:
+                    assert abs(s) / scale < Fraction(1, 2 ** (256 - 40)), (r, j)
+                else:
+                    assert exact.bits_agree(s, D[r - 1]) > 256 - 40, r
+
+
 def test_thread_count_does_not_change_bits(oracle_lib):
     A = inputs.random_mantissas((33, 33), 3, 5)
     a = oracle_lib.factor(A, threads=1)
