@@ -21,6 +21,15 @@
 // The product's top limbs P-1 .. 2P-1 go to the same record buffer, in the
 // same limb-major layout, as the MFMA path's epilogue writes, and the same
 // finish kernel forms a_ij = RZ_p(a_ij - RZ_p(l_i u_j)).
+//
+// Only those limbs are kept, so the columns below c0 = lane_short_start(P)
+// are not formed at all (a truncated, or "short", product: about 47% fewer
+// multiply-adds at P = 128).  What they would add, E = sum_{r < c0} s_r
+// 2^(28r), is below ND 2^56 2^(28 c0) / (2^28 - 1) < 2^(28 c0 + 36), so the
+// kept limbs of the sum from c0 up are exact unless every bit of it from
+// 28 c0 + 36 up to bit 32 (P - 1) is a one (a carry out of E could then run
+// into limb P-1).  c0 leaves at least 32 such guard bits; when a lane finds
+// them all ones the wave forms the whole product again from column 0.
 #pragma once
 
 #include "kernels_mfma.h"
@@ -40,6 +49,12 @@ __host__ __device__ inline int lane_digits(int P) { return (32 * P + kDigit - 1)
 __host__ __device__ inline size_t lane_lds_bytes(int P) {
     const int nd = lane_digits(P);
     return ((size_t)(nd + kPadLo + kPadHi) * (kLaneFT + 1) + (size_t)kLaneRows * nd) * 4u;
+}
+// first product column formed (0: the whole product): the largest c0 with
+// 28 c0 + 36 + 32 <= 32 (P - 1), when that skips at least one Comba block
+__host__ __device__ inline int lane_short_start(int P) {
+    const int c0 = (32 * (P - 1) - 36 - 32) / kDigit;
+    return c0 >= kLaneW ? c0 : 0;
 }
 // workgroups for an m x m trailing block
 __host__ __device__ inline int64_t lane_update_blocks(int64_t m) {
@@ -112,11 +127,17 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, MatDev A, uint32_t
     uint32_t *rec = T + (ip * njb + jp / 32) * (int64_t)TP * 32 + (jp % 32);
 
     const uint32_t *col = tile + e;  // digit x at col[x * FTP], -kPadLo <= x < ND + kPadHi
+    constexpr int W = kLaneW;
+    for (int c0 = lane_short_start(P);; c0 = 0) {
+    // the guard bits 28 c0 + 36 .. 32 (P - 1) - 1 lie in limbs tw .. P-2
+    const int tb = kDigit * c0 + 36, tw = tb >> 5;
+    const uint32_t tmask = (1u << (tb & 31)) - 1u;
+    uint32_t ones = 0xffffffffu;     // AND of the guard bits (bits below tb forced to one)
     uint64_t carry = 0;              // carry into the next column (< 2^37)
     uint64_t pk = 0;                 // bits of the product not yet emitted as a limb
-    int pkn = 0, lout = 0;           // their count; index of the next limb
-    constexpr int W = kLaneW;
-    for (int r0 = 0; r0 < 2 * ND; r0 += W) {
+    int pkn = (kDigit * c0) & 31;    // their count (zeros stand below bit 28 c0)
+    int lout = (kDigit * c0) >> 5;   // index of the next limb
+    for (int r0 = c0; r0 < 2 * ND; r0 += W) {
         const int alo = max(0, r0 - ND + 1), ahi = min(r0 + W - 1, ND - 1);
         // window w_c = u[r0 + c - a] at a = alo; r0 + c - alo <= ND - 1 + c
         uint32_t wv[W];
@@ -181,12 +202,18 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, MatDev A, uint32_t
             pk |= (t & ((1u << kDigit) - 1u)) << pkn;
             pkn += kDigit;
             if (pkn >= 32) {  // the same on every lane
-                if (lout >= P - 1 && lout < 2 * P) rec[(int64_t)(lout - (P - 1)) * 32] = (uint32_t)pk;
+                if (lout >= P - 1 && lout < 2 * P)
+                    rec[(int64_t)(lout - (P - 1)) * 32] = (uint32_t)pk;
+                else if (lout >= tw && lout < P - 1)
+                    ones &= (uint32_t)pk | (lout == tw ? tmask : 0u);
                 pk >>= 32;
                 pkn -= 32;
                 ++lout;
             }
         }
+    }
+    // a short product whose guard bits are all ones may be missing a carry
+    if (c0 == 0 || !__any(ones == 0xffffffffu)) break;
     }
 }
 

@@ -233,6 +233,31 @@ def test_tile_finish_patterns(path):
     check_against_oracle(A, path, "tile finish patterns")
 
 
+@pytest.mark.parametrize("path,P", [("valu", 16), ("valu", 32), ("valu", 64), ("valu", 128),
+                                    ("mfma", 72), ("mfma", 128), ("mfma", 264), ("mfma", 1024)])
+def test_short_product_guard(path, P):
+    """Both product kernels form only the columns the kept limbs need and redo
+    the whole product when the guard bits below those limbs cannot rule out a
+    carry (all ones) or, with the MFMA path's signed digits, a borrow (all
+    zeros).  Step 0 with a_00 = 1 (so l_i = a_i0 exactly) multiplies
+    all-ones mantissas by 2^(p-1) + 1 (bits below the kept limbs all ones; in
+    balanced digits the skipped part is -1, a borrow) and by all-ones ones
+    (a carry from the skipped columns)."""
+    N = 24 if P <= 264 else 10
+    say(f"[short product guard] {path} P={P}")
+    A = inputs.random_mantissas((N, N), P, 300 + P)
+    ones = np.full(P, 0xFFFFFFFF, np.uint32)
+    top1 = np.zeros(P, np.uint32)
+    top1[P - 1], top1[0] = 0x80000000, 1
+    A.limbs[0, 0, :] = 0
+    A.limbs[0, 0, P - 1] = 0x80000000
+    A.exp[0, 0], A.sign[0, 0] = 1, 0
+    for i in range(1, N):
+        A.limbs[i, 0] = ones if i % 3 else top1
+        A.limbs[0, i] = top1 if i % 2 else ones
+    check_against_oracle(A, path, f"short product guard P={P}")
+
+
 def test_mfma_digit_carry_extremes():
     """Bytes 0x7F/0x80/0xFF patterns drive every balanced-digit carry case."""
     P = 16
@@ -267,7 +292,7 @@ def test_mfma_carry_into_zero_limbs():
     check_against_oracle(A, "mfma", "borrow into zero limbs")
 
 
-@pytest.mark.parametrize("P", [32, 64])
+@pytest.mark.parametrize("P", [32, 64, 128, 264])
 def test_mfma_sparse_bytes(P):
     """Mantissas made mostly of 0x00 and 0xFF bytes: long zero runs, negative
     column sums and all-ones limbs throughout the products."""
