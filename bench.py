@@ -79,6 +79,46 @@ def mfma_copies(P: int) -> int:
     return 4 if 4 * lr * 2 <= 64 * 1024 else 1
 
 
+def lane_issued_mac32(P: int) -> int:
+    """v_mad_u64_u32 the VALU lane product issues per element update: radix-2^28
+    digits, Comba blocks of 8 columns from the first column it forms (the
+    truncated product), full groups only -- a wave's rare second, whole
+    product is not counted.  The algorithmic figure is P^2."""
+    nd = (32 * P + 27) // 28
+    c0 = (32 * (P - 1) - 68) // 28
+    c0 = c0 if c0 >= 8 else 0
+    steps = 0
+    for r0 in range(c0, 2 * nd, 8):
+        steps += max(0, min(r0 + 7, nd - 1) - max(0, r0 - nd + 1) + 1)
+    return 8 * steps
+
+
+def mfma_issued_mac8(P: int) -> int:
+    """int8 MACs the MFMA update issues per element update: every K-step of a
+    chunk is 8 MFMAs of 32x32x32, 8 * 32 * 32 MACs per column, over the chunks
+    from the first one formed (the truncated product); a wave's rare second,
+    whole product is not counted.  The algorithmic figure is (4P)^2."""
+    P8 = 4 * P
+    cs = 0 if P8 >= 1 << 15 else max(0, (32 * P - 88) // 2048)
+    steps = 0
+    for chunk in range(cs, (2 * P8 + 255) // 256):
+        r0 = 256 * chunk
+        c_lo = r0 - 31 - P8
+        c_lo = 0 if c_lo <= 0 else (c_lo + 31) & ~31
+        steps += (min(P8, r0 + 224) - c_lo) // 32 + 1
+    return steps * 8 * 32 * 32
+
+
+def issued(kind: str, P: int, frac: float) -> dict:
+    """What the kernel multiplies per update next to the algorithmic figure,
+    and the share of the unit's peak those issued multiply-adds take."""
+    if kind == "alu":
+        n, alg = lane_issued_mac32(P), P * P
+    else:
+        n, alg = mfma_issued_mac8(P), 16 * P * P
+    return {"issued_per_update": n, "issued_over_algorithmic": n / alg, "issued_frac": frac * n / alg}
+
+
 def kernel_source_sha256() -> str:
     import glob
     import hashlib
@@ -325,6 +365,7 @@ def bench_elimination_steps(args):
                     "unit": "TOP/s", "frac": ach / PEAK_INT8_MAC, "kernel": f"k_update_mfma<{mfma_copies(P)}>",
                     "measured_peak": 2 * mp / 1e12, "frac_of_measured_peak": ach / mp, "traffic": None,
                     "avg_launch_ms": kms / kn, "launches": kn}
+            roof.update(issued("mfma", P, roof["frac"]))
         else:
             ach = s2 * P * P / (kms / 1e3)
             roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_VALU_MAC32 / 1e12, "unit": "Tmac32/s",
@@ -505,6 +546,8 @@ def main():
                  "unit": "Tmac32/s", "frac": achieved / PEAK_VALU_MAC32,
                  "kernel": kname_of("k_prod_lane" if (P <= 128 and P % 4 == 0) else "k_update_valu"),
                  "measured_peak": mp / 1e12, "frac_of_measured_peak": achieved / mp}
+            if P <= 128 and P % 4 == 0:
+                r.update(issued("alu", P, r["frac"]))
         elif kname == "update_mfma":
             achieved = macs / secs
             mp = measured_peak("mfma_i8")
@@ -512,6 +555,7 @@ def main():
                  "unit": "TOP/s", "frac": achieved / PEAK_INT8_MAC,
                  "kernel": kname_of("k_update_mfma") + f"<{mfma_copies(P)}>",
                  "measured_peak": 2 * mp / 1e12, "frac_of_measured_peak": achieved / mp}
+            r.update(issued("mfma", P, r["frac"]))
         else:
             achieved = upd * FINISH_BYTES(P) / secs
             r = {"bound": "hbm", "achieved": achieved / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",

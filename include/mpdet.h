@@ -70,7 +70,8 @@ enum {
 };
 
 enum {
-    MPDET_PATH_AUTO = 0, /* library chooses (MFMA when nlimbs allows it) */
+    MPDET_PATH_AUTO = 0, /* library chooses: MFMA when nlimbs allows it and
+                            is above 64, else VALU */
     MPDET_PATH_VALU = 1, /* 32x32->64-bit integer VALU limb products */
     MPDET_PATH_MFMA = 2  /* exact INT8 MFMA Toeplitz contraction of 8-bit limbs */
 };

@@ -218,7 +218,8 @@ def _resolve(path: str, n: int, P: int) -> int:
 
 def factor(A: DeviceMp, path: str = "auto", D: DeviceMp | None = None, info=None, stream=None):
     """mp_det_factor in place on A.  Returns (D, info) device tensors.
-    path: "auto" (MFMA where the limb count allows), "valu", "mfma" or "tuned"."""
+    path: "auto" (MFMA where the limb count allows and is above 64), "valu",
+    "mfma" or "tuned"."""
     import torch
     n = A.rows
     if D is None:

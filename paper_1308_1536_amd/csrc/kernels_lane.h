@@ -41,14 +41,15 @@ constexpr int kLaneFT = 64;    // columns per workgroup (one per lane)
 constexpr int kLaneRows = 4;   // rows per workgroup (one per wave)
 constexpr int kLaneW = 8;      // product columns per Comba block
 constexpr int kDigit = 28;     // bits per digit of the product
-constexpr int kPadLo = 8;      // zero tile rows below digit 0 ...
+constexpr int kPadLo = 24;     // zero tile rows below digit 0 ...
 constexpr int kPadHi = 8;      // ... and above digit ND-1, read instead of clamping
+constexpr int kPadL = 16;      // zero multiplier digits above digit ND-1
 
 __host__ __device__ inline bool lane_update_ok(int P) { return P <= kLaneMaxP && P % 4 == 0; }
 __host__ __device__ inline int lane_digits(int P) { return (32 * P + kDigit - 1) / kDigit; }
 __host__ __device__ inline size_t lane_lds_bytes(int P) {
     const int nd = lane_digits(P);
-    return ((size_t)(nd + kPadLo + kPadHi) * (kLaneFT + 1) + (size_t)kLaneRows * nd) * 4u;
+    return ((size_t)(nd + kPadLo + kPadHi) * (kLaneFT + 1) + (size_t)kLaneRows * (nd + kPadL)) * 4u;
 }
 // first product column formed (0: the whole product): the largest c0 with
 // 28 c0 + 36 + 32 <= 32 (P - 1), when that skips at least one Comba block
@@ -86,10 +87,11 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, MatDev A, uint32_t
     // tile rows -kPadLo .. ND+kPadHi-1 of FTP words (digit d of element e at
     // row d, column e; rows outside 0..ND-1 hold zeros)
     uint32_t *tile = lds + kPadLo * FTP;
-    uint32_t *lsh = lds + (size_t)(ND + kPadLo + kPadHi) * FTP + wave * ND;  // this wave's multiplier digits
+    // this wave's multiplier digits, kPadL zeros above
+    uint32_t *lsh = lds + (size_t)(ND + kPadLo + kPadHi) * FTP + wave * (ND + kPadL);
     const bool row_ok = ip < m;
     const uint32_t *lm = el(A, k + 1 + (row_ok ? ip : 0), k, P);
-    for (int d = lane; d < ND; d += MP_WAVE) lsh[d] = digit28(lm, P, d);
+    for (int d = lane; d < ND + kPadL; d += MP_WAVE) lsh[d] = d < ND ? digit28(lm, P, d) : 0u;
     {
         const int nt = (int)blockDim.x, tid = (int)threadIdx.x;
         for (int z = tid; z < kPadLo * FTP; z += nt) lds[z] = 0u;
@@ -139,59 +141,56 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, MatDev A, uint32_t
     int lout = (kDigit * c0) >> 5;   // index of the next limb
     for (int r0 = c0; r0 < 2 * ND; r0 += W) {
         const int alo = max(0, r0 - ND + 1), ahi = min(r0 + W - 1, ND - 1);
-        // window w_c = u[r0 + c - a] at a = alo; r0 + c - alo <= ND - 1 + c
-        uint32_t wv[W];
+        // Steps a = alo .. ahi, padded to nb whole blocks of W: a padding step
+        // multiplies a zero digit (a >= ND) or reads only zero rows below digit
+        // 0 (a > r0 + W - 1), so it adds nothing.  In a block starting at a0,
+        // ring slot y & 7 holds u[r0 - a0 + y] for the window y = c - t of step
+        // a0 + t; the slot that column 7 frees receives the next digit down, so
+        // the window turns by renaming and is back in place after W steps.
+        const int nb = (ahi - alo + W) / W;
+        uint32_t R[W];
 #pragma unroll
-        for (int c = 0; c < W; ++c) wv[c] = col[(r0 + c - alo) * FTP];
+        for (int c = 0; c < W; ++c) R[c] = col[(r0 + c - alo) * FTP];
         uint64_t s[W];
 #pragma unroll
         for (int c = 0; c < W; ++c) s[c] = 0;
-        // one step at a: multiply l[a] into the window, then slide it down by
-        // one digit, u[r0 - a - 1] entering (>= -W: a zero pad row below digit 0)
-        auto step = [&](uint32_t la, uint32_t vn) __attribute__((always_inline)) {
+        // a block's digits: l[a0 + t] at lp[t]; the digit entering at step
+        // a0 + t, u[r0 - a0 - t - 1], at up[(W - 1 - t) FTP]; each block moves
+        // lp up and up down by W digits.  Up to one block past the last is
+        // fetched: a <= ahi + 2W - 1 <= ND + 2W - 2 and r0 - a - 1 >= -3W.
+        const uint32_t *lp = lsh + alo;
+        const uint32_t *up = col + (r0 - alo - W) * FTP;
+        auto fetch = [&](uint32_t (&l)[W], uint32_t (&u)[W]) __attribute__((always_inline)) {
 #pragma unroll
-            for (int c = 0; c < W; ++c) s[c] += (uint64_t)la * wv[c];
-#pragma unroll
-            for (int c = W - 1; c > 0; --c) wv[c] = wv[c - 1];
-            wv[0] = vn;
+            for (int t = 0; t < W; ++t) {
+                l[t] = lp[t];
+                u[t] = up[(W - 1 - t) * FTP];
+            }
+            lp += W;
+            up -= W * FTP;
         };
-        const uint32_t *urd = col + (r0 - alo - 1) * FTP;  // row of the digit entering at step alo
-        // groups of four steps, ping-pong buffered: a group's LDS reads are
-        // issued while the previous group computes
-        int a = alo;
-        uint32_t la[4], ua[4], lb[4], ubf[4];
-        auto load4 = [&](uint32_t (&l)[4], uint32_t (&u)[4], int a0) __attribute__((always_inline)) {
+        auto run = [&](const uint32_t (&l)[W], const uint32_t (&u)[W]) __attribute__((always_inline)) {
 #pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                l[t] = lsh[a0 + t];
-                u[t] = urd[-(a0 - alo + t) * FTP];
+            for (int t = 0; t < W; ++t) {
+#pragma unroll
+                for (int c = 0; c < W; ++c) s[c] += (uint64_t)l[t] * R[(c - t) & (W - 1)];
+                R[(W - 1 - t) & (W - 1)] = u[t];
             }
         };
-        auto run4 = [&](const uint32_t (&l)[4], const uint32_t (&u)[4]) __attribute__((always_inline)) {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) step(l[t], u[t]);
-        };
-        const int nfull = (ahi + 1 - alo) / 4;  // full groups
-        int g = 0;
-        if (nfull > 0) {
-            load4(la, ua, a);
-            for (; g + 2 < nfull; g += 2, a += 8) {
-                load4(lb, ubf, a + 4);
-                run4(la, ua);
-                load4(la, ua, a + 8);
-                run4(lb, ubf);
-            }
-            if (g + 1 < nfull) {
-                load4(lb, ubf, a + 4);
-                run4(la, ua);
-                run4(lb, ubf);
-                a += 8;
-            } else {
-                run4(la, ua);
-                a += 4;
-            }
+        // two blocks per iteration, each one's LDS reads issued while the
+        // other computes; the barriers keep a buffer's refill after its use
+        uint32_t lA[W], uA[W], lB[W], uB[W];
+        fetch(lA, uA);
+        int b = 0;
+        for (; b + 2 <= nb; b += 2) {
+            fetch(lB, uB);
+            run(lA, uA);
+            __builtin_amdgcn_sched_barrier(0);
+            fetch(lA, uA);
+            run(lB, uB);
+            __builtin_amdgcn_sched_barrier(0);
         }
-        for (; a <= ahi; ++a) step(lsh[a], urd[-(a - alo) * FTP]);
+        if (b < nb) run(lA, uA);
         // carry the W columns in radix 2^28 (every sum and carry fits 64 bits)
         // and repack the digits into 32-bit limbs; the record keeps limbs
         // P-1 .. 2P-1

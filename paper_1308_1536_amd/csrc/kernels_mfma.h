@@ -757,13 +757,12 @@ __device__ __forceinline__ void finish_tile_body(uint32_t *lds, MatDev A, const 
                 const int na = P - oa;  // step q reads a real limb of a iff q < na
                 const int arow_max = P * FTP;  // LDS offset of row P (reads clamp there)
                 int abase = oa * FTP;           // LDS offset of a's limb q0 + oa
-                auto step1 = [&](int q, int u) __attribute__((always_inline)) {
+                auto step1 = [&](int q, int u, uint32_t ar) __attribute__((always_inline)) {
                     const uint32_t whi = q <= xlim ? ring[u] : 0u;
                     ring[u] = rp[(q + PF) * 32];
                     const uint32_t tsh = sh ? __builtin_amdgcn_alignbit(whi, wlo, 31) : whi;
                     const uint32_t tv = q + ot < P ? tsh : 0u;
                     wlo = whi;
-                    const uint32_t ar = col[min(abase + u * FTP, arow_max)];
                     const uint32_t av = q < na ? ar : 0u;
                     const uint32_t xq = a_is_x ? av : tv;
                     const uint32_t yhi = a_is_x ? tv : av;
@@ -778,16 +777,28 @@ __device__ __forceinline__ void finish_tile_body(uint32_t *lds, MatDev A, const 
                     xprev = xq;
                     ylo = yhi;
                 };
-                // full blocks (one load per step on every path), then the rest
+                // full blocks (one load per step on every path), then the rest.
+                // A block's limbs of a are read from LDS before its steps
+                // write: step u reads row q0 + oa + u and writes row q0 + u or
+                // q0 + u - 1, so no row is read after the block writes it, and
+                // the reads need not wait for the writes.
                 int q0 = 0;
                 for (; q0 + PF <= P + 1; q0 += PF, abase += PF * FTP) {
+                    uint32_t ab[PF];
 #pragma unroll
-                    for (int u = 0; u < PF; ++u) step1(q0 + u, u);
+                    for (int u = 0; u < PF; ++u) ab[u] = col[min(abase + u * FTP, arow_max)];
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) step1(q0 + u, u, ab[u]);
                 }
+                {
+                    uint32_t ab[PF];
 #pragma unroll
-                for (int u = 0; u < PF; ++u) {
-                    if (q0 + u > P) break;
-                    step1(q0 + u, u);
+                    for (int u = 0; u < PF; ++u) ab[u] = col[min(abase + u * FTP, arow_max)];
+#pragma unroll
+                    for (int u = 0; u < PF; ++u) {
+                        if (q0 + u > P) break;
+                        step1(q0 + u, u, ab[u]);
+                    }
                 }
                 // pass 2: normalise G (limbs 0..P, G < 2^(p+2)) to p bits, in place
                 int qt = P;
