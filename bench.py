@@ -205,6 +205,29 @@ def _rel_err_bits(got, exact):
                                                                 - math.log2(exact.denominator))
 
 
+def all_minors_invariant_bits(A_host, C_host, D_host, rows):
+    """Exact check of sampled rows of the minors of every leading block:
+    sum_{i<=r} C[r][i] a_ir = D_{r+1} for the leading (r+1) x (r+1) block
+    (Sec. 3 per block), as log2(|sum - D| / sum |terms|); the worst row."""
+    import math
+    P = A_host.limbs.shape[-1]
+    worst = float("-inf")
+    for r in rows:
+        terms = []
+        for i in range(r + 1):
+            mc, ec = _mp_int(C_host.limbs[r, i], C_host.exp[r, i], C_host.sign[r, i], P)
+            ma, ea = _mp_int(A_host.limbs[i, r], A_host.exp[i, r], A_host.sign[i, r], P)
+            terms.append((mc * ma, ec + ea))
+        md, ed = _mp_int(D_host.limbs[r], D_host.exp[r], D_host.sign[r], P)
+        emin = min([e for _, e in terms] + [ed])
+        S = sum(v << (e - emin) for v, e in terms)
+        absS = sum(abs(v) << (e - emin) for v, e in terms)
+        diff = abs(S - (md << (ed - emin)))
+        if diff:
+            worst = max(worst, math.log2(diff) - math.log2(absS))
+    return worst
+
+
 def full_size_checks(cfg, name, A_host, LU_dev, D_host, c_host, size, steps_done=None):
     """Exact checks at the workload's full size (no oracle run needed):
     - Cauchy matrices: sampled pivots u_kk against the closed form
@@ -392,6 +415,54 @@ def bench_elimination_steps(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_all_minors(args, mats, work, Ds, cs, binfo, infos, P):
+    """mp_det_all_minors on every factored matrix: wall time per pass over the
+    workload, the VALU rate of its row sweeps (N^3/6 - N/6 multiply-subtracts
+    of P-limb numbers, P^2 32-bit MACs each, timed live with HIP events), row
+    N-1 against mp_det_minors bit for bit, and the exact invariant on sampled
+    rows."""
+    import torch
+
+    from paper_1308_1536_amd import binding
+    Cs = [binding.DeviceMp.empty(w.rows, w.rows, P, w.limbs.device) for w in work]
+    info_of = [binfo[b:b + 1] if binfo is not None else infos[b] for b in range(len(work))]
+
+    def run():
+        for w, D, C, inf in zip(work, Ds, Cs, info_of):
+            binding.all_minors(w, D, inf, C)
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    binding.profile_begin()
+    run()
+    prof = binding.profile_end()
+    kms, _ = prof["all_minors"]
+    ops = sum((w.rows ** 3 - w.rows) // 6 for w in work)
+    launches = sum(w.rows - 1 for w in work)
+    rate = ops * P * P / (kms / 1e3)
+    mp = binding.measure_peak("mad64")
+    last_same = all(torch.equal(C.limbs[-1], c.limbs[0]) and torch.equal(C.exp[-1], c.exp[0])
+                    and torch.equal(C.sign[-1], c.sign[0]) for C, c in zip(Cs, cs))
+    checks = {}
+    if not args.no_checks:
+        for (nm, m), C, D in zip(mats, Cs, Ds):
+            n = m.exp.shape[0]
+            rows = sorted(set([0, 1, n // 3, (2 * n) // 3, n - 2, n - 1]) & set(range(n)))
+            checks[nm] = {"rows": rows, "max_rel_err_bits": all_minors_invariant_bits(m, C.to_host(), D.row(0),
+                                                                                      rows)}
+    return {"ms_per_pass": ms, "multiply_subtracts": ops,
+            "roofline": {"bound": "alu", "kernel": "k_adj_w", "achieved": rate / 1e12,
+                         "peak": PEAK_VALU_MAC32 / 1e12, "unit": "Tmac32/s", "frac": rate / PEAK_VALU_MAC32,
+                         "measured_peak": mp / 1e12, "frac_of_measured_peak": rate / mp,
+                         "avg_launch_ms": kms / launches, "launches": launches},
+            "last_row_equals_minors": bool(last_same), "invariant_checks": checks}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -420,6 +491,9 @@ def main():
     ap.add_argument("--no-checks", action="store_true",
                     help="skip the exact full-size checks (Cauchy pivots against their closed form, the "
                          "minors' invariant sum_i c_i a_iN = det)")
+    ap.add_argument("--all-minors", action="store_true",
+                    help="after the timed factorisations, also time mp_det_all_minors (the last-column minors "
+                         "of every leading block) on each matrix and check its rows")
     ap.add_argument("--factor-steps", type=int, default=0, metavar="K",
                     help="time only K elimination steps of the first matrix, after --warmup untimed ones "
                          "(a partial run for matrices too large to repeat the path on; default for config 5: 24)")
@@ -593,6 +667,8 @@ def main():
                     checks[nm] = r
         print("[bench] full-size checks done", file=sys.stderr, flush=True)
         out["full_size_checks"] = checks
+    if args.all_minors:
+        out["all_minors"] = bench_all_minors(args, mats, work, Ds, cs, binfo if batched else None, infos, P)
     if compare != "none":
         # the other update path on the same inputs: its time, and whether every
         # D_k and minor it returns has the same bits

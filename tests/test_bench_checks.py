@@ -50,3 +50,18 @@ def test_checks_see_a_planted_ulp(where):
     r = bench.full_size_checks(2, "cauchy", A, _as_dev(LU), f.D, cc, 0)
     key = "cauchy_pivot_max_rel_err_bits" if where == "pivot" else "minors_invariant_rel_err_bits"
     assert r[key] > -115
+
+
+def test_all_minors_invariant_check():
+    """The check of sampled rows of the minors of every leading block holds on
+    the oracle's all_minors and sees an error of about 2^-76 (relative)
+    planted in a row's largest term."""
+    A, f, _ = _run()
+    C = oracle.all_minors(A)
+    rows = [0, 1, 5, 11]
+    assert bench.all_minors_invariant_bits(A, C, f.D, rows) < -115
+    Cb = C.copy()
+    a = np.array([abs(float(np.ldexp(1.0, int(A.exp[i, 7])))) for i in range(8)])
+    big = int(np.argmax(a * np.array([float(np.ldexp(1.0, int(Cb.exp[7, i]))) for i in range(8)])))
+    Cb.limbs[7, big, 1] ^= np.uint32(1 << 20)
+    assert bench.all_minors_invariant_bits(A, Cb, f.D, [7]) > -115
