@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(64) k_batch_update_valu(const BatchMat *mats, 
 __global__ void __launch_bounds__(64 * kLaneRows) k_batch_prod_lane(const BatchMat *mats, const int32_t *order,
                                                                     const int64_t *off, int cnt, int64_t k, int P) {
     MPK_BATCH_PROLOGUE
-    prod_lane_body(lds_raw, M.A, M.T, M.info, k, M.n, P, loc);
+    prod_lane_body(lds_raw, elim_rank1(M.A, k, M.n), M.T, M.info, P, loc);
 }
 
 __global__ void __launch_bounds__(64) k_batch_prep(const BatchMat *mats, const int32_t *order, const int64_t *off,

@@ -57,10 +57,11 @@ __host__ __device__ inline int lane_short_start(int P) {
     const int c0 = (32 * (P - 1) - 36 - 32) / kDigit;
     return c0 >= kLaneW ? c0 : 0;
 }
-// workgroups for an m x m trailing block
-__host__ __device__ inline int64_t lane_update_blocks(int64_t m) {
-    return ((m + kLaneRows - 1) / kLaneRows) * ((m + kLaneFT - 1) / kLaneFT);
+// workgroups for an mr x mc block (an m x m trailing block: mr = mc = m)
+__host__ __device__ inline int64_t lane_update_blocks(int64_t mr, int64_t mc) {
+    return ((mr + kLaneRows - 1) / kLaneRows) * ((mc + kLaneFT - 1) / kLaneFT);
 }
+__host__ __device__ inline int64_t lane_update_blocks(int64_t m) { return lane_update_blocks(m, m); }
 
 // digit d (bits 28d .. 28d+27) of a P-limb mantissa
 __device__ __forceinline__ uint32_t digit28(const uint32_t *m, int P, int d) {
@@ -69,28 +70,28 @@ __device__ __forceinline__ uint32_t digit28(const uint32_t *m, int P, int d) {
     return __builtin_amdgcn_alignbit(hi, lo, sh) & ((1u << kDigit) - 1u);
 }
 
-// The record of element (i', j') (i' = i - k - 1, j' = j - k - 1) is word x
-// at T[((i' njb + j' / 32) TP + x) 32 + j' % 32], x = 0..P: product limb P-1+x.
-__device__ __forceinline__ void prod_lane_body(uint32_t *lds, MatDev A, uint32_t *T, const int32_t *info, int64_t k,
-                                               int64_t n, int P, int64_t bx) {
+// The record of element (i', j') of the rank-1 update R (i' < R.mr, j' <
+// R.mc) is word x at T[((i' njb + j' / 32) TP + x) 32 + j' % 32], njb =
+// ceil(R.mc / 32), x = 0..P: limb P-1+x of x_i' y_j'.
+__device__ __forceinline__ void prod_lane_body(uint32_t *lds, const Rank1 &R, uint32_t *T, const int32_t *info,
+                                               int P, int64_t bx) {
     if (*info != 0) return;
-    const int64_t m = n - k - 1;
     const int FT = kLaneFT, FTP = FT + 1;
     const int ND = lane_digits(P);
-    const int64_t ncol = (m + FT - 1) / FT;
+    const int64_t ncol = (R.mc + FT - 1) / FT;
     const int64_t rg = bx / ncol, j0 = (bx % ncol) * FT;
-    if (rg * kLaneRows >= m) return;  // uniform over the workgroup
+    if (rg * kLaneRows >= R.mr) return;  // uniform over the workgroup
     const int wave = (int)(threadIdx.x >> 6);
     const int lane = mpw::lane();
     const int64_t ip = rg * kLaneRows + wave;
-    const int cnt = (int)min((int64_t)FT, m - j0);
+    const int cnt = (int)min((int64_t)FT, R.mc - j0);
     // tile rows -kPadLo .. ND+kPadHi-1 of FTP words (digit d of element e at
     // row d, column e; rows outside 0..ND-1 hold zeros)
     uint32_t *tile = lds + kPadLo * FTP;
     // this wave's multiplier digits, kPadL zeros above
     uint32_t *lsh = lds + (size_t)(ND + kPadLo + kPadHi) * FTP + wave * (ND + kPadL);
-    const bool row_ok = ip < m;
-    const uint32_t *lm = el(A, k + 1 + (row_ok ? ip : 0), k, P);
+    const bool row_ok = ip < R.mr;
+    const uint32_t *lm = el(R.X, R.xr + (row_ok ? ip : 0), R.xc, P);
     for (int d = lane; d < ND + kPadL; d += MP_WAVE) lsh[d] = d < ND ? digit28(lm, P, d) : 0u;
     {
         const int nt = (int)blockDim.x, tid = (int)threadIdx.x;
@@ -101,7 +102,7 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, MatDev A, uint32_t
         // neighbours of the next item's, so the loads mostly hit the cache).
         // For w < 2^14, ND <= 147 the quotient is (w * magic) >> 24 exactly.
         // Columns cnt..63 are never read.
-        const uint32_t *urow = el(A, k, k + 1 + j0, P);
+        const uint32_t *urow = el(R.Y, R.yr, R.yc + j0, P);
         const int nw = cnt * ND;
         const uint32_t magic = (1u << 24) / (uint32_t)ND + 1u;
         for (int w0 = 0; w0 < nw; w0 += 8 * nt) {
@@ -123,8 +124,8 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, MatDev A, uint32_t
     const int e = lane;
     if (!row_ok || e >= cnt || lm[P - 1] == 0u) return;
     const int64_t jp = j0 + e;
-    if (el(A, k, k + 1 + jp, P)[P - 1] == 0u) return;  // u_j = 0: a_ij is left as it is
-    const int64_t njb = (m + 31) / 32;
+    if (el(R.Y, R.yr, R.yc + jp, P)[P - 1] == 0u) return;  // u_j = 0: a_ij is left as it is
+    const int64_t njb = (R.mc + 31) / 32;
     const int TP = mfma_geom(P).TP;
     uint32_t *rec = T + (ip * njb + jp / 32) * (int64_t)TP * 32 + (jp % 32);
 
@@ -219,7 +220,13 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, MatDev A, uint32_t
 __global__ void __launch_bounds__(64 * kLaneRows) k_prod_lane(MatDev A, uint32_t *T, const int32_t *info, int64_t k,
                                                               int64_t n, int P) {
     extern __shared__ uint32_t lds_raw[];
-    prod_lane_body(lds_raw, A, T, info, k, n, P, flat_block());
+    prod_lane_body(lds_raw, elim_rank1(A, k, n), T, info, P, flat_block());
+}
+
+// the products of any rank-1 update (k_finish_r1 completes it)
+__global__ void __launch_bounds__(64 * kLaneRows) k_prod_lane_r1(Rank1 R, uint32_t *T, const int32_t *info, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    prod_lane_body(lds_raw, R, T, info, P, flat_block());
 }
 
 }  // namespace mpk

@@ -614,29 +614,43 @@ __device__ __forceinline__ bool lza_length(int P, int gsh, int w, int b, bool su
     return !ambiguous && hbits >= 32;
 }
 
-__device__ __forceinline__ void finish_tile_body(uint32_t *lds, MatDev A, const uint32_t *__restrict__ T, int64_t k,
-                                                 int64_t n, int P, int64_t ip0, int64_t rows, int64_t bx) {
-    const MfmaGeom g = mfma_geom(P);
+// A rank-1 update z_ab <- RZ_p(z_ab - RZ_p(x_a y_b)) over a block of mr rows
+// and mc columns: x_a = X[xr + a][xc], y_b = Y[yr][yc + b], z_ab = Z[zr + a][zc
+// + b].  Step k of the elimination is X = Y = Z = A with x the multipliers of
+// column k, y the pivot row and z the trailing block; a row sweep of L^-1 is
+// another instance (mp_det_all_minors, mp_det_adjugate).  The z block must not
+// overlap the x column or the y row.
+struct Rank1 {
+    MatDev X, Y, Z;
+    int64_t xr, xc, yr, yc, zr, zc, mr, mc;
+};
+__host__ __device__ inline Rank1 elim_rank1(MatDev A, int64_t k, int64_t n) {
     const int64_t m = n - k - 1;
-    const int64_t njb = (m + 31) / 32;
+    return Rank1{A, A, A, k + 1, k, k, k + 1, k + 1, k + 1, m, m};
+}
+
+__device__ __forceinline__ void finish_tile_body(uint32_t *lds, const Rank1 &R, const uint32_t *__restrict__ T,
+                                                 int P, int64_t ip0, int64_t rows, int64_t bx) {
+    const MfmaGeom g = mfma_geom(P);
+    const int64_t njb = (R.mc + 31) / 32;
     const int FT = finish_tile(P), FTP = FT + 1;
-    const int64_t ntile = (m + FT - 1) / FT;
+    const int64_t ntile = (R.mc + FT - 1) / FT;
     const int64_t ip = ip0 + bx / ntile, j0 = (bx % ntile) * FT;
-    if (bx / ntile >= rows || ip >= m) return;
-    const int64_t i = k + 1 + ip;
-    if (el(A, i, k, P)[P - 1] == 0u) return;  // zero multiplier: the row keeps its values
-    const int cnt = (int)min((int64_t)FT, m - j0);
-    uint32_t *arow = el(A, i, k + 1 + j0, P);  // cnt elements, cnt * P contiguous limbs
+    if (bx / ntile >= rows || ip >= R.mr) return;
+    const int64_t i = R.zr + ip, xi = R.xr + ip;
+    if (el(R.X, xi, R.xc, P)[P - 1] == 0u) return;  // zero multiplier: the row keeps its values
+    const int cnt = (int)min((int64_t)FT, R.mc - j0);
+    uint32_t *arow = el(R.Z, i, R.zc + j0, P);  // cnt elements, cnt * P contiguous limbs
     const int lane = mpw::lane();
     const int e = lane;
     const bool live = e < cnt;
-    const int64_t jp = j0 + (live ? e : 0), j = k + 1 + jp;
+    const int64_t jp = j0 + (live ? e : 0), j = R.zc + jp, yj = R.yc + jp;
     // per-lane scalars first, so their latency overlaps the tile copy
     const uint32_t *raw = T + ((ip - ip0) * njb + jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
-    const uint32_t utop = el(A, k, j, P)[P - 1];
+    const uint32_t utop = el(R.Y, R.yr, yj, P)[P - 1];
     const uint32_t rtop = raw[(int64_t)P * 32];
-    const int64_t eik = ex(A, i, k), ekj = ex(A, k, j), ea = ex(A, i, j);
-    const int32_t sik = sg(A, i, k), skj = sg(A, k, j), sa = sg(A, i, j);
+    const int64_t eik = ex(R.X, xi, R.xc), ekj = ex(R.Y, R.yr, yj), ea = ex(R.Z, i, j);
+    const int32_t sik = sg(R.X, xi, R.xc), skj = sg(R.Y, R.yr, yj), sa = sg(R.Z, i, j);
 
     // tile copy in 16-byte chunks, 16 per lane in flight: chunk c holds limbs
     // 4(c mod cpe) .. +3 of element c / cpe, cpe = P / 4 (c < 4096, so the
@@ -684,8 +698,8 @@ __device__ __forceinline__ void finish_tile_body(uint32_t *lds, MatDev A, const 
         auto al = [&](int q) -> uint32_t { return (q >= 0 && q < P) ? col[q * FTP] : 0u; };
         const int64_t et = eik + ekj - 1 + top;
         const int32_t sy = sik ^ skj ^ 1;  // sign of -t
-        int64_t *eo = &ex(A, i, j);
-        int32_t *so = &sg(A, i, j);
+        int64_t *eo = &ex(R.Z, i, j);
+        int32_t *so = &sg(R.Z, i, j);
         if (col[(P - 1) * FTP] == 0u) {  // 0 - t
             for (int q = 0; q < P; ++q) col[q * FTP] = tl(q);
             *eo = et;
@@ -1124,7 +1138,7 @@ __device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, uint32_t *_
                                             int64_t rows, int64_t bx, MatDev D, uint32_t *rw) {
     if (*info != 0) return;
     if constexpr (STREAM) finish_stream_body(lds, A, T, k, n, P, ip0, rows, bx);
-    else finish_tile_body(lds, A, T, k, n, P, ip0, rows, bx);
+    else finish_tile_body(lds, elim_rank1(A, k, n), T, P, ip0, rows, bx);
     // (block 0 of the panel holding row k+1 holds a_{k+1,k+1})
     if (rw != nullptr && ip0 == 0 && bx == 0 && k + 1 < n) {
         __syncthreads();  // the tile's stores are visible to the workgroup, its LDS is free
@@ -1149,6 +1163,14 @@ __global__ void __launch_bounds__(64) k_finish(MatDev A, uint32_t *T, const int3
                                                int64_t n, int P, int64_t ip0, int64_t rows, MatDev D, uint32_t *rw) {
     extern __shared__ uint32_t lds_raw[];
     finish_body<STREAM>(lds_raw, A, T, info, k, n, P, ip0, rows, flat_block(), D, rw);
+}
+
+// The LDS-tile finish of any rank-1 update (P <= 256): all R.mr rows, the
+// records from k_prod_lane_r1; nothing when info != 0.
+__global__ void __launch_bounds__(64) k_finish_r1(Rank1 R, const uint32_t *T, const int32_t *info, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    if (*info != 0) return;
+    finish_tile_body(lds_raw, R, T, P, 0, R.mr, flat_block());
 }
 
 }  // namespace mpk

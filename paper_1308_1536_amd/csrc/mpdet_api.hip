@@ -805,6 +805,38 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
     return MPDET_OK;
 }
 
+// Row sweeps of W = L^-1, j = n-1..1: W_ri <- RZ(W_ri - RZ(W_rj l_ji)) for
+// every row r >= j and column i < j.  Sweep j is a rank-1 update of the
+// (n - j) x j block of W at (j, 0), x the column j of W and y the row j of
+// L, so where the lane product applies it runs on the lane product and the
+// tile finish (the factorisation's record workspace holds its records);
+// otherwise one wave per multiply-subtract (k_adj_w).  Either way every
+// element sees the same operations in the same order.
+static int w_sweeps(mpdet_handle *h, mpk::MatDev lu, mpk::MatDev W, const int32_t *info, int64_t n, int P,
+             hipStream_t s) {
+    int rc;
+    if (mpk::lane_update_ok(P) && n > 1) {
+        MfmaWs w{};
+        if ((rc = mfma_workspace(h, n, P, n, &w))) return rc;
+        const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_lds_bytes(P);
+        for (int64_t j = n - 1; j >= 1; --j) {
+            const mpk::Rank1 R{W, lu, W, j, j, j, 0, j, 0, n - j, j};
+            hipLaunchKernelGGL(mpk::k_prod_lane_r1, grid_for(mpk::lane_update_blocks(n - j, j)),
+                               dim3(64 * mpk::kLaneRows), lds_prod, s, R, w.T, info, P);
+            hipLaunchKernelGGL(mpk::k_finish_r1, grid_for(mpk::finish_blocks(n - j, j, P)), dim3(64), lds_fin, s, R,
+                               (const uint32_t *)w.T, info, P);
+            if ((rc = last_launch())) return rc;
+        }
+        return MPDET_OK;
+    }
+    const size_t lds = mpk::pivot_lds_bytes(P);
+    for (int64_t j = n - 1; j >= 1; --j) {
+        hipLaunchKernelGGL(mpk::k_adj_w, grid_for((n - j) * j), dim3(64), lds, s, lu, W, info, j, n, P);
+        if ((rc = last_launch())) return rc;
+    }
+    return MPDET_OK;
+}
+
 int mp_det_all_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat C, const int32_t *info_dev,
                       void *stream) {
     if (!h || !info_dev) return MPDET_EINVAL;
@@ -842,10 +874,7 @@ int mp_det_all_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat C, c
     if ((rc = last_launch())) return rc;
     {
         Prof pr(h, s, K_ALL_MINORS);
-        for (int64_t j = n - 1; j >= 1; --j) {
-            hipLaunchKernelGGL(mpk::k_adj_w, grid_for((n - j) * j), dim3(64), lds, s, lu, W, info_dev, j, n, P);
-            if ((rc = last_launch())) return rc;
-        }
+        if ((rc = w_sweeps(h, lu, W, info_dev, n, P, s))) return rc;
         hipLaunchKernelGGL(mpk::k_all_minors_final, grid_for((int64_t)nn), dim3(64), lds, s, d, W, cm, info_dev,
                            n, P);
     }
@@ -902,10 +931,7 @@ int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT, 
     if ((rc = last_launch())) return rc;
     {
         Prof pr(h, s, K_ADJUGATE);
-        for (int64_t j = n - 1; j >= 1; --j) {
-            hipLaunchKernelGGL(mpk::k_adj_w, grid_for((n - j) * j), dim3(64), lds, s, lu, W, info_dev, j, n, P);
-            if ((rc = last_launch())) return rc;
-        }
+        if ((rc = w_sweeps(h, lu, W, info_dev, n, P, s))) return rc;
         hipLaunchKernelGGL(mpk::k_adj_s, dim3(1), dim3(64), lds, s, lu, S, info_dev, n, P);
         hipLaunchKernelGGL(mpk::k_adj_diag, dim3((unsigned)n), dim3(64), lds, s, d, S, J, info_dev, n, P);
         hipLaunchKernelGGL(mpk::k_adj_recips, dim3((unsigned)n), dim3(64), lds, s, lu, rw, info_dev, n, P);
