@@ -91,7 +91,7 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, const Rank1 &R, ui
     // this wave's multiplier digits, kPadL zeros above
     uint32_t *lsh = lds + (size_t)(ND + kPadLo + kPadHi) * FTP + wave * (ND + kPadL);
     const bool row_ok = ip < R.mr;
-    const uint32_t *lm = el(R.X, R.xr + (row_ok ? ip : 0), R.xc, P);
+    const uint32_t *lm = r1x(R, row_ok ? ip : 0, P);
     for (int d = lane; d < ND + kPadL; d += MP_WAVE) lsh[d] = d < ND ? digit28(lm, P, d) : 0u;
     {
         const int nt = (int)blockDim.x, tid = (int)threadIdx.x;
@@ -102,7 +102,9 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, const Rank1 &R, ui
         // neighbours of the next item's, so the loads mostly hit the cache).
         // For w < 2^14, ND <= 147 the quotient is (w * magic) >> 24 exactly.
         // Columns cnt..63 are never read.
-        const uint32_t *urow = el(R.Y, R.yr, R.yc + j0, P);
+        // element b of the tile at ub + b * ustep (a row of Y or a column)
+        const uint32_t *ub = r1y(R, j0, P);
+        const int64_t ustep = (R.ydr * R.Y.ld + R.ydc) * (int64_t)P;
         const int nw = cnt * ND;
         const uint32_t magic = (1u << 24) / (uint32_t)ND + 1u;
         for (int w0 = 0; w0 < nw; w0 += 8 * nt) {
@@ -113,7 +115,7 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, const Rank1 &R, ui
                 const int w = min(w0 + u * nt + tid, nw - 1);
                 ee[u] = (int)(((uint64_t)w * magic) >> 24);
                 dd[u] = w - ee[u] * ND;
-                v[u] = digit28(urow + (int64_t)ee[u] * P, P, dd[u]);
+                v[u] = digit28(ub + (int64_t)ee[u] * ustep, P, dd[u]);
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u)
@@ -124,7 +126,7 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, const Rank1 &R, ui
     const int e = lane;
     if (!row_ok || e >= cnt || lm[P - 1] == 0u) return;
     const int64_t jp = j0 + e;
-    if (el(R.Y, R.yr, R.yc + jp, P)[P - 1] == 0u) return;  // u_j = 0: a_ij is left as it is
+    if (r1y(R, jp, P)[P - 1] == 0u) return;  // u_j = 0: a_ij is left as it is
     const int64_t njb = (R.mc + 31) / 32;
     const int TP = mfma_geom(P).TP;
     uint32_t *rec = T + (ip * njb + jp / 32) * (int64_t)TP * 32 + (jp % 32);

@@ -614,20 +614,33 @@ __device__ __forceinline__ bool lza_length(int P, int gsh, int w, int b, bool su
     return !ambiguous && hbits >= 32;
 }
 
-// A rank-1 update z_ab <- RZ_p(z_ab - RZ_p(x_a y_b)) over a block of mr rows
-// and mc columns: x_a = X[xr + a][xc], y_b = Y[yr][yc + b], z_ab = Z[zr + a][zc
-// + b].  Step k of the elimination is X = Y = Z = A with x the multipliers of
-// column k, y the pivot row and z the trailing block; a row sweep of L^-1 is
-// another instance (mp_det_all_minors, mp_det_adjugate).  The z block must not
-// overlap the x column or the y row.
+// A rank-1 update z_ab <- RZ_p(z_ab - RZ_p(x_a s y_b)), s = -1 if yneg else 1,
+// over a block of mr rows and mc columns: x_a = X[xr + a xdr][xc + a xdc],
+// y_b = Y[yr + b ydr][yc + b ydc], z_ab = Z[zr + a][zc + b] (RZ is odd, so
+// yneg gives z + RZ_p(x y)).  Step k of the elimination is X = Y = Z = A with
+// x the multipliers of column k, y the pivot row and z the trailing block;
+// the row sweeps of L^-1 and the adjugate's back substitution and
+// accumulation are other instances.  The z block must not overlap x or y.
 struct Rank1 {
     MatDev X, Y, Z;
-    int64_t xr, xc, yr, yc, zr, zc, mr, mc;
+    int64_t xr, xc, xdr, xdc, yr, yc, ydr, ydc, zr, zc, mr, mc;
+    int32_t yneg;
 };
 __host__ __device__ inline Rank1 elim_rank1(MatDev A, int64_t k, int64_t n) {
     const int64_t m = n - k - 1;
-    return Rank1{A, A, A, k + 1, k, k, k + 1, k + 1, k + 1, m, m};
+    return Rank1{A, A, A, k + 1, k, 1, 0, k, k + 1, 0, 1, k + 1, k + 1, m, m, 0};
 }
+// x_a and y_b of a rank-1 update: limbs, exponent and sign
+__device__ __forceinline__ uint32_t *r1x(const Rank1 &R, int64_t a, int P) {
+    return el(R.X, R.xr + a * R.xdr, R.xc + a * R.xdc, P);
+}
+__device__ __forceinline__ int64_t r1x_e(const Rank1 &R, int64_t a) { return ex(R.X, R.xr + a * R.xdr, R.xc + a * R.xdc); }
+__device__ __forceinline__ int32_t r1x_s(const Rank1 &R, int64_t a) { return sg(R.X, R.xr + a * R.xdr, R.xc + a * R.xdc); }
+__device__ __forceinline__ uint32_t *r1y(const Rank1 &R, int64_t b, int P) {
+    return el(R.Y, R.yr + b * R.ydr, R.yc + b * R.ydc, P);
+}
+__device__ __forceinline__ int64_t r1y_e(const Rank1 &R, int64_t b) { return ex(R.Y, R.yr + b * R.ydr, R.yc + b * R.ydc); }
+__device__ __forceinline__ int32_t r1y_s(const Rank1 &R, int64_t b) { return sg(R.Y, R.yr + b * R.ydr, R.yc + b * R.ydc); }
 
 __device__ __forceinline__ void finish_tile_body(uint32_t *lds, const Rank1 &R, const uint32_t *__restrict__ T,
                                                  int P, int64_t ip0, int64_t rows, int64_t bx) {
@@ -637,20 +650,20 @@ __device__ __forceinline__ void finish_tile_body(uint32_t *lds, const Rank1 &R, 
     const int64_t ntile = (R.mc + FT - 1) / FT;
     const int64_t ip = ip0 + bx / ntile, j0 = (bx % ntile) * FT;
     if (bx / ntile >= rows || ip >= R.mr) return;
-    const int64_t i = R.zr + ip, xi = R.xr + ip;
-    if (el(R.X, xi, R.xc, P)[P - 1] == 0u) return;  // zero multiplier: the row keeps its values
+    const int64_t i = R.zr + ip;
+    if (r1x(R, ip, P)[P - 1] == 0u) return;  // zero multiplier: the row keeps its values
     const int cnt = (int)min((int64_t)FT, R.mc - j0);
     uint32_t *arow = el(R.Z, i, R.zc + j0, P);  // cnt elements, cnt * P contiguous limbs
     const int lane = mpw::lane();
     const int e = lane;
     const bool live = e < cnt;
-    const int64_t jp = j0 + (live ? e : 0), j = R.zc + jp, yj = R.yc + jp;
+    const int64_t jp = j0 + (live ? e : 0), j = R.zc + jp;
     // per-lane scalars first, so their latency overlaps the tile copy
     const uint32_t *raw = T + ((ip - ip0) * njb + jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
-    const uint32_t utop = el(R.Y, R.yr, yj, P)[P - 1];
+    const uint32_t utop = r1y(R, jp, P)[P - 1];
     const uint32_t rtop = raw[(int64_t)P * 32];
-    const int64_t eik = ex(R.X, xi, R.xc), ekj = ex(R.Y, R.yr, yj), ea = ex(R.Z, i, j);
-    const int32_t sik = sg(R.X, xi, R.xc), skj = sg(R.Y, R.yr, yj), sa = sg(R.Z, i, j);
+    const int64_t eik = r1x_e(R, ip), ekj = r1y_e(R, jp), ea = ex(R.Z, i, j);
+    const int32_t sik = r1x_s(R, ip), skj = r1y_s(R, jp) ^ R.yneg, sa = sg(R.Z, i, j);
 
     // tile copy in 16-byte chunks, 16 per lane in flight: chunk c holds limbs
     // 4(c mod cpe) .. +3 of element c / cpe, cpe = P / 4 (c < 4096, so the

@@ -820,7 +820,8 @@ static int w_sweeps(mpdet_handle *h, mpk::MatDev lu, mpk::MatDev W, const int32_
         if ((rc = mfma_workspace(h, n, P, n, &w))) return rc;
         const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_lds_bytes(P);
         for (int64_t j = n - 1; j >= 1; --j) {
-            const mpk::Rank1 R{W, lu, W, j, j, j, 0, j, 0, n - j, j};
+            // x_r = W[r][j] (r >= j), y_i = l_ji (i < j), z = W[r][i]
+            const mpk::Rank1 R{W, lu, W, j, j, 1, 0, j, 0, 0, 1, j, 0, n - j, j, 0};
             hipLaunchKernelGGL(mpk::k_prod_lane_r1, grid_for(mpk::lane_update_blocks(n - j, j)),
                                dim3(64 * mpk::kLaneRows), lds_prod, s, R, w.T, info, P);
             hipLaunchKernelGGL(mpk::k_finish_r1, grid_for(mpk::finish_blocks(n - j, j, P)), dim3(64), lds_fin, s, R,
@@ -936,16 +937,36 @@ int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT, 
         hipLaunchKernelGGL(mpk::k_adj_diag, dim3((unsigned)n), dim3(64), lds, s, d, S, J, info_dev, n, P);
         hipLaunchKernelGGL(mpk::k_adj_recips, dim3((unsigned)n), dim3(64), lds, s, lu, rw, info_dev, n, P);
         if ((rc = last_launch())) return rc;
+        // Where the lane product applies, the back substitution's updates and
+        // the accumulation are rank-1 updates on the lane product and the
+        // tile finish (the same operation on every element, in the same
+        // order, as k_adj_u_upd and k_adj_prod)
+        const bool lane = mpk::lane_update_ok(P);
+        MfmaWs ws{};
+        if (lane && (rc = mfma_workspace(h, n, P, n, &ws))) return rc;
+        const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_lds_bytes(P);
+        auto rank1 = [&](const mpk::Rank1 &R) {
+            hipLaunchKernelGGL(mpk::k_prod_lane_r1, grid_for(mpk::lane_update_blocks(R.mr, R.mc)),
+                               dim3(64 * mpk::kLaneRows), lds_prod, s, R, ws.T, info_dev, P);
+            hipLaunchKernelGGL(mpk::k_finish_r1, grid_for(mpk::finish_blocks(R.mr, R.mc, P)), dim3(64), lds_fin, s,
+                               R, (const uint32_t *)ws.T, info_dev, P);
+        };
         for (int64_t k = n - 1; k >= 1; --k) {
-            hipLaunchKernelGGL(mpk::k_adj_u_upd, grid_for(k * (n - k)), dim3(64), lds, s, lu, J, info_dev, k, n,
-                               P);
+            if (lane)  // x_i = u_ik (i < k), y_j = J_kj (j >= k), z = J_ij
+                rank1(mpk::Rank1{lu, J, J, 0, k, 1, 0, k, k, 0, 1, 0, k, k, n - k, 0});
+            else
+                hipLaunchKernelGGL(mpk::k_adj_u_upd, grid_for(k * (n - k)), dim3(64), lds, s, lu, J, info_dev, k, n,
+                                   P);
             hipLaunchKernelGGL(mpk::k_adj_u_div, dim3((unsigned)(n - k)), dim3(64), lds, s, lu, J,
                                (const uint32_t *)rw, info_dev, k, n, P);
             if ((rc = last_launch())) return rc;
         }
         for (int64_t k = 0; k < n; ++k) {
-            hipLaunchKernelGGL(mpk::k_adj_prod, grid_for((k + 1) * (k + 1)), dim3(64), lds, s, J, W, t, info_dev,
-                               k, P);
+            if (lane)  // x_m = W_km, y_i = J_ik (negated: an addition), z = adjT_mi (m, i <= k)
+                rank1(mpk::Rank1{W, J, t, k, 0, 0, 1, 0, k, 1, 0, 0, 0, k + 1, k + 1, 1});
+            else
+                hipLaunchKernelGGL(mpk::k_adj_prod, grid_for((k + 1) * (k + 1)), dim3(64), lds, s, J, W, t,
+                                   info_dev, k, P);
             if ((rc = last_launch())) return rc;
         }
     }
