@@ -466,6 +466,84 @@ def bench_all_minors(args, mats, work, Ds, cs, binfo, infos, P):
             "last_row_equals_minors": bool(last_same), "invariant_checks": checks}
 
 
+def adjugate_column_bits(A_host, adjT_host, det_host, cols):
+    """Exact check of sampled columns of adj(A)^T: Laplace expansion along
+    column j, sum_i adjT[i][j] a_ij = det(A), as log2(|sum - det| / sum |terms|);
+    the worst column."""
+    import math
+    P = A_host.limbs.shape[-1]
+    N = A_host.exp.shape[0]
+    md, ed = _mp_int(det_host.limbs, det_host.exp, det_host.sign, P)
+    worst = float("-inf")
+    for j in cols:
+        terms = []
+        for i in range(N):
+            mc, ec = _mp_int(adjT_host.limbs[i, j], adjT_host.exp[i, j], adjT_host.sign[i, j], P)
+            ma, ea = _mp_int(A_host.limbs[i, j], A_host.exp[i, j], A_host.sign[i, j], P)
+            terms.append((mc * ma, ec + ea))
+        emin = min([e for _, e in terms] + [ed])
+        S = sum(v << (e - emin) for v, e in terms)
+        absS = sum(abs(v) << (e - emin) for v, e in terms)
+        diff = abs(S - (md << (ed - emin)))
+        if diff:
+            worst = max(worst, math.log2(diff) - math.log2(absS))
+    return worst
+
+
+def bench_backward(args, mats, work, Ds, cs, binfo, infos, P):
+    """The determinant's backward, adj(A)^T = d det / d A (mp_det_adjugate), on
+    every factored matrix: wall time per pass over the workload, the VALU rate
+    of its multiply-adds (2N^3/3 of P-limb numbers per matrix: the row sweeps
+    of L^-1, the back substitution and the accumulation, P^2 32-bit MACs each;
+    timed live with HIP events), column N against the minors bit for bit, and
+    Laplace's expansion along sampled columns evaluated exactly."""
+    import torch
+
+    from paper_1308_1536_amd import binding
+    outs = [binding.DeviceMp.empty(w.rows, w.rows, P, w.limbs.device) for w in work]
+    info_of = [binfo[b:b + 1] if binfo is not None else infos[b] for b in range(len(work))]
+
+    def run():
+        for w, D, t, inf in zip(work, Ds, outs, info_of):
+            binding.adjugate(w, D, inf, t)
+
+    run()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    binding.profile_begin()
+    run()
+    prof = binding.profile_end()
+    kms, _ = prof["adjugate"]
+    ops = sum(2 * w.rows ** 3 // 3 for w in work)
+    rate = ops * P * P / (kms / 1e3)
+    mp = binding.measure_peak("mad64")
+    last_same = all(torch.equal(t.limbs[:, -1], c.limbs[0]) and torch.equal(t.exp[:, -1], c.exp[0])
+                    and torch.equal(t.sign[:, -1], c.sign[0]) for t, c in zip(outs, cs))
+    checks = {}
+    if not args.no_checks:
+        order = sorted(range(len(mats)), key=lambda b: mats[b][1].exp.shape[0])
+        for b in sorted(set([order[0], order[len(order) // 2], order[-1]])):
+            nm, m = mats[b]
+            n = m.exp.shape[0]
+            cols = sorted(set([0, n // 2, n - 1]))
+            Dh = Ds[b].row(0)
+            from paper_1308_1536_amd.binding import HostMp
+            det = HostMp(Dh.limbs[n - 1], Dh.exp[n - 1], Dh.sign[n - 1])
+            checks[f"{b}:{nm}:N={n}"] = {"cols": cols,
+                                         "max_rel_err_bits": adjugate_column_bits(m, outs[b].to_host(), det, cols)}
+    lane = P <= 128 and P % 4 == 0
+    return {"ms_per_pass": ms, "multiply_adds": ops,
+            "roofline": {"bound": "alu", "kernel": "k_prod_lane_r1 + k_finish_r1" if lane else "k_adj_w",
+                         "achieved": rate / 1e12, "peak": PEAK_VALU_MAC32 / 1e12, "unit": "Tmac32/s",
+                         "frac": rate / PEAK_VALU_MAC32, "measured_peak": mp / 1e12,
+                         "frac_of_measured_peak": rate / mp, "region_ms": kms},
+            "last_column_equals_minors": bool(last_same), "laplace_checks": checks}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -497,6 +575,9 @@ def main():
     ap.add_argument("--all-minors", action="store_true",
                     help="after the timed factorisations, also time mp_det_all_minors (the last-column minors "
                          "of every leading block) on each matrix and check its rows")
+    ap.add_argument("--backward", action="store_true",
+                    help="after the timed factorisations, also time the determinant's backward "
+                         "(mp_det_adjugate, adj(A)^T) on each matrix and check it")
     ap.add_argument("--factor-steps", type=int, default=0, metavar="K",
                     help="time only K elimination steps of the first matrix, after --warmup untimed ones "
                          "(a partial run for matrices too large to repeat the path on; default for config 5: 24)")
@@ -672,6 +753,8 @@ def main():
         out["full_size_checks"] = checks
     if args.all_minors:
         out["all_minors"] = bench_all_minors(args, mats, work, Ds, cs, binfo if batched else None, infos, P)
+    if args.backward:
+        out["backward"] = bench_backward(args, mats, work, Ds, cs, binfo if batched else None, infos, P)
     if compare != "none":
         # the other update path on the same inputs: its time, and whether every
         # D_k and minor it returns has the same bits

@@ -65,3 +65,18 @@ def test_all_minors_invariant_check():
     big = int(np.argmax(a * np.array([float(np.ldexp(1.0, int(Cb.exp[7, i]))) for i in range(8)])))
     Cb.limbs[7, big, 1] ^= np.uint32(1 << 20)
     assert bench.all_minors_invariant_bits(A, Cb, f.D, [7]) > -115
+
+
+def test_adjugate_column_check():
+    """Laplace's expansion along sampled columns of the oracle's adj(A)^T
+    holds to within a few bits of p, and a 2^-76 (relative) error planted in
+    a column's largest term is seen."""
+    from paper_1308_1536_amd.binding import HostMp
+    A, f, _ = _run()
+    T = oracle.adjugate_t(f)
+    det = HostMp(f.D.limbs[-1], f.D.exp[-1], f.D.sign[-1])
+    assert bench.adjugate_column_bits(A, T, det, [0, 5, 11]) < -115
+    Tb = T.copy()
+    big = int(np.argmax([int(Tb.exp[i, 5]) + int(A.exp[i, 5]) for i in range(12)]))
+    Tb.limbs[big, 5, 1] ^= np.uint32(1 << 20)
+    assert bench.adjugate_column_bits(A, Tb, det, [5]) > -115
