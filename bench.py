@@ -492,34 +492,36 @@ def adjugate_column_bits(A_host, adjT_host, det_host, cols):
 
 def bench_backward(args, mats, work, Ds, cs, binfo, infos, P):
     """The determinant's backward, adj(A)^T = d det / d A (mp_det_adjugate), on
-    every factored matrix: wall time per pass over the workload, the VALU rate
-    of its multiply-adds (2N^3/3 of P-limb numbers per matrix: the row sweeps
-    of L^-1, the back substitution and the accumulation, P^2 32-bit MACs each;
-    timed live with HIP events), column N against the minors bit for bit, and
-    Laplace's expansion along sampled columns evaluated exactly."""
+    every factored matrix (several matrices at once on separate streams and
+    handles): wall time per pass over the workload, the VALU rate of its
+    multiply-adds over that time (2N^3/3 of P-limb numbers per matrix: the
+    row sweeps of L^-1, the back substitution and the accumulation, P^2
+    32-bit MACs each), column N against the minors bit for bit, and Laplace's
+    expansion along sampled columns evaluated exactly."""
     import torch
 
     from paper_1308_1536_amd import binding
     outs = [binding.DeviceMp.empty(w.rows, w.rows, P, w.limbs.device) for w in work]
     info_of = [binfo[b:b + 1] if binfo is not None else infos[b] for b in range(len(work))]
+    # independent matrices run concurrently: S streams (default priority),
+    # each with a handle (workspace) of its own
+    S = min(4, len(work))
+    streams = [torch.cuda.Stream() for _ in range(S)]
+    handles = [binding.Handle(work[0].limbs.device.index or 0) for _ in range(S)]
 
     def run():
-        for w, D, t, inf in zip(work, Ds, outs, info_of):
-            binding.adjugate(w, D, inf, t)
+        torch.cuda.synchronize()
+        for b, (w, D, t, inf) in enumerate(zip(work, Ds, outs, info_of)):
+            binding.adjugate(w, D, inf, t, stream=streams[b % S], h=handles[b % S])
+        torch.cuda.synchronize()
 
     run()
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         run()
-    torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    binding.profile_begin()
-    run()
-    prof = binding.profile_end()
-    kms, _ = prof["adjugate"]
     ops = sum(2 * w.rows ** 3 // 3 for w in work)
-    rate = ops * P * P / (kms / 1e3)
+    rate = ops * P * P / (ms / 1e3)
     mp = binding.measure_peak("mad64")
     last_same = all(torch.equal(t.limbs[:, -1], c.limbs[0]) and torch.equal(t.exp[:, -1], c.exp[0])
                     and torch.equal(t.sign[:, -1], c.sign[0]) for t, c in zip(outs, cs))
@@ -540,7 +542,7 @@ def bench_backward(args, mats, work, Ds, cs, binfo, infos, P):
             "roofline": {"bound": "alu", "kernel": "k_prod_lane_r1 + k_finish_r1" if lane else "k_adj_w",
                          "achieved": rate / 1e12, "peak": PEAK_VALU_MAC32 / 1e12, "unit": "Tmac32/s",
                          "frac": rate / PEAK_VALU_MAC32, "measured_peak": mp / 1e12,
-                         "frac_of_measured_peak": rate / mp, "region_ms": kms},
+                         "frac_of_measured_peak": rate / mp, "streams": S},
             "last_column_equals_minors": bool(last_same), "laplace_checks": checks}
 
 

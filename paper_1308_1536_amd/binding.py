@@ -258,24 +258,29 @@ def minors(LU: DeviceMp, D: DeviceMp, info, c: DeviceMp | None = None, stream=No
     return c
 
 
-def adjugate(LU: DeviceMp, D: DeviceMp, info, adjT: DeviceMp | None = None, stream=None) -> DeviceMp:
-    """mp_det_adjugate: adj(A)^T = d det / d A from the factored matrix."""
+def adjugate(LU: DeviceMp, D: DeviceMp, info, adjT: DeviceMp | None = None, stream=None,
+             h: Handle | None = None) -> DeviceMp:
+    """mp_det_adjugate: adj(A)^T = d det / d A from the factored matrix.  `h`:
+    a handle of one's own (its workspace), e.g. to run calls on several
+    streams at once; default: the device's shared handle."""
     n = LU.rows
     if adjT is None:
         adjT = DeviceMp.empty(n, n, LU.P, LU.limbs.device)
-    h = handle(LU.limbs.device.index or 0)
+    h = h or handle(LU.limbs.device.index or 0)
     _check("mp_det_adjugate", lib().mp_det_adjugate(h.ptr, LU.mat(), D.mat(), adjT.mat(), info.data_ptr(),
                                                     _stream(stream)))
     return adjT
 
 
-def all_minors(LU: DeviceMp, D: DeviceMp, info, C: DeviceMp | None = None, stream=None) -> DeviceMp:
+def all_minors(LU: DeviceMp, D: DeviceMp, info, C: DeviceMp | None = None, stream=None,
+               h: Handle | None = None) -> DeviceMp:
     """mp_det_all_minors: row r of C holds the signed last-column cofactors of
-    the leading (r+1) x (r+1) block (zeros above the diagonal)."""
+    the leading (r+1) x (r+1) block (zeros above the diagonal).  `h` as for
+    adjugate()."""
     n = LU.rows
     if C is None:
         C = DeviceMp.empty(n, n, LU.P, LU.limbs.device)
-    h = handle(LU.limbs.device.index or 0)
+    h = h or handle(LU.limbs.device.index or 0)
     _check("mp_det_all_minors", lib().mp_det_all_minors(h.ptr, LU.mat(), D.mat(), C.mat(), info.data_ptr(),
                                                         _stream(stream)))
     return C
