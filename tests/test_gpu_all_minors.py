@@ -48,3 +48,23 @@ def test_all_minors_zero_pivot_gives_zeros():
     A = inputs.from_values([[1, 2, 3], [2, 4, 5], [1, 1, 1]], 8)
     got, _, info = gpu_all(A, "auto")
     assert info == 2 and not got.limbs.any() and not got.exp.any() and not got.sign.any()
+
+
+@pytest.mark.parametrize("P", [8, 64])
+def test_padded_leading_dimensions(P):
+    """Factor, adjugate and all-minors with every matrix at a padded leading
+    dimension (the rank-1 kernels step through rows and columns by ld)."""
+    import torch
+    from paper_1308_1536_amd import binding
+    N = 37
+    say(f"[all_minors] padded ld N={N} P={P}")
+    A_host = inputs.random_mantissas((N, N), P, 4100 + P)
+    A = binding.DeviceMp.from_host(A_host, ld=N + 5)
+    D, info = binding.factor(A, "valu")
+    C = binding.all_minors(A, D, info, binding.DeviceMp.empty(N, N, P, "cuda", ld=N + 3))
+    T = binding.adjugate(A, D, info, binding.DeviceMp.empty(N, N, P, "cuda", ld=N + 7))
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    f = oracle.factor(A_host)
+    assert_same(C.to_host(), oracle.all_minors(A_host), "all_minors padded ld")
+    assert_same(T.to_host(), oracle.adjugate_t(f), "adjugate padded ld")
