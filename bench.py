@@ -99,10 +99,10 @@ def mfma_issued_mac8(P: int) -> int:
     from the first one formed (the truncated product); a wave's rare second,
     whole product is not counted.  The algorithmic figure is (4P)^2."""
     P8 = 4 * P
-    cs = 0 if P8 >= 1 << 15 else max(0, (32 * P - 88) // 2048)
+    rb = 0 if P8 >= 1 << 15 else max(0, (4 * P - 11) // 32 * 32)
     steps = 0
-    for chunk in range(cs, (2 * P8 + 255) // 256):
-        r0 = 256 * chunk
+    for chunk in range((2 * P8 - rb + 255) // 256):
+        r0 = rb + 256 * chunk
         c_lo = r0 - 31 - P8
         c_lo = 0 if c_lo <= 0 else (c_lo + 31) & ~31
         steps += (min(P8, r0 + 224) - c_lo) // 32 + 1

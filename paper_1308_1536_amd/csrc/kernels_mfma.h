@@ -27,15 +27,16 @@
 // buffer; the finish kernel truncates the product to p bits and forms
 // RZ_p(a_ij - RZ_p(l_i u_j)).
 //
-// Truncated product.  Only chunks cs = mfma_short_start(P) and up are formed
-// (at 32K bits 15 of 32 chunks, about 44% of the MFMAs, are skipped).  The
-// skipped columns add E = sum_{r < R0} S_r 256^r, R0 = 256 cs, of either sign,
+// Truncated product.  Only the byte positions r >= R0 = mfma_short_start(P)
+// are formed, in chunks of 256 from R0 (a multiple of the 32-row tile; at
+// 32K bits R0 = 4064 of 8192, about half the MFMAs skipped).  The skipped
+// columns add E = sum_{r < R0} S_r 256^r, of either sign,
 // |E| < (P8+1) 2^14 256^R0 / 255 < 2^(8 R0 + 22) for P8 < 2^15; the kept
 // limbs of the formed sum are those of the whole product unless its bits
 // 8 R0 + 24 .. 32 (P - 1) - 1 (at least 32 of them) are all ones (E > 0 could
 // carry through) or all zeros (E < 0 could borrow through).  A wave in which
 // some column's guard bits are like that forms its products again from
-// chunk 0.
+// R0 = 0.
 #pragma once
 
 #include <type_traits>
@@ -72,12 +73,12 @@ __host__ __device__ inline MfmaGeom mfma_geom(int P) {
 
 __host__ __device__ inline bool mfma_shape_ok(int P) { return P >= 8 && P % 8 == 0; }
 
-// first product chunk formed (0: all): the largest cs with
-// 2048 cs + 24 + 32 <= 32 (P - 1), i.e. at least 32 guard bits
+// first product byte position formed (0: all): the largest multiple R0 of 32
+// with 8 R0 + 24 + 32 <= 32 (P - 1), i.e. at least 32 guard bits
 __host__ __device__ inline int mfma_short_start(int P) {
     if (4 * P >= (1 << 15)) return 0;  // the bound on E above needs P8 < 2^15
-    const int cs = (32 * P - 88) / 2048;
-    return cs > 0 ? cs : 0;
+    const int r = (4 * P - 11) / 32 * 32;
+    return r > 0 ? r : 0;
 }
 
 // Pivot-row digits in fragment-major order: digit c of column j' = 32 jb + j
@@ -332,15 +333,16 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
     // sa - d on, sa = Q - tile_pos(j) + 16h; ash = the start's byte offset mod 4
     const int sa = g.Q - tile_pos(j) + 16 * h;
     const uint32_t ash = (uint32_t)sa & 3u;
-    for (int cs = mfma_short_start(P);; cs = 0) {
+    for (int rb = mfma_short_start(P);; rb = 0) {
     uint32_t xw_prev = 0;  // exchange word of tile 7 of the chunk below (carry into this chunk)
     // guard limbs tw .. P-2 (bits below 24 of limb tw excluded): AND and OR
     // of this lane's share
-    const int tw = 64 * cs;
+    const int tw = rb / 4;
     uint32_t g_and = 0xffffffffu, g_or = 0u;
+    const int nch = (2 * g.P8 - rb + 255) / 256;  // chunks of 256 rows from rb
 
-    for (int chunk = cs; chunk < g.nchunks; ++chunk) {
-        const int r0 = chunk * 256;
+    for (int chunk = 0; chunk < nch; ++chunk) {
+        const int r0 = rb + chunk * 256;
         v16i acc[8];
         int c_lo = r0 - 31 - P8;
         c_lo = c_lo <= 0 ? 0 : ((c_lo + 31) & ~31);
@@ -498,7 +500,7 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
         xw_prev = next_prev;
         // limb q = r0/4 + 8t + 4h + gq of the product; the record keeps P-1 .. 2P-1
         const int qbase = r0 / 4;
-        if (cs > 0 && qbase <= P - 2 && qbase + 63 >= tw) {
+        if (rb > 0 && qbase <= P - 2 && qbase + 63 >= tw) {
 #pragma unroll
             for (int t = 0; t < 8; ++t)
 #pragma unroll
@@ -529,7 +531,7 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
             }
         }
     }
-    if (cs == 0) break;
+    if (rb == 0) break;
     // column j's guard limbs are split between lanes j and j + 32; a column
     // past m or with u_j = 0 has no product to keep
     const uint32_t p_and = partner_of(g_and, g_and, h), p_or = partner_of(g_or, g_or, h);
