@@ -25,7 +25,8 @@ def gpu_adj(A_host, path):
     return adjT.to_host(), int(info.item())
 
 
-@pytest.mark.parametrize("N,P,path", [(1, 2, "valu"), (2, 8, "mfma"), (7, 3, "valu"), (20, 8, "mfma"),
+@pytest.mark.parametrize("N,P,path", [(1, 2, "valu"), (1, 8, "valu"), (2, 8, "valu"), (2, 8, "mfma"),
+                                      (7, 3, "valu"), (20, 8, "mfma"),
                                       (33, 16, "auto"), (48, 64, "mfma")])
 def test_adjugate_matches_oracle(N, P, path):
     say(f"[adj] N={N} P={P} {path}")

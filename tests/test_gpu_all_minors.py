@@ -22,7 +22,7 @@ def gpu_all(A_host, path):
     return C.to_host(), c.to_host(), int(info.item())
 
 
-@pytest.mark.parametrize("N,P,path", [(1, 2, "valu"), (2, 8, "mfma"), (9, 3, "valu"), (20, 8, "mfma"),
+@pytest.mark.parametrize("N,P,path", [(1, 2, "valu"), (1, 8, "valu"), (2, 8, "mfma"), (9, 3, "valu"), (20, 8, "mfma"),
                                       (33, 16, "auto"), (48, 64, "mfma"), (70, 4, "valu")])
 def test_all_minors_match_oracle(N, P, path):
     say(f"[all_minors] N={N} P={P} {path}")
