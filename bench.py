@@ -82,14 +82,15 @@ def mfma_copies(P: int) -> int:
 def lane_issued_mac32(P: int) -> int:
     """v_mad_u64_u32 the VALU lane product issues per element update: radix-2^28
     digits, Comba blocks of 8 columns from the first column it forms (the
-    truncated product), full groups only -- a wave's rare second, whole
-    product is not counted.  The algorithmic figure is P^2."""
+    truncated product), steps padded to whole blocks of 8 -- a wave's rare
+    second, whole product is not counted.  The algorithmic figure is P^2."""
     nd = (32 * P + 27) // 28
     c0 = (32 * (P - 1) - 68) // 28
     c0 = c0 if c0 >= 8 else 0
     steps = 0
     for r0 in range(c0, 2 * nd, 8):
-        steps += max(0, min(r0 + 7, nd - 1) - max(0, r0 - nd + 1) + 1)
+        alo, ahi = max(0, r0 - nd + 1), min(r0 + 7, nd - 1)
+        steps += (ahi - alo + 8) // 8 * 8  # padded to whole blocks of 8 steps
     return 8 * steps
 
 
