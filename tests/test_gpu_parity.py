@@ -100,6 +100,28 @@ def test_zero_pivots(path):
     assert info == 5
 
 
+@pytest.mark.parametrize("P", [264, 520])
+def test_zero_pivot_and_overflow_large_p(P):
+    """At P > 256 the MFMA path examines pivot k+1 on a second stream beside
+    step k's finish, its code going through the pending word: a zero pivot
+    at step 5 and an exponent overflow at step 2 must still stop the
+    factorisation with the oracle's info, D and factors."""
+    A, L, U = inputs.triangular_product(12, P, 4)
+    U[4, 4] = 0
+    A = inputs.from_values((L.astype(object) @ U.astype(object)), P)
+    _, D, _, info = check_against_oracle(A, "mfma", f"zero pivot 5 P={P}")
+    assert info == 5
+    B = inputs.from_values([[1, 0, 0], [0, 1, 0], [0, 0, 1]], P)
+    B.exp[0, 0] = 2 ** 61
+    B.exp[1, 1] = 2 ** 61 + 5
+    B.exp[2, 2] = 2 ** 61
+    say(f"[parity] overflow P={P}")
+    _, D, _, info = gpu_det(B, "mfma")
+    f = oracle.factor(B)
+    assert info == f.info == -1
+    assert_same(D, f.D, "overflow D")
+
+
 @pytest.mark.parametrize("path", PATHS)
 def test_exponent_overflow(path):
     P = 8 if path == "mfma" else 2
