@@ -252,15 +252,6 @@ __global__ void __launch_bounds__(64) k_pivot_recip(MatDev A, MatDev D, int32_t 
     pivot_recip_body(lds_raw, A, D, info, info, rw, k, n, P, (int)blockIdx.x);
 }
 
-// The same, with the zero / overflow code going to the pending word rw[P + 2]
-// (step k+1's divide moves it into info): the factorisation runs this on a
-// second stream while the previous step's finish still reads info.
-__global__ void __launch_bounds__(64) k_pivot_recip_pend(MatDev A, MatDev D, const int32_t *info, uint32_t *rw,
-                                                         int64_t k, int64_t n, int P) {
-    extern __shared__ uint32_t lds_raw[];
-    pivot_recip_body(lds_raw, A, D, info, (int32_t *)(rw + P + 2), rw, k, n, P, (int)blockIdx.x);
-}
-
 // clear the pending pivot code (rw[P + 2]) before a factorisation, and move a
 // code still pending after the last step into info
 __global__ void k_pend_clear(uint32_t *rw, int P) {

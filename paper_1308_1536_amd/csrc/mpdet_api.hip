@@ -62,10 +62,6 @@ struct mpdet_handle {
     size_t bh_bytes;
     hipEvent_t bh_done;
     bool bh_pending;
-    // second stream (default priority) for the next pivot beside the finish,
-    // and the events that order it: row k+1 finished, pivot k+1 done
-    hipStream_t side;
-    hipEvent_t ev_row, ev_piv;
 };
 
 namespace {
@@ -303,17 +299,6 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     return pend_promote(info, rw, P, s);
 }
 
-// the handle's second stream and its two events, created on first use;
-// false if any of them cannot be made (the caller then stays on one stream)
-bool side_stream(mpdet_handle *h) {
-    if (h->side && h->ev_row && h->ev_piv) return true;
-    if (!h->side && hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) h->side = nullptr;
-    if (!h->ev_row && hipEventCreateWithFlags(&h->ev_row, hipEventDisableTiming) != hipSuccess) h->ev_row = nullptr;
-    if (!h->ev_piv && hipEventCreateWithFlags(&h->ev_piv, hipEventDisableTiming) != hipSuccess) h->ev_piv = nullptr;
-    (void)hipGetLastError();
-    return h->side && h->ev_row && h->ev_piv;
-}
-
 int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, int64_t k_begin,
                 int64_t k_end, hipStream_t s) {
     const int64_t n = A.rows;
@@ -332,15 +317,8 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     uint32_t *rw = nullptr;
     if ((rc = recip_ws(h, P, &rw)) || (rc = pend_clear(rw, P, s))) return rc;
     const bool ahead = mpk::finish_lookahead_ok(P);  // the finish launch examines the next pivot
-    // Otherwise (large P: the pivot's LDS would crowd the finish) the finish
-    // of row k+1 goes first, and the pivot of step k+1 runs on the second
-    // stream beside the finish of the other rows; its zero / overflow code
-    // goes to the pending word, and step k+1 waits for it before its divide.
-    const bool overlap = !ahead && side_stream(h);
     for (int64_t k = k_begin; k < k_end; ++k) {
-        const bool piv_done = (ahead || overlap) && k > k_begin;
-        if (overlap && k > k_begin && hipStreamWaitEvent(s, h->ev_piv, 0) != hipSuccess) return MPDET_EHIP;
-        if ((rc = pivot_step(h, a, d, info, rw, k, n, P, piv_done, s))) return rc;
+        if ((rc = pivot_step(h, a, d, info, rw, k, n, P, ahead && k > k_begin, s))) return rc;
         const int64_t m = n - k - 1;
         if (m <= 0) continue;
         {
@@ -359,31 +337,7 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
                                    (const uint8_t *)w.Ub, w.T, cinfo, k, n, P, ip0, rows);
             }
             if ((rc = last_launch())) return rc;
-            if (overlap && ip0 == 0 && k + 1 < k_end) {
-                // row k+1 (panel row 0), the next pivot on the second stream,
-                // then the panel's other rows (their records one row further on)
-                const size_t rec_row = (size_t)((m + 31) / 32) * 32u * (size_t)mpk::mfma_geom(P).TP;
-                {
-                    Prof pr(h, s, K_UPDATE_FINISH);
-                    hipLaunchKernelGGL(fin_kernel, grid_for(mpk::finish_blocks(1, m, P)), dim3(64), lds_fin, s, a,
-                                       w.T, cinfo, k, n, P, (int64_t)0, (int64_t)1, d, (uint32_t *)nullptr);
-                }
-                if ((rc = last_launch())) return rc;
-                if (hipEventRecord(h->ev_row, s) != hipSuccess || hipStreamWaitEvent(h->side, h->ev_row, 0) != hipSuccess)
-                    return MPDET_EHIP;
-                // (not profiled: it overlaps the finish, and its event pair would
-                // time the wait for a free CU as well)
-                hipLaunchKernelGGL(mpk::k_pivot_recip_pend, dim3(2), dim3(64), mpk::pivot_lds_bytes(P), h->side, a, d,
-                                   cinfo, rw, k + 1, n, P);
-                if ((rc = last_launch())) return rc;
-                if (hipEventRecord(h->ev_piv, h->side) != hipSuccess) return MPDET_EHIP;
-                if (rows > 1) {
-                    Prof pr(h, s, K_UPDATE_FINISH);
-                    hipLaunchKernelGGL(fin_kernel, grid_for(mpk::finish_blocks(rows - 1, m, P)), dim3(64), lds_fin, s,
-                                       a, w.T + rec_row, cinfo, k, n, P, (int64_t)1, rows - 1, d,
-                                       (uint32_t *)nullptr);
-                }
-            } else {
+            {
                 Prof pr(h, s, K_UPDATE_FINISH);
                 hipLaunchKernelGGL(fin_kernel, grid_for(mpk::finish_blocks(rows, m, P)), dim3(64), lds_fin, s, a,
                                    w.T, cinfo, k, n, P, ip0, rows, d, ahead ? rw : nullptr);
@@ -435,9 +389,6 @@ int mpdet_destroy(mpdet_handle *h) {
     if (h->bw) (void)hipFree(h->bw);
     if (h->bh) (void)hipHostFree(h->bh);
     if (h->bh_done) (void)hipEventDestroy(h->bh_done);
-    if (h->ev_row) (void)hipEventDestroy(h->ev_row);
-    if (h->ev_piv) (void)hipEventDestroy(h->ev_piv);
-    if (h->side) (void)hipStreamDestroy(h->side);
     free(h);
     return MPDET_OK;
 }

@@ -102,10 +102,10 @@ def test_zero_pivots(path):
 
 @pytest.mark.parametrize("P", [264, 520])
 def test_zero_pivot_and_overflow_large_p(P):
-    """At P > 256 the MFMA path examines pivot k+1 on a second stream beside
-    step k's finish, its code going through the pending word: a zero pivot
-    at step 5 and an exponent overflow at step 2 must still stop the
-    factorisation with the oracle's info, D and factors."""
+    """At P > 256 the MFMA path runs each pivot in a launch of its own (no
+    look-ahead inside the finish): a zero pivot at step 5 and an exponent
+    overflow at step 2 must stop the factorisation with the oracle's info, D
+    and factors."""
     A, L, U = inputs.triangular_product(12, P, 4)
     U[4, 4] = 0
     A = inputs.from_values((L.astype(object) @ U.astype(object)), P)
