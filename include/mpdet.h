@@ -170,7 +170,11 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
  *   LU    n x n factor output;  D  1 x n leading determinants;
  *   adjT  n x n output (its own ld);  info_dev  the factorisation's info:
  *         when it is not 0, adjT is written as all zeros.
- * The library allocates a workspace of about 2 n^2 numbers in the handle.
+ * The library allocates a workspace of about 2 n^2 numbers in the handle,
+ * and, where the lane product applies (nlimbs <= 128, a multiple of 4), the
+ * factorisation's record buffer for an n x n block (n * ceil(n/32) * 32
+ * records of nlimbs + 4 words); the O(n^3) phases then run as rank-1 updates
+ * on the factorisation's kernels, with the same bits.
  */
 int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT,
                     const int32_t *info_dev, void *stream);
@@ -188,7 +192,8 @@ int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT,
  *   LU    n x n factor output;  D  1 x n leading determinants;
  *   C     n x n output (its own ld);  info_dev  the factorisation's info:
  *         when it is not 0, C is written as all zeros.
- * The library allocates a workspace of about n^2 numbers in the handle.
+ * The library allocates a workspace of about n^2 numbers in the handle (plus
+ * the record buffer, as mp_det_adjugate).
  */
 int mp_det_all_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat C,
                       const int32_t *info_dev, void *stream);

@@ -13,7 +13,12 @@
 //           x_{k-1} = RZ(t_{k-1} / u_{k-1,k-1});
 //   adj(A): for k = 0..n-1, acc_im <- RZ(acc_im + RZ(adj(U)_ik W_km)) for
 //           i, m <= k (each entry sums its terms in ascending k).
-// Every launch is one wave per number operation (wave-cooperative limbs).
+// The kernels here take one wave per number operation (wave-cooperative
+// limbs).  Where the lane product applies (P <= 128, P a multiple of 4) the
+// host runs the three O(n^3) phases -- the W sweeps, the back substitution's
+// updates and the accumulation -- as rank-1 updates on the lane product and
+// the tile finish instead (k_prod_lane_r1, k_finish_r1): the same operation
+// on every element, in the same order, so the same bits.
 // Row n-1 of adj(A) is RZ(D_{n-2} W_{n-1,m}), the last-column minors.
 #pragma once
 
