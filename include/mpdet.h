@@ -199,6 +199,17 @@ int mp_det_all_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat C,
                       const int32_t *info_dev, void *stream);
 
 /*
+ * mp_det_normalize_minors -- the normalised minors of eq. (minors):
+ * out[r][i] = RZ_p(C[r][i] / C[r][0]), every row divided by its first entry
+ * (C = mp_det_minors' 1 x n vector gives delta_{N,n} = c_n / c_1; C =
+ * mp_det_all_minors' n x n output gives them for every leading block).
+ *   C    rows x cols input (read only);  out  rows x cols output, its own
+ *        ld, same nlimbs, not overlapping C (else MPDET_EINVAL).
+ * A row whose first entry is zero is written as zeros.
+ */
+int mp_det_normalize_minors(mpdet_handle *h, mpdet_mat C, mpdet_mat out, void *stream);
+
+/*
  * mp_to_f64 -- (mantissa, exponent) pairs: mant = (-1)^s * RZ_53(m / 2^p) in
  * +-[0.5, 1) and exp_out = exp (zero -> 0.0, 0).  x is any rows x cols matrix;
  * outputs are dense [rows][cols] device arrays.

@@ -16,7 +16,8 @@ blocks), which is an independent, deliberately plain implementation of:
 * the signed last-column minors from the [A I] derivation (Sec. 3);
 * the adjugate adj(A)^T = d det / d A (Sec. 3, Baur-Strassen remark);
 * the last-column minors of every leading block (the minors above applied to
-  each leading block, factored afresh);
+  each leading block, factored afresh), and the normalised minors (each row
+  divided by its first entry, eq. (minors));
 * conversion of a number to a (float64 mantissa, int64 exponent) pair.
 
 Arrays use the element-contiguous host layout: limbs [..., P] uint32,
@@ -131,8 +132,9 @@ def _binop(name, a, b):
     P = a.P
     r = _zeros((), P)
     fn = getattr(_load(), name)
-    rc = fn(P, _p(a.limbs, _u32p), int(a.exp), int(a.sign), _p(b.limbs, _u32p),
-            int(b.exp), int(b.sign), _p(r.limbs, _u32p), _p(r.exp, _i64p), _p(r.sign, _i32p))
+    rc = fn(P, _p(a.limbs, _u32p), int(a.exp.reshape(())), int(a.sign.reshape(())), _p(b.limbs, _u32p),
+            int(b.exp.reshape(())), int(b.sign.reshape(())), _p(r.limbs, _u32p), _p(r.exp, _i64p),
+            _p(r.sign, _i32p))
     if rc not in (None, 0):
         raise ZeroDivisionError("mpref_div: division by zero")
     return r
@@ -252,6 +254,25 @@ def all_minors(A, threads: int | None = None) -> Mp:
         c = minors(f, threads)
         C.limbs[r - 1, :r], C.exp[r - 1, :r], C.sign[r - 1, :r] = c.limbs, c.exp, c.sign
     return C
+
+
+def normalize_minors(C) -> Mp:
+    """The normalised minors of eq. (minors): every row of C divided by its
+    first entry, RZ_p(C[r][i] / C[r][0]); a row whose first entry is zero
+    becomes zeros."""
+    C = _as_mp(C)
+    if C.exp.ndim == 1:
+        C = Mp(C.limbs[None], C.exp[None], C.sign[None])
+    rows, cols = C.exp.shape
+    out = _zeros((rows, cols), C.P)
+    for r in range(rows):
+        den = Mp(C.limbs[r, 0], C.exp[r, 0], C.sign[r, 0])
+        if not den.limbs.any():
+            continue
+        for i in range(cols):
+            q = div(Mp(C.limbs[r, i], C.exp[r, i], C.sign[r, i]), den)
+            out.limbs[r, i], out.exp[r, i], out.sign[r, i] = q.limbs, q.exp, q.sign
+    return out
 
 
 def to_f64(x) -> tuple[np.ndarray, np.ndarray]:

@@ -82,6 +82,8 @@ def lib() -> ctypes.CDLL:
         L.mp_det_adjugate.restype = ctypes.c_int
         L.mp_det_all_minors.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, vp, vp]
         L.mp_det_all_minors.restype = ctypes.c_int
+        L.mp_det_normalize_minors.argtypes = [vp, MpdetMat, MpdetMat, vp]
+        L.mp_det_normalize_minors.restype = ctypes.c_int
         L.mp_to_f64_scaled.argtypes = [vp, MpdetMat, vp, vp, vp]
         L.mp_to_f64_scaled.restype = ctypes.c_int
         L.mpdet_measure_peak.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
@@ -284,6 +286,16 @@ def all_minors(LU: DeviceMp, D: DeviceMp, info, C: DeviceMp | None = None, strea
     _check("mp_det_all_minors", lib().mp_det_all_minors(h.ptr, LU.mat(), D.mat(), C.mat(), info.data_ptr(),
                                                         _stream(stream)))
     return C
+
+
+def normalize_minors(C: DeviceMp, out: DeviceMp | None = None, stream=None) -> DeviceMp:
+    """mp_det_normalize_minors: every row of C divided by its first entry
+    (the normalised minors delta_{N,n} = c_n / c_1)."""
+    if out is None:
+        out = DeviceMp.empty(C.rows, C.cols, C.P, C.limbs.device)
+    h = handle(C.limbs.device.index or 0)
+    _check("mp_det_normalize_minors", lib().mp_det_normalize_minors(h.ptr, C.mat(), out.mat(), _stream(stream)))
+    return out
 
 
 MPDET_WANT_MINORS = 1

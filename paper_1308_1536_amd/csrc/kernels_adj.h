@@ -211,4 +211,31 @@ __global__ void __launch_bounds__(64) k_all_minors_final(MatDev D, MatDev W, Mat
     mpw::store(cm, &ex(C, r, i), &sg(C, r, i), L.sc.t3, hr, P);
 }
 
+// Normalised minors (eq. (minors)): O[r][i] = RZ_p(C[r][i] / C[r][0]), each
+// row divided by its first entry (for mp_det_minors' vector, delta_{N,n}; for
+// mp_det_all_minors' rows, the same for every leading block).  A row whose
+// first entry is zero is written as zeros.  O must not overlap C.  Block b ->
+// (b / cols, b % cols).
+__global__ void __launch_bounds__(64) k_norm_minors(MatDev C, MatDev O, int64_t rows, int64_t cols, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    const int64_t b = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
+    if (b >= rows * cols) return;
+    const int64_t r = b / cols, i = b % cols;
+    uint32_t *om = el(O, r, i, P);
+    const uint32_t *ym = el(C, r, 0, P);
+    if (ym[P - 1] == 0u) {
+        for (int q = mpw::lane(); q < P; q += MP_WAVE) om[q] = 0u;
+        if (mpw::lane() == 0) {
+            ex(O, r, i) = 0;
+            sg(O, r, i) = 0;
+        }
+        return;
+    }
+    mpw::DivBufs B = mpw::div_bufs(lds_raw, P);
+    mpw::Hdr hx = mpw::load(B.a, el(C, r, i, P), ex(C, r, i), sg(C, r, i), P);
+    mpw::Hdr hy = mpw::load(B.v, ym, ex(C, r, 0), sg(C, r, 0), P);
+    mpw::Hdr hq = mpw::div(B.t3, B.a, hx, B.v, hy, B.prod, B.t0, B.t1, B.t2, P);
+    mpw::store(om, &ex(O, r, i), &sg(O, r, i), B.t3, hq, P);
+}
+
 }  // namespace mpk

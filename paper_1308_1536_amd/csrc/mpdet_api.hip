@@ -882,6 +882,21 @@ int mp_det_all_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat C, c
     return last_launch();
 }
 
+int mp_det_normalize_minors(mpdet_handle *h, mpdet_mat C, mpdet_mat out, void *stream) {
+    if (!h) return MPDET_EINVAL;
+    const int64_t cnt = C.rows * C.cols;
+    if (!mat_ok(C, cnt > 0) || !mat_ok(out, cnt > 0)) return MPDET_EINVAL;
+    if (out.rows != C.rows || out.cols != C.cols || out.nlimbs != C.nlimbs) return MPDET_EINVAL;
+    if (cnt == 0) return MPDET_OK;
+    if (out.limbs == C.limbs || out.exp == C.exp || out.sign == C.sign) return MPDET_EINVAL;
+    DeviceGuard g(h->device);
+    if (!g.ok) return MPDET_EHIP;
+    const int P = C.nlimbs;
+    hipLaunchKernelGGL(mpk::k_norm_minors, grid_for(cnt), dim3(64), mpk::pivot_lds_bytes(P), (hipStream_t)stream,
+                       dev(C), dev(out), C.rows, C.cols, P);
+    return last_launch();
+}
+
 int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT, const int32_t *info_dev,
                     void *stream) {
     if (!h || !info_dev) return MPDET_EINVAL;

@@ -68,3 +68,23 @@ def test_padded_leading_dimensions(P):
     f = oracle.factor(A_host)
     assert_same(C.to_host(), oracle.all_minors(A_host), "all_minors padded ld")
     assert_same(T.to_host(), oracle.adjugate_t(f), "adjugate padded ld")
+
+
+@pytest.mark.parametrize("N,P", [(20, 8), (33, 64)])
+def test_normalized_minors_match_oracle(N, P):
+    """mp_det_normalize_minors on the minors vector and on every leading
+    block's minors, bit for bit against the oracle's divisions."""
+    import torch
+    from paper_1308_1536_amd import binding
+    say(f"[normalize] N={N} P={P}")
+    A_host = inputs.random_mantissas((N, N), P, 7000 + N + P)
+    A = binding.DeviceMp.from_host(A_host)
+    D, info = binding.factor(A, "valu")
+    c = binding.minors(A, D, info)
+    C = binding.all_minors(A, D, info)
+    nc = binding.normalize_minors(c)
+    nC = binding.normalize_minors(C)
+    torch.cuda.synchronize()
+    f = oracle.factor(A_host)
+    assert_same(nc.to_host(), oracle.normalize_minors(oracle.minors(f)), "normalised minors")
+    assert_same(nC.to_host(), oracle.normalize_minors(oracle.all_minors(A_host)), "normalised all minors")

@@ -306,3 +306,30 @@ def test_p_vs_2p_agreement(oracle_lib):
     d1, d2 = vals(f1.D), vals(f2.D)
     for k in range(32):
         assert exact.bits_agree(d1[k], d2[k]) > 128 - 40
+
+
+def test_normalize_minors_is_rz_of_the_exact_ratio(oracle_lib):
+    """The normalised minors of eq. (minors): in the exact case the minors are
+    the exact cofactors, so row entry i must be RZ_p(c_i / c_1) of the exact
+    rational (same sign, below it in magnitude by less than one unit in the
+    last place); the first entry is exactly 1, and a row starting with zero
+    gives zeros."""
+    P = 4
+    A, L, U = inputs.triangular_product(7, P, 9)
+    C = oracle_lib.all_minors(A)
+    Nrm = vals(oracle_lib.normalize_minors(C))
+    M = (L.astype(object) @ U.astype(object)).tolist()
+    for r in range(1, 8):
+        c = exact.last_col_cofactors_exact([row[:r] for row in M[:r]])
+        assert Nrm[r - 1, 0] == 1
+        for i in range(r):
+            want = Fraction(c[i], c[0])
+            got = Nrm[r - 1, i]
+            if want == 0:
+                assert got == 0
+                continue
+            assert (got > 0) == (want > 0) and abs(got) <= abs(want)
+            ulp = Fraction(2) ** (math.floor(math.log2(abs(got))) - (32 * P - 1))
+            assert abs(want) - abs(got) < ulp, (r, i)
+    Z = inputs.from_values([[0, 1, 2]], P)
+    assert not oracle_lib.normalize_minors(Z).limbs.any()
