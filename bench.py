@@ -418,9 +418,10 @@ def bench_elimination_steps(args):
 
 def bench_all_minors(args, mats, work, Ds, cs, binfo, infos, P):
     """mp_det_all_minors on every factored matrix: wall time per pass over the
-    workload, the VALU rate of its row sweeps (N^3/6 - N/6 multiply-subtracts
-    of P-limb numbers, P^2 32-bit MACs each, timed live with HIP events over
-    the whole call; avg_launch_ms is that time over the sweep launches), row
+    workload (the matrices at once on separate streams and handles), the VALU
+    rate of its row sweeps (N^3/6 - N/6 multiply-subtracts of P-limb numbers,
+    P^2 32-bit MACs each, timed live with HIP events over the calls made one
+    after another; avg_launch_ms is that time over the sweep launches), row
     N-1 against mp_det_minors bit for bit, and the exact invariant on sampled
     rows."""
     import torch
@@ -428,20 +429,28 @@ def bench_all_minors(args, mats, work, Ds, cs, binfo, infos, P):
     from paper_1308_1536_amd import binding
     Cs = [binding.DeviceMp.empty(w.rows, w.rows, P, w.limbs.device) for w in work]
     info_of = [binfo[b:b + 1] if binfo is not None else infos[b] for b in range(len(work))]
+    # independent matrices run concurrently, as in bench_backward
+    S = min(int(os.environ.get("MPDET_BWD_STREAMS", "16")), len(work))
+    streams = [torch.cuda.Stream() for _ in range(S)]
+    handles = [binding.Handle(work[0].limbs.device.index or 0) for _ in range(S)]
 
-    def run():
-        for w, D, C, inf in zip(work, Ds, Cs, info_of):
-            binding.all_minors(w, D, inf, C)
+    def run(concurrent=True):
+        torch.cuda.synchronize()
+        for b, (w, D, C, inf) in enumerate(zip(work, Ds, Cs, info_of)):
+            if concurrent:
+                binding.all_minors(w, D, inf, C, stream=streams[b % S], h=handles[b % S])
+            else:
+                binding.all_minors(w, D, inf, C)
+        torch.cuda.synchronize()
 
     run()
-    torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         run()
-    torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # kernel time of one pass, one matrix after another on the shared handle
     binding.profile_begin()
-    run()
+    run(concurrent=False)
     prof = binding.profile_end()
     kms, _ = prof["all_minors"]
     ops = sum((w.rows ** 3 - w.rows) // 6 for w in work)
@@ -458,7 +467,7 @@ def bench_all_minors(args, mats, work, Ds, cs, binfo, infos, P):
             rows = sorted(set([0, 1, n // 3, (2 * n) // 3, n - 2, n - 1]) & set(range(n)))
             checks[nm] = {"rows": rows, "max_rel_err_bits": all_minors_invariant_bits(m, C.to_host(), D.row(0),
                                                                                       rows)}
-    return {"ms_per_pass": ms, "multiply_subtracts": ops,
+    return {"ms_per_pass": ms, "streams": S, "multiply_subtracts": ops,
             "roofline": {"bound": "alu", "kernel": "k_prod_lane_r1 + k_finish_r1" if lane else "k_adj_w",
                          "achieved": rate / 1e12,
                          "peak": PEAK_VALU_MAC32 / 1e12, "unit": "Tmac32/s", "frac": rate / PEAK_VALU_MAC32,
