@@ -293,3 +293,101 @@ def bits_agree_mp(approx, exact_mpf, prec: int) -> float:
         if a == exact_mpf:
             return math.inf
         return float(-mpmath.log(abs(a - exact_mpf) / abs(exact_mpf), 2))
+
+
+# ---------------------------------------------------------------------------
+# the method's rounding sequence, step by step in exact rationals
+# ---------------------------------------------------------------------------
+# Each function below executes the elimination (Algorithm 1 steps 2.1-2.2.2),
+# the last-column minors (Sec. 3, [A I] derivation, solved as x^T L = e_N^T)
+# and the adjugate in the orders the method fixes, with every product,
+# difference and quotient formed exactly in Fractions and then truncated
+# toward zero to p = 32P bits (``truncate``).  Nothing here shares code with
+# the oracle; tiny sizes only.
+
+def ge_rz(M, P: int):
+    """Elimination without pivoting with two roundings per update:
+    a_ij <- RZ(a_ij - RZ(l_ik a_kj)), l_ik = RZ(a_ik / a_kk),
+    D_k = RZ(D_{k-1} a_kk).  Returns (LU as a list of lists, D list, info)."""
+    A = [[Fraction(v) for v in row] for row in M]
+    n = len(A)
+    D = [Fraction(0)] * n
+    for k in range(n):
+        piv = A[k][k]
+        if piv == 0:
+            return A, D, k + 1
+        D[k] = piv if k == 0 else truncate(D[k - 1] * piv, P)
+        for i in range(k + 1, n):
+            A[i][k] = truncate(A[i][k] / piv, P)
+        for i in range(k + 1, n):
+            for j in range(k + 1, n):
+                A[i][j] = truncate(A[i][j] - truncate(A[i][k] * A[k][j], P), P)
+    return A, D, 0
+
+
+def minors_rz(LU, D, P: int):
+    """x^T L = e_N^T by sweeps j = N..2 (axpy form, one rounding per product
+    and per difference), then c_i = RZ(D_{N-1} x_i), c_N = D_{N-1}."""
+    n = len(LU)
+    if n == 1:
+        return [Fraction(1)]
+    s = [Fraction(0)] * n
+    for j in range(n - 1, 0, -1):
+        x = Fraction(1) if j == n - 1 else s[j]
+        for i in range(j):
+            s[i] = truncate(s[i] - truncate(x * LU[j][i], P), P)
+    c = [truncate(D[n - 2] * s[i], P) for i in range(n - 1)]
+    return c + [D[n - 2]]
+
+
+def adjugate_t_rz(LU, D, P: int):
+    """adj(A)^T in the fixed order adj(A) = adj(U) W, W = L^-1:
+    - row r of W: the minors sweep with e_r (j descending);
+    - S_{N+1} = 1, S_i = RZ(u_ii S_{i+1}); adj(U)_ii = RZ(D_{i-1} S_{i+1}) (D_0 = 1
+      gives S_2 itself);
+    - strict upper part of adj(U): right-looking back substitution of
+      U x = det(U) e_j: for k = N..2, t_i <- RZ(t_i - RZ(u_ik x_k)) for i < k,
+      then x_{k-1} = RZ(t_{k-1} / u_{k-1,k-1});
+    - adj(A)_im = sum over k >= max(i, m) of RZ(adj(U)_ik W_km), accumulated
+      in ascending k, one rounding per product and per sum.
+    Returned as T[m][i] = adj(A)_im."""
+    n = len(LU)
+    Z = Fraction(0)
+    W = [[Z] * n for _ in range(n)]
+    for r in range(n):
+        W[r][r] = Fraction(1)
+        for j in range(r, 0, -1):
+            x = W[r][j]
+            for i in range(j):
+                W[r][i] = truncate(W[r][i] - truncate(x * LU[j][i], P), P)
+    S = [Z] * (n + 1)
+    S[n] = Fraction(1)
+    for i in range(n - 1, -1, -1):
+        S[i] = truncate(LU[i][i] * S[i + 1], P)
+    J = [[Z] * n for _ in range(n)]
+    for i in range(n):
+        J[i][i] = S[1] if i == 0 else truncate(D[i - 1] * S[i + 1], P)
+    for k in range(n - 1, 0, -1):
+        for j in range(k, n):
+            for i in range(k):
+                J[i][j] = truncate(J[i][j] - truncate(LU[i][k] * J[k][j], P), P)
+            J[k - 1][j] = truncate(J[k - 1][j] / LU[k - 1][k - 1], P)
+    T = [[Z] * n for _ in range(n)]
+    for i in range(n):
+        for m in range(n):
+            acc = Z
+            for k in range(max(i, m), n):
+                acc = truncate(acc + truncate(J[i][k] * W[k][m], P), P)
+            T[m][i] = acc
+    return T
+
+
+def all_minors_rz(M, P: int):
+    """Row r-1: minors_rz of the leading r x r block, factored afresh."""
+    n = len(M)
+    C = [[Fraction(0)] * n for _ in range(n)]
+    for r in range(1, n + 1):
+        LU, D, info = ge_rz([row[:r] for row in M[:r]], P)
+        assert info == 0
+        C[r - 1][:r] = minors_rz(LU, D, P)
+    return C
