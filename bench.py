@@ -1,20 +1,29 @@
 #!/usr/bin/env python3
 """Throughput of the multiprecision determinant hot path on one MI355X.
 
-A step is one pass of the whole path -- Gaussian elimination without pivoting
-(every D_k and det), then the last-column minors -- over every matrix of the
-workload, starting from pristine copies already resident in HBM (the copy
-into the work buffer is inside the timed region).
+The default workload is configuration 3: one N=2048 Cauchy matrix of
+32768-bit numbers on the INT8-MFMA path.  Its whole solve -- Gaussian
+elimination without pivoting (every D_k and det), then the last-column minors
+-- takes tens of seconds, so one timed solve is split into K consecutive
+segments of about equal trailing-update work: step s runs elimination steps
+b_s .. b_{s+1}-1 in place, the last step also the minors, and the K steps
+together are exactly one time to solution (the copy of the pristine matrix
+into the work buffer is inside the first step).  The W warm-up steps are the
+first W segments of a throwaway solve.
 
-    python bench.py [--steps K] [--warmup W] [--config 2] [--path auto|valu|mfma]
+    python bench.py [--steps K] [--warmup W] [--config 3] [--path auto|valu|mfma]
+
+Configurations 1, 2 and 4 keep whole passes as steps: one step is the whole
+path over every matrix of the workload.  Configuration 5 is timed in part
+(--factor-steps).
 
 Prints ONE JSON line.  `value` is algorithmic 8-bit limb MACs per second:
 U(N) * (p/8)^2 per matrix, U(N) = (N-1)N(2N-1)/6 trailing updates, divided by
-the wall time of a step.  `roofline` describes the dominant kernel, timed
-live with HIP events on its launch stream; `cpu_baseline` times the CPU oracle
-on a bounded leading block of the first matrix (same unit), which also checks
-the GPU's D_1..D_K bit for bit (prefix property of elimination without
-pivoting).
+the wall time.  `roofline` describes the dominant kernel, timed live with HIP
+events on its launch stream during the timed steps; `cpu_baseline` times the
+CPU oracle on a bounded leading block of the first matrix (same unit), which
+also checks the GPU's D_1..D_K bit for bit (prefix property of elimination
+without pivoting).
 """
 from __future__ import annotations
 
@@ -557,18 +566,234 @@ def bench_backward(args, mats, work, Ds, cs, binfo, infos, P):
             "last_column_equals_minors": bool(last_same), "laplace_checks": checks}
 
 
+# configurations whose one matrix is timed as K segments of a single solve
+SEGMENTED = {3}
+
+
+def segment_bounds(N: int, K: int) -> list[int]:
+    """Elimination-step boundaries 0 = b_0 < b_1 < ... < b_K = N that split one
+    solve into K segments of about equal trailing-update work (sum of m^2 over
+    the steps, m = N - k - 1 the trailing block's order at step k)."""
+    K = max(1, min(K, N))
+    w = [(N - k - 1) ** 2 for k in range(N)]
+    total = max(1, sum(w))
+    b, cum, s = [0], 0, 1
+    for k in range(N):
+        cum += w[k]
+        if s < K and cum * K >= total * s:
+            b.append(k + 1)
+            s += 1
+    b.append(N)
+    # strictly increasing, K segments, each at least one step
+    for t in range(1, K):
+        b[t] = max(b[t], b[t - 1] + 1)
+    for t in range(K - 1, 0, -1):
+        b[t] = min(b[t], b[t + 1] - 1)
+    assert len(b) == K + 1 and all(b[t] < b[t + 1] for t in range(K))
+    return b
+
+
+def compare_paths_on_block(Ah, L: int, paths=("mfma", "valu"), reps: int = 1):
+    """Factor + minors of the leading L x L block on each update path: the time
+    of one whole solve on each, and whether LU, every D_k and every minor have
+    the same bits."""
+    import torch
+
+    from paper_1308_1536_amd import binding
+    from paper_1308_1536_amd.inputs import MpArray
+    blk = MpArray(Ah.limbs[:L, :L].copy(), Ah.exp[:L, :L].copy(), Ah.sign[:L, :L].copy())
+    pristine = binding.DeviceMp.from_host(blk)
+    out = {"size": L, "paths": {}}
+    results = []
+    for path in paths:
+        w = binding.DeviceMp.empty(L, L, pristine.P)
+        D = binding.DeviceMp.empty(1, L, pristine.P)
+        c = binding.DeviceMp.empty(1, L, pristine.P)
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        times = []
+        for _ in range(reps + 1):  # the first run also allocates the path's workspace
+            for t, f in zip((w.limbs, w.exp, w.sign), (pristine.limbs, pristine.exp, pristine.sign)):
+                t.copy_(f)
+            info.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            binding.factor(w, path, D=D, info=info)
+            binding.minors(w, D, info, c=c)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        print(f"[bench] leading {L}x{L} block on the {path} path: {min(times[1:]):.3f} s", file=sys.stderr,
+              flush=True)
+        out["paths"][path] = {"seconds": min(times[1:]), "info": int(info.item())}
+        results.append((w, D, c))
+    same = all(torch.equal(a, b) for (w0, D0, c0) in results[:1] for (w1, D1, c1) in results[1:]
+               for a, b in zip((w0.limbs, w0.exp, w0.sign, D0.limbs, D0.exp, D0.sign, c0.limbs, c0.exp, c0.sign),
+                               (w1.limbs, w1.exp, w1.sign, D1.limbs, D1.exp, D1.sign, c1.limbs, c1.exp, c1.sign)))
+    out["same_bits_LU_D_minors"] = bool(same)
+    t = {p: out["paths"][p]["seconds"] for p in paths}
+    if "mfma" in t and "valu" in t:
+        out["valu_over_mfma_time"] = t["valu"] / t["mfma"]
+    return out
+
+
+def bench_segmented(args):
+    """One whole solve of the workload's matrix, timed as K segments (see the
+    module docstring)."""
+    import numpy as np
+
+    from paper_1308_1536_amd.inputs import MpArray, limb_macs_int8, u_count
+    desc, mats = cached_workload(args.config, args.input_cache)
+    name, Ah = mats[0]
+    if args.size:
+        Ah = MpArray(Ah.limbs[:args.size, :args.size].copy(), Ah.exp[:args.size, :args.size].copy(),
+                     Ah.sign[:args.size, :args.size].copy())
+        desc += f" -- leading {args.size}x{args.size} block"
+    N, P = Ah.exp.shape[0], Ah.limbs.shape[-1]
+    K = max(1, min(args.steps, N))
+    W = max(0, min(args.warmup, K))
+    b = segment_bounds(N, K)
+    print(f"[bench] {desc}: {K} segments {b}", file=sys.stderr, flush=True)
+
+    import torch
+
+    from paper_1308_1536_amd import binding
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    pristine = binding.DeviceMp.from_host(Ah)
+    work = binding.DeviceMp.empty(N, N, P)
+    D = binding.DeviceMp.empty(1, N, P)
+    c = binding.DeviceMp.empty(1, N, P)
+    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    path = args.path or DEFAULT_PATH[args.config]
+
+    def reset():
+        for t, f in zip((work.limbs, work.exp, work.sign), (pristine.limbs, pristine.exp, pristine.sign)):
+            t.copy_(f)
+        info.zero_()
+
+    def segment(s):
+        binding.factor_steps(work, D, info, b[s], b[s + 1], path)
+        if s == K - 1:
+            binding.minors(work, D, info, c=c)
+
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.empty(nbytes // 4, dtype=torch.int32, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    # warm-up: the first W segments of a throwaway solve (allocates the workspace)
+    reset()
+    for s in range(W):
+        segment(s)
+        torch.cuda.synchronize()
+        print(f"[bench] warm-up step {s + 1}/{W} done", file=sys.stderr, flush=True)
+
+    # the timed solve; per-kernel HIP events on the launch stream throughout
+    torch.cuda.synchronize()
+    binding.profile_begin()
+    seg_s = []
+    t0 = time.perf_counter()
+    for s in range(K):
+        ts = time.perf_counter()
+        if s == 0:
+            reset()
+        segment(s)
+        torch.cuda.synchronize()
+        seg_s.append(time.perf_counter() - ts)
+        print(f"[bench] step {s + 1}/{K} (elimination steps {b[s]}..{b[s + 1] - 1}"
+              f"{' + minors' if s == K - 1 else ''}) {seg_s[-1]:.2f} s", file=sys.stderr, flush=True)
+    secs = time.perf_counter() - t0
+    prof = binding.profile_end()
+    if int(info.item()) != 0:
+        raise SystemExit(f"bench.py: factorisation reported info {int(info.item())}")
+    macs, upd = limb_macs_int8(N, P), u_count(N)
+    value = macs / secs
+
+    traffic_db = load_traffic(args.config)
+
+    def traffic(kernel):
+        t = traffic_db.get(kernel)
+        if t is None:
+            return None
+        return {"bytes_per_launch": t["fetch_bytes_per_launch"] + t["write_bytes_per_launch"],
+                "fetch_bytes_per_launch": t["fetch_bytes_per_launch"],
+                "write_bytes_per_launch": t["write_bytes_per_launch"]}
+
+    roof, other = None, {}
+    if prof["update_mfma"][1]:
+        kms, kn = prof["update_mfma"]
+        mp = binding.measure_peak("mfma_i8")
+        ach = macs / (kms / 1e3)
+        kern = f"k_update_mfma<{mfma_copies(P)}>"
+        roof = {"bound": "mfma", "achieved": 2 * ach / 1e12, "peak": PEAK_INT8_MFMA_TOPS / 1e12, "unit": "TOP/s",
+                "frac": ach / PEAK_INT8_MAC, "kernel": kern, "measured_peak": 2 * mp / 1e12,
+                "frac_of_measured_peak": ach / mp, "traffic": traffic(kern), "avg_launch_ms": kms / kn,
+                "launches": kn}
+        roof.update(issued("mfma", P, roof["frac"]))
+    elif prof["update_valu"][1]:
+        kms, kn = prof["update_valu"]
+        ach = upd * P * P / (kms / 1e3)
+        kern = "k_prod_lane" if (P <= 128 and P % 4 == 0) else "k_update_valu"
+        roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_VALU_MAC32 / 1e12, "unit": "Tmac32/s",
+                "frac": ach / PEAK_VALU_MAC32, "kernel": kern, "traffic": traffic(kern), "avg_launch_ms": kms / kn,
+                "launches": kn}
+    if prof["update_finish"][1]:
+        kms, kn = prof["update_finish"]
+        ach = upd * FINISH_BYTES(P) / (kms / 1e3)
+        kern = "k_finish" + ("<true>" if P > 256 else "<false>")
+        other["update_finish"] = {"bound": "hbm", "achieved": ach / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                                  "frac": ach / PEAK_HBM, "kernel": kern, "traffic": traffic(kern),
+                                  "avg_launch_ms": kms / kn, "launches": kn}
+    if roof is None:
+        raise SystemExit("bench.py: no trailing-update launches were timed")
+    roof["other_update_kernels"] = other
+    roof["kernel_s_per_solve"] = {k: round(v[0] / 1e3, 3) for k, v in prof.items() if v[1]}
+
+    out = {"metric": METRIC, "value": value, "unit": "limb-MAC/s", "n_gpus": 1, "steps": K, "warmup": W,
+           "ms_per_step": secs * 1e3 / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "i8" if prof["update_mfma"][1] else "u32", "data": "synthetic",
+           "config": {"workload": desc, "N": N, "bits": 32 * P, "matrices": 1, "path": path,
+                      "step": "one of K consecutive segments of one whole solve (elimination steps b_s..b_{s+1}-1; "
+                              "the last also runs the minors): the K steps are one time to solution",
+                      "segment_bounds": b, "segment_seconds": [round(v, 3) for v in seg_s],
+                      "time_to_solution_s": secs, "updates": upd, "limb_macs": macs},
+           "end_to_end_frac_of_int8_peak": value / PEAK_INT8_MAC,
+           "roofline": roof}
+    Dh, ch = D.row(0), c.row(0)
+    if not args.no_cpu_baseline:
+        lead = min(N, 256)
+        sub = MpArray(Ah.limbs[:lead, :lead].copy(), Ah.exp[:lead, :lead].copy(), Ah.sign[:lead, :lead].copy())
+        out["cpu_baseline"] = cpu_baseline(sub, Dh, args.cpu_budget)
+        print("[bench] cpu baseline done", file=sys.stderr, flush=True)
+    if not args.no_checks:
+        out["full_size_checks"] = {name: full_size_checks(args.config, name, Ah, work, Dh, ch, args.size)}
+        print("[bench] full-size checks done", file=sys.stderr, flush=True)
+    del work, pristine
+    torch.cuda.empty_cache()
+    if args.compare != "none" and args.compare_size > 0:
+        other_path = "valu" if path == "mfma" else "mfma"
+        out["comparison"] = compare_paths_on_block(Ah, min(N, args.compare_size), (path, other_path))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default: 10 segments of one solve for configuration 3, 3 passes otherwise)")
+    ap.add_argument("--warmup", type=int, default=None, help="untimed steps (default: 2 for 3, 1 otherwise)")
+    ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--path", default=None, choices=["auto", "valu", "mfma", "tuned"],
                     help="trailing-update path (default: the configuration's own -- VALU for the plain "
                          "configurations 1 and 2, MFMA for 3, auto for the batched 4)")
     ap.add_argument("--compare", default="default", choices=["default", "none", "valu", "mfma"],
                     help="also time the other update path on the same workload and check that it gives the "
                          "same bits (default: MFMA beside the VALU path of configuration 2)")
+    ap.add_argument("--compare-size", type=int, default=256, metavar="L",
+                    help="configuration 3: time both update paths on the leading L x L block and compare their "
+                         "bits (0: skip)")
     ap.add_argument("--cpu-budget", type=float, default=20.0, help="seconds of oracle work")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--input-cache", default=None, metavar="DIR",
@@ -602,8 +827,16 @@ def main():
         sys.exit(2)
     if args.config == 5 and not args.factor_steps:
         args.factor_steps = 24
+    seg = args.config in SEGMENTED and not args.factor_steps
+    if args.steps is None:
+        args.steps = 10 if seg else (24 if args.factor_steps else 3)
+    if args.warmup is None:
+        args.warmup = 2 if seg else (1 if not args.factor_steps else 0)
     if args.factor_steps:
         bench_elimination_steps(args)
+        return
+    if seg:
+        bench_segmented(args)
         return
 
     # inputs first: the generator may fork worker processes, which must

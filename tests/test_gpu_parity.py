@@ -190,6 +190,15 @@ def test_mfma_shapes(N, P):
     check_against_oracle(A, "mfma", f"mfma shape N={N} P={P}")
 
 
+@pytest.mark.parametrize("N,P", [(20, 264), (20, 520), (10, 1024)])
+def test_valu_large_limbs(N, P):
+    """VALU path (one wave per element update) at the MFMA path's large limb
+    counts, on the same inputs as test_mfma_shapes: both paths must give the
+    oracle's bits, so they agree with each other at 32768 bits too."""
+    A = inputs.random_mantissas((N, N), P, 4000 + 13 * N + P)
+    check_against_oracle(A, "valu", f"valu shape N={N} P={P}")
+
+
 @pytest.mark.parametrize("case", ["wide_exponents", "cancellation", "zero_entries", "zero_pivot", "patterns"])
 def test_streaming_finish_cases(case):
     """P > 256 takes the streaming finish (chunked a_ij, intermediate kept in
