@@ -204,12 +204,19 @@ def factor(A, threads: int | None = None) -> Factorization:
     return Factorization(A, D, int(info))
 
 
+def _complete(f: Factorization, n: int) -> bool:
+    """Elimination ran all its steps: info 0, or info n (only the last pivot
+    u_nn is zero, so det = 0 while the minors and the adjugate, which never
+    divide by u_nn, stay defined -- eq. (minors) needs them where det = 0)."""
+    return f.info == 0 or f.info == n
+
+
 def minors(f: Factorization, threads: int | None = None) -> Mp:
     """Signed last-column cofactors c (c . A[:, n] = det) from a factorization."""
-    if f.info != 0:
-        raise ValueError("minors: factorization did not complete (info=%d)" % f.info)
     LU, D = _as_mp(f.LU), _as_mp(f.D)
     n, P = int(LU.exp.shape[0]), LU.P
+    if not _complete(f, n):
+        raise ValueError("minors: factorization did not complete (info=%d)" % f.info)
     c = _zeros((n,), P)
     rc = _load().mpref_minors(n, P, _p(LU.limbs, _u32p), _p(LU.exp, _i64p),
                               _p(LU.sign, _i32p), _p(D.limbs, _u32p), _p(D.exp, _i64p),
@@ -222,10 +229,10 @@ def minors(f: Factorization, threads: int | None = None) -> Mp:
 
 def adjugate_t(f: Factorization, threads: int | None = None) -> Mp:
     """adj(A)^T = d det / d A from a factorization (column n equals minors())."""
-    if f.info != 0:
-        raise ValueError("adjugate_t: factorization did not complete (info=%d)" % f.info)
     LU, D = _as_mp(f.LU), _as_mp(f.D)
     n, P = int(LU.exp.shape[0]), LU.P
+    if not _complete(f, n):
+        raise ValueError("adjugate_t: factorization did not complete (info=%d)" % f.info)
     t = _zeros((n, n), P)
     rc = _load().mpref_adjugate_t(n, P, _p(LU.limbs, _u32p), _p(LU.exp, _i64p),
                                   _p(LU.sign, _i32p), _p(D.limbs, _u32p), _p(D.exp, _i64p),
@@ -249,7 +256,7 @@ def all_minors(A, threads: int | None = None) -> Mp:
     for r in range(1, n + 1):
         block = Mp(A.limbs[:r, :r].copy(), A.exp[:r, :r].copy(), A.sign[:r, :r].copy())
         f = factor(block, threads)
-        if f.info != 0:
+        if not _complete(f, r):
             raise ValueError("all_minors: leading block %d did not factor (info=%d)" % (r, f.info))
         c = minors(f, threads)
         C.limbs[r - 1, :r], C.exp[r - 1, :r], C.sign[r - 1, :r] = c.limbs, c.exp, c.sign
@@ -290,5 +297,6 @@ def to_f64(x) -> tuple[np.ndarray, np.ndarray]:
 def det_pipeline(A, threads: int | None = None):
     """factor + minors, the whole hot path: returns (Factorization, c or None)."""
     f = factor(A, threads)
-    c = minors(f, threads) if f.info == 0 else None
+    n = int(f.LU.exp.shape[0])
+    c = minors(f, threads) if _complete(f, n) else None
     return f, c

@@ -13,6 +13,13 @@ N = 384, so the Function works on a float64 *proxy* leaf of shape (n, n):
 exponent (not differentiable).  The backward runs mp_det_adjugate on the
 stored factors; the exact multiprecision adj(A)^T is kept on `holder.adjT`
 (a DeviceMp) when a holder is given.  Everything runs in libmpdet.so.
+
+Elimination without pivoting stops at an exactly zero pivot.  The forward
+reads the factorisation's info (one device-to-host copy) and raises
+ZeroPivotError when a pivot before the last one is zero: det(A) itself may be
+nonzero there, and the method cannot give it.  When only the last pivot u_nn
+is zero the factors are complete, det(A) = 0 is exact (mant = 0, e = 0) and
+the backward still returns adj(A)^T, which never divides by u_nn.
 """
 from __future__ import annotations
 
@@ -30,12 +37,28 @@ class GradHolder:
         self.info = None
 
 
+class ZeroPivotError(ArithmeticError):
+    """Elimination without pivoting met an exactly zero pivot before step n
+    (info = k) or an exponent overflow (info = -1)."""
+
+    def __init__(self, info: int, n: int):
+        what = "an exponent overflow" if info < 0 else f"an exactly zero pivot at step {info} of {n}"
+        super().__init__(f"mp_det: the factorisation stopped at {what}; the determinant is not defined "
+                         "by elimination without pivoting")
+        self.info = info
+
+
 class MpDet(torch.autograd.Function):
     @staticmethod
     def forward(ctx, proxy, A, path="auto", holder=None):
         n = A.rows
         LU = binding.DeviceMp(A.limbs.clone(), A.exp.clone(), A.sign.clone(), A.rows, A.cols)
         D, info = binding.factor(LU, path)
+        code = int(info.item())
+        if holder is not None:
+            holder.info = info
+        if code != 0 and code != n:
+            raise ZeroPivotError(code, n)
         mant, e = binding.to_f64(D)
         dm = mant[0, n - 1].clone()
         de = e[0, n - 1].clone()

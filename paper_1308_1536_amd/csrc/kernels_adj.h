@@ -115,11 +115,15 @@ __global__ void __launch_bounds__(64) k_adj_recips(MatDev LU, uint32_t *rw, cons
     extern __shared__ uint32_t lds_raw[];
     if (*info != 0) return;
     const int64_t i = blockIdx.x;
+    uint32_t *r = rw + i * (int64_t)(P + 2);
+    if (el(LU, i, i, P)[P - 1] == 0u) {  // u_nn = 0 (info == n): never a divisor
+        if (mpw::lane() == 0) r[P + 1] = 0u;
+        return;
+    }
     mpw::DivBufs B = mpw::div_bufs(lds_raw, P);
     mpw::gload(B.v, el(LU, i, i, P), P);
     mpw::wsync();
     const bool ok = mpw::recip(B, P);
-    uint32_t *r = rw + i * (int64_t)(P + 2);
     for (int q = mpw::lane(); q < P + 1; q += MP_WAVE) r[q] = B.x[q];
     if (mpw::lane() == 0) r[P + 1] = ok ? 1u : 0u;
 }
@@ -155,6 +159,13 @@ __global__ void __launch_bounds__(64) k_adj_u_div(MatDev LU, MatDev J, const uin
     if (R[P + 1] != 0u) done = mpw::div_by_recip(B.t3, hq, ht, hu, R, B, P);
     if (!done) hq = mpw::div(B.t3, B.a, ht, B.v, hu, B.prod, B.t0, B.t1, B.t2, P);
     mpw::store(tm, &ex(J, i, j), &sg(J, i, j), B.t3, hq, P);
+}
+
+// The gate the adjugate's and all-minors' kernels test instead of info: 0
+// when the factors are complete (info 0, or info == n: only u_nn is zero),
+// else info (those kernels then write zeros or nothing).
+__global__ void k_factors_gate(const int32_t *info, int64_t n, int32_t *gate) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *gate = factors_complete(*info, n) ? 0 : *info;
 }
 
 // adj(A) accumulation step k: block b -> (i, m) = (b / (k+1), b % (k+1)):

@@ -18,14 +18,15 @@
 // per K-step (the row's digits are staged there reversed).  Fragments outside
 // the band 0 <= r - c <= P8 are zero; every MFMA of a K-step is issued.
 //
-// Epilogue.  Column sums are biased, S'_r = S_r + 2^27 - 2^19 [r >= 1], which
-// makes them positive (< 2^28) and adds sum_r bias_r 256^r = 2^27 256^(R-1)
-// -- a multiple of 2^(2p) -- to the total, invisible in the low 2p bits.
-// Four consecutive S' form a 64-bit limb column V_q < 2^53.  The limbs follow
-// from the V_q by one carry-lookahead per chunk of 64 limbs, in registers
-// (see update_mfma_body).  Limbs P-1 .. 2P-1 of each product go to a record
-// buffer; the finish kernel truncates the product to p bits and forms
-// RZ_p(a_ij - RZ_p(l_i u_j)).
+// Epilogue.  The signed column sums of a limb's four byte positions form
+// V = sum_b S_b 256^b = lo + hi 2^32 (three v_mad_i64_i32); with
+// y_L = lo_L + hi_{L-1}, limb L of the product is (y_L + c_L) mod 2^32 for a
+// carry c_L in {-1, 0, 1}.  The fast path takes c_{L+1} = floor(y_L / 2^32),
+// exact unless some y_L + c_L leaves [0, 2^32) in its low word; one ballot
+// per chunk detects that, and such a chunk redoes its carries limb by limb
+// (see update_mfma_body).  The top limbs of each product, from limb P-1 up,
+// go to a record buffer; the finish kernel truncates the product to p bits
+// and forms RZ_p(a_ij - RZ_p(l_i u_j)).
 //
 // Truncated product.  Only the byte positions r >= R0 = mfma_short_start(P)
 // are formed, in chunks of 256 from R0 (a multiple of the 32-row tile; at

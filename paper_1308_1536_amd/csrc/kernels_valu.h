@@ -174,6 +174,14 @@ __device__ __forceinline__ void update_valu_body(uint32_t *lds_raw, MatDev A, co
     mpw::store(am, &ex(A, i, j), &sg(A, i, j), L.sc.t2, hr, P);
 }
 
+// The factors are complete when elimination ran all its steps: info == 0, or
+// info == n (only the last pivot, u_nn, is zero -- det = D_n = 0, but the
+// minors and the adjugate never divide by u_nn and stay defined; eq. (minors)
+// needs them exactly where det vanishes).
+__host__ __device__ __forceinline__ bool factors_complete(int32_t info, int64_t n) {
+    return info == 0 || (int64_t)info == n;
+}
+
 // ---------------------------------------------------------------------------
 // Last-column minors (Sec. 3, [A I] derivation): x^T L = e_n^T by sweeps.
 // ---------------------------------------------------------------------------
@@ -188,9 +196,10 @@ __global__ void k_minors_init(MatDev c, int64_t n, int P) {
 }
 
 // sweep j: s_i = RZ_p(s_i - RZ_p(x_j l_ji)), i < j; x_{n-1} = 1, x_j = s_j otherwise
+// (nothing unless the factors are complete; k_minors_init wrote zeros)
 __device__ __forceinline__ void minors_sweep_body(uint32_t *lds_raw, MatDev LU, MatDev c, const int32_t *info, int64_t j,
                                   int64_t n, int P, int64_t i) {
-    if (*info != 0) return;
+    if (!factors_complete(*info, n)) return;
     Lds L(lds_raw, P);
     const uint32_t *lm = el(LU, j, i, P);
     if (lm[P - 1] == 0u) return;
@@ -213,7 +222,7 @@ __device__ __forceinline__ void minors_sweep_body(uint32_t *lds_raw, MatDev LU, 
 // c_i = RZ_p(D_{n-1} x_i) for i < n-1 (block i), c_{n-1} = D_{n-1}; n == 1: c = 1
 __device__ __forceinline__ void minors_final_body(uint32_t *lds_raw, MatDev D, MatDev c, const int32_t *info, int64_t n, int P,
                                   int64_t i) {
-    if (*info != 0) return;
+    if (!factors_complete(*info, n)) return;
     uint32_t *cm = el(c, 0, i, P);
     if (n == 1) {
         for (int q = mpw::lane(); q < P; q += MP_WAVE) cm[q] = (q == P - 1) ? 0x80000000u : 0u;

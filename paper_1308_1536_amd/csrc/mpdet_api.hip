@@ -854,7 +854,7 @@ int mp_det_all_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat C, c
     auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
     const size_t nn = (size_t)n * (size_t)n;
     const size_t ml = up(nn * (size_t)P * 4u), me = up(nn * 8u), ms = up(nn * 4u);
-    const size_t need = ml + me + ms;
+    const size_t need = ml + me + ms + 256;  // + the factors gate
     if (need > h->aw_bytes) {
         if (h->aw) (void)hipFree(h->aw);
         h->aw = nullptr;
@@ -868,16 +868,17 @@ int mp_det_all_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat C, c
     }
     uint8_t *base = (uint8_t *)h->aw;
     mpk::MatDev W{(uint32_t *)base, (int64_t *)(base + ml), (int32_t *)(base + ml + me), n};
+    int32_t *gate = (int32_t *)(base + ml + me + ms);
     mpk::MatDev lu = dev(LU), d = dev(D), cm = dev(C);
     const size_t lds = mpk::pivot_lds_bytes(P);
     int rc;
+    hipLaunchKernelGGL(mpk::k_factors_gate, dim3(1), dim3(64), 0, s, info_dev, n, gate);
     hipLaunchKernelGGL(mpk::k_adj_init, grid_for(((int64_t)nn + 255) / 256), dim3(256), 0, s, W, n, P, 1);
     if ((rc = last_launch())) return rc;
     {
         Prof pr(h, s, K_ALL_MINORS);
-        if ((rc = w_sweeps(h, lu, W, info_dev, n, P, s))) return rc;
-        hipLaunchKernelGGL(mpk::k_all_minors_final, grid_for((int64_t)nn), dim3(64), lds, s, d, W, cm, info_dev,
-                           n, P);
+        if ((rc = w_sweeps(h, lu, W, gate, n, P, s))) return rc;
+        hipLaunchKernelGGL(mpk::k_all_minors_final, grid_for((int64_t)nn), dim3(64), lds, s, d, W, cm, gate, n, P);
     }
     return last_launch();
 }
@@ -915,7 +916,7 @@ int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT, 
     const size_t ml = up(nn * (size_t)P * 4u), me = up(nn * 8u), ms = up(nn * 4u);
     const size_t sl = up((size_t)(n + 1) * P * 4u), se = up((size_t)(n + 1) * 8u), ss = up((size_t)(n + 1) * 4u);
     const size_t rb = up((size_t)n * (P + 2) * 4u);
-    const size_t need = 2 * (ml + me + ms) + sl + se + ss + rb;
+    const size_t need = 2 * (ml + me + ms) + sl + se + ss + rb + 256;  // + the factors gate
     if (need > h->aw_bytes) {
         if (h->aw) (void)hipFree(h->aw);
         h->aw = nullptr;
@@ -937,20 +938,22 @@ int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT, 
     mpk::MatDev J{(uint32_t *)carve(ml), (int64_t *)carve(me), (int32_t *)carve(ms), n};
     mpk::MatDev S{(uint32_t *)carve(sl), (int64_t *)carve(se), (int32_t *)carve(ss), n + 1};
     uint32_t *rw = (uint32_t *)carve(rb);
+    int32_t *gate = (int32_t *)carve(256);
     mpk::MatDev lu = dev(LU), d = dev(D), t = dev(adjT);
     const size_t lds = mpk::pivot_lds_bytes(P);
     int rc;
     const int64_t cells = (int64_t)nn;
+    hipLaunchKernelGGL(mpk::k_factors_gate, dim3(1), dim3(64), 0, s, info_dev, n, gate);
     hipLaunchKernelGGL(mpk::k_adj_init, grid_for((cells + 255) / 256), dim3(256), 0, s, W, n, P, 1);
     hipLaunchKernelGGL(mpk::k_adj_init, grid_for((cells + 255) / 256), dim3(256), 0, s, J, n, P, 0);
     hipLaunchKernelGGL(mpk::k_adj_init, grid_for((cells + 255) / 256), dim3(256), 0, s, t, n, P, 0);
     if ((rc = last_launch())) return rc;
     {
         Prof pr(h, s, K_ADJUGATE);
-        if ((rc = w_sweeps(h, lu, W, info_dev, n, P, s))) return rc;
-        hipLaunchKernelGGL(mpk::k_adj_s, dim3(1), dim3(64), lds, s, lu, S, info_dev, n, P);
-        hipLaunchKernelGGL(mpk::k_adj_diag, dim3((unsigned)n), dim3(64), lds, s, d, S, J, info_dev, n, P);
-        hipLaunchKernelGGL(mpk::k_adj_recips, dim3((unsigned)n), dim3(64), lds, s, lu, rw, info_dev, n, P);
+        if ((rc = w_sweeps(h, lu, W, gate, n, P, s))) return rc;
+        hipLaunchKernelGGL(mpk::k_adj_s, dim3(1), dim3(64), lds, s, lu, S, gate, n, P);
+        hipLaunchKernelGGL(mpk::k_adj_diag, dim3((unsigned)n), dim3(64), lds, s, d, S, J, gate, n, P);
+        hipLaunchKernelGGL(mpk::k_adj_recips, dim3((unsigned)n), dim3(64), lds, s, lu, rw, gate, n, P);
         if ((rc = last_launch())) return rc;
         // Where the lane product applies, the back substitution's updates and
         // the accumulation are rank-1 updates on the lane product and the
@@ -962,18 +965,18 @@ int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT, 
         const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_lds_bytes(P);
         auto rank1 = [&](const mpk::Rank1 &R) {
             hipLaunchKernelGGL(mpk::k_prod_lane_r1, grid_for(mpk::lane_update_blocks(R.mr, R.mc)),
-                               dim3(64 * mpk::kLaneRows), lds_prod, s, R, ws.T, info_dev, P);
+                               dim3(64 * mpk::kLaneRows), lds_prod, s, R, ws.T, gate, P);
             hipLaunchKernelGGL(mpk::k_finish_r1, grid_for(mpk::finish_blocks(R.mr, R.mc, P)), dim3(64), lds_fin, s,
-                               R, (const uint32_t *)ws.T, info_dev, P);
+                               R, (const uint32_t *)ws.T, gate, P);
         };
         for (int64_t k = n - 1; k >= 1; --k) {
             if (lane)  // x_i = u_ik (i < k), y_j = J_kj (j >= k), z = J_ij
                 rank1(mpk::Rank1{lu, J, J, 0, k, 1, 0, k, k, 0, 1, 0, k, k, n - k, 0});
             else
-                hipLaunchKernelGGL(mpk::k_adj_u_upd, grid_for(k * (n - k)), dim3(64), lds, s, lu, J, info_dev, k, n,
+                hipLaunchKernelGGL(mpk::k_adj_u_upd, grid_for(k * (n - k)), dim3(64), lds, s, lu, J, gate, k, n,
                                    P);
             hipLaunchKernelGGL(mpk::k_adj_u_div, dim3((unsigned)(n - k)), dim3(64), lds, s, lu, J,
-                               (const uint32_t *)rw, info_dev, k, n, P);
+                               (const uint32_t *)rw, gate, k, n, P);
             if ((rc = last_launch())) return rc;
         }
         for (int64_t k = 0; k < n; ++k) {
@@ -981,7 +984,7 @@ int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT, 
                 rank1(mpk::Rank1{W, J, t, k, 0, 0, 1, 0, k, 1, 0, 0, 0, k + 1, k + 1, 1});
             else
                 hipLaunchKernelGGL(mpk::k_adj_prod, grid_for((k + 1) * (k + 1)), dim3(64), lds, s, J, W, t,
-                                   info_dev, k, P);
+                                   gate, k, P);
             if ((rc = last_launch())) return rc;
         }
     }

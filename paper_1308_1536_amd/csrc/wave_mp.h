@@ -169,8 +169,8 @@ __device__ __forceinline__ int cmp(const uint32_t *a, const uint32_t *b, int n) 
 // prod[0..ncols) = (x * y) mod 2^(32 ncols) for x of nx limbs and y of ny
 // limbs (ncols <= nx + ny).  x: LDS; ypad: LDS, y at ypad + MP_YPAD with
 // MP_YPAD zero limbs on each side; t0..t3: LDS scratch of ncols limbs each.
-__device__ void mul_gen(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *ypad, int ny,
-                        uint32_t *t0, uint32_t *t1, uint32_t *t2, uint32_t *t3) {
+__device__ void mul_cols(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *ypad, int ny,
+                         uint32_t *t0, uint32_t *t1, uint32_t *t2, uint32_t *t3) {
     const int R = ncols;
     const uint32_t *y = ypad + MP_YPAD;
     for (int base = 0; base < R; base += MP_WAVE) {
@@ -229,10 +229,162 @@ __device__ void mul_gen(uint32_t *prod, int ncols, const uint32_t *x, int nx, co
     wsync();
 }
 
+
+// ---------------------------------------------------------------------------
+// The same product in radix 2^28 with register windows (the form every
+// product of a few dozen limbs or more takes).  Both operands are cut into
+// 28-bit digits in LDS, so a digit product is below 2^56 and one
+// v_mad_u64_u32 adds it into a 64-bit column sum; every 128 steps the sums
+// fold their bits above 28 into a second word, so they never overflow.
+// Lane t owns a window of 8 consecutive digit columns r0 = 8w .. 8w+7 (64
+// windows per round) and forms them by columns (Comba): at step a it adds
+// x_a * y_{r0+c-a} for c = 0..7, where x_a is the same for every lane (a
+// broadcast LDS read) and the y digits come from a 16-register ring that
+// moves by one digit per step -- y is stored reversed, so one aligned 16-byte
+// read brings the digits of four steps, issued one group of four steps
+// ahead.  The steps of a round run over the union of its windows' ranges;
+// digits outside y read as zero (the read index is clamped into zero guard
+// words).  A window's column sums are carried into 8 digits plus a carry
+// (224 + 41 bits), i.e. 7 whole limbs and two overlapping the next window:
+// the 7 go to prod, the 2 to an overflow vector, and one carry-lookahead
+// addition merges the two.  Needs the scratch words mul_win_words()
+// reports; callers fall back to mul_cols where they do not fit.
+// ---------------------------------------------------------------------------
+constexpr uint32_t kDigMask = (1u << 28) - 1u;
+
+// bits [28d, 28d + 28) of the n-limb integer a
+__device__ __forceinline__ uint32_t digit_of(const uint32_t *a, int n, int d) {
+    const int bit = 28 * d, q = bit >> 5, sh = bit & 31;
+    uint32_t v = (q < n ? a[q] : 0u) >> sh;
+    if (sh > 4) v |= (q + 1 < n ? a[q + 1] : 0u) << (32 - sh);
+    return v & kDigMask;
+}
+
+struct WinGeom {
+    int NC, NXd, NYd, W;   // digit columns, digits of x and y taken, windows
+    int ov, dx, K, len;    // words: overflow vector, x digits, reversed y (DYR[K - b] = y_b), its length
+    __device__ WinGeom(int ncols, int nx, int ny) {
+        NC = (32 * ncols + 27) / 28;
+        NXd = min((32 * nx + 27) / 28, NC);
+        NYd = min((32 * ny + 27) / 28, NC);
+        W = (NC + 7) / 8;
+        ov = (ncols + 3) & ~3;
+        dx = (NXd + 15 + 3) & ~3;       // the last block's x reads end below NXd + 15
+        K = (NYd + 3 + 3) & ~3;         // at least 4 zero words below y's lowest stored digit
+        len = K + 8;                    // and 7 above its highest
+    }
+    __device__ int words() const { return 3 + ov + dx + len; }  // 3: 16-byte alignment of the base
+};
+
+__device__ void mul_win(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *y, int ny,
+                        uint32_t *ws) {
+    const WinGeom g(ncols, nx, ny);
+    uint32_t *base = (uint32_t *)(((uintptr_t)ws + 15u) & ~(uintptr_t)15u);
+    uint32_t *OV = base, *DX = base + g.ov, *DY = DX + g.dx;
+    for (int t = lane(); t < g.dx; t += MP_WAVE) DX[t] = t < g.NXd ? digit_of(x, nx, t) : 0u;
+    for (int t = lane(); t < g.len; t += MP_WAVE) {
+        const int b = g.K - t;
+        DY[t] = (b >= 0 && b < g.NYd) ? digit_of(y, ny, b) : 0u;
+    }
+    wsync();
+    // a 16-byte read DY[t..t+3] with t clamped into [lo_c, hi_c]: outside
+    // that range every digit it stands for is zero, and so are the clamped words
+    const int lo_c = ((g.K - g.NYd + 1) & ~3) - 4, hi_c = g.K + 4;
+    for (int w0 = 0; w0 < g.W; w0 += MP_WAVE) {
+        const int w = w0 + lane();
+        const int r0 = 8 * w;
+        const int wl = min(g.W, w0 + MP_WAVE) - 1;
+        const int A0 = max(0, 8 * w0 - g.NYd + 1) & ~15;
+        const int A1 = min(g.NXd - 1, 8 * wl + 7);
+        const int nblocks = A1 >= A0 ? (A1 - A0 + 16) / 16 : 0;
+        uint64_t acc[8], hi[8];
+        uint32_t ring[16];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[c] = hi[c] = 0;
+        auto load4 = [&](int slot, int a) {
+            int t = g.K - r0 + a;
+            t = min(max(t, lo_c), hi_c);
+            const uint4 v = *(const uint4 *)(DY + t);
+            ring[slot] = v.x;
+            ring[slot + 1] = v.y;
+            ring[slot + 2] = v.z;
+            ring[slot + 3] = v.w;
+        };
+        // the digit of step j is y_{r0 - j}, kept in slot (j - A0) mod 16
+        load4(8, A0 - 8);
+        load4(12, A0 - 4);
+        load4(0, A0);
+#pragma unroll 1
+        for (int blk = 0; blk < nblocks; ++blk) {
+            const int a0 = A0 + 16 * blk;
+            const uint4 *xq = (const uint4 *)(DX + a0);
+            const uint4 xv0 = xq[0], xv1 = xq[1], xv2 = xq[2], xv3 = xq[3];
+            const uint32_t xs[16] = {xv0.x, xv0.y, xv0.z, xv0.w, xv1.x, xv1.y, xv1.z, xv1.w,
+                                     xv2.x, xv2.y, xv2.z, xv2.w, xv3.x, xv3.y, xv3.z, xv3.w};
+#pragma unroll
+            for (int gq = 0; gq < 4; ++gq) {
+                load4(((gq + 1) & 3) * 4, a0 + 4 * gq + 4);  // the next group's digits
+#pragma unroll
+                for (int u4 = 0; u4 < 4; ++u4) {
+                    const int u = 4 * gq + u4;
+#pragma unroll
+                    for (int c = 0; c < 8; ++c) acc[c] += (uint64_t)xs[u] * (uint64_t)ring[(u - c) & 15];
+                }
+            }
+            if ((blk & 7) == 7) {
+#pragma unroll
+                for (int c = 0; c < 8; ++c) {
+                    hi[c] += acc[c] >> 28;
+                    acc[c] &= kDigMask;
+                }
+            }
+        }
+        if (w < g.W) {
+            uint32_t d[8];
+            uint64_t carry = 0;
+#pragma unroll
+            for (int c = 0; c < 8; ++c) {
+                const uint64_t sm = acc[c] + carry;
+                d[c] = (uint32_t)sm & kDigMask;
+                carry = (sm >> 28) + hi[c];
+            }
+            const uint32_t L[9] = {d[0] | (d[1] << 28),         (d[1] >> 4) | (d[2] << 24),
+                                   (d[2] >> 8) | (d[3] << 20),  (d[3] >> 12) | (d[4] << 16),
+                                   (d[4] >> 16) | (d[5] << 12), (d[5] >> 20) | (d[6] << 8),
+                                   (d[6] >> 24) | (d[7] << 4),  (uint32_t)carry,
+                                   (uint32_t)(carry >> 32)};
+            const int q0 = 7 * w;
+#pragma unroll
+            for (int i = 0; i < 7; ++i)
+                if (q0 + i < ncols) prod[q0 + i] = L[i];
+#pragma unroll
+            for (int i = 2; i < 9; ++i)
+                if (q0 + i < ncols) OV[q0 + i] = i >= 7 ? L[i] : 0u;
+            if (w == 0) {
+                OV[0] = 0u;
+                if (ncols > 1) OV[1] = 0u;
+            }
+        }
+    }
+    wsync();
+    add(prod, prod, OV, ncols, 0u);
+    wsync();
+}
+
+// prod[0..ncols) = (x * y) mod 2^(32 ncols); t0..t3 are one contiguous
+// scratch block of 4 * tsz words (the layouts in use place them so).
+__device__ __forceinline__ void mul_gen(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *ypad,
+                                        int ny, uint32_t *t0, uint32_t *t1, uint32_t *t2, uint32_t *t3, int tsz) {
+    if (WinGeom(ncols, nx, ny).words() <= 4 * tsz && ncols >= 16)
+        mul_win(prod, ncols, x, nx, ypad + MP_YPAD, ny, t0);
+    else
+        mul_cols(prod, ncols, x, nx, ypad, ny, t0, t1, t2, t3);
+}
+
 // prod[0..2P) = x * y for two P-limb integers
 __device__ __forceinline__ void mul_full(uint32_t *prod, const uint32_t *x, const uint32_t *ypad, int P,
                                          uint32_t *t0, uint32_t *t1, uint32_t *t2, uint32_t *t3) {
-    mul_gen(prod, 2 * P, x, P, ypad, P, t0, t1, t2, t3);
+    mul_gen(prod, 2 * P, x, P, ypad, P, t0, t1, t2, t3, 2 * P + 2);
 }
 
 // place n limbs of src as the y operand of mul_gen (zero pads around)
@@ -569,7 +721,7 @@ __device__ bool recip(const DivBufs &B, int P) {
         }
         wsync();
         const int nT = nV + nX;
-        mul_gen(B.prod, nT, B.x, nX, B.ypad, nV, B.t0, B.t1, B.t2, B.t3);
+        mul_gen(B.prod, nT, B.x, nX, B.ypad, nV, B.t0, B.t1, B.t2, B.t3, 2 * P + 4);
         // e = 2^(f+g) - T modulo 2^(32 nT): power of two minus the product
         fill(B.t0, nT, 0u);
         wsync();
@@ -590,7 +742,7 @@ __device__ bool recip(const DivBufs &B, int P) {
         set_y(B.ypad, B.prod, ne, max(nV, ne));
         wsync();
         const int nD = nX + ne;
-        mul_gen(B.prod, nD, B.x, nX, B.ypad, ne, B.t0, B.t1, B.t2, B.t3);
+        mul_gen(B.prod, nD, B.x, nX, B.ypad, ne, B.t0, B.t1, B.t2, B.t3, 2 * P + 4);
         // X' = X 2^(f'-f) +- (X |e|) >> (2f + g - f')
         const int nX2 = limbs_for_bits(f2 + 2) + 1;
         shift(B.t0, nX2, B.x, nX, f2 - f);
@@ -607,7 +759,7 @@ __device__ bool recip(const DivBufs &B, int P) {
     fill(B.x + nX, P + 4 - nX, 0u);
     set_y(B.ypad, B.v, P, P + 4);
     wsync();
-    mul_gen(B.prod, nE, B.x, P + 2, B.ypad, P, B.t0, B.t1, B.t2, B.t3);
+    mul_gen(B.prod, nE, B.x, P + 2, B.ypad, P, B.t0, B.t1, B.t2, B.t3, 2 * P + 4);
     fill(B.t0, nE, 0u);
     wsync();
     if (lane() == 0) B.t0[2 * P] = 1u;
@@ -661,12 +813,12 @@ __device__ bool div_by_recip(uint32_t *out, Hdr &hq, Hdr ha, Hdr hb, const uint3
         B.ypad[q] = (kq >= 0 && kq < P + 1) ? R[kq] : 0u;
     }
     wsync();
-    mul_gen(B.prod, 2 * P + 1, B.x, P, B.ypad, P + 1, B.t0, B.t1, B.t2, B.t3);
+    mul_gen(B.prod, 2 * P + 1, B.x, P, B.ypad, P + 1, B.t0, B.t1, B.t2, B.t3, 2 * P + 4);
     shift(B.x, n2, B.prod, 2 * P + 1, -(p - 1));  // Q0 (P + 2 limbs)
     set_y(B.ypad, B.v, P, P + 4);
     wsync();
     // low half of Q0 m_b
-    mul_gen(B.prod, n2, B.x, n2, B.ypad, P, B.t0, B.t1, B.t2, B.t3);
+    mul_gen(B.prod, n2, B.x, n2, B.ypad, P, B.t0, B.t1, B.t2, B.t3, 2 * P + 4);
     // rem = (m_a 2^(p+1) - Q0 m_b) mod 2^(32 n2)
     shift(B.t0, n2, B.a, P, p + 1);
     fill(B.t1, n2, 0u);

@@ -54,6 +54,21 @@ def test_adjugate_zero_pivot_gives_zeros():
     assert info == 1 and not got.limbs.any()
 
 
+@pytest.mark.parametrize("N,P,path", [(2, 8, "valu"), (6, 8, "mfma"), (30, 64, "auto"), (12, 264, "mfma")])
+def test_adjugate_singular_last_pivot(N, P, path):
+    """Only u_nn is zero (info = n): adj(A)^T is still defined (the back
+    substitution never divides by u_nn) and must be the oracle's."""
+    say(f"[adj] singular last pivot N={N} P={P} {path}")
+    A, L, U = inputs.triangular_product(N, P, 60 + N)
+    U[N - 1, N - 1] = 0
+    A = inputs.from_values((L.astype(object) @ U.astype(object)), P)
+    got, info = gpu_adj(A, path)
+    f = oracle.factor(A)
+    assert info == f.info == N
+    assert_same(got, oracle.adjugate_t(f), f"adjT singular N={N}")
+    assert got.limbs.any()
+
+
 def test_autograd_backward_equals_cofactors_and_finite_differences():
     import torch
     from paper_1308_1536_amd import binding
@@ -97,3 +112,32 @@ def test_autograd_backward_equals_cofactors_and_finite_differences():
             dets.append(exact.values(oracle.factor(Ap).D)[-1])
         fd = (dets[0] - dets[1]) / (2 * h)
         assert exact.bits_agree(fd, C[i, j]) > 900, (i, j)
+
+
+def test_autograd_zero_pivot_raises_and_singular_last_pivot_differentiates():
+    """A zero pivot before the last step makes the forward raise (the method
+    cannot give det there); a zero last pivot gives det = 0 exactly and the
+    backward still returns adj(A)^T (the oracle's, bit for bit)."""
+    import torch
+    from paper_1308_1536_amd import binding
+    from paper_1308_1536_amd.autograd import GradHolder, ZeroPivotError, mp_det
+    say("[adj] autograd zero pivots")
+    A = binding.DeviceMp.from_host(inputs.from_values([[0, 1], [1, 1]], 8))
+    with pytest.raises(ZeroPivotError) as e:
+        mp_det(A)
+    assert e.value.info == 1
+    N = 7
+    A_host, L, U = inputs.triangular_product(N, 8, 5)
+    U[N - 1, N - 1] = 0
+    A_host = inputs.from_values((L.astype(object) @ U.astype(object)), 8)
+    holder = GradHolder()
+    proxy = torch.zeros((N, N), dtype=torch.float64, device="cuda", requires_grad=True)
+    mant, e = mp_det(binding.DeviceMp.from_host(A_host), proxy, "auto", holder)
+    assert float(mant.item()) == 0.0 and int(e.item()) == 0
+    mant.backward()
+    torch.cuda.synchronize()
+    f = oracle.factor(A_host)
+    assert f.info == N and int(holder.info.item()) == N
+    assert_same(holder.adjT.to_host(), oracle.adjugate_t(f), "autograd adjT singular")
+    am, ae = oracle.to_f64(oracle.adjugate_t(f))
+    assert np.array_equal(proxy.grad.cpu().numpy(), np.ldexp(am, ae))

@@ -50,6 +50,21 @@ def test_all_minors_zero_pivot_gives_zeros():
     assert info == 2 and not got.limbs.any() and not got.exp.any() and not got.sign.any()
 
 
+@pytest.mark.parametrize("path", ["valu", "mfma"])
+def test_all_minors_singular_last_pivot(path):
+    """Only u_nn is zero (info = n): every leading block's minors, the whole
+    matrix's included, are still the oracle's."""
+    say(f"[all_minors] singular last pivot {path}")
+    N = 14
+    A, L, U = inputs.triangular_product(N, 8, 71)
+    U[N - 1, N - 1] = 0
+    A = inputs.from_values((L.astype(object) @ U.astype(object)), 8)
+    got, c, info = gpu_all(A, path)
+    assert info == N
+    assert_same(got, oracle.all_minors(A), "all_minors singular")
+    assert np.array_equal(got.limbs[-1], c.limbs[0]) and got.limbs[-1].any()
+
+
 @pytest.mark.parametrize("P", [8, 64])
 def test_padded_leading_dimensions(P):
     """Factor, adjugate and all-minors with every matrix at a padded leading

@@ -28,7 +28,7 @@ def check_against_oracle(A, path, what, ld=None):
     assert info == f.info, (what, info, f.info)
     assert_same(D, f.D, f"{what} D")
     assert_same(LU, f.LU, f"{what} LU")
-    if f.info == 0 and cw is not None:
+    if cw is not None:  # complete factors: info 0, or info n (only u_nn = 0)
         assert_same(c, cw, f"{what} c")
     return LU, D, c, info
 
@@ -98,6 +98,19 @@ def test_zero_pivots(path):
     A = inputs.from_values((L.astype(object) @ U.astype(object)), P)
     _, D, _, info = check_against_oracle(A, path, "zero pivot 5")
     assert info == 5
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("N", [2, 9, 40])
+def test_singular_last_pivot(path, N):
+    """Only u_nn is zero: info = n, D_n = 0, and the last-column minors are
+    still the oracle's (they never divide by u_nn)."""
+    P = 8
+    A, L, U = inputs.triangular_product(N, P, 40 + N)
+    U[N - 1, N - 1] = 0
+    A = inputs.from_values((L.astype(object) @ U.astype(object)), P)
+    _, D, c, info = check_against_oracle(A, path, f"singular last pivot N={N}")
+    assert info == N and not D.limbs[N - 1].any() and c.limbs.any()
 
 
 @pytest.mark.parametrize("P", [264, 520])

@@ -223,6 +223,28 @@ def test_thread_count_does_not_change_bits(oracle_lib):
     assert np.array_equal(ca.limbs, cb.limbs) and np.array_equal(ca.exp, cb.exp)
 
 
+def test_singular_last_pivot_keeps_minors(oracle_lib):
+    """Only the last pivot is zero (A = L U with u_nn = 0, every step exact):
+    info = n and D_n = 0, while the last-column minors and the adjugate --
+    which never divide by u_nn -- are the exact cofactors of the singular
+    matrix (eq. (minors) needs them exactly where det vanishes)."""
+    for N, seed in [(2, 3), (4, 5), (6, 7)]:
+        A, L, U = inputs.triangular_product(N, 4, seed)
+        U[N - 1, N - 1] = 0
+        M = (L.astype(object) @ U.astype(object))
+        A = inputs.from_values(M, 4)
+        f = oracle_lib.factor(A, threads=2)
+        assert f.info == N
+        D = vals(f.D)
+        assert D[N - 1] == 0 and all(D[k] != 0 for k in range(N - 1))
+        c = vals(oracle_lib.minors(f))
+        assert list(c) == exact.last_col_cofactors_exact(M.tolist())
+        adjT = vals(oracle_lib.adjugate_t(f))
+        C = exact.cofactors_exact(M.tolist())
+        assert all(adjT[i, j] == C[i][j] for i in range(N) for j in range(N))
+        assert sum(c[i] * M[i, N - 1] for i in range(N)) == 0
+
+
 def test_zero_pivot_and_overflow_info(oracle_lib):
     P = 2
     M = [[0, 1, 2], [3, 4, 5], [6, 7, 9]]
