@@ -116,6 +116,21 @@ int mp_det_factor_steps(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info
                         int64_t k_begin, int64_t k_end, int path, void *stream);
 
 /*
+ * mpdet_workspace_size -- device bytes of workspace mp_det_factor takes from
+ * the handle for an n x n matrix of nlimbs-limb numbers on `path` (with the
+ * handle's current panel setting, see mpdet_set_panel_rows): the pivot's
+ * reciprocal and, on the MFMA path and the VALU lane product (nlimbs <= 128,
+ * a multiple of 4), the product records of one row panel (MFMA: plus the
+ * digit strings of the multipliers and the pivot row).  mp_det_minors takes
+ * none.  The handle keeps the largest workspace any call needed until
+ * mpdet_destroy.  h may be NULL (the default panel setting).  Writes *bytes
+ * on the host; touches no device.
+ *   n >= 0, nlimbs in [2, 1024], path as for mp_det_factor, else
+ *   MPDET_EINVAL (MPDET_ENOTSUP: MFMA with nlimbs % 8 != 0).
+ */
+int mpdet_workspace_size(mpdet_handle *h, int64_t n, int32_t nlimbs, int path, size_t *bytes);
+
+/*
  * mpdet_set_panel_rows -- rows per panel of the MFMA path's trailing update
  * (the product records of one panel of rows are formed and consumed before the
  * next panel's; their buffer grows with the panel).  0 (the default) sizes

@@ -66,6 +66,8 @@ def lib() -> ctypes.CDLL:
         L.mp_det_factor.argtypes = [vp, MpdetMat, MpdetMat, vp, ctypes.c_int, vp]
         L.mp_det_factor_steps.argtypes = [vp, MpdetMat, MpdetMat, vp, i64, i64, ctypes.c_int, vp]
         L.mpdet_set_panel_rows.argtypes = [vp, i64]
+        L.mpdet_workspace_size.argtypes = [vp, i64, i32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
+        L.mpdet_workspace_size.restype = ctypes.c_int
         L.mp_det_minors.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, vp, vp]
         L.mp_to_f64.argtypes = [vp, MpdetMat, vp, vp, vp]
         L.mpdet_profile_begin.argtypes = [vp]
@@ -242,6 +244,17 @@ def factor_steps(A: DeviceMp, D: DeviceMp, info, k_begin: int, k_end: int, path:
                                                             int(k_end), _resolve(path, A.rows, A.P),
                                                             _stream(stream)))
     return D, info
+
+
+def workspace_size(n: int, P: int, path: str = "auto", device: int | None = None) -> int:
+    """mpdet_workspace_size: device bytes mp_det_factor takes from the handle
+    for an n x n matrix of P-limb numbers (device None: the default panel
+    setting, no handle and no GPU needed)."""
+    out = ctypes.c_size_t()
+    h = handle(device).ptr if device is not None else None
+    _check("mpdet_workspace_size", lib().mpdet_workspace_size(h, int(n), int(P), _resolve(path, n, P),
+                                                              ctypes.byref(out)))
+    return out.value
 
 
 def set_panel_rows(rows: int, device: int = 0):

@@ -144,10 +144,12 @@ struct DeviceGuard {
     }
 };
 
+size_t recip_bytes(int P) { return ((size_t)(P + 3) * 4u + 255) & ~(size_t)255; }
+
 // Scratch for the pivot's reciprocal: P + 2 limbs (R and its exactness flag),
 // then the pending pivot code (see finish_body).
 int recip_ws(mpdet_handle *h, int P, uint32_t **rw) {
-    const size_t need = ((size_t)(P + 3) * 4u + 255) & ~(size_t)255;
+    const size_t need = recip_bytes(P);
     if (need > h->rw_bytes) {
         if (h->rw) (void)hipFree(h->rw);
         h->rw = nullptr;
@@ -217,18 +219,29 @@ size_t mfma_rec_bytes(int64_t rows, int64_t m, int P) {
 // (a 6144 x 6144 matrix of 32768-bit numbers alone takes 155 GB).
 constexpr size_t kRecBudget = (size_t)24 << 30;
 
-// rows per panel for trailing blocks up to m x m
+size_t up256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// bytes of the reversed multiplier digits and the pivot-row digits for an
+// m x m trailing block (the MFMA path only)
+size_t mfma_digit_bytes(int64_t m, int P) {
+    return up256((size_t)m * mpk::mfma_geom(P).LR) + up256(mpk::ub_bytes(m, P));
+}
+
+// rows per panel for trailing blocks up to m x m: the handle's setting, else
+// as many as fit kRecBudget
 int64_t panel_rows(const mpdet_handle *h, int64_t m, int P) {
-    if (h->panel_rows > 0) return h->panel_rows < m ? h->panel_rows : m;
     const size_t per_row = (size_t)((m + 31) / 32) * 32u * (size_t)mpk::mfma_geom(P).TP * 4u;
+    if (h->panel_rows > 0) return h->panel_rows < m ? h->panel_rows : m;
     const int64_t r = (int64_t)(kRecBudget / per_row);
     return r < 1 ? 1 : (r < m ? r : m);
 }
 
-int mfma_workspace(mpdet_handle *h, int64_t m, int P, int64_t rows, MfmaWs *w) {
+// digits: the MFMA path's digit strings are needed (the lane product reads
+// only the records)
+int mfma_workspace(mpdet_handle *h, int64_t m, int P, int64_t rows, MfmaWs *w, bool digits = true) {
     const mpk::MfmaGeom g = mpk::mfma_geom(P);
-    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
-    const size_t lr = up((size_t)m * g.LR), ub = up(mpk::ub_bytes(m, P));
+    auto up = up256;
+    const size_t lr = digits ? up((size_t)m * g.LR) : 0, ub = digits ? up(mpk::ub_bytes(m, P)) : 0;
     const size_t t = up(mfma_rec_bytes(rows, m, P));
     const size_t need = lr + ub + t;
     if (need > h->ws_bytes) {
@@ -243,8 +256,8 @@ int mfma_workspace(mpdet_handle *h, int64_t m, int P, int64_t rows, MfmaWs *w) {
         h->ws_bytes = need;
     }
     uint8_t *base = (uint8_t *)h->ws;
-    w->Lr = base;
-    w->Ub = base + lr;
+    w->Lr = digits ? base : nullptr;
+    w->Ub = digits ? base + lr : nullptr;
     w->T = (uint32_t *)(base + lr + ub);
     return MPDET_OK;
 }
@@ -261,7 +274,7 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     MfmaWs w{};
     if (lane) {
         const int64_t m0 = n > 1 ? n - 1 : 1;
-        int rc = mfma_workspace(h, m0, P, m0, &w);
+        int rc = mfma_workspace(h, m0, P, m0, &w, false);
         if (rc) return rc;
     }
     const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_launch_lds(P);
@@ -490,16 +503,31 @@ static bool auto_uses_mfma(int P) {
     return mpk::mfma_supported(P) && !(P <= 64 && mpk::lane_update_ok(P));
 }
 
-int mp_det_factor_steps(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, int64_t k_begin,
-                        int64_t k_end, int path, void *stream) {
-    if (!h || !info_dev) return MPDET_EINVAL;
+}  // extern "C"
+
+namespace {
+// argument checks of the factorisation; *use_mfma receives the path taken
+int factor_args(const mpdet_mat &A, const mpdet_mat &D, const int32_t *info_dev, int64_t k_begin, int64_t k_end,
+                int path, bool *use_mfma) {
+    if (!info_dev) return MPDET_EINVAL;
     if (!mat_ok(A, A.rows > 0) || !mat_ok(D, A.rows > 0)) return MPDET_EINVAL;
     if (A.rows != A.cols || D.nlimbs != A.nlimbs || D.rows < 1 || D.cols < A.rows) return MPDET_EINVAL;
     if (k_begin < 0 || k_end < k_begin || k_end > A.rows) return MPDET_EINVAL;
     if (path != MPDET_PATH_AUTO && path != MPDET_PATH_VALU && path != MPDET_PATH_MFMA) return MPDET_EINVAL;
     const bool mfma_ok = mpk::mfma_supported(A.nlimbs);
     if (path == MPDET_PATH_MFMA && !mfma_ok) return MPDET_ENOTSUP;
-    const bool use_mfma = path == MPDET_PATH_MFMA || (path == MPDET_PATH_AUTO && auto_uses_mfma(A.nlimbs));
+    *use_mfma = path == MPDET_PATH_MFMA || (path == MPDET_PATH_AUTO && auto_uses_mfma(A.nlimbs));
+    return MPDET_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int mp_det_factor_steps(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, int64_t k_begin,
+                        int64_t k_end, int path, void *stream) {
+    if (!h) return MPDET_EINVAL;
+    bool use_mfma = false;
+    if (int rc = factor_args(A, D, info_dev, k_begin, k_end, path, &use_mfma)) return rc;
     DeviceGuard g(h->device);
     if (!g.ok) return MPDET_EHIP;
     hipStream_t s = (hipStream_t)stream;
@@ -515,6 +543,24 @@ int mp_det_factor_steps(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info
 
 int mp_det_factor(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, int path, void *stream) {
     return mp_det_factor_steps(h, A, D, info_dev, 0, A.rows, path, stream);
+}
+
+int mpdet_workspace_size(mpdet_handle *h, int64_t n, int32_t nlimbs, int path, size_t *bytes) {
+    if (!bytes || n < 0 || nlimbs < 2 || nlimbs > kMaxLimbs) return MPDET_EINVAL;
+    if (path != MPDET_PATH_AUTO && path != MPDET_PATH_VALU && path != MPDET_PATH_MFMA) return MPDET_EINVAL;
+    if (path == MPDET_PATH_MFMA && !mpk::mfma_supported(nlimbs)) return MPDET_ENOTSUP;
+    const bool use_mfma = path == MPDET_PATH_MFMA || (path == MPDET_PATH_AUTO && auto_uses_mfma(nlimbs));
+    const int P = nlimbs;
+    const int64_t m0 = n > 1 ? n - 1 : 1;
+    mpdet_handle dflt{};  // the default panel setting when no handle is given
+    size_t total = n > 0 ? recip_bytes(P) : 0;
+    if (n > 1 && use_mfma)
+        total += mfma_digit_bytes(m0, P) + up256(mfma_rec_bytes(h ? panel_rows(h, m0, P) : panel_rows(&dflt, m0, P),
+                                                               m0, P));
+    else if (n > 1 && mpk::lane_update_ok(P))
+        total += up256(mfma_rec_bytes(m0, m0, P));
+    *bytes = total;
+    return MPDET_OK;
 }
 
 int mpdet_set_panel_rows(mpdet_handle *h, int64_t rows) {

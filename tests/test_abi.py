@@ -17,11 +17,17 @@ def lib():
     return binding.lib()
 
 
+# the boundary's calls: handle life cycle, workspace query, factorisation,
+# minors, the batch, the gradient, output conversion, status names
+BOUNDARY = ("mpdet_create", "mpdet_destroy", "mpdet_workspace_size", "mp_det_factor", "mp_det_minors",
+            "mp_det_batched", "mp_det_adjugate", "mp_to_f64", "mpdet_strerror")
+
+
 def test_header_declares_the_entry_points():
     names = binding.header_functions()
-    for fn in ("mpdet_create", "mpdet_destroy", "mpdet_strerror", "mp_det_factor",
-               "mp_det_minors", "mp_to_f64"):
-        assert fn in names
+    for fn in BOUNDARY + ("mp_det_factor_steps", "mp_det_all_minors", "mp_det_normalize_minors",
+                          "mp_to_f64_scaled"):
+        assert fn in names, fn
 
 
 def test_library_exports_every_declared_symbol(lib):
@@ -34,6 +40,31 @@ def test_strerror(lib):
     assert binding.strerror(binding.MPDET_EINVAL) == "invalid argument"
     assert binding.strerror(binding.MPDET_ENOTSUP) == "not supported"
     assert binding.strerror(12345) == "unknown status"
+
+
+def test_workspace_size_on_host(lib):
+    """mpdet_workspace_size needs no GPU (NULL handle: default panels) and
+    follows the layout the header states."""
+    ws = binding.workspace_size
+    assert ws(0, 8, "valu") == 0
+    assert ws(1, 8, "valu") == ws(1, 8, "mfma") == 256      # the reciprocal only
+    assert ws(100, 6, "valu") == 256                         # one-wave update: no records
+    # lane product (P <= 128, P % 4 == 0): records of the whole trailing block
+    rec = lambda rows, m, P: (rows * ((m + 31) // 32) * 32 * (P + 4) + (P + 40) * 32) * 4
+    up = lambda x: (x + 255) // 256 * 256
+    assert ws(64, 32, "valu") == 256 + up(rec(63, 63, 32))
+    # MFMA adds the digit strings; the records stay one panel up to 24 GiB
+    assert ws(512, 128, "mfma") > ws(512, 128, "valu")
+    assert ws(2048, 1024, "mfma") >= rec(2047, 2047, 1024)
+    big = ws(6144, 1024, "mfma")  # 155 GB matrix: panels keep the records under 24 GiB
+    assert rec(6143, 6143, 1024) > 24 << 30 > big - 6143 * 2 * (4 * 1024 + 608)
+    sizes = [ws(n, 64, "valu") for n in range(0, 200, 7)]
+    assert sizes == sorted(sizes)
+    out = ctypes.c_size_t()
+    assert lib.mpdet_workspace_size(None, -1, 8, 0, ctypes.byref(out)) == binding.MPDET_EINVAL
+    assert lib.mpdet_workspace_size(None, 8, 1, 0, ctypes.byref(out)) == binding.MPDET_EINVAL
+    assert lib.mpdet_workspace_size(None, 8, 12, 2, ctypes.byref(out)) == binding.MPDET_ENOTSUP
+    assert lib.mpdet_workspace_size(None, 8, 8, 0, None) == binding.MPDET_EINVAL
 
 
 def test_null_handle_and_bad_args_rejected_on_host(lib):
