@@ -66,7 +66,8 @@ enum {
     MPDET_EINVAL = -1,
     MPDET_ENOMEM = -2,
     MPDET_EHIP = -3,
-    MPDET_ENOTSUP = -4
+    MPDET_ENOTSUP = -4,
+    MPDET_ERANGE = -5 /* the workspace would exceed mp_det_factor_noalloc's scratch */
 };
 
 enum {
@@ -140,6 +141,34 @@ int mpdet_workspace_size(mpdet_handle *h, int64_t n, int32_t nlimbs, int path, s
  *   rows >= 0, else MPDET_EINVAL.
  */
 int mpdet_set_panel_rows(mpdet_handle *h, int64_t rows);
+
+/*
+ * mp_det_factor_noalloc -- mp_det_factor for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments (no handle), same bits; it calls no
+ * hipMalloc, hipFree or other allocating routine.  Its workspace (the
+ * reciprocal, the digits and the product records) lives in one static device
+ * array of MPDET_NOALLOC_SCRATCH_BYTES per GPU, loaded with the library and
+ * held until the process ends; its address is taken once per device (in
+ * mpdet_create, or on the first call on that device).  Runs on the current
+ * HIP device.
+ *   Sizes whose workspace does not fit the array return MPDET_ERANGE before
+ *   any launch: on the VALU lane product (nlimbs <= 128, a multiple of 4) the
+ *   records of the whole (n-1) x (n-1) trailing block must fit (n <= 482 at
+ *   64 limbs, n <= 353 at 128); on the MFMA path the update runs over row
+ *   panels sized to the array, and the digit strings plus one row's records
+ *   must fit (n <= 5156 at 1024 limbs); other VALU limb counts need only the
+ *   reciprocal.
+ *   Every call on one GPU uses that GPU's one array, which keeps what the last
+ *   call left: calls that overlap in time on one GPU (other streams, other
+ *   threads) race and give wrong results.  Whatever a call uses from the
+ *   array it wrote earlier in the same call (the pending-pivot word is cleared
+ *   by a kernel at the start; the read-ahead past the last record and the
+ *   padding columns are read but never used), so earlier contents never reach
+ *   a result.
+ */
+#define MPDET_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int mp_det_factor_noalloc(mpdet_mat A, mpdet_mat D, int32_t *info_dev, int path, void *stream);
 
 /*
  * mp_det_minors -- signed last-column cofactors c_i = (-1)^(i+n) M_{i,n}

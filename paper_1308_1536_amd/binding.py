@@ -22,7 +22,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmpdet.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "mpdet.h")
 
-MPDET_OK, MPDET_EINVAL, MPDET_ENOMEM, MPDET_EHIP, MPDET_ENOTSUP = 0, -1, -2, -3, -4
+MPDET_OK, MPDET_EINVAL, MPDET_ENOMEM, MPDET_EHIP, MPDET_ENOTSUP, MPDET_ERANGE = 0, -1, -2, -3, -4, -5
+NOALLOC_SCRATCH_BYTES = 64 << 20  # MPDET_NOALLOC_SCRATCH_BYTES
 PATH_AUTO, PATH_VALU, PATH_MFMA = 0, 1, 2
 PATHS = {"auto": PATH_AUTO, "valu": PATH_VALU, "mfma": PATH_MFMA}
 
@@ -66,6 +67,8 @@ def lib() -> ctypes.CDLL:
         L.mp_det_factor.argtypes = [vp, MpdetMat, MpdetMat, vp, ctypes.c_int, vp]
         L.mp_det_factor_steps.argtypes = [vp, MpdetMat, MpdetMat, vp, i64, i64, ctypes.c_int, vp]
         L.mpdet_set_panel_rows.argtypes = [vp, i64]
+        L.mp_det_factor_noalloc.argtypes = [MpdetMat, MpdetMat, vp, ctypes.c_int, vp]
+        L.mp_det_factor_noalloc.restype = ctypes.c_int
         L.mpdet_workspace_size.argtypes = [vp, i64, i32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
         L.mpdet_workspace_size.restype = ctypes.c_int
         L.mp_det_minors.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, vp, vp]
@@ -243,6 +246,17 @@ def factor_steps(A: DeviceMp, D: DeviceMp, info, k_begin: int, k_end: int, path:
     _check("mp_det_factor_steps", lib().mp_det_factor_steps(h.ptr, A.mat(), D.mat(), info.data_ptr(), int(k_begin),
                                                             int(k_end), _resolve(path, A.rows, A.P),
                                                             _stream(stream)))
+    return D, info
+
+
+def factor_noalloc(A: DeviceMp, D: DeviceMp, info, path: str = "auto", stream=None):
+    """mp_det_factor_noalloc: mp_det_factor in place on A with the library's
+    static per-device scratch (no device allocation; the caller passes D and
+    info).  Runs on A's device."""
+    import torch
+    with torch.cuda.device(A.limbs.device):
+        _check("mp_det_factor_noalloc", lib().mp_det_factor_noalloc(A.mat(), D.mat(), info.data_ptr(),
+                                                                    _resolve(path, A.rows, A.P), _stream(stream)))
     return D, info
 
 

@@ -17,6 +17,7 @@
 #include "kernels_lane.h"
 #include "peaks.h"
 #include <algorithm>
+#include <mutex>
 #include <numeric>
 #include <vector>
 
@@ -144,12 +145,25 @@ struct DeviceGuard {
     }
 };
 
+// A fixed device region the factorisation's workspace is carved from instead
+// of the handle's allocations (the allocation-free entry point's scratch): the
+// pivot's reciprocal first, then the update's digits and records.
+struct Arena {
+    uint8_t *base;
+    size_t cap;
+};
+
 size_t recip_bytes(int P) { return ((size_t)(P + 3) * 4u + 255) & ~(size_t)255; }
 
 // Scratch for the pivot's reciprocal: P + 2 limbs (R and its exactness flag),
 // then the pending pivot code (see finish_body).
-int recip_ws(mpdet_handle *h, int P, uint32_t **rw) {
+int recip_ws(mpdet_handle *h, int P, uint32_t **rw, const Arena *ar = nullptr) {
     const size_t need = recip_bytes(P);
+    if (ar) {
+        if (need > ar->cap) return MPDET_ERANGE;
+        *rw = (uint32_t *)ar->base;
+        return MPDET_OK;
+    }
     if (need > h->rw_bytes) {
         if (h->rw) (void)hipFree(h->rw);
         h->rw = nullptr;
@@ -228,9 +242,16 @@ size_t mfma_digit_bytes(int64_t m, int P) {
 }
 
 // rows per panel for trailing blocks up to m x m: the handle's setting, else
-// as many as fit kRecBudget
-int64_t panel_rows(const mpdet_handle *h, int64_t m, int P) {
+// as many as fit kRecBudget; from a fixed arena, as many as fit what the
+// reciprocal and the digits leave of it (0 if not one row fits)
+int64_t panel_rows(const mpdet_handle *h, int64_t m, int P, const Arena *ar = nullptr) {
     const size_t per_row = (size_t)((m + 31) / 32) * 32u * (size_t)mpk::mfma_geom(P).TP * 4u;
+    if (ar) {
+        const size_t fixed = recip_bytes(P) + mfma_digit_bytes(m, P) + up256(mfma_rec_bytes(0, m, P)) + 256u;
+        if (fixed + per_row > ar->cap) return 0;
+        const int64_t r = (int64_t)((ar->cap - fixed) / per_row);
+        return r < m ? r : m;
+    }
     if (h->panel_rows > 0) return h->panel_rows < m ? h->panel_rows : m;
     const int64_t r = (int64_t)(kRecBudget / per_row);
     return r < 1 ? 1 : (r < m ? r : m);
@@ -238,12 +259,22 @@ int64_t panel_rows(const mpdet_handle *h, int64_t m, int P) {
 
 // digits: the MFMA path's digit strings are needed (the lane product reads
 // only the records)
-int mfma_workspace(mpdet_handle *h, int64_t m, int P, int64_t rows, MfmaWs *w, bool digits = true) {
+int mfma_workspace(mpdet_handle *h, int64_t m, int P, int64_t rows, MfmaWs *w, bool digits = true,
+                   const Arena *ar = nullptr) {
     const mpk::MfmaGeom g = mpk::mfma_geom(P);
     auto up = up256;
     const size_t lr = digits ? up((size_t)m * g.LR) : 0, ub = digits ? up(mpk::ub_bytes(m, P)) : 0;
     const size_t t = up(mfma_rec_bytes(rows, m, P));
     const size_t need = lr + ub + t;
+    if (ar) {
+        const size_t off = recip_bytes(P);
+        if (off > ar->cap || need > ar->cap - off) return MPDET_ERANGE;
+        uint8_t *base = ar->base + off;
+        w->Lr = digits ? base : nullptr;
+        w->Ub = digits ? base + lr : nullptr;
+        w->T = (uint32_t *)(base + lr + ub);
+        return MPDET_OK;
+    }
     if (need > h->ws_bytes) {
         if (h->ws) (void)hipFree(h->ws);
         h->ws = nullptr;
@@ -266,7 +297,7 @@ int mfma_workspace(mpdet_handle *h, int64_t m, int P, int64_t rows, MfmaWs *w, b
 // lane-per-element product kernel into the record buffer, then the finish
 // kernel the MFMA path uses; otherwise one wave per element update.
 int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, int64_t k_begin,
-                int64_t k_end, hipStream_t s) {
+                int64_t k_end, hipStream_t s, const Arena *ar = nullptr) {
     const int64_t n = A.rows;
     const int P = A.nlimbs;
     const size_t lds = mpk::lds_bytes(P);
@@ -274,7 +305,7 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     MfmaWs w{};
     if (lane) {
         const int64_t m0 = n > 1 ? n - 1 : 1;
-        int rc = mfma_workspace(h, m0, P, m0, &w, false);
+        int rc = mfma_workspace(h, m0, P, m0, &w, false, ar);
         if (rc) return rc;
     }
     const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_launch_lds(P);
@@ -283,7 +314,7 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     const int32_t *cinfo = info;
     uint32_t *rw = nullptr;
     const bool ahead = lane && mpk::finish_lookahead_ok(P);  // the finish launch examines the next pivot
-    int rc0 = recip_ws(h, P, &rw);
+    int rc0 = recip_ws(h, P, &rw, ar);
     if (rc0 || (rc0 = pend_clear(rw, P, s))) return rc0;
     for (int64_t k = k_begin; k < k_end; ++k) {
         // with the finish kernel, step k's pivot was examined by step k-1's finish launch
@@ -313,13 +344,14 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
 }
 
 int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, int64_t k_begin,
-                int64_t k_end, hipStream_t s) {
+                int64_t k_end, hipStream_t s, const Arena *ar = nullptr) {
     const int64_t n = A.rows;
     const int P = A.nlimbs;
     MfmaWs w;
     const int64_t m0 = n - k_begin - 1 > 1 ? n - k_begin - 1 : 1;
-    const int64_t R = panel_rows(h, m0, P);
-    int rc = mfma_workspace(h, m0, P, R, &w);
+    const int64_t R = panel_rows(h, m0, P, ar);
+    if (R < 1) return MPDET_ERANGE;
+    int rc = mfma_workspace(h, m0, P, R, &w, true, ar);
     if (rc) return rc;
     const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
     const size_t lds_fin = mpk::finish_launch_lds(P);
@@ -328,7 +360,7 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     mpk::MatDev a = dev(A), d = dev(D);
     const int32_t *cinfo = info;
     uint32_t *rw = nullptr;
-    if ((rc = recip_ws(h, P, &rw)) || (rc = pend_clear(rw, P, s))) return rc;
+    if ((rc = recip_ws(h, P, &rw, ar)) || (rc = pend_clear(rw, P, s))) return rc;
     const bool ahead = mpk::finish_lookahead_ok(P);  // the finish launch examines the next pivot
     for (int64_t k = k_begin; k < k_end; ++k) {
         if ((rc = pivot_step(h, a, d, info, rw, k, n, P, ahead && k > k_begin, s))) return rc;
@@ -361,6 +393,32 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     return pend_promote(info, rw, P, s);
 }
 
+// The allocation-free entry point's workspace: one static array per device,
+// loaded with the code object and held until the process ends.  Host code
+// never uses the array's name as an address: each device's address comes from
+// hipGetSymbolAddress, taken once with that device current.
+__device__ __align__(256) uint8_t scratch[MPDET_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint8_t *g_scratch_ptr[kMaxDevices];
+
+// the scratch array's address on `device` (which must be current), resolved
+// on first use; nullptr if the runtime cannot give it
+uint8_t *scratch_on(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        g_scratch_ptr[device] = (uint8_t *)ptr;
+    }
+    return g_scratch_ptr[device];
+}
+
 }  // namespace
 
 extern "C" {
@@ -372,6 +430,7 @@ const char *mpdet_strerror(int status) {
         case MPDET_ENOMEM: return "out of device memory";
         case MPDET_EHIP: return "HIP runtime error";
         case MPDET_ENOTSUP: return "not supported";
+        case MPDET_ERANGE: return "workspace exceeds the allocation-free entry point's scratch";
         default: return "unknown status";
     }
 }
@@ -384,6 +443,14 @@ int mpdet_create(mpdet_handle **h, int device) {
     mpdet_handle *p = (mpdet_handle *)calloc(1, sizeof(mpdet_handle));
     if (!p) return MPDET_ENOMEM;
     p->device = device;
+    {
+        // resolve the device's scratch address for mp_det_factor_noalloc
+        DeviceGuard g(device);
+        if (!g.ok || !scratch_on(device)) {
+            free(p);
+            return MPDET_EHIP;
+        }
+    }
     *h = p;
     return MPDET_OK;
 }
@@ -506,7 +573,8 @@ static bool auto_uses_mfma(int P) {
 }  // extern "C"
 
 namespace {
-// argument checks of the factorisation; *use_mfma receives the path taken
+// argument checks shared by mp_det_factor_steps and mp_det_factor_noalloc;
+// *use_mfma receives the path taken
 int factor_args(const mpdet_mat &A, const mpdet_mat &D, const int32_t *info_dev, int64_t k_begin, int64_t k_end,
                 int path, bool *use_mfma) {
     if (!info_dev) return MPDET_EINVAL;
@@ -543,6 +611,29 @@ int mp_det_factor_steps(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info
 
 int mp_det_factor(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, int path, void *stream) {
     return mp_det_factor_steps(h, A, D, info_dev, 0, A.rows, path, stream);
+}
+
+int mp_det_factor_noalloc(mpdet_mat A, mpdet_mat D, int32_t *info_dev, int path, void *stream) {
+    bool use_mfma = false;
+    if (int rc = factor_args(A, D, info_dev, 0, A.rows, path, &use_mfma)) return rc;
+    int device = -1;
+    if (hipGetDevice(&device) != hipSuccess) return MPDET_EHIP;
+    uint8_t *base = scratch_on(device);
+    if (!base) return MPDET_EHIP;
+    const Arena ar{base, (size_t)MPDET_NOALLOC_SCRATCH_BYTES};
+    // the workspace must fit before anything is launched
+    const int P = A.nlimbs;
+    const int64_t m0 = A.rows > 1 ? A.rows - 1 : 1;
+    if (use_mfma ? A.rows > 1 && panel_rows(nullptr, m0, P, &ar) < 1
+                 : recip_bytes(P) + (mpk::lane_update_ok(P) && A.rows > 1 ? up256(mfma_rec_bytes(m0, m0, P)) : 0) >
+                       ar.cap)
+        return MPDET_ERANGE;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(mpk::k_set_info, dim3(1), dim3(64), 0, s, info_dev, 0);
+    if (int rc = last_launch()) return rc;
+    if (A.rows == 0) return MPDET_OK;
+    return use_mfma ? factor_mfma(nullptr, A, D, info_dev, 0, A.rows, s, &ar)
+                    : factor_valu(nullptr, A, D, info_dev, 0, A.rows, s, &ar);
 }
 
 int mpdet_workspace_size(mpdet_handle *h, int64_t n, int32_t nlimbs, int path, size_t *bytes) {

@@ -26,7 +26,7 @@ BOUNDARY = ("mpdet_create", "mpdet_destroy", "mpdet_workspace_size", "mp_det_fac
 def test_header_declares_the_entry_points():
     names = binding.header_functions()
     for fn in BOUNDARY + ("mp_det_factor_steps", "mp_det_all_minors", "mp_det_normalize_minors",
-                          "mp_to_f64_scaled"):
+                          "mp_to_f64_scaled", "mp_det_factor_noalloc"):
         assert fn in names, fn
 
 
@@ -40,6 +40,7 @@ def test_strerror(lib):
     assert binding.strerror(binding.MPDET_EINVAL) == "invalid argument"
     assert binding.strerror(binding.MPDET_ENOTSUP) == "not supported"
     assert binding.strerror(12345) == "unknown status"
+    assert "scratch" in binding.strerror(binding.MPDET_ERANGE)
 
 
 def test_workspace_size_on_host(lib):
@@ -73,6 +74,9 @@ def test_null_handle_and_bad_args_rejected_on_host(lib):
     assert lib.mp_det_minors(None, m, m, m, None, None) == binding.MPDET_EINVAL
     assert lib.mp_to_f64(None, m, None, None, None) == binding.MPDET_EINVAL
     assert lib.mpdet_create(None, 0) == binding.MPDET_EINVAL
+    assert lib.mp_det_factor_noalloc(m, m, None, 0, None) == binding.MPDET_EINVAL  # no info
+    bad = binding.MpdetMat(None, None, None, 4, 5, 5, 8)  # not square
+    assert lib.mp_det_factor_noalloc(bad, m, 8, 0, None) == binding.MPDET_EINVAL
     assert lib.mpdet_destroy(None) == binding.MPDET_EINVAL
 
 
