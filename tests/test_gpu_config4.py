@@ -1,0 +1,77 @@
+"""Configuration 4 whole: its 256 matrices (N uniform in [16, 384], 2048-bit,
+half random mantissas, half Cauchy) in one batched call, against the
+oracle's outputs stored by tests/golden/make_config4_golden.py (per matrix the
+info code, a hash of every D_k and every minor, a digest of the factored
+matrix), and the determinant's backward adj(A)^T on the stored sample of
+matrices against the oracle's digests."""
+import json
+import os
+import sys
+
+import pytest
+
+from gpu_util import say
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.join(HERE, "golden"))
+from golden_util import digest, entry_hashes  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(HERE, "golden", "config4_oracle.json")
+
+
+@pytest.fixture(scope="module")
+def batch():
+    from paper_1308_1536_amd import inputs
+    with open(GOLDEN) as fh:
+        g = json.load(fh)
+    mats = [m for _, m in inputs.config_c4()]
+    assert [m.exp.shape[0] for m in mats] == g["sizes"]
+    for b, m in enumerate(mats):
+        assert digest(m) == g["matrices"][b]["input_sha256"], f"the seeded generator changed (matrix {b})"
+    return g, mats
+
+
+@pytest.fixture(scope="module")
+def factored(batch):
+    import torch
+    from paper_1308_1536_amd import binding
+    g, hosts = batch
+    say(f"[config4] one batched call over {len(hosts)} matrices")
+    mats = [binding.DeviceMp.from_host(h) for h in hosts]
+    Ds, cs, info = binding.batched(mats, "auto")
+    torch.cuda.synchronize()
+    return mats, Ds, cs, info.cpu().numpy()
+
+
+def test_config4_batched_against_oracle(batch, factored):
+    g, _ = batch
+    mats, Ds, cs, info = factored
+    bad = []
+    for b, want in enumerate(g["matrices"]):
+        if int(info[b]) != want["info"]:
+            bad.append((b, "info"))
+            continue
+        if entry_hashes(Ds[b].row(0)) != want["D"]:
+            bad.append((b, "D"))
+        if want["c"] is not None and entry_hashes(cs[b].row(0)) != want["c"]:
+            bad.append((b, "c"))
+        if digest(mats[b].to_host()) != want["LU_sha256"]:
+            bad.append((b, "LU"))
+    assert not bad, f"{len(bad)} mismatches, first {bad[:6]}"
+
+
+def test_config4_backward_sample_against_oracle(batch, factored):
+    import torch
+    from paper_1308_1536_amd import binding
+    g, _ = batch
+    mats, Ds, cs, info = factored
+    for b in g["adjugate_sample"]:
+        want = g["matrices"][b].get("adjT_sha256")
+        if want is None:
+            continue
+        say(f"[config4] backward of matrix {b} (N={mats[b].rows})")
+        adjT = binding.adjugate(mats[b], Ds[b], torch.tensor(info[b:b + 1], device="cuda"))
+        torch.cuda.synchronize()
+        assert digest(adjT.to_host()) == want, f"adj(A)^T of matrix {b}"
