@@ -526,13 +526,20 @@ def bench_backward(args, mats, work, Ds, cs, binfo, infos, P):
     # each with a handle (workspace) of its own; config 4 measured 8.17 s per
     # pass on 1 stream, 4.48 s on 4, 3.59 s on 8, 3.16 s on 16
     S = min(int(os.environ.get("MPDET_BWD_STREAMS", "16")), len(work))
+    persistent = args.backward_schedule == "persistent" and binfo is not None
+    if persistent:
+        S = 1
     streams = [torch.cuda.Stream() for _ in range(S)]
     handles = [binding.Handle(work[0].limbs.device.index or 0) for _ in range(S)]
+    status = torch.zeros(len(work), dtype=torch.int32, device=work[0].limbs.device)
 
     def run():
         torch.cuda.synchronize()
-        for b, (w, D, t, inf) in enumerate(zip(work, Ds, outs, info_of)):
-            binding.adjugate(w, D, inf, t, stream=streams[b % S], h=handles[b % S])
+        if persistent:  # every matrix's backward in one persistent launch
+            binding.adjugate_batched(work, Ds, binfo, outs, status)
+        else:
+            for b, (w, D, t, inf) in enumerate(zip(work, Ds, outs, info_of)):
+                binding.adjugate(w, D, inf, t, stream=streams[b % S], h=handles[b % S])
         torch.cuda.synchronize()
 
     run()
@@ -558,8 +565,12 @@ def bench_backward(args, mats, work, Ds, cs, binfo, infos, P):
             checks[f"{b}:{nm}:N={n}"] = {"cols": cols,
                                          "max_rel_err_bits": adjugate_column_bits(m, outs[b].to_host(), det, cols)}
     lane = P <= 128 and P % 4 == 0
+    if persistent and status.any():
+        raise SystemExit(f"bench.py: batched backward status {status.cpu().tolist()}")
+    kern = "k_persist_adj" if persistent else ("k_prod_lane_r1 + k_finish_r1" if lane else "k_adj_w")
     return {"ms_per_pass": ms, "multiply_adds": ops,
-            "roofline": {"bound": "alu", "kernel": "k_prod_lane_r1 + k_finish_r1" if lane else "k_adj_w",
+            "schedule": "persistent" if persistent else f"one call per matrix on {S} streams",
+            "roofline": {"bound": "alu", "kernel": kern,
                          "achieved": rate / 1e12, "peak": PEAK_VALU_MAC32 / 1e12, "unit": "Tmac32/s",
                          "frac": rate / PEAK_VALU_MAC32, "measured_peak": mp / 1e12,
                          "frac_of_measured_peak": rate / mp, "streams": S},
@@ -816,6 +827,12 @@ def main():
     ap.add_argument("--backward", action="store_true",
                     help="after the timed factorisations, also time the determinant's backward "
                          "(mp_det_adjugate, adj(A)^T) on each matrix and check it")
+    ap.add_argument("--schedule", default="auto", choices=["auto", "persistent", "lockstep"],
+                    help="schedule of a batched call (configs 2 and 4): one persistent launch over a task "
+                         "queue, or one launch per phase per step (lockstep, the default)")
+    ap.add_argument("--backward-schedule", default="persistent", choices=["persistent", "streams"],
+                    help="--backward on a batch: one persistent launch over every matrix "
+                         "(mp_det_adjugate_batched) or one mp_det_adjugate call per matrix on 16 streams")
     ap.add_argument("--factor-steps", type=int, default=0, metavar="K",
                     help="time only K elimination steps of the first matrix, after --warmup untimed ones "
                          "(a partial run for matrices too large to repeat the path on; default for config 5: 24)")
@@ -876,7 +893,7 @@ def main():
             w.exp.copy_(p.exp)
             w.sign.copy_(p.sign)
         if batched:
-            binding.batched(work, path, minors=True, Ds=Ds, cs=cs, info=binfo)
+            binding.batched(work, path, minors=True, Ds=Ds, cs=cs, info=binfo, schedule=args.schedule)
             return
         for w, D, c, info in zip(work, Ds, cs, infos):
             binding.factor(w, path, D=D, info=info)
@@ -943,7 +960,18 @@ def main():
         HBM bytes (read a_ij and the product record, write a_ij)."""
         kms, kn = prof[kname]
         secs = kms / 1e3
-        if kname == "update_valu":
+        if kname == "batch_persistent":
+            # the whole batch in one launch: every phase of every step inside it
+            achieved = upd * P * P / secs
+            mp = measured_peak("mad64")
+            r = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_MAC32 / 1e12,
+                 "unit": "Tmac32/s", "frac": achieved / PEAK_VALU_MAC32, "kernel": "k_persist",
+                 "measured_peak": mp / 1e12, "frac_of_measured_peak": achieved / mp,
+                 "note": "one launch holds the products, the finish, the multipliers, the pivots and the "
+                         "minors of every matrix"}
+            if P <= 128 and P % 4 == 0:
+                r.update(issued("alu", P, r["frac"]))
+        elif kname == "update_valu":
             achieved = upd * P * P / secs
             mp = measured_peak("mad64")
             r = {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_VALU_MAC32 / 1e12,
@@ -967,7 +995,7 @@ def main():
         r.update({"traffic": measured_traffic(r["kernel"]), "avg_launch_ms": kms / kn, "launches": kn})
         return r
 
-    cands = [k for k in ("update_valu", "update_mfma", "update_finish") if prof[k][1] > 0]
+    cands = [k for k in ("update_valu", "update_mfma", "update_finish", "batch_persistent") if prof[k][1] > 0]
     if not cands:
         raise SystemExit("bench.py: no trailing-update launches were timed")
     dom = max(cands, key=lambda k: prof[k][0])
@@ -979,7 +1007,9 @@ def main():
            "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "i8" if prof["update_mfma"][1] > 0 else "u32", "data": "synthetic",
            "config": {"workload": desc, "N": int(max(m.exp.shape[0] for _, m in mats)), "bits": 32 * P,
-                      "matrices": len(mats), "path": path, "batched": batched, "updates_per_step": upd,
+                      "matrices": len(mats), "path": path, "batched": batched,
+                      "schedule": (("persistent" if prof["batch_persistent"][1] > 0 else "lockstep")
+                                   if batched else None), "updates_per_step": upd,
                       "limb_macs_per_step": macs},
            "roofline": roof}
     if not args.no_cpu_baseline:

@@ -117,6 +117,47 @@ int mp_det_factor_steps(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info
                         int64_t k_begin, int64_t k_end, int path, void *stream);
 
 /*
+ * mp_det_extend -- grow a factorisation (Sec. 4.1: the largest size need not
+ * be fixed in advance; determinants of sizes N_b, 2 N_b, 3 N_b, ... follow as
+ * blocks are added).  A is n x n; its leading n_old x n_old block holds
+ * mp_det_factor's output for that block (U and the multipliers) and D holds
+ * its D_1 .. D_{n_old}; the other entries of A are the new rows and columns,
+ * not yet eliminated.  The call applies elimination steps 0 .. n_old-1 to the
+ * new entries (the new rows' multipliers, then each step's update of the new
+ * rows and of the new columns, in step order), then runs steps n_old .. n-1,
+ * so A, D and info end bit-identical to mp_det_factor on the whole n x n
+ * matrix (every entry gets the same operations in the same order).
+ *   info_dev must hold the leading factorisation's info; a nonzero value makes
+ *   the call do nothing.  0 <= n_old <= n (n_old = 0: mp_det_factor).  The
+ *   steps 0 .. n_old-1 on the new entries run on the VALU kernels (the lane
+ *   product where nlimbs <= 128 is a multiple of 4, else one wave per
+ *   element); the steps from n_old on take `path`.
+ */
+int mp_det_extend(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, int64_t n_old, int path,
+                  void *stream);
+
+/*
+ * mp_truncate -- y = RZ to 32*y.nlimbs bits of x, element by element
+ * (y.nlimbs <= x.nlimbs; same rows and cols, each its own ld): the top
+ * y.nlimbs limbs of every mantissa, the same exponent and sign.
+ */
+int mp_truncate(mpdet_handle *h, mpdet_mat x, mpdet_mat y, void *stream);
+
+/*
+ * mp_det_factor_reduced -- elimination with reduced precision in its later
+ * steps (Sec. 4.3: after the unavoidable loss of accuracy, the later
+ * iterations need not run at full precision).  Steps 0 .. k_switch-1 run on A
+ * (nlimbs P) with D receiving D_1 .. D_{k_switch} at full precision; then A
+ * and D_1 .. D_{k_switch} are truncated (mp_truncate) into A2 and D2 (nlimbs
+ * P2 <= P, n x n and 1 x n), and steps k_switch .. n-1 run there on path2.
+ * Afterwards A2 holds the factors at P2 (mp_det_minors on A2, D2 gives the
+ * minors at P2) and D2 all of D_1 .. D_n at P2.  info as for mp_det_factor.
+ *   0 <= k_switch <= n; other arguments as for mp_det_factor.
+ */
+int mp_det_factor_reduced(mpdet_handle *h, mpdet_mat A, mpdet_mat D, mpdet_mat A2, mpdet_mat D2, int32_t *info_dev,
+                          int64_t k_switch, int path, int path2, void *stream);
+
+/*
  * mpdet_workspace_size -- device bytes of workspace mp_det_factor takes from
  * the handle for an n x n matrix of nlimbs-limb numbers on `path` (with the
  * handle's current panel setting, see mpdet_set_panel_rows): the pivot's
@@ -171,6 +212,18 @@ int mpdet_set_panel_rows(mpdet_handle *h, int64_t rows);
 int mp_det_factor_noalloc(mpdet_mat A, mpdet_mat D, int32_t *info_dev, int path, void *stream);
 
 /*
+ * mpdet_set_tuning -- launch shapes of the trailing update on this handle
+ * (the autotuner's knobs; every setting gives the same bits):
+ *   lane_rows   rows (= waves) per workgroup of the VALU lane product, each
+ *               workgroup a lane_rows x 64 tile: 2, 4 or 8 (0: 4);
+ *   mfma_waves  waves per workgroup of the MFMA update, each a row of one
+ *               32-column block: 1, 2 or 4 (0: 2); a value whose LDS does not
+ *               fit makes MFMA calls return MPDET_ENOTSUP.
+ * The persistent batched launches keep 4 waves per workgroup.
+ */
+int mpdet_set_tuning(mpdet_handle *h, int32_t lane_rows, int32_t mfma_waves);
+
+/*
  * mp_det_minors -- signed last-column cofactors c_i = (-1)^(i+n) M_{i,n}
  * (eq. (minorsdef); Sec. 3 [A I] derivation), from mp_det_factor's output.
  * With L the unit lower factor, x^T L = e_n^T is solved by sweeps j = n..2,
@@ -185,23 +238,65 @@ int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c,
 
 /*
  * mp_det_batched -- mp_det_factor (and, with MPDET_WANT_MINORS, mp_det_minors)
- * on `batch` matrices of uneven n in lockstep: the batch is ordered by n
- * (largest first) and every phase of every elimination step is one launch
- * covering all matrices still active at that step.  Results are bit-identical
- * to calling mp_det_factor / mp_det_minors on each matrix.
+ * on `batch` matrices of uneven n.  Results are bit-identical to calling
+ * mp_det_factor / mp_det_minors on each matrix (every matrix gets exactly the
+ * operations of its own elimination; only the schedule differs).
  *   A_arr, D_arr, c_arr  host arrays of `batch` descriptors (device buffers),
  *                        shapes as for mp_det_factor / mp_det_minors; all
  *                        matrices share one nlimbs;  c_arr may be NULL
  *                        without MPDET_WANT_MINORS.
  *   info_dev             device int32[batch], one info per matrix (a failing
- *                        matrix does not affect the others).
- *   flags                0 or MPDET_WANT_MINORS.
- * The descriptor tables are staged through pinned host memory owned by the
- * handle; per-matrix scratch lives in the handle's device workspace.
+ *                        matrix does not affect the others); besides the codes
+ *                        above, -2 means a wait of the persistent launch
+ *                        expired (mpdet_set_wait_limit) and the matrix's
+ *                        results are unspecified.
+ *   flags                MPDET_WANT_MINORS, and at most one schedule flag.
+ * Schedules (Sec. 4.1: a queue of tasks, each taken by an idle worker once the
+ * tasks it depends on are done):
+ *   lockstep (the default): the batch ordered by n, every phase of every step
+ *     one launch over all matrices still active at that step.
+ *   persistent (MPDET_BATCH_PERSISTENT; the VALU path only, MPDET_ENOTSUP on
+ *     MFMA): ONE launch of resident workgroups works through a queue of
+ *     tickets -- every phase of every elimination step and minors sweep of
+ *     every matrix, ordered by step, then phase, then matrix size (largest
+ *     first) -- and a ticket starts once its matrix's count of completed
+ *     tickets shows every earlier phase of that matrix done, so a matrix never
+ *     waits for another.  Two small launches around it reset the counters and
+ *     turn expired waits into info = -2.  Every wait is bounded.
+ *   MPDET_BATCH_LOCKSTEP names the default explicitly.  Which is faster depends
+ *   on the batch (the autotuner measures both).
+ * The descriptor and schedule tables are staged through pinned host memory
+ * owned by the handle; per-matrix scratch lives in the handle's device
+ * workspace.
  */
-enum { MPDET_WANT_MINORS = 1 };
+enum { MPDET_WANT_MINORS = 1, MPDET_BATCH_LOCKSTEP = 2, MPDET_BATCH_PERSISTENT = 4 };
 int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const mpdet_mat *D_arr,
                    const mpdet_mat *c_arr, int32_t *info_dev, int flags, int path, void *stream);
+
+/*
+ * mpdet_set_wait_limit -- bound, in seconds, on every wait of the persistent
+ * batched launch (default 10 s; no correct run waits more than one phase of
+ * one matrix).  A wait that expires stops the launch: every later ticket is
+ * skipped and the matrices it touched report info = -2.  0 makes any wait
+ * that is not already satisfied expire (a test of that path).
+ *   0 <= seconds <= 3600, else MPDET_EINVAL.
+ */
+int mpdet_set_wait_limit(mpdet_handle *h, double seconds);
+
+/*
+ * mpdet_batched_plan -- the persistent launch's schedule for matrices of sizes
+ * n_host[0..batch) (host only; touches no device): *nrec phase records and
+ * *ntickets tickets (a lane-product ticket is one tile for the whole
+ * workgroup; any other ticket gives each of the workgroup's 4 waves one unit).  With recs_out (cap >= *nrec records of 32 bytes: int64
+ * need, int64 units, int64 k, int32 matrix, int32 kind) the records are
+ * copied out in queue order; `need` is the number of that matrix's tickets
+ * that must be complete before the record's tickets start.  Kinds: 0 init,
+ * 1 pivot, 2 multipliers, 3 lane products, 4 finish, 5 one-wave update,
+ * 6 pending-code promotion, 7 minors sweep (k = its column j), 8 minors' last
+ * step.  MPDET_ENOTSUP where the batch would run on MFMA (lockstep only).
+ */
+int mpdet_batched_plan(int64_t batch, const int64_t *n_host, int32_t nlimbs, int path, int flags, void *recs_out,
+                       int64_t cap, int64_t *nrec, int64_t *ntickets);
 
 /*
  * mp_det_adjugate -- adjT = adj(A)^T, i.e. adjT[i][j] = C_ij = d det(A) / d a_ij
@@ -222,6 +317,32 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
  */
 int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT,
                     const int32_t *info_dev, void *stream);
+
+/*
+ * mp_det_adjugate_batched -- mp_det_adjugate on `batch` factored matrices of
+ * uneven n (the backward of mp_det_batched), bit-identical to one
+ * mp_det_adjugate call per matrix.  By default ONE persistent launch works
+ * through a queue holding every phase of every matrix's adjugate (the W
+ * sweeps, S and the diagonal of adj(U), the reciprocals, the back
+ * substitution, the accumulation; each O(n^3) step a rank-1 update on the
+ * lane product and the tile finish where nlimbs <= 128 is a multiple of 4),
+ * as mp_det_batched's persistent schedule does for the forward;
+ * MPDET_BATCH_LOCKSTEP runs one mp_det_adjugate call per matrix instead.
+ *   LU_arr, D_arr, adjT_arr  host arrays of `batch` descriptors, shapes as for
+ *                            mp_det_adjugate; all share one nlimbs.
+ *   info_dev                 device int32[batch]: the factorisations' infos.
+ *   status_dev               device int32[batch] or NULL: 0 (adjT written),
+ *                            the factorisation's info (factors incomplete:
+ *                            adjT is zero), or -2 (a wait of the persistent
+ *                            launch expired, see mpdet_set_wait_limit: adjT
+ *                            unspecified).
+ *   flags                    0 or MPDET_BATCH_LOCKSTEP.
+ * Workspace (in the handle): about 2 n^2 numbers per matrix plus, on the lane
+ * product, the records of an n x n block per matrix.
+ */
+int mp_det_adjugate_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *LU_arr, const mpdet_mat *D_arr,
+                            const mpdet_mat *adjT_arr, const int32_t *info_dev, int32_t *status_dev, int flags,
+                            void *stream);
 
 /*
  * mp_det_all_minors -- the last-column cofactors of every leading block
@@ -296,8 +417,8 @@ int mpdet_measure_peak(mpdet_handle *h, int kind, double *per_second);
  * kernel: "pivot_divide" (leading determinant and the pivot's reciprocal),
  * "divide" (multipliers), "update_valu", "update_mfma", "mfma_prep",
  * "minors_sweep", "minors_final", "update_finish" (the MFMA path's per-element
- * rounding and subtraction), "adjugate" or "other" (MPDET_EINVAL for other
- * names).
+ * rounding and subtraction), "adjugate", "all_minors", "batch_persistent" (the
+ * persistent batched launch) or "other" (MPDET_EINVAL for other names).
  */
 int mpdet_profile_begin(mpdet_handle *h);
 int mpdet_profile_end(mpdet_handle *h);

@@ -77,6 +77,12 @@ def _load():
         mat = [ctypes.c_int64, ctypes.c_int32, _u32p, _i64p, _i32p]
         lib.mpref_factor.argtypes = mat + [_u32p, _i64p, _i32p, _i32p, ctypes.c_int32]
         lib.mpref_factor.restype = ctypes.c_int
+        lib.mpref_factor_range.argtypes = mat + [_u32p, _i64p, _i32p, _i32p, ctypes.c_int64, ctypes.c_int64,
+                                                 ctypes.c_int32]
+        lib.mpref_factor_range.restype = ctypes.c_int
+        lib.mpref_truncate.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _u32p, _i64p, _i32p,
+                                       _u32p, _i64p, _i32p]
+        lib.mpref_truncate.restype = ctypes.c_int
         lib.mpref_minors.argtypes = mat + [_u32p, _i64p, _i32p, _u32p, _i64p, _i32p,
                                            ctypes.c_int32]
         lib.mpref_minors.restype = ctypes.c_int
@@ -292,6 +298,52 @@ def to_f64(x) -> tuple[np.ndarray, np.ndarray]:
     _load().mpref_to_f64(cnt, P, _p(x.limbs, _u32p), _p(x.exp, _i64p), _p(x.sign, _i32p),
                          _p(mant, _f64p), _p(ex, _i64p))
     return mant, ex
+
+
+def factor_range(f: Factorization, k_begin: int, k_end: int, threads: int | None = None) -> Factorization:
+    """Elimination steps k_begin .. k_end-1 continued from the state of f (a
+    copy); Algorithm 1's steps in order, each reading only what the steps
+    before it left."""
+    LU = f.LU.copy()
+    D = f.D.copy()
+    n, P = int(LU.exp.shape[0]), LU.P
+    info = np.array(f.info, np.int32)
+    rc = _load().mpref_factor_range(n, P, _p(LU.limbs, _u32p), _p(LU.exp, _i64p), _p(LU.sign, _i32p),
+                                    _p(D.limbs, _u32p), _p(D.exp, _i64p), _p(D.sign, _i32p), _p(info, _i32p),
+                                    int(k_begin), int(k_end), threads or default_threads())
+    if rc != 0:
+        raise ValueError("mpref_factor_range: bad argument")
+    return Factorization(LU, D, int(info))
+
+
+def truncate(x, P2: int) -> Mp:
+    """RZ to 32 * P2 bits of every number of x (P2 <= x's limbs)."""
+    x = _as_mp(x)
+    out = _zeros(x.exp.shape, P2)
+    rc = _load().mpref_truncate(int(x.exp.size), x.P, int(P2), _p(np.ascontiguousarray(x.limbs), _u32p),
+                                _p(np.ascontiguousarray(x.exp), _i64p), _p(np.ascontiguousarray(x.sign), _i32p),
+                                _p(out.limbs, _u32p), _p(out.exp, _i64p), _p(out.sign, _i32p))
+    if rc != 0:
+        raise ValueError("mpref_truncate: bad argument")
+    return out
+
+
+def det_pipeline_reduced(A, k_switch: int, P2: int, threads: int | None = None):
+    """The elimination with reduced precision in its later steps (Sec. 4.3's
+    remark that the later iterations need not run at full precision): steps
+    0 .. k_switch-1 at A's precision, then the whole state (the factored
+    matrix so far and D_1..D_{k_switch}) truncated to 32 * P2 bits, the
+    remaining steps and the minors at that precision.  Returns
+    (Factorization at P2, c or None, D_1..D_{k_switch} at full precision)."""
+    A = _as_mp(A)
+    n = int(A.exp.shape[0])
+    f0 = Factorization(A.copy(), _zeros((n,), A.P), 0)
+    f1 = factor_range(f0, 0, k_switch, threads)
+    lead = f1.D.copy()
+    f2 = Factorization(truncate(f1.LU, P2), truncate(f1.D, P2), f1.info)
+    f3 = factor_range(f2, k_switch, n, threads)
+    c = minors(f3, threads) if _complete(f3, n) else None
+    return f3, c, lead
 
 
 def det_pipeline(A, threads: int | None = None):

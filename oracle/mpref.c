@@ -392,11 +392,28 @@ static int64_t iabs64(int64_t x) { return x < 0 ? -x : x; }
 int mpref_factor(int64_t n, int32_t P, uint32_t *limbs, int64_t *exp, int32_t *sign,
                  uint32_t *Dl, int64_t *De, int32_t *Ds, int32_t *info, int32_t threads)
 {
+    if (!info) return -1;
+    *info = 0;
+    return mpref_factor_range(n, P, limbs, exp, sign, Dl, De, Ds, info, 0, n, threads);
+}
+
+/*
+ * Steps k_begin .. k_end-1 of the elimination above, continuing from the
+ * state an earlier range left (the matrix, D_1..D_{k_begin} and *info; a
+ * nonzero *info means the elimination already stopped).  Ranges [0, k_1),
+ * [k_1, k_2), ... applied in order are the whole elimination: each step reads
+ * only what the steps before it left.
+ */
+int mpref_factor_range(int64_t n, int32_t P, uint32_t *limbs, int64_t *exp, int32_t *sign,
+                       uint32_t *Dl, int64_t *De, int32_t *Ds, int32_t *info, int64_t k_begin,
+                       int64_t k_end, int32_t threads)
+{
     if (n < 0 || P < 1 || !info || (n > 0 && (!limbs || !exp || !sign || !Dl || !De || !Ds)))
         return -1;
+    if (k_begin < 0 || k_end < k_begin || k_end > n) return -1;
     if (threads < 1) threads = 1;
-    *info = 0;
-    for (int64_t k = 0; k < n; k++) {
+    if (*info != 0) return 0;
+    for (int64_t k = k_begin; k < k_end; k++) {
         /* step 2.1: the pivot is a_kk after k-1 elimination steps */
         if (num_is_zero(EL(k, k), P)) {
             *info = (int32_t)(k + 1);
@@ -641,4 +658,22 @@ void mpref_to_f64(int64_t count, int32_t P, const uint32_t *limbs, const int64_t
         mant[t] = sign[t] ? -x : x;
         eout[t] = exp[t];
     }
+}
+
+/*
+ * RZ to p2 = 32 P2 bits of numbers held with P >= P2 limbs: the exact value
+ * truncated toward zero.  A nonzero mantissa has its top bit set, so that is
+ * its top P2 limbs with the same exponent and sign (value m' 2^(e - 32 P2)).
+ */
+int mpref_truncate(int64_t count, int32_t P, int32_t P2, const uint32_t *limbs, const int64_t *exp,
+                   const int32_t *sign, uint32_t *ol, int64_t *oe, int32_t *os)
+{
+    if (count < 0 || P2 < 1 || P2 > P || (count > 0 && (!limbs || !exp || !sign || !ol || !oe || !os)))
+        return -1;
+    for (int64_t t = 0; t < count; t++) {
+        memcpy(ol + t * P2, limbs + t * P + (P - P2), sizeof(uint32_t) * (size_t)P2);
+        oe[t] = exp[t];
+        os[t] = sign[t];
+    }
+    return 0;
 }

@@ -58,6 +58,14 @@ int mpref_bn_divmod(uint32_t *q, uint32_t *r, const uint32_t *u, int32_t m,
  * l_ik = a_ik / a_kk below it; D receives the leading determinants D_1..D_n. */
 int mpref_factor(int64_t n, int32_t P, uint32_t *limbs, int64_t *exp, int32_t *sign,
                  uint32_t *Dl, int64_t *De, int32_t *Ds, int32_t *info, int32_t threads);
+/* Steps k_begin .. k_end-1 of the same elimination, continuing from the state
+ * (matrix, D, *info) an earlier range left; *info is not reset. */
+int mpref_factor_range(int64_t n, int32_t P, uint32_t *limbs, int64_t *exp, int32_t *sign,
+                       uint32_t *Dl, int64_t *De, int32_t *Ds, int32_t *info, int64_t k_begin,
+                       int64_t k_end, int32_t threads);
+/* RZ to 32*P2 bits (P2 <= P) of `count` numbers: the top P2 limbs. */
+int mpref_truncate(int64_t count, int32_t P, int32_t P2, const uint32_t *limbs, const int64_t *exp,
+                   const int32_t *sign, uint32_t *ol, int64_t *oe, int32_t *os);
 
 /* Signed last-column cofactors c_i = (-1)^(i+n) M_{i,n} from factor's output. */
 int mpref_minors(int64_t n, int32_t P, const uint32_t *limbs, const int64_t *exp,

@@ -80,6 +80,58 @@ class MpDet(torch.autograd.Function):
         return g_mant * grad, None, None, None
 
 
+class MpDetBatch(torch.autograd.Function):
+    """det of every matrix of a batch (mp_det_batched), with the backward of
+    all of them at once (mp_det_adjugate_batched).  Inputs: one float64 proxy
+    leaf per matrix (its gradient is that matrix's adj(A)^T * 2^-e_det), then
+    the list of DeviceMp matrices, the path, the batched backward's schedule
+    and an optional list of GradHolders.  Outputs: (mantissas [B], exponents
+    [B]); a matrix whose elimination stopped before its last step raises
+    ZeroPivotError."""
+
+    @staticmethod
+    def forward(ctx, mats, path, schedule, holders, *proxies):
+        LUs = [binding.DeviceMp(A.limbs.clone(), A.exp.clone(), A.sign.clone(), A.rows, A.cols) for A in mats]
+        Ds, _, info = binding.batched(LUs, path, minors=False)
+        codes = info.cpu().tolist()
+        for A, code in zip(mats, codes):
+            if code != 0 and code != A.rows:
+                raise ZeroPivotError(code, A.rows)
+        mants, exps = [], []
+        for A, D in zip(mats, Ds):
+            mant, e = binding.to_f64(D)
+            mants.append(mant[0, A.rows - 1])
+            exps.append(e[0, A.rows - 1])
+        dm, de = torch.stack(mants), torch.stack(exps)
+        ctx.LUs, ctx.Ds, ctx.info, ctx.holders, ctx.schedule = LUs, Ds, info, holders, schedule
+        ctx.save_for_backward(de)
+        if holders is not None:
+            for hd, D in zip(holders, Ds):
+                hd.D, hd.info = D, info
+        ctx.mark_non_differentiable(de)
+        return dm, de
+
+    @staticmethod
+    def backward(ctx, g_mant, g_e):
+        (de,) = ctx.saved_tensors
+        adjTs, _ = binding.adjugate_batched(ctx.LUs, ctx.Ds, ctx.info, schedule=ctx.schedule)
+        grads = []
+        for b, adjT in enumerate(adjTs):
+            if ctx.holders is not None:
+                ctx.holders[b].adjT = adjT
+            grads.append(g_mant[b] * binding.to_f64_scaled(adjT, de[b:b + 1]))
+        return (None, None, None, None, *grads)
+
+
+def mp_det_batch(mats, proxies=None, path: str = "auto", schedule: str = "persistent", holders=None):
+    """Differentiable determinants of a list of DeviceMp matrices: returns
+    (mantissas [B], exponents [B]); backward gives every proxy adj(A)^T 2^-e."""
+    if proxies is None:
+        proxies = [torch.zeros((A.rows, A.cols), dtype=torch.float64, device=A.limbs.device, requires_grad=True)
+                   for A in mats]
+    return MpDetBatch.apply(mats, path, schedule, holders, *proxies)
+
+
 def mp_det(A, proxy=None, path: str = "auto", holder: GradHolder | None = None):
     """Differentiable determinant of a DeviceMp A: returns (mantissa, exponent)."""
     if proxy is None:

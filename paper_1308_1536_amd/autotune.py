@@ -1,10 +1,20 @@
-"""Choice of the trailing-update path by measurement.
+"""Choice of the trailing update's path and launch shapes by measurement.
 
-Every path computes the same bits (the number format and the truncation rule
-fix every result), so the choice only affects speed.  For a key (arch, limbs P,
-size bucket) the tuner times the candidate paths on a seeded random-mantissa
-matrix of the bucket's size (capped) and caches the fastest in a JSON file
-(``MPDET_AUTOTUNE_CACHE``, default ``~/.cache/mpdet/autotune.json``).
+Every candidate computes the same bits (the number format and the truncation
+rule fix every result, and each element gets the same operations in the same
+order whatever the tiling), so tuning only changes speed.  Candidates:
+- the path: the VALU lane product / one-wave update, or the INT8 MFMA
+  Toeplitz contraction (P a multiple of 8);
+- the tile of the VALU lane product: 2, 4 or 8 rows (= waves) x 64 columns
+  per workgroup;
+- the MFMA update's waves (= rows of one 32-column block) per workgroup: 1, 2
+  or 4 (where their LDS fits);
+- for a batch, the schedule: one launch per phase per step (lockstep) or one
+  persistent launch over a task queue (VALU path).
+For a key (arch, limbs P, size bucket[, batch]) the tuner times the
+candidates on seeded random-mantissa matrices of the bucket's size (capped)
+and caches the fastest in a JSON file (``MPDET_AUTOTUNE_CACHE``, default
+``~/.cache/mpdet/autotune.json``).
 """
 from __future__ import annotations
 
@@ -15,6 +25,9 @@ import time
 from . import binding, inputs
 
 ARCH = "gfx950"
+LANE_ROWS = (2, 4, 8)
+MFMA_WAVES = (1, 2, 4)
+MFMA_LDS_MAX = 64 * 1024
 
 
 def cache_path() -> str:
@@ -46,47 +59,85 @@ def _save(db: dict) -> None:
     os.replace(tmp, p)
 
 
-def candidates(P: int) -> list[str]:
-    return ["valu", "mfma"] if P >= 8 and P % 8 == 0 else ["valu"]
+def lane_ok(P: int) -> bool:
+    return P <= 128 and P % 4 == 0
 
 
-def measure(n: int, P: int, path: str, reps: int = 2) -> float:
-    """Seconds for factor + minors on a seeded n x n random-mantissa matrix."""
+def mfma_waves_ok(P: int, waves: int) -> bool:
+    """the MFMA update's LDS (one reversed digit row per wave) fits a workgroup"""
+    return P >= 8 and P % 8 == 0 and (4 * P + 608) * waves <= MFMA_LDS_MAX
+
+
+def candidates(P: int, batch: bool = False) -> list[dict]:
+    """Every launch configuration to try for P-limb numbers."""
+    out = []
+    if lane_ok(P):
+        out += [{"path": "valu", "lane_rows": r} for r in LANE_ROWS]
+        if batch:
+            out.append({"path": "valu", "lane_rows": 4, "schedule": "persistent"})
+    else:
+        out.append({"path": "valu", "lane_rows": 0})
+        if batch:
+            out.append({"path": "valu", "lane_rows": 0, "schedule": "persistent"})
+    out += [{"path": "mfma", "mfma_waves": w} for w in MFMA_WAVES if mfma_waves_ok(P, w)]
+    return out
+
+
+def apply(cfg: dict, device: int = 0) -> None:
+    """Set the handle's launch shapes for a candidate."""
+    binding.set_tuning(cfg.get("lane_rows", 0), cfg.get("mfma_waves", 0), device=device)
+
+
+def measure(n: int, P: int, cfg: dict, reps: int = 2, batch: int = 0) -> float:
+    """Seconds for factor + minors on a seeded n x n random-mantissa matrix
+    (batch > 0: `batch` matrices of sizes spread up to n in one batched call)."""
     import torch
-    A = inputs.random_mantissas((n, n), P, 97 + n)
-    pristine = binding.DeviceMp.from_host(A)
-    work = binding.DeviceMp.empty(n, n, P)
-    D = binding.DeviceMp.empty(1, n, P)
-    c = binding.DeviceMp.empty(1, n, P)
-    info = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sizes = [n] if not batch else [max(2, n * (b + 1) // batch) for b in range(batch)]
+    hosts = [inputs.random_mantissas((s, s), P, 97 + s + 7 * b) for b, s in enumerate(sizes)]
+    pristine = [binding.DeviceMp.from_host(h) for h in hosts]
+    work = [binding.DeviceMp.empty(s, s, P) for s in sizes]
+    apply(cfg)
 
     def once():
-        work.limbs.copy_(pristine.limbs)
-        work.exp.copy_(pristine.exp)
-        work.sign.copy_(pristine.sign)
-        binding.factor(work, path, D=D, info=info)
-        binding.minors(work, D, info, c=c)
+        for p, w in zip(pristine, work):
+            w.limbs.copy_(p.limbs)
+            w.exp.copy_(p.exp)
+            w.sign.copy_(p.sign)
+        if batch:
+            binding.batched(work, cfg["path"], schedule=cfg.get("schedule", "lockstep"))
+        else:
+            D, info = binding.factor(work[0], cfg["path"])
+            binding.minors(work[0], D, info)
 
-    once()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(reps):
+    try:
         once()
-    torch.cuda.synchronize()
-    return (time.perf_counter() - t0) / reps
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            once()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+    finally:
+        apply({})
+
+
+def choose(n: int, P: int, cap: int = 256, batch: int = 0, retune: bool = False) -> dict:
+    """The fastest candidate for (P, size bucket[, batch]); measured once and cached."""
+    cands = candidates(P, batch=bool(batch))
+    key = f"{ARCH}/P{P}/N{bucket(n)}" + (f"/B{batch}" if batch else "")
+    db = _load()
+    if not retune and key in db and "config" in db[key]:
+        return db[key]["config"]
+    size = min(bucket(n), cap)
+    times = [measure(size, P, c, batch=batch) for c in cands]
+    best = min(range(len(cands)), key=lambda i: times[i])
+    db[key] = {"config": cands[best], "candidates": cands, "seconds": times, "measured_n": size}
+    _save(db)
+    return cands[best]
 
 
 def choose_path(n: int, P: int, cap: int = 256, retune: bool = False) -> str:
-    cands = candidates(P)
-    if len(cands) == 1:
-        return cands[0]
-    key = f"{ARCH}/P{P}/N{bucket(n)}"
-    db = _load()
-    if not retune and key in db:
-        return db[key]["path"]
-    size = min(bucket(n), cap)
-    times = {p: measure(size, P, p) for p in cands}
-    best = min(times, key=times.get)
-    db[key] = {"path": best, "seconds": times, "measured_n": size}
-    _save(db)
-    return best
+    """The path of the fastest candidate, with the handle set to its launch shapes."""
+    cfg = choose(n, P, cap=cap, retune=retune)
+    apply(cfg)
+    return cfg["path"]

@@ -67,6 +67,15 @@ def lib() -> ctypes.CDLL:
         L.mp_det_factor.argtypes = [vp, MpdetMat, MpdetMat, vp, ctypes.c_int, vp]
         L.mp_det_factor_steps.argtypes = [vp, MpdetMat, MpdetMat, vp, i64, i64, ctypes.c_int, vp]
         L.mpdet_set_panel_rows.argtypes = [vp, i64]
+        L.mp_truncate.argtypes = [vp, MpdetMat, MpdetMat, vp]
+        L.mp_truncate.restype = ctypes.c_int
+        L.mp_det_factor_reduced.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, MpdetMat, vp, i64, ctypes.c_int,
+                                            ctypes.c_int, vp]
+        L.mp_det_factor_reduced.restype = ctypes.c_int
+        L.mpdet_set_tuning.argtypes = [vp, i32, i32]
+        L.mpdet_set_tuning.restype = ctypes.c_int
+        L.mp_det_extend.argtypes = [vp, MpdetMat, MpdetMat, vp, i64, ctypes.c_int, vp]
+        L.mp_det_extend.restype = ctypes.c_int
         L.mp_det_factor_noalloc.argtypes = [MpdetMat, MpdetMat, vp, ctypes.c_int, vp]
         L.mp_det_factor_noalloc.restype = ctypes.c_int
         L.mpdet_workspace_size.argtypes = [vp, i64, i32, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)]
@@ -83,8 +92,16 @@ def lib() -> ctypes.CDLL:
         L.mp_det_batched.argtypes = [vp, i64, ctypes.POINTER(MpdetMat), ctypes.POINTER(MpdetMat),
                                      ctypes.POINTER(MpdetMat), vp, ctypes.c_int, ctypes.c_int, vp]
         L.mp_det_batched.restype = ctypes.c_int
+        L.mpdet_set_wait_limit.argtypes = [vp, ctypes.c_double]
+        L.mpdet_set_wait_limit.restype = ctypes.c_int
+        L.mpdet_batched_plan.argtypes = [i64, ctypes.POINTER(ctypes.c_int64), i32, ctypes.c_int, ctypes.c_int, vp, i64,
+                                         ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
+        L.mpdet_batched_plan.restype = ctypes.c_int
         L.mp_det_adjugate.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, vp, vp]
         L.mp_det_adjugate.restype = ctypes.c_int
+        L.mp_det_adjugate_batched.argtypes = [vp, i64, ctypes.POINTER(MpdetMat), ctypes.POINTER(MpdetMat),
+                                              ctypes.POINTER(MpdetMat), vp, vp, ctypes.c_int, vp]
+        L.mp_det_adjugate_batched.restype = ctypes.c_int
         L.mp_det_all_minors.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, vp, vp]
         L.mp_det_all_minors.restype = ctypes.c_int
         L.mp_det_normalize_minors.argtypes = [vp, MpdetMat, MpdetMat, vp]
@@ -271,6 +288,52 @@ def workspace_size(n: int, P: int, path: str = "auto", device: int | None = None
     return out.value
 
 
+def extend(A: DeviceMp, D: DeviceMp, info, n_old: int, path: str = "auto", stream=None):
+    """mp_det_extend: A's leading n_old x n_old block (and D_1..D_{n_old}) hold
+    a factorisation; eliminate the new rows and columns and continue, in
+    place, to the factorisation of the whole matrix."""
+    h = handle(A.limbs.device.index or 0)
+    _check("mp_det_extend", lib().mp_det_extend(h.ptr, A.mat(), D.mat(), info.data_ptr(), int(n_old),
+                                                _resolve(path, A.rows, A.P), _stream(stream)))
+    return D, info
+
+
+def truncate(x: DeviceMp, P2: int, stream=None) -> DeviceMp:
+    """mp_truncate: x rounded toward zero to P2 limbs (a new array)."""
+    y = DeviceMp.empty(x.rows, x.cols, P2, x.limbs.device)
+    h = handle(x.limbs.device.index or 0)
+    _check("mp_truncate", lib().mp_truncate(h.ptr, x.mat(), y.mat(), _stream(stream)))
+    return y
+
+
+def factor_reduced(A: DeviceMp, k_switch: int, P2: int, path: str = "auto", path2: str = "auto", stream=None):
+    """mp_det_factor_reduced: steps before k_switch at A's precision (in place
+    on A), the rest at P2 limbs.  Returns (A2, D2, D_lead, info): A2 and D2 the
+    factors and D_1..D_n at P2, D_lead D_1..D_{k_switch} at full precision."""
+    import torch
+    n = A.rows
+    dev = A.limbs.device
+    D = DeviceMp.empty(1, n, A.P, dev)
+    A2 = DeviceMp.empty(n, n, P2, dev)
+    D2 = DeviceMp.empty(1, n, P2, dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    h = handle(dev.index or 0)
+    _check("mp_det_factor_reduced",
+           lib().mp_det_factor_reduced(h.ptr, A.mat(), D.mat(), A2.mat(), D2.mat(), info.data_ptr(), int(k_switch),
+                                       _resolve(path, n, A.P), _resolve(path2, n, P2), _stream(stream)))
+    return A2, D2, D, info
+
+
+def set_tuning(lane_rows: int = 0, mfma_waves: int = 0, panel_rows: int | None = None, device: int = 0):
+    """mpdet_set_tuning (and mpdet_set_panel_rows) on the device's handle:
+    rows per workgroup of the lane product (2, 4, 8), waves per workgroup of
+    the MFMA update (1, 2, 4); 0 restores a default."""
+    h = handle(device).ptr
+    _check("mpdet_set_tuning", lib().mpdet_set_tuning(h, int(lane_rows), int(mfma_waves)))
+    if panel_rows is not None:
+        _check("mpdet_set_panel_rows", lib().mpdet_set_panel_rows(h, int(panel_rows)))
+
+
 def set_panel_rows(rows: int, device: int = 0):
     """mpdet_set_panel_rows on the device's handle (0: automatic)."""
     _check("mpdet_set_panel_rows", lib().mpdet_set_panel_rows(handle(device).ptr, int(rows)))
@@ -301,6 +364,31 @@ def adjugate(LU: DeviceMp, D: DeviceMp, info, adjT: DeviceMp | None = None, stre
     return adjT
 
 
+def adjugate_batched(LUs: list, Ds: list, info, adjTs: list | None = None, status=None, stream=None,
+                     schedule: str = "persistent"):
+    """mp_det_adjugate_batched: adj(A)^T of every factored matrix of a batch
+    (info: the factorisations' int32[batch] device tensor).  schedule:
+    "persistent" (one launch) or "lockstep" (one mp_det_adjugate call per
+    matrix).  Returns (adjTs, status int32[batch])."""
+    import torch
+    B = len(LUs)
+    dev = LUs[0].limbs.device
+    if adjTs is None:
+        adjTs = [DeviceMp.empty(m.rows, m.rows, m.P, dev) for m in LUs]
+    if status is None:
+        status = torch.zeros(B, dtype=torch.int32, device=dev)
+    La = (MpdetMat * B)(*[m.mat() for m in LUs])
+    Da = (MpdetMat * B)(*[d.mat() for d in Ds])
+    Ta = (MpdetMat * B)(*[t.mat() for t in adjTs])
+    if schedule not in ("persistent", "lockstep"):
+        raise ValueError(f"schedule {schedule!r}: persistent or lockstep")
+    flags = MPDET_BATCH_LOCKSTEP if schedule == "lockstep" else 0
+    h = handle(dev.index or 0)
+    _check("mp_det_adjugate_batched", lib().mp_det_adjugate_batched(h.ptr, B, La, Da, Ta, info.data_ptr(),
+                                                                    status.data_ptr(), flags, _stream(stream)))
+    return adjTs, status
+
+
 def all_minors(LU: DeviceMp, D: DeviceMp, info, C: DeviceMp | None = None, stream=None,
                h: Handle | None = None) -> DeviceMp:
     """mp_det_all_minors: row r of C holds the signed last-column cofactors of
@@ -325,13 +413,42 @@ def normalize_minors(C: DeviceMp, out: DeviceMp | None = None, stream=None) -> D
     return out
 
 
-MPDET_WANT_MINORS = 1
+MPDET_WANT_MINORS, MPDET_BATCH_LOCKSTEP, MPDET_BATCH_PERSISTENT = 1, 2, 4
+SCHEDULES = {"auto": 0, "lockstep": MPDET_BATCH_LOCKSTEP, "persistent": MPDET_BATCH_PERSISTENT}
+
+# one record of mpdet_batched_plan
+PLAN_DTYPE = np.dtype([("need", "<i8"), ("units", "<i8"), ("k", "<i8"), ("mat", "<i4"), ("kind", "<i4")])
+PLAN_KINDS = ("init", "pivot", "divide", "prod", "finish", "updv", "pend", "msweep", "mfinal")
+
+
+def batched_plan(sizes, P: int, path: str = "auto", minors: bool = True):
+    """mpdet_batched_plan (host only): the persistent launch's records in queue
+    order (PLAN_DTYPE) and the total number of tickets."""
+    B = len(sizes)
+    n = (ctypes.c_int64 * max(B, 1))(*[int(x) for x in sizes])
+    nrec, nt = ctypes.c_int64(), ctypes.c_int64()
+    flags = MPDET_WANT_MINORS if minors else 0
+    pid = PATHS[path]
+    _check("mpdet_batched_plan", lib().mpdet_batched_plan(B, n, int(P), pid, flags, None, 0, ctypes.byref(nrec),
+                                                          ctypes.byref(nt)))
+    out = np.zeros(nrec.value, dtype=PLAN_DTYPE)
+    _check("mpdet_batched_plan", lib().mpdet_batched_plan(B, n, int(P), pid, flags, out.ctypes.data, nrec.value,
+                                                          ctypes.byref(nrec), ctypes.byref(nt)))
+    return out, nt.value
+
+
+def set_wait_limit(seconds: float, device: int = 0):
+    """mpdet_set_wait_limit on the device's handle: bound on every wait of the
+    persistent batched launch."""
+    _check("mpdet_set_wait_limit", lib().mpdet_set_wait_limit(handle(device).ptr, float(seconds)))
 
 
 def batched(mats: list, path: str = "auto", minors: bool = True, Ds=None, cs=None, info=None,
-            stream=None):
+            stream=None, schedule: str = "auto"):
     """mp_det_batched on a list of square DeviceMp matrices (factored in place).
-    Returns (Ds, cs or None, info[batch])."""
+    schedule: "auto" (the library's default, lockstep), "persistent" (one
+    launch over a task queue; VALU path) or "lockstep".  Returns (Ds, cs or
+    None, info[batch])."""
     import torch
     B = len(mats)
     dev = mats[0].limbs.device
@@ -346,7 +463,7 @@ def batched(mats: list, path: str = "auto", minors: bool = True, Ds=None, cs=Non
     Ca = (MpdetMat * B)(*[c.mat() for c in cs]) if minors else None
     h = handle(dev.index or 0)
     _check("mp_det_batched", lib().mp_det_batched(h.ptr, B, Aa, Da, Ca, info.data_ptr(),
-                                                  MPDET_WANT_MINORS if minors else 0,
+                                                  (MPDET_WANT_MINORS if minors else 0) | SCHEDULES[schedule],
                                                   _resolve(path, max(m.rows for m in mats), mats[0].P),
                                                   _stream(stream)))
     return Ds, (cs if minors else None), info
@@ -389,7 +506,7 @@ def measure_peak(kind: str, device: int = 0) -> float:
 
 
 KERNELS = ("pivot_divide", "divide", "update_valu", "update_mfma", "mfma_prep", "minors_sweep",
-           "minors_final", "update_finish", "adjugate", "all_minors", "other")
+           "minors_final", "update_finish", "adjugate", "all_minors", "batch_persistent", "other")
 
 
 def profile_begin(device: int = 0):

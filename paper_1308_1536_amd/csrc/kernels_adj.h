@@ -22,7 +22,7 @@
 // Row n-1 of adj(A) is RZ(D_{n-2} W_{n-1,m}), the last-column minors.
 #pragma once
 
-#include "kernels_valu.h"
+#include "kernels_mfma.h"
 
 namespace mpk {
 
@@ -53,23 +53,26 @@ __device__ __forceinline__ void fma_like(uint32_t *cm, int64_t *ce, int32_t *cs,
     mpw::store(cm, ce, cs, L.sc.t2, hr, P);
 }
 
-// W sweep j: block b -> (r, i) = (j + b / j, b % j)
-__global__ void __launch_bounds__(64) k_adj_w(MatDev LU, MatDev W, const int32_t *info, int64_t j, int64_t n,
-                                              int P) {
-    extern __shared__ uint32_t lds_raw[];
+// W sweep j: unit b -> (r, i) = (j + b / j, b % j)
+__device__ __forceinline__ void adj_w_body(uint32_t *lds_raw, MatDev LU, MatDev W, const int32_t *info, int64_t j,
+                                           int64_t n, int P, int64_t b) {
     if (*info != 0) return;
-    const int64_t b = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
     if (b >= (n - j) * j) return;
     const int64_t r = j + b / j, i = b % j;
     Lds L(lds_raw, P);
     fma_like(el(W, r, i, P), &ex(W, r, i), &sg(W, r, i), el(W, r, j, P), ex(W, r, j), sg(W, r, j),
              el(LU, j, i, P), ex(LU, j, i), sg(LU, j, i), true, L, P);
 }
+__global__ void __launch_bounds__(64) k_adj_w(MatDev LU, MatDev W, const int32_t *info, int64_t j, int64_t n,
+                                              int P) {
+    extern __shared__ uint32_t lds_raw[];
+    adj_w_body(lds_raw, LU, W, info, j, n, P, (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x);
+}
 
 // S_n = 1, S_i = RZ(u_ii S_{i+1}) (one wave, sequential), then the diagonal
 // of adj(U) is written by k_adj_diag
-__global__ void __launch_bounds__(64) k_adj_s(MatDev LU, MatDev S, const int32_t *info, int64_t n, int P) {
-    extern __shared__ uint32_t lds_raw[];
+__device__ __forceinline__ void adj_s_body(uint32_t *lds_raw, MatDev LU, MatDev S, const int32_t *info, int64_t n,
+                                           int P) {
     if (*info != 0) return;
     Lds L(lds_raw, P);
     // the running product stays in LDS as the y operand (S_n = 1)
@@ -91,13 +94,15 @@ __global__ void __launch_bounds__(64) k_adj_s(MatDev LU, MatDev S, const int32_t
         hs = hr;
     }
 }
+__global__ void __launch_bounds__(64) k_adj_s(MatDev LU, MatDev S, const int32_t *info, int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    adj_s_body(lds_raw, LU, S, info, n, P);
+}
 
 // adj(U)_ii = RZ(D_{i-1} S_{i+1}), D_0 = 1 (so adj(U)_00 = S_1)
-__global__ void __launch_bounds__(64) k_adj_diag(MatDev D, MatDev S, MatDev J, const int32_t *info, int64_t n,
-                                                 int P) {
-    extern __shared__ uint32_t lds_raw[];
+__device__ __forceinline__ void adj_diag_body(uint32_t *lds_raw, MatDev D, MatDev S, MatDev J, const int32_t *info,
+                                              int P, int64_t i) {
     if (*info != 0) return;
-    const int64_t i = blockIdx.x;
     Lds L(lds_raw, P);
     mpw::Hdr hs = mpw::load(L.sc.t3, el(S, 0, i + 1, P), ex(S, 0, i + 1), sg(S, 0, i + 1), P);
     mpw::Hdr hr = hs;
@@ -108,13 +113,17 @@ __global__ void __launch_bounds__(64) k_adj_diag(MatDev D, MatDev S, MatDev J, c
     }
     mpw::store(el(J, i, i, P), &ex(J, i, i), &sg(J, i, i), L.sc.t3, hr, P);
 }
+__global__ void __launch_bounds__(64) k_adj_diag(MatDev D, MatDev S, MatDev J, const int32_t *info, int64_t n,
+                                                 int P) {
+    extern __shared__ uint32_t lds_raw[];
+    (void)n;
+    adj_diag_body(lds_raw, D, S, J, info, P, blockIdx.x);
+}
 
 // reciprocals of the pivots u_ii (block i), as k_pivot_recip's block 1
-__global__ void __launch_bounds__(64) k_adj_recips(MatDev LU, uint32_t *rw, const int32_t *info, int64_t n,
-                                                   int P) {
-    extern __shared__ uint32_t lds_raw[];
+__device__ __forceinline__ void adj_recip_body(uint32_t *lds_raw, MatDev LU, uint32_t *rw, const int32_t *info,
+                                               int P, int64_t i) {
     if (*info != 0) return;
-    const int64_t i = blockIdx.x;
     uint32_t *r = rw + i * (int64_t)(P + 2);
     if (el(LU, i, i, P)[P - 1] == 0u) {  // u_nn = 0 (info == n): never a divisor
         if (mpw::lane() == 0) r[P + 1] = 0u;
@@ -127,27 +136,35 @@ __global__ void __launch_bounds__(64) k_adj_recips(MatDev LU, uint32_t *rw, cons
     for (int q = mpw::lane(); q < P + 1; q += MP_WAVE) r[q] = B.x[q];
     if (mpw::lane() == 0) r[P + 1] = ok ? 1u : 0u;
 }
+__global__ void __launch_bounds__(64) k_adj_recips(MatDev LU, uint32_t *rw, const int32_t *info, int64_t n,
+                                                   int P) {
+    extern __shared__ uint32_t lds_raw[];
+    (void)n;
+    adj_recip_body(lds_raw, LU, rw, info, P, blockIdx.x);
+}
 
 // back substitution step k, part 1: block b -> (i, j) = (b % k, k + b / k):
 // J_ij <- RZ(J_ij - RZ(u_ik J_kj))
-__global__ void __launch_bounds__(64) k_adj_u_upd(MatDev LU, MatDev J, const int32_t *info, int64_t k, int64_t n,
-                                                  int P) {
-    extern __shared__ uint32_t lds_raw[];
+__device__ __forceinline__ void adj_u_upd_body(uint32_t *lds_raw, MatDev LU, MatDev J, const int32_t *info, int64_t k,
+                                               int64_t n, int P, int64_t b) {
     if (*info != 0) return;
-    const int64_t b = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
     if (b >= k * (n - k)) return;
     const int64_t i = b % k, j = k + b / k;
     Lds L(lds_raw, P);
     fma_like(el(J, i, j, P), &ex(J, i, j), &sg(J, i, j), el(LU, i, k, P), ex(LU, i, k), sg(LU, i, k),
              el(J, k, j, P), ex(J, k, j), sg(J, k, j), true, L, P);
 }
-
-// part 2: block b -> j = k + b: J_{k-1,j} <- RZ(J_{k-1,j} / u_{k-1,k-1})
-__global__ void __launch_bounds__(64) k_adj_u_div(MatDev LU, MatDev J, const uint32_t *rw, const int32_t *info,
-                                                  int64_t k, int64_t n, int P) {
+__global__ void __launch_bounds__(64) k_adj_u_upd(MatDev LU, MatDev J, const int32_t *info, int64_t k, int64_t n,
+                                                  int P) {
     extern __shared__ uint32_t lds_raw[];
+    adj_u_upd_body(lds_raw, LU, J, info, k, n, P, (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x);
+}
+
+// part 2: unit b -> j = k + b: J_{k-1,j} <- RZ(J_{k-1,j} / u_{k-1,k-1})
+__device__ __forceinline__ void adj_u_div_body(uint32_t *lds_raw, MatDev LU, MatDev J, const uint32_t *rw,
+                                               const int32_t *info, int64_t k, int P, int64_t b) {
     if (*info != 0) return;
-    const int64_t j = k + (int64_t)blockIdx.x;
+    const int64_t j = k + b;
     const int64_t i = k - 1;
     mpw::DivBufs B = mpw::div_bufs(lds_raw, P);
     uint32_t *tm = el(J, i, j, P);
@@ -160,6 +177,30 @@ __global__ void __launch_bounds__(64) k_adj_u_div(MatDev LU, MatDev J, const uin
     if (!done) hq = mpw::div(B.t3, B.a, ht, B.v, hu, B.prod, B.t0, B.t1, B.t2, P);
     mpw::store(tm, &ex(J, i, j), &sg(J, i, j), B.t3, hq, P);
 }
+__global__ void __launch_bounds__(64) k_adj_u_div(MatDev LU, MatDev J, const uint32_t *rw, const int32_t *info,
+                                                  int64_t k, int64_t n, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    (void)n;
+    adj_u_div_body(lds_raw, LU, J, rw, info, k, P, blockIdx.x);
+}
+
+// Any rank-1 update R, one wave per element: unit b -> (a, c) = (b / R.mc,
+// b % R.mc), z_ac <- RZ(z_ac - RZ(x_a (+-y_c))) (fma_like: the operations of
+// the elimination's update, a product then a difference, each truncated).
+__device__ __forceinline__ void rank1_wave_body(uint32_t *lds_raw, const Rank1 &R, const int32_t *info, int P,
+                                                int64_t b) {
+    if (*info != 0) return;
+    if (b >= R.mr * R.mc) return;
+    const int64_t a = b / R.mc, c = b % R.mc;
+    const int64_t zi = R.zr + a, zj = R.zc + c;
+    Lds L(lds_raw, P);
+    fma_like(el(R.Z, zi, zj, P), &ex(R.Z, zi, zj), &sg(R.Z, zi, zj), r1x(R, a, P), r1x_e(R, a), r1x_s(R, a),
+             r1y(R, c, P), r1y_e(R, c), r1y_s(R, c), R.yneg == 0, L, P);
+}
+__global__ void __launch_bounds__(64) k_rank1_wave(Rank1 R, const int32_t *info, int P) {
+    extern __shared__ uint32_t lds_raw[];
+    rank1_wave_body(lds_raw, R, info, P, (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x);
+}
 
 // The gate the adjugate's and all-minors' kernels test instead of info: 0
 // when the factors are complete (info 0, or info == n: only u_nn is zero),
@@ -170,17 +211,20 @@ __global__ void k_factors_gate(const int32_t *info, int64_t n, int32_t *gate) {
 
 // adj(A) accumulation step k: block b -> (i, m) = (b / (k+1), b % (k+1)):
 // adjT_mi <- RZ(adjT_mi + RZ(J_ik W_km))
-__global__ void __launch_bounds__(64) k_adj_prod(MatDev J, MatDev W, MatDev T, const int32_t *info, int64_t k,
-                                                 int P) {
-    extern __shared__ uint32_t lds_raw[];
+__device__ __forceinline__ void adj_prod_body(uint32_t *lds_raw, MatDev J, MatDev W, MatDev T, const int32_t *info,
+                                              int64_t k, int P, int64_t b) {
     if (*info != 0) return;
-    const int64_t b = (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
     const int64_t k1 = k + 1;
     if (b >= k1 * k1) return;
     const int64_t i = b / k1, m = b % k1;
     Lds L(lds_raw, P);
     fma_like(el(T, m, i, P), &ex(T, m, i), &sg(T, m, i), el(J, i, k, P), ex(J, i, k), sg(J, i, k),
              el(W, k, m, P), ex(W, k, m), sg(W, k, m), false, L, P);
+}
+__global__ void __launch_bounds__(64) k_adj_prod(MatDev J, MatDev W, MatDev T, const int32_t *info, int64_t k,
+                                                 int P) {
+    extern __shared__ uint32_t lds_raw[];
+    adj_prod_body(lds_raw, J, W, T, info, k, P, (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x);
 }
 
 // The last-column minors of every leading block (mp_det_all_minors): row r

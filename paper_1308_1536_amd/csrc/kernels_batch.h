@@ -59,10 +59,11 @@ __global__ void __launch_bounds__(64) k_batch_update_valu(const BatchMat *mats, 
     update_valu_body(lds_raw, M.A, M.info, k, M.n, P, loc);
 }
 
-__global__ void __launch_bounds__(64 * kLaneRows) k_batch_prod_lane(const BatchMat *mats, const int32_t *order,
-                                                                    const int64_t *off, int cnt, int64_t k, int P) {
+template <int ROWS>
+__global__ void __launch_bounds__(64 * ROWS) k_batch_prod_lane(const BatchMat *mats, const int32_t *order,
+                                                               const int64_t *off, int cnt, int64_t k, int P) {
     MPK_BATCH_PROLOGUE
-    prod_lane_body(lds_raw, elim_rank1(M.A, k, M.n), M.T, M.info, P, loc);
+    prod_lane_body<ROWS>(lds_raw, elim_rank1(M.A, k, M.n), M.T, M.info, P, loc);
 }
 
 __global__ void __launch_bounds__(64) k_batch_prep(const BatchMat *mats, const int32_t *order, const int64_t *off,
@@ -71,13 +72,13 @@ __global__ void __launch_bounds__(64) k_batch_prep(const BatchMat *mats, const i
     mfma_prep_body(lds_raw, M.A, M.Lr, M.Ub, M.info, k, M.n, P, loc);
 }
 
-template <int NC>
-__global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_per_eu(2, 2))) k_batch_update_mfma(const BatchMat *mats, const int32_t *order,
-                                                          const int64_t *off, int cnt, int64_t k, int P) {
+template <int NC, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2)))
+k_batch_update_mfma(const BatchMat *mats, const int32_t *order, const int64_t *off, int cnt, int64_t k, int P) {
     MPK_BATCH_PROLOGUE
     // every matrix's block count is a multiple of 8, so loc and bx agree mod 8
     // and the XCD-aware column mapping holds inside each matrix
-    update_mfma_body<NC>(lds_raw, M.A, M.Lr, M.Ub, M.T, M.info, k, M.n, P, 0, M.n - k - 1, loc, true);
+    update_mfma_body<NC, WAVES>(lds_raw, M.A, M.Lr, M.Ub, M.T, M.info, k, M.n, P, 0, M.n - k - 1, loc, true);
 }
 
 template <bool STREAM>

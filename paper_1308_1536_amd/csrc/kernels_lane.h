@@ -38,7 +38,7 @@ namespace mpk {
 
 constexpr int kLaneMaxP = 128;
 constexpr int kLaneFT = 64;    // columns per workgroup (one per lane)
-constexpr int kLaneRows = 4;   // rows per workgroup (one per wave)
+constexpr int kLaneRows = 4;   // rows per workgroup (one per wave): the default of 2, 4 or 8
 constexpr int kLaneW = 8;      // product columns per Comba block
 constexpr int kDigit = 28;     // bits per digit of the product
 constexpr int kPadLo = 24;     // zero tile rows below digit 0 ...
@@ -47,9 +47,9 @@ constexpr int kPadL = 16;      // zero multiplier digits above digit ND-1
 
 __host__ __device__ inline bool lane_update_ok(int P) { return P <= kLaneMaxP && P % 4 == 0; }
 __host__ __device__ inline int lane_digits(int P) { return (32 * P + kDigit - 1) / kDigit; }
-__host__ __device__ inline size_t lane_lds_bytes(int P) {
+__host__ __device__ inline size_t lane_lds_bytes(int P, int rows = kLaneRows) {
     const int nd = lane_digits(P);
-    return ((size_t)(nd + kPadLo + kPadHi) * (kLaneFT + 1) + (size_t)kLaneRows * (nd + kPadL)) * 4u;
+    return ((size_t)(nd + kPadLo + kPadHi) * (kLaneFT + 1) + (size_t)rows * (nd + kPadL)) * 4u;
 }
 // first product column formed (0: the whole product): the largest c0 with
 // 28 c0 + 36 + 32 <= 32 (P - 1), when that skips at least one Comba block
@@ -58,8 +58,8 @@ __host__ __device__ inline int lane_short_start(int P) {
     return c0 >= kLaneW ? c0 : 0;
 }
 // workgroups for an mr x mc block (an m x m trailing block: mr = mc = m)
-__host__ __device__ inline int64_t lane_update_blocks(int64_t mr, int64_t mc) {
-    return ((mr + kLaneRows - 1) / kLaneRows) * ((mc + kLaneFT - 1) / kLaneFT);
+__host__ __device__ inline int64_t lane_update_blocks(int64_t mr, int64_t mc, int rows = kLaneRows) {
+    return ((mr + rows - 1) / rows) * ((mc + kLaneFT - 1) / kLaneFT);
 }
 __host__ __device__ inline int64_t lane_update_blocks(int64_t m) { return lane_update_blocks(m, m); }
 
@@ -73,6 +73,8 @@ __device__ __forceinline__ uint32_t digit28(const uint32_t *m, int P, int d) {
 // The record of element (i', j') of the rank-1 update R (i' < R.mr, j' <
 // R.mc) is word x at T[((i' njb + j' / 32) TP + x) 32 + j' % 32], njb =
 // ceil(R.mc / 32), x = 0..P: limb P-1+x of x_i' y_j'.
+// ROWS: rows (= waves) of the workgroup's tile; any value gives the same bits.
+template <int ROWS = kLaneRows>
 __device__ __forceinline__ void prod_lane_body(uint32_t *lds, const Rank1 &R, uint32_t *T, const int32_t *info,
                                                int P, int64_t bx) {
     if (*info != 0) return;
@@ -80,10 +82,10 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, const Rank1 &R, ui
     const int ND = lane_digits(P);
     const int64_t ncol = (R.mc + FT - 1) / FT;
     const int64_t rg = bx / ncol, j0 = (bx % ncol) * FT;
-    if (rg * kLaneRows >= R.mr) return;  // uniform over the workgroup
+    if (rg * ROWS >= R.mr) return;  // uniform over the workgroup
     const int wave = (int)(threadIdx.x >> 6);
     const int lane = mpw::lane();
-    const int64_t ip = rg * kLaneRows + wave;
+    const int64_t ip = rg * ROWS + wave;
     const int cnt = (int)min((int64_t)FT, R.mc - j0);
     // tile rows -kPadLo .. ND+kPadHi-1 of FTP words (digit d of element e at
     // row d, column e; rows outside 0..ND-1 hold zeros)
@@ -219,16 +221,18 @@ __device__ __forceinline__ void prod_lane_body(uint32_t *lds, const Rank1 &R, ui
     }
 }
 
-__global__ void __launch_bounds__(64 * kLaneRows) k_prod_lane(MatDev A, uint32_t *T, const int32_t *info, int64_t k,
-                                                              int64_t n, int P) {
+template <int ROWS>
+__global__ void __launch_bounds__(64 * ROWS) k_prod_lane(MatDev A, uint32_t *T, const int32_t *info, int64_t k,
+                                                         int64_t n, int P) {
     extern __shared__ uint32_t lds_raw[];
-    prod_lane_body(lds_raw, elim_rank1(A, k, n), T, info, P, flat_block());
+    prod_lane_body<ROWS>(lds_raw, elim_rank1(A, k, n), T, info, P, flat_block());
 }
 
 // the products of any rank-1 update (k_finish_r1 completes it)
-__global__ void __launch_bounds__(64 * kLaneRows) k_prod_lane_r1(Rank1 R, uint32_t *T, const int32_t *info, int P) {
+template <int ROWS>
+__global__ void __launch_bounds__(64 * ROWS) k_prod_lane_r1(Rank1 R, uint32_t *T, const int32_t *info, int P) {
     extern __shared__ uint32_t lds_raw[];
-    prod_lane_body(lds_raw, R, T, info, P, flat_block());
+    prod_lane_body<ROWS>(lds_raw, R, T, info, P, flat_block());
 }
 
 }  // namespace mpk

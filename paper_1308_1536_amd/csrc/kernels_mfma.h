@@ -98,13 +98,13 @@ constexpr int kBufferRsrcWord3 = 0x00020000;
 // Waves per workgroup of k_update_mfma: the waves take consecutive rows i of
 // the same 32-column block, so the pivot-row digit fragments they stream are
 // the same cache lines and are fetched into the CU's L1 once for all of them.
-constexpr int kMfmaWaves = 2;
+constexpr int kMfmaWaves = 2;  // the default of 1, 2 or 4
 // LDS one workgroup of k_update_mfma may take
 constexpr size_t kMfmaLdsMax = 64 * 1024;
 
 // workgroups of k_update_mfma for `rows` rows of an m x m trailing block
-__host__ __device__ inline int64_t mfma_update_blocks(int64_t rows, int64_t m) {
-    const int64_t njb = (m + 31) / 32, nrg = (rows + kMfmaWaves - 1) / kMfmaWaves;
+__host__ __device__ inline int64_t mfma_update_blocks(int64_t rows, int64_t m, int waves = kMfmaWaves) {
+    const int64_t njb = (m + 31) / 32, nrg = (rows + waves - 1) / waves;
     return njb >= kXcds ? kXcds * nrg * ((njb + kXcds - 1) / kXcds) : nrg * njb;
 }
 
@@ -225,12 +225,12 @@ __device__ __forceinline__ const uint32_t *a_word(const uint8_t *lr, int LR, int
 }
 
 // LDS copies of the digit row that fit a workgroup (0: the MFMA update does not fit)
-__host__ __device__ inline int mfma_copies(int P) {
-    const size_t lr = (size_t)mfma_geom(P).LR * kMfmaWaves;
+__host__ __device__ inline int mfma_copies(int P, int waves = kMfmaWaves) {
+    const size_t lr = (size_t)mfma_geom(P).LR * waves;
     return 4 * lr <= kMfmaLdsMax ? 4 : (lr <= kMfmaLdsMax ? 1 : 0);
 }
-__host__ __device__ inline size_t mfma_lds_bytes(int P) {
-    return (size_t)mfma_geom(P).LR * kMfmaWaves * (size_t)mfma_copies(P);
+__host__ __device__ inline size_t mfma_lds_bytes(int P, int waves = kMfmaWaves) {
+    return (size_t)mfma_geom(P).LR * waves * (size_t)mfma_copies(P, waves);
 }
 __host__ __device__ inline bool mfma_supported(int P) { return mfma_shape_ok(P) && mfma_copies(P) > 0; }
 
@@ -265,14 +265,16 @@ __device__ __forceinline__ uint32_t partner_of(uint32_t a, uint32_t b, int h) {
 // column block jb of 32, word x <= P of the record of column j' = 32 jb + j is
 // limb P-1+x of l * u_{j'}, stored limb-major across the block's 32 columns:
 // T[((i' njb + jb) TP + x) 32 + j].
-template <int NC>
+// WAVES: waves (= consecutive rows of one column block) per workgroup; any
+// value gives the same bits.
+template <int NC, int WAVES = kMfmaWaves>
 __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, const uint8_t *Lr, const uint8_t *Ub,
                                                  uint32_t *T, const int32_t *info, int64_t k, int64_t n, int P,
                                                  int64_t ip0, int64_t rows, int64_t bx, bool xcd_aware) {
     if (*info != 0) return;
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
-    const int64_t njb = (m + 31) / 32, nrg = (rows + kMfmaWaves - 1) / kMfmaWaves;
+    const int64_t njb = (m + 31) / 32, nrg = (rows + WAVES - 1) / WAVES;
     int64_t rg, jb;
     if (xcd_aware && njb >= kXcds) {
         // workgroups go to the 8 XCDs round-robin: XCD x takes the column
@@ -288,12 +290,12 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
         rg = bx / njb;
         jb = bx % njb;
     }
-    // wave w of the workgroup takes row i' = ip0 + kMfmaWaves rg + w of the
+    // wave w of the workgroup takes row i' = ip0 + WAVES rg + w of the
     // panel [ip0, ip0 + rows) and fills its own part of LDS; after the one
     // barrier, which every wave reaches, a wave without a row (or with a zero
     // multiplier) leaves
     const int wave = (int)(threadIdx.x >> 6);
-    const int64_t ip = ip0 + rg * kMfmaWaves + wave;
+    const int64_t ip = ip0 + rg * WAVES + wave;
     const bool inrow = ip < ip0 + rows && ip < m;
     const bool active = inrow && el(A, k + 1 + (inrow ? ip : 0), k, P)[P - 1] != 0u;
     const int LR = g.LR;
@@ -885,12 +887,12 @@ __global__ void __launch_bounds__(64) k_mfma_prep(MatDev A, uint8_t *Lr, uint8_t
     mfma_prep_body(lds_raw, A, Lr, Ub, info, k, n, P, flat_block());
 }
 
-template <int NC>
-__global__ void __launch_bounds__(64 * kMfmaWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
+template <int NC, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T, const int32_t *info, int64_t k, int64_t n,
               int P, int64_t ip0, int64_t rows) {
     extern __shared__ uint32_t lds_raw[];
-    update_mfma_body<NC>(lds_raw, A, Lr, Ub, T, info, k, n, P, ip0, rows, flat_block(), true);
+    update_mfma_body<NC, WAVES>(lds_raw, A, Lr, Ub, T, info, k, n, P, ip0, rows, flat_block(), true);
 }
 
 // The finish of step k, and the first part of step k+1: the workgroup that
@@ -1157,10 +1159,10 @@ __device__ __forceinline__ void finish_body(uint32_t *lds, MatDev A, uint32_t *_
     else finish_tile_body(lds, elim_rank1(A, k, n), T, P, ip0, rows, bx);
     // (block 0 of the panel holding row k+1 holds a_{k+1,k+1})
     if (rw != nullptr && ip0 == 0 && bx == 0 && k + 1 < n) {
-        __syncthreads();  // the tile's stores are visible to the workgroup, its LDS is free
+        mpw::wsync();  // the tile's stores are visible to the wave, its LDS is free
         int32_t *pend = (int32_t *)(rw + P + 2);
         pivot_recip_body(lds, A, D, info, pend, rw, k + 1, n, P, 1);
-        __syncthreads();
+        mpw::wsync();
         pivot_recip_body(lds, A, D, info, pend, rw, k + 1, n, P, 0);
     }
 }

@@ -276,6 +276,14 @@ __global__ void __launch_bounds__(64) k_divide(MatDev A, const uint32_t *rw, int
     divide_body(lds_raw, A, rw, info, k, n, P, flat_block());
 }
 
+// multipliers of rows row0 .. n-1 only (growing a factorisation: the rows
+// added after the leading block was factored)
+__global__ void __launch_bounds__(64) k_divide_from(MatDev A, const uint32_t *rw, int32_t *info, int64_t k,
+                                                    int64_t n, int P, int64_t row0) {
+    extern __shared__ uint32_t lds_raw[];
+    divide_body(lds_raw, A, rw, info, k, n, P, row0 - k - 1 + (int64_t)blockIdx.x);
+}
+
 __global__ void __launch_bounds__(64) k_update_valu(MatDev A, const int32_t *info, int64_t k, int64_t n, int P) {
     extern __shared__ uint32_t lds_raw[];
     update_valu_body(lds_raw, A, info, k, n, P, flat_block());
@@ -332,6 +340,21 @@ __global__ void k_to_f64_scaled(MatDev x, int64_t rows, int64_t cols, int P, con
     // v 2^(s-53) in two exact-or-once-rounded steps: v 2^-53 is exact
     double d = ldexp(ldexp((double)v, -53), (int)s);
     val[t] = sg(x, i, j) ? -d : d;
+}
+
+// RZ to 32 P2 bits of a rows x cols block (P2 <= P): a nonzero mantissa has
+// its top bit set, so that is its top P2 limbs, same exponent and sign.  One
+// thread per output limb.
+__global__ void k_truncate(MatDev X, MatDev Y, int64_t rows, int64_t cols, int P, int P2) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x + (int64_t)blockIdx.y * gridDim.x * blockDim.x;
+    const int64_t total = rows * cols * (int64_t)P2;
+    if (t >= total) return;
+    const int64_t e = t / P2, q = t % P2, i = e / cols, j = e % cols;
+    el(Y, i, j, P2)[q] = el(X, i, j, P)[P - P2 + q];
+    if (q == 0) {
+        ex(Y, i, j) = ex(X, i, j);
+        sg(Y, i, j) = sg(X, i, j);
+    }
 }
 
 __global__ void k_set_info(int32_t *info, int32_t v) {

@@ -15,6 +15,7 @@
 #include "kernels_adj.h"
 #include "kernels_batch.h"
 #include "kernels_lane.h"
+#include "kernels_persist.h"
 #include "peaks.h"
 #include <algorithm>
 #include <mutex>
@@ -25,10 +26,10 @@
 // events recorded on the launch stream; mpdet_profile_end folds the elapsed
 // times into per-kernel totals.
 enum KernelId { K_PIVOT_DIVIDE = 0, K_DIVIDE, K_UPDATE_VALU, K_UPDATE_MFMA, K_MFMA_PREP, K_MINORS_SWEEP,
-                K_MINORS_FINAL, K_UPDATE_FINISH, K_ADJUGATE, K_ALL_MINORS, K_OTHER, K_COUNT };
+                K_MINORS_FINAL, K_UPDATE_FINISH, K_ADJUGATE, K_ALL_MINORS, K_BATCH_PERSIST, K_OTHER, K_COUNT };
 static const char *kKernelNames[K_COUNT] = {"pivot_divide", "divide",       "update_valu",   "update_mfma",
                                             "mfma_prep",    "minors_sweep", "minors_final",  "update_finish",
-                                            "adjugate",     "all_minors",    "other"};
+                                            "adjugate",     "all_minors",   "batch_persistent", "other"};
 
 struct ProfRec {
     int kernel;
@@ -63,6 +64,13 @@ struct mpdet_handle {
     size_t bh_bytes;
     hipEvent_t bh_done;
     bool bh_pending;
+    // tuning (0: the defaults): rows per workgroup of the VALU lane product
+    // (2, 4, 8) and waves per workgroup of the MFMA update (1, 2, 4)
+    int32_t lane_rows, mfma_waves;
+    // persistent batched launch: the bound on each of its waits in seconds
+    // (10 s before the first setting)
+    double wait_limit_s;
+    bool wait_limit_set;
 };
 
 namespace {
@@ -293,6 +301,50 @@ int mfma_workspace(mpdet_handle *h, int64_t m, int P, int64_t rows, MfmaWs *w, b
     return MPDET_OK;
 }
 
+// The tuned variants (every one gives the same bits).
+int lane_rows_of(const mpdet_handle *h) { return h && h->lane_rows ? h->lane_rows : mpk::kLaneRows; }
+int mfma_waves_of(const mpdet_handle *h) { return h && h->mfma_waves ? h->mfma_waves : mpk::kMfmaWaves; }
+
+using LaneKernel = void (*)(mpk::MatDev, uint32_t *, const int32_t *, int64_t, int64_t, int);
+using LaneR1Kernel = void (*)(mpk::Rank1, uint32_t *, const int32_t *, int);
+using MfmaKernel = void (*)(mpk::MatDev, const uint8_t *, const uint8_t *, uint32_t *, const int32_t *, int64_t,
+                            int64_t, int, int64_t, int64_t);
+using BatchKernel = void (*)(const mpk::BatchMat *, const int32_t *, const int64_t *, int, int64_t, int);
+
+LaneKernel lane_kernel(int rows) {
+    return rows == 2 ? mpk::k_prod_lane<2> : rows == 8 ? mpk::k_prod_lane<8> : mpk::k_prod_lane<4>;
+}
+LaneR1Kernel lane_r1_kernel(int rows) {
+    return rows == 2 ? mpk::k_prod_lane_r1<2> : rows == 8 ? mpk::k_prod_lane_r1<8> : mpk::k_prod_lane_r1<4>;
+}
+BatchKernel batch_lane_kernel(int rows) {
+    return rows == 2 ? mpk::k_batch_prod_lane<2> : rows == 8 ? mpk::k_batch_prod_lane<8> : mpk::k_batch_prod_lane<4>;
+}
+MfmaKernel mfma_kernel(int copies, int waves) {
+    if (copies == 4) return waves == 1 ? mpk::k_update_mfma<4, 1> : waves == 4 ? mpk::k_update_mfma<4, 4>
+                                                                                : mpk::k_update_mfma<4, 2>;
+    return waves == 1 ? mpk::k_update_mfma<1, 1> : waves == 4 ? mpk::k_update_mfma<1, 4> : mpk::k_update_mfma<1, 2>;
+}
+BatchKernel batch_mfma_kernel(int copies, int waves) {
+    if (copies == 4)
+        return waves == 1 ? mpk::k_batch_update_mfma<4, 1>
+                          : waves == 4 ? mpk::k_batch_update_mfma<4, 4> : mpk::k_batch_update_mfma<4, 2>;
+    return waves == 1 ? mpk::k_batch_update_mfma<1, 1>
+                      : waves == 4 ? mpk::k_batch_update_mfma<1, 4> : mpk::k_batch_update_mfma<1, 2>;
+}
+
+// one rank-1 update on the lane product and the tile finish (records in T)
+int lane_rank1(const mpdet_handle *h, const mpk::Rank1 &R, uint32_t *T, const int32_t *info, int P,
+               hipStream_t s) {
+    if (R.mr <= 0 || R.mc <= 0) return MPDET_OK;
+    const int rows = lane_rows_of(h);
+    hipLaunchKernelGGL(lane_r1_kernel(rows), grid_for(mpk::lane_update_blocks(R.mr, R.mc, rows)), dim3(64 * rows),
+                       mpk::lane_lds_bytes(P, rows), s, R, T, info, P);
+    hipLaunchKernelGGL(mpk::k_finish_r1, grid_for(mpk::finish_blocks(R.mr, R.mc, P)), dim3(64),
+                       mpk::finish_lds_bytes(P), s, R, (const uint32_t *)T, info, P);
+    return last_launch();
+}
+
 // VALU path.  For P <= 128 (P a multiple of 4) each step runs the
 // lane-per-element product kernel into the record buffer, then the finish
 // kernel the MFMA path uses; otherwise one wave per element update.
@@ -308,7 +360,8 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
         int rc = mfma_workspace(h, m0, P, m0, &w, false, ar);
         if (rc) return rc;
     }
-    const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_launch_lds(P);
+    const int lrows = lane_rows_of(h);
+    const size_t lds_prod = mpk::lane_lds_bytes(P, lrows), lds_fin = mpk::finish_launch_lds(P);
     auto fin_kernel = mpk::finish_streams(P) ? mpk::k_finish<true> : mpk::k_finish<false>;
     mpk::MatDev a = dev(A), d = dev(D);
     const int32_t *cinfo = info;
@@ -325,7 +378,7 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
         if (lane) {
             {
                 Prof pr(h, s, K_UPDATE_VALU);
-                hipLaunchKernelGGL(mpk::k_prod_lane, grid_for(mpk::lane_update_blocks(m)), dim3(64 * mpk::kLaneRows),
+                hipLaunchKernelGGL(lane_kernel(lrows), grid_for(mpk::lane_update_blocks(m, m, lrows)), dim3(64 * lrows),
                                    lds_prod, s, a, w.T, cinfo, k, n, P);
             }
             if ((rc = last_launch())) return rc;
@@ -353,10 +406,12 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     if (R < 1) return MPDET_ERANGE;
     int rc = mfma_workspace(h, m0, P, R, &w, true, ar);
     if (rc) return rc;
-    const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
+    const int mw = mfma_waves_of(h);
+    if (mpk::mfma_copies(P, mw) == 0) return MPDET_ENOTSUP;
+    const size_t lds_mfma = mpk::mfma_lds_bytes(P, mw), lds_prep = (size_t)(P + 1) * 4;
     const size_t lds_fin = mpk::finish_launch_lds(P);
     auto fin_kernel = mpk::finish_streams(P) ? mpk::k_finish<true> : mpk::k_finish<false>;
-    auto upd_kernel = mpk::mfma_copies(P) == 4 ? mpk::k_update_mfma<4> : mpk::k_update_mfma<1>;
+    auto upd_kernel = mfma_kernel(mpk::mfma_copies(P, mw), mw);
     mpk::MatDev a = dev(A), d = dev(D);
     const int32_t *cinfo = info;
     uint32_t *rw = nullptr;
@@ -377,8 +432,8 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
             const int64_t rows = m - ip0 < R ? m - ip0 : R;
             {
                 Prof pr(h, s, K_UPDATE_MFMA);
-                hipLaunchKernelGGL(upd_kernel, grid_for(mpk::mfma_update_blocks(rows, m)),
-                                   dim3(64 * mpk::kMfmaWaves), lds_mfma, s, a, (const uint8_t *)w.Lr,
+                hipLaunchKernelGGL(upd_kernel, grid_for(mpk::mfma_update_blocks(rows, m, mw)),
+                                   dim3(64 * mw), lds_mfma, s, a, (const uint8_t *)w.Lr,
                                    (const uint8_t *)w.Ub, w.T, cinfo, k, n, P, ip0, rows);
             }
             if ((rc = last_launch())) return rc;
@@ -613,6 +668,99 @@ int mp_det_factor(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, 
     return mp_det_factor_steps(h, A, D, info_dev, 0, A.rows, path, stream);
 }
 
+int mp_det_extend(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, int64_t n_old, int path,
+                  void *stream) {
+    if (!h) return MPDET_EINVAL;
+    bool use_mfma = false;
+    if (int rc = factor_args(A, D, info_dev, 0, A.rows, path, &use_mfma)) return rc;
+    const int64_t N = A.rows;
+    if (n_old < 0 || n_old > N) return MPDET_EINVAL;
+    if (n_old == N) return MPDET_OK;
+    DeviceGuard g(h->device);
+    if (!g.ok) return MPDET_EHIP;
+    hipStream_t s = (hipStream_t)stream;
+    const int P = A.nlimbs;
+    int rc;
+    if (n_old > 0) {
+        // Steps 0 .. n_old-1 were applied to the leading block; apply them to
+        // the rest in step order: the new rows' multipliers, then the two
+        // regions each step updates outside the leading block -- (a) the new
+        // rows right of column k, (b) the leading rows below row k in the new
+        // columns.  Neither reads what the other writes in the same step.
+        uint32_t *rw = nullptr;
+        if ((rc = recip_ws(h, P, &rw)) || (rc = pend_clear(rw, P, s))) return rc;
+        const bool lane = mpk::lane_update_ok(P);
+        MfmaWs w{};
+        if (lane) {  // records of the larger region: (N - n_old) x (N - 1) or n_old x (N - n_old)
+            const int64_t rows = std::max(N - n_old, n_old), cols = N;
+            if ((rc = mfma_workspace(h, cols, P, rows, &w, false))) return rc;
+        }
+        mpk::MatDev a = dev(A), d = dev(D);
+        const size_t lds = mpk::pivot_lds_bytes(P);
+        auto rank1 = [&](const mpk::Rank1 &R) -> int {
+            if (R.mr <= 0 || R.mc <= 0) return MPDET_OK;
+            if (lane) {
+                return lane_rank1(h, R, w.T, info_dev, P, s);
+            } else {
+                hipLaunchKernelGGL(mpk::k_rank1_wave, grid_for(R.mr * R.mc), dim3(64), mpk::lds_bytes(P), s, R,
+                                   (const int32_t *)info_dev, P);
+            }
+            return last_launch();
+        };
+        for (int64_t k = 0; k < n_old; ++k) {
+            // the pivot's reciprocal (D_k is written again with the same bits)
+            hipLaunchKernelGGL(mpk::k_pivot_recip, dim3(2), dim3(64), lds, s, a, d, info_dev, rw, k, N, P);
+            if ((rc = last_launch())) return rc;
+            hipLaunchKernelGGL(mpk::k_divide_from, dim3((unsigned)(N - n_old)), dim3(64), lds, s, a,
+                               (const uint32_t *)rw, info_dev, k, N, P, n_old);
+            if ((rc = last_launch())) return rc;
+            // (a) rows n_old.. x columns k+1..: x = column k below, y = row k
+            if ((rc = rank1(mpk::Rank1{a, a, a, n_old, k, 1, 0, k, k + 1, 0, 1, n_old, k + 1, N - n_old, N - k - 1, 0})))
+                return rc;
+            // (b) rows k+1..n_old-1 x columns n_old..
+            if ((rc = rank1(mpk::Rank1{a, a, a, k + 1, k, 1, 0, k, n_old, 0, 1, k + 1, n_old, n_old - k - 1, N - n_old,
+                                       0})))
+                return rc;
+        }
+    }
+    // steps n_old .. N-1 as a factorisation continued from n_old
+    return use_mfma ? factor_mfma(h, A, D, info_dev, n_old, N, s) : factor_valu(h, A, D, info_dev, n_old, N, s);
+}
+
+int mp_truncate(mpdet_handle *h, mpdet_mat x, mpdet_mat y, void *stream) {
+    if (!h) return MPDET_EINVAL;
+    const int64_t cnt = x.rows * x.cols;
+    if (!mat_ok(x, cnt > 0) || !mat_ok(y, cnt > 0) || y.rows != x.rows || y.cols != x.cols ||
+        y.nlimbs > x.nlimbs)
+        return MPDET_EINVAL;
+    if (cnt == 0) return MPDET_OK;
+    DeviceGuard g(h->device);
+    if (!g.ok) return MPDET_EHIP;
+    const int64_t total = cnt * y.nlimbs;
+    hipLaunchKernelGGL(mpk::k_truncate, grid_for((total + 255) / 256), dim3(256), 0, (hipStream_t)stream, dev(x),
+                       dev(y), x.rows, x.cols, x.nlimbs, y.nlimbs);
+    return last_launch();
+}
+
+int mp_det_factor_reduced(mpdet_handle *h, mpdet_mat A, mpdet_mat D, mpdet_mat A2, mpdet_mat D2, int32_t *info_dev,
+                          int64_t k_switch, int path, int path2, void *stream) {
+    if (!h) return MPDET_EINVAL;
+    bool m1 = false, m2 = false;
+    if (int rc = factor_args(A, D, info_dev, 0, A.rows, path, &m1)) return rc;
+    if (int rc = factor_args(A2, D2, info_dev, 0, A2.rows, path2, &m2)) return rc;
+    if (A2.rows != A.rows || A2.nlimbs > A.nlimbs || k_switch < 0 || k_switch > A.rows) return MPDET_EINVAL;
+    int rc;
+    if ((rc = mp_det_factor_steps(h, A, D, info_dev, 0, k_switch, path, stream))) return rc;
+    mpdet_mat Dk = D, Dk2 = D2;  // the leading determinants computed so far
+    Dk.rows = Dk2.rows = 1;
+    if ((rc = mp_truncate(h, A, A2, stream))) return rc;
+    if (k_switch > 0) {
+        Dk.cols = Dk2.cols = k_switch;
+        if ((rc = mp_truncate(h, Dk, Dk2, stream))) return rc;
+    }
+    return mp_det_factor_steps(h, A2, D2, info_dev, k_switch, A.rows, path2, stream);
+}
+
 int mp_det_factor_noalloc(mpdet_mat A, mpdet_mat D, int32_t *info_dev, int path, void *stream) {
     bool use_mfma = false;
     if (int rc = factor_args(A, D, info_dev, 0, A.rows, path, &use_mfma)) return rc;
@@ -713,12 +861,280 @@ int grow_device(void **p, size_t *have, size_t need) {
 
 }  // namespace
 
+}  // extern "C"
+
+namespace {
+
+// The persistent launch's schedule (kernels_persist.h): phase records of every
+// matrix, ordered by (virtual time, phase slot, rank in the size order), each
+// with the count of its matrix's tickets that must be complete before it runs;
+// pre[r] = tickets before record r, pre[nrec] = all tickets.
+struct PersistPlan {
+    std::vector<mpk::PersistRec> recs;
+    std::vector<int64_t> pre;
+};
+
+struct PlanKey {
+    int64_t vt;
+    int32_t slot, rank;
+    mpk::PersistRec rec;
+};
+
+// order the records by (virtual time, phase slot, rank) and give each its
+// matrix's count of earlier tickets; wg(kind): one ticket per unit
+template <typename WgKind>
+void persist_order(std::vector<PlanKey> &keys, size_t nmat, WgKind wg, PersistPlan *out) {
+    std::sort(keys.begin(), keys.end(), [](const PlanKey &a, const PlanKey &b) {
+        if (a.vt != b.vt) return a.vt < b.vt;
+        if (a.slot != b.slot) return a.slot < b.slot;
+        return a.rank < b.rank;
+    });
+    std::vector<int64_t> doneb(nmat, 0);
+    out->recs.clear();
+    out->pre.assign(1, 0);
+    out->recs.reserve(keys.size());
+    out->pre.reserve(keys.size() + 1);
+    for (const PlanKey &kk : keys) {
+        mpk::PersistRec r = kk.rec;
+        const int64_t tk = wg(r.kind) ? r.units : (r.units + mpk::kPersistWaves - 1) / mpk::kPersistWaves;
+        r.need = doneb[(size_t)r.mat];
+        doneb[(size_t)r.mat] += tk;
+        out->recs.push_back(r);
+        out->pre.push_back(out->pre.back() + tk);
+    }
+}
+
+// n[b]: sizes; order: matrices by size, largest first
+void persist_plan(const std::vector<int64_t> &n, const std::vector<int32_t> &order, int P, bool lane,
+                  bool lookahead, bool minors, PersistPlan *out) {
+    using Key = PlanKey;
+    std::vector<Key> keys;
+    for (int32_t t = 0; t < (int32_t)order.size(); ++t) {
+        const int32_t b = order[(size_t)t];
+        const int64_t nb = n[(size_t)b];
+        auto add = [&](int64_t vt, int32_t slot, int32_t kind, int64_t k, int64_t units) {
+            if (units > 0) keys.push_back(Key{vt, slot, t, mpk::PersistRec{0, units, k, b, kind}});
+        };
+        add(0, 0, mpk::PK_INIT, 0, 1);
+        for (int64_t k = 0; k < nb; ++k) {
+            const int64_t m = nb - k - 1;
+            if (!lookahead || k == 0) add(k, 1, mpk::PK_PIVOT, k, 2);
+            if (m <= 0) continue;
+            add(k, 2, mpk::PK_DIVIDE, k, m);
+            if (lane) {
+                add(k, 3, mpk::PK_PROD, k, mpk::lane_update_blocks(m));
+                add(k, 4, mpk::PK_FINISH, k, mpk::finish_blocks(m, m, P));
+            } else {
+                add(k, 3, mpk::PK_UPDV, k, m * m);
+            }
+        }
+        add(nb - 1, 5, mpk::PK_PEND, nb - 1, 1);
+        if (minors) {
+            for (int64_t sw = 0; sw + 2 <= nb; ++sw) add(nb + sw, 6, mpk::PK_MSWEEP, nb - 1 - sw, nb - 1 - sw);
+            add(2 * nb - 1, 7, mpk::PK_MFINAL, 0, nb);
+        }
+    }
+    persist_order(keys, n.size(), [](int kind) { return mpk::persist_wg_kind(kind); }, out);
+}
+
+// The backward's schedule: per matrix the phases of mp_det_adjugate in order
+// (virtual times: W sweeps 1..n-1, S and the diagonal n, back substitution
+// n+1..2n-1, accumulation 2n..3n-1)
+void persist_plan_adj(const std::vector<int64_t> &n, const std::vector<int32_t> &order, int P, bool lane,
+                      PersistPlan *out) {
+    std::vector<PlanKey> keys;
+    for (int32_t t = 0; t < (int32_t)order.size(); ++t) {
+        const int32_t b = order[(size_t)t];
+        const int64_t nb = n[(size_t)b];
+        auto add = [&](int64_t vt, int32_t slot, int32_t kind, int64_t k, int64_t units) {
+            if (units > 0) keys.push_back(PlanKey{vt, slot, t, mpk::PersistRec{0, units, k, b, kind}});
+        };
+        add(0, 0, mpk::AK_INIT, 0, nb);
+        for (int64_t j = nb - 1; j >= 1; --j) {
+            const int64_t vt = nb - j;
+            if (lane) {
+                add(vt, 1, mpk::AK_WPROD, j, mpk::lane_update_blocks(nb - j, j));
+                add(vt, 2, mpk::AK_WFIN, j, mpk::finish_blocks(nb - j, j, P));
+            } else {
+                add(vt, 1, mpk::AK_WONE, j, (nb - j) * j);
+            }
+        }
+        add(nb, 1, mpk::AK_S, 0, 1);
+        add(nb, 2, mpk::AK_DIAGREC, 0, 2 * nb);
+        for (int64_t k = nb - 1; k >= 1; --k) {
+            const int64_t vt = nb + (nb - k);
+            if (lane) {
+                add(vt, 1, mpk::AK_UPROD, k, mpk::lane_update_blocks(k, nb - k));
+                add(vt, 2, mpk::AK_UFIN, k, mpk::finish_blocks(k, nb - k, P));
+            } else {
+                add(vt, 1, mpk::AK_UONE, k, k * (nb - k));
+            }
+            add(vt, 3, mpk::AK_UDIV, k, nb - k);
+        }
+        for (int64_t k = 0; k < nb; ++k) {
+            const int64_t vt = 2 * nb + k;
+            if (lane) {
+                add(vt, 1, mpk::AK_APROD, k, mpk::lane_update_blocks(k + 1, k + 1));
+                add(vt, 2, mpk::AK_AFIN, k, mpk::finish_blocks(k + 1, k + 1, P));
+            } else {
+                add(vt, 1, mpk::AK_AONE, k, (k + 1) * (k + 1));
+            }
+        }
+    }
+    persist_order(keys, n.size(), [](int kind) { return mpk::adj_wg_kind(kind); }, out);
+}
+
+// LDS words of one wave's slice in the persistent kernel, and the workgroup's bytes
+int64_t persist_lds_wave(int P, bool lane) {
+    size_t b = mpk::pivot_lds_bytes(P);
+    b = std::max(b, mpk::lds_bytes(P));
+    if (lane) b = std::max(b, mpk::finish_launch_lds(P));
+    return (int64_t)((b / 4 + 3) / 4 * 4);
+}
+size_t persist_lds_bytes(int P, bool lane) {
+    const size_t waves = (size_t)mpk::kPersistWaves * (size_t)persist_lds_wave(P, lane) * 4u;
+    return lane ? std::max(waves, mpk::lane_lds_bytes(P)) : waves;
+}
+
+// Device workspace of a persistent launch, in the handle's batch buffer:
+// [descriptors | records | prefix] (staged from the pinned host buffer), then
+// the per-matrix ticket counts and marks, the queue control word and the
+// per-matrix scratch.
+struct PersistStage {
+    uint8_t *host_desc;  // pinned: the caller writes its descriptors here
+    uint8_t *dev_desc;
+    const mpk::PersistRec *recs;
+    const int64_t *pre;
+    int64_t *done;
+    int32_t *skipped;
+    mpk::PersistCtl *ctl;
+    uint8_t *scratch;
+    size_t desc_bytes, rec_bytes, pre_bytes;
+};
+
+int persist_alloc(mpdet_handle *h, size_t desc_raw, const PersistPlan &plan, int64_t batch, size_t scratch_bytes,
+                  PersistStage *st) {
+    const size_t nrec = plan.recs.size();
+    st->desc_bytes = up256(desc_raw);
+    st->rec_bytes = up256(sizeof(mpk::PersistRec) * nrec);
+    st->pre_bytes = up256(sizeof(int64_t) * (nrec + 1));
+    const size_t host_bytes = st->desc_bytes + st->rec_bytes + st->pre_bytes;
+    const size_t done_bytes = up256(sizeof(int64_t) * (size_t)batch), skip_bytes = up256(sizeof(int32_t) * (size_t)batch);
+    const size_t ctl_bytes = up256(sizeof(mpk::PersistCtl));
+    int rc = grow_device(&h->bw, &h->bw_bytes, host_bytes + done_bytes + skip_bytes + ctl_bytes + scratch_bytes);
+    if (rc) return rc;
+    if (h->bh_pending) {  // the pinned buffer is still being copied from
+        (void)hipEventSynchronize(h->bh_done);
+        h->bh_pending = false;
+    }
+    if (host_bytes > h->bh_bytes) {
+        if (h->bh) (void)hipHostFree(h->bh);
+        h->bh = nullptr;
+        h->bh_bytes = 0;
+        if (hipHostMalloc(&h->bh, host_bytes, hipHostMallocDefault) != hipSuccess) {
+            h->bh = nullptr;
+            (void)hipGetLastError();
+            return MPDET_ENOMEM;
+        }
+        h->bh_bytes = host_bytes;
+    }
+    if (!h->bh_done && hipEventCreateWithFlags(&h->bh_done, hipEventDisableTiming) != hipSuccess) return MPDET_EHIP;
+    uint8_t *dev = (uint8_t *)h->bw;
+    st->host_desc = (uint8_t *)h->bh;
+    st->dev_desc = dev;
+    st->recs = (const mpk::PersistRec *)(dev + st->desc_bytes);
+    st->pre = (const int64_t *)(dev + st->desc_bytes + st->rec_bytes);
+    st->done = (int64_t *)(dev + host_bytes);
+    st->skipped = (int32_t *)(dev + host_bytes + done_bytes);
+    st->ctl = (mpk::PersistCtl *)(dev + host_bytes + done_bytes + skip_bytes);
+    st->scratch = dev + host_bytes + done_bytes + skip_bytes + ctl_bytes;
+    return MPDET_OK;
+}
+
+// copy the descriptors (already in the pinned buffer), records and prefix to the device
+int persist_upload(mpdet_handle *h, const PersistPlan &plan, PersistStage *st, hipStream_t s) {
+    uint8_t *hst = st->host_desc;
+    memcpy(hst + st->desc_bytes, plan.recs.data(), sizeof(mpk::PersistRec) * plan.recs.size());
+    memcpy(hst + st->desc_bytes + st->rec_bytes, plan.pre.data(), sizeof(int64_t) * plan.pre.size());
+    const size_t host_bytes = st->desc_bytes + st->rec_bytes + st->pre_bytes;
+    if (hipMemcpyAsync(st->dev_desc, hst, host_bytes, hipMemcpyHostToDevice, s) != hipSuccess) return MPDET_EHIP;
+    if (hipEventRecord(h->bh_done, s) != hipSuccess) return MPDET_EHIP;
+    h->bh_pending = true;
+    return MPDET_OK;
+}
+
+// grid: every workgroup that fits on the device at once (at most one per
+// ticket); limit: the wait bound in wall-clock ticks
+int persist_shape(mpdet_handle *h, const void *kernel, size_t lds, int64_t tickets, int64_t *grid, uint64_t *limit) {
+    if (lds > 64u * 1024u &&
+        hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds) != hipSuccess)
+        return MPDET_EHIP;
+    int per_cu = 0, cus = 0, khz = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 64 * mpk::kPersistWaves, lds) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess ||
+        hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device) != hipSuccess)
+        return MPDET_EHIP;
+    if (per_cu < 1 || cus < 1 || khz < 1) return MPDET_ENOTSUP;
+    *grid = std::max<int64_t>(1, std::min<int64_t>(tickets, (int64_t)per_cu * cus));
+    const double lim_s = h->wait_limit_set ? h->wait_limit_s : 10.0;
+    *limit = (uint64_t)(lim_s * (double)khz * 1000.0);
+    return MPDET_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mpdet_set_tuning(mpdet_handle *h, int32_t lane_rows, int32_t mfma_waves) {
+    if (!h) return MPDET_EINVAL;
+    if (lane_rows != 0 && lane_rows != 2 && lane_rows != 4 && lane_rows != 8) return MPDET_EINVAL;
+    if (mfma_waves != 0 && mfma_waves != 1 && mfma_waves != 2 && mfma_waves != 4) return MPDET_EINVAL;
+    h->lane_rows = lane_rows;
+    h->mfma_waves = mfma_waves;
+    return MPDET_OK;
+}
+
+int mpdet_set_wait_limit(mpdet_handle *h, double seconds) {
+    if (!h || !(seconds >= 0.0) || seconds > 3600.0) return MPDET_EINVAL;
+    h->wait_limit_s = seconds;
+    h->wait_limit_set = true;
+    return MPDET_OK;
+}
+
+int mpdet_batched_plan(int64_t batch, const int64_t *n_host, int32_t nlimbs, int path, int flags, void *recs_out,
+                       int64_t cap, int64_t *nrec, int64_t *ntickets) {
+    if (batch < 0 || (batch > 0 && !n_host) || !nrec || !ntickets || nlimbs < 2 || nlimbs > kMaxLimbs)
+        return MPDET_EINVAL;
+    if (path != MPDET_PATH_AUTO && path != MPDET_PATH_VALU && path != MPDET_PATH_MFMA) return MPDET_EINVAL;
+    if (path == MPDET_PATH_MFMA || (path == MPDET_PATH_AUTO && auto_uses_mfma(nlimbs))) return MPDET_ENOTSUP;
+    std::vector<int64_t> n((size_t)batch);
+    for (int64_t b = 0; b < batch; ++b) {
+        if (n_host[b] < 1) return MPDET_EINVAL;
+        n[(size_t)b] = n_host[b];
+    }
+    std::vector<int32_t> order((size_t)batch);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return n[(size_t)a] > n[(size_t)b]; });
+    const bool lane = mpk::lane_update_ok(nlimbs);
+    PersistPlan plan;
+    persist_plan(n, order, nlimbs, lane, lane && mpk::finish_lookahead_ok(nlimbs), (flags & MPDET_WANT_MINORS) != 0,
+                 &plan);
+    *nrec = (int64_t)plan.recs.size();
+    *ntickets = plan.pre.back();
+    if (recs_out) {
+        if (cap < *nrec) return MPDET_EINVAL;
+        memcpy(recs_out, plan.recs.data(), plan.recs.size() * sizeof(mpk::PersistRec));
+    }
+    return MPDET_OK;
+}
+
 int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const mpdet_mat *D_arr,
                    const mpdet_mat *c_arr, int32_t *info_dev, int flags, int path, void *stream) {
     if (!h || batch < 0) return MPDET_EINVAL;
     if (batch == 0) return MPDET_OK;
     if (!A_arr || !D_arr || !info_dev) return MPDET_EINVAL;
-    if (flags & ~MPDET_WANT_MINORS) return MPDET_EINVAL;
+    if (flags & ~(MPDET_WANT_MINORS | MPDET_BATCH_LOCKSTEP | MPDET_BATCH_PERSISTENT)) return MPDET_EINVAL;
+    if ((flags & MPDET_BATCH_LOCKSTEP) && (flags & MPDET_BATCH_PERSISTENT)) return MPDET_EINVAL;
     const bool minors = (flags & MPDET_WANT_MINORS) != 0;
     if (minors && !c_arr) return MPDET_EINVAL;
     if (path != MPDET_PATH_AUTO && path != MPDET_PATH_VALU && path != MPDET_PATH_MFMA) return MPDET_EINVAL;
@@ -738,6 +1154,9 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
     if (path == MPDET_PATH_MFMA && !mfma_ok) return MPDET_ENOTSUP;
     const bool use_mfma = path == MPDET_PATH_MFMA || (path == MPDET_PATH_AUTO && auto_uses_mfma(P));
     const bool lane_valu = !use_mfma && mpk::lane_update_ok(P);
+    const int lrows = lane_rows_of(h), mw = mfma_waves_of(h);
+    if (use_mfma && mpk::mfma_copies(P, mw) == 0) return MPDET_ENOTSUP;
+    if (use_mfma && (flags & MPDET_BATCH_PERSISTENT)) return MPDET_ENOTSUP;
     DeviceGuard g(h->device);
     if (!g.ok) return MPDET_EHIP;
     hipStream_t s = (hipStream_t)stream;
@@ -747,6 +1166,60 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
     std::iota(order.begin(), order.end(), 0);
     std::stable_sort(order.begin(), order.end(),
                      [&](int32_t a, int32_t b) { return A_arr[a].rows > A_arr[b].rows; });
+    // the persistent schedule on request (measured slower than lockstep on
+    // config 4's forward: 1.25 s against 0.57 s)
+    const bool persistent = !use_mfma && (flags & MPDET_BATCH_PERSISTENT);
+    if (persistent) {
+        // one persistent launch over the whole schedule (kernels_persist.h)
+        const bool lookahead = lane_valu && mpk::finish_lookahead_ok(P);
+        std::vector<int64_t> nv((size_t)batch);
+        for (int64_t b = 0; b < batch; ++b) nv[(size_t)b] = A_arr[b].rows;
+        PersistPlan plan;
+        persist_plan(nv, order, P, lane_valu, lookahead, minors, &plan);
+        std::vector<size_t> scratch((size_t)batch);
+        size_t total_scratch = 0;
+        for (int64_t b = 0; b < batch; ++b) {
+            const int64_t n = A_arr[b].rows, m = n > 1 ? n - 1 : 1;
+            scratch[(size_t)b] = recip_bytes(P) + (lane_valu ? up256(mfma_rec_bytes(m, m, P)) : 0);
+            total_scratch += scratch[(size_t)b];
+        }
+        PersistStage st;
+        int rc = persist_alloc(h, sizeof(mpk::BatchMat) * (size_t)batch, plan, batch, total_scratch, &st);
+        if (rc) return rc;
+        mpk::BatchMat *hm = (mpk::BatchMat *)st.host_desc;
+        uint8_t *sp = st.scratch;
+        for (int64_t b = 0; b < batch; ++b) {
+            mpk::BatchMat &M = hm[b];
+            M.A = dev_mat(A_arr[b]);
+            M.D = dev_mat(D_arr[b]);
+            M.c = minors ? dev_mat(c_arr[b]) : mpk::MatDev{nullptr, nullptr, nullptr, 0};
+            M.info = info_dev + b;
+            M.n = A_arr[b].rows;
+            M.rw = (uint32_t *)sp;
+            M.Lr = M.Ub = nullptr;
+            M.T = lane_valu ? (uint32_t *)(sp + recip_bytes(P)) : nullptr;
+            sp += scratch[(size_t)b];
+        }
+        const size_t lds = persist_lds_bytes(P, lane_valu);
+        int64_t grid = 0;
+        uint64_t limit = 0;
+        if ((rc = persist_upload(h, plan, &st, s)) ||
+            (rc = persist_shape(h, (const void *)mpk::k_persist, lds, plan.pre.back(), &grid, &limit)))
+            return rc;
+        const unsigned bb = (unsigned)((batch + 255) / 256);
+        hipLaunchKernelGGL(mpk::k_persist_begin, dim3(bb), dim3(256), 0, s, st.ctl, st.done, st.skipped, batch);
+        if ((rc = last_launch())) return rc;
+        const mpk::BatchMat *dmats = (const mpk::BatchMat *)st.dev_desc;
+        {
+            Prof pr(h, s, K_BATCH_PERSIST);
+            hipLaunchKernelGGL(mpk::k_persist, dim3((unsigned)grid), dim3(64 * mpk::kPersistWaves), lds, s, dmats,
+                               st.recs, st.pre, (int64_t)plan.recs.size(), st.done, st.skipped, st.ctl, P,
+                               lookahead ? 1 : 0, minors ? 1 : 0, persist_lds_wave(P, lane_valu), limit);
+        }
+        if ((rc = last_launch())) return rc;
+        hipLaunchKernelGGL(mpk::k_persist_end, dim3(bb), dim3(256), 0, s, dmats, (const int32_t *)st.skipped, batch);
+        return last_launch();
+    }
     auto nof = [&](int t) { return A_arr[order[(size_t)t]].rows; };
 
     // block counts per (step, phase) -> prefix offsets, all in one table
@@ -756,8 +1229,8 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
             case BP_PIVOT: return 2;
             case BP_DIVIDE: return m;
             case BP_UPD:
-                if (use_mfma) return (mpk::mfma_update_blocks(m, m) + 7) / 8 * 8;
-                return lane_valu ? mpk::lane_update_blocks(m) : m * m;
+                if (use_mfma) return (mpk::mfma_update_blocks(m, m, mw) + 7) / 8 * 8;
+                return lane_valu ? mpk::lane_update_blocks(m, m, lrows) : m * m;
             case BP_PREP: return 2 * m;
             case BP_SUB: return mpk::finish_blocks(m, m, P);
         }
@@ -887,10 +1360,10 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
                        batch);
     if ((rc = last_launch())) return rc;
     const size_t lds_piv = mpk::pivot_lds_bytes(P), lds = mpk::lds_bytes(P);
-    const size_t lds_mfma = mpk::mfma_lds_bytes(P), lds_prep = (size_t)(P + 1) * 4;
+    const size_t lds_mfma = mpk::mfma_lds_bytes(P, mw), lds_prep = (size_t)(P + 1) * 4;
     const size_t lds_fin = mpk::finish_launch_lds(P);
     auto bfin_kernel = mpk::finish_streams(P) ? mpk::k_batch_finish<true> : mpk::k_batch_finish<false>;
-    auto bupd_kernel = mpk::mfma_copies(P) == 4 ? mpk::k_batch_update_mfma<4> : mpk::k_batch_update_mfma<1>;
+    auto bupd_kernel = batch_mfma_kernel(mpk::mfma_copies(P, mw), mw);
     // with the finish kernel, step k's pivot is examined by step k-1's finish launch
     const bool lookahead = (use_mfma || lane_valu) && mpk::finish_lookahead_ok(P);
     hipLaunchKernelGGL(mpk::k_batch_pend, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, dmats, batch, P, 0);
@@ -913,13 +1386,13 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
         if (use_mfma) {
             if ((rc = launch(K_MFMA_PREP, mpk::k_batch_prep, base + BP_PREP, lds_prep, k))) return rc;
             if ((rc = launch(K_UPDATE_MFMA, bupd_kernel, base + BP_UPD, lds_mfma, k,
-                             64 * mpk::kMfmaWaves)))
+                             64 * mw)))
                 return rc;
             if ((rc = launch(K_UPDATE_FINISH, bfin_kernel, base + BP_SUB, lds_fin, k))) return rc;
         } else {
             if (lane_valu) {
-                if ((rc = launch(K_UPDATE_VALU, mpk::k_batch_prod_lane, base + BP_UPD, mpk::lane_lds_bytes(P), k,
-                                 64 * mpk::kLaneRows)))
+                if ((rc = launch(K_UPDATE_VALU, batch_lane_kernel(lrows), base + BP_UPD, mpk::lane_lds_bytes(P, lrows),
+                                 k, 64 * lrows)))
                     return rc;
                 if ((rc = launch(K_UPDATE_FINISH, bfin_kernel, base + BP_SUB, lds_fin, k))) return rc;
             } else if ((rc = launch(K_UPDATE_VALU, mpk::k_batch_update_valu, base + BP_UPD, lds, k))) {
@@ -955,15 +1428,10 @@ static int w_sweeps(mpdet_handle *h, mpk::MatDev lu, mpk::MatDev W, const int32_
     if (mpk::lane_update_ok(P) && n > 1) {
         MfmaWs w{};
         if ((rc = mfma_workspace(h, n, P, n, &w))) return rc;
-        const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_lds_bytes(P);
         for (int64_t j = n - 1; j >= 1; --j) {
             // x_r = W[r][j] (r >= j), y_i = l_ji (i < j), z = W[r][i]
             const mpk::Rank1 R{W, lu, W, j, j, 1, 0, j, 0, 0, 1, j, 0, n - j, j, 0};
-            hipLaunchKernelGGL(mpk::k_prod_lane_r1, grid_for(mpk::lane_update_blocks(n - j, j)),
-                               dim3(64 * mpk::kLaneRows), lds_prod, s, R, w.T, info, P);
-            hipLaunchKernelGGL(mpk::k_finish_r1, grid_for(mpk::finish_blocks(n - j, j, P)), dim3(64), lds_fin, s, R,
-                               (const uint32_t *)w.T, info, P);
-            if ((rc = last_launch())) return rc;
+            if ((rc = lane_rank1(h, R, w.T, info, P, s))) return rc;
         }
         return MPDET_OK;
     }
@@ -1099,13 +1567,7 @@ int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT, 
         const bool lane = mpk::lane_update_ok(P);
         MfmaWs ws{};
         if (lane && (rc = mfma_workspace(h, n, P, n, &ws))) return rc;
-        const size_t lds_prod = mpk::lane_lds_bytes(P), lds_fin = mpk::finish_lds_bytes(P);
-        auto rank1 = [&](const mpk::Rank1 &R) {
-            hipLaunchKernelGGL(mpk::k_prod_lane_r1, grid_for(mpk::lane_update_blocks(R.mr, R.mc)),
-                               dim3(64 * mpk::kLaneRows), lds_prod, s, R, ws.T, gate, P);
-            hipLaunchKernelGGL(mpk::k_finish_r1, grid_for(mpk::finish_blocks(R.mr, R.mc, P)), dim3(64), lds_fin, s,
-                               R, (const uint32_t *)ws.T, gate, P);
-        };
+        auto rank1 = [&](const mpk::Rank1 &R) { (void)lane_rank1(h, R, ws.T, gate, P, s); };
         for (int64_t k = n - 1; k >= 1; --k) {
             if (lane)  // x_i = u_ik (i < k), y_j = J_kj (j >= k), z = J_ij
                 rank1(mpk::Rank1{lu, J, J, 0, k, 1, 0, k, k, 0, 1, 0, k, k, n - k, 0});
@@ -1126,6 +1588,138 @@ int mp_det_adjugate(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat adjT, 
         }
     }
     return MPDET_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// status[b] of the batched backward when it runs one call per matrix
+__global__ void k_adj_status(const int32_t *info, const int64_t *n, int32_t *status, int64_t batch) {
+    const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < batch) status[b] = mpk::factors_complete(info[b], n[b]) ? 0 : info[b];
+}
+}  // namespace
+
+extern "C" {
+
+int mp_det_adjugate_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *LU_arr, const mpdet_mat *D_arr,
+                            const mpdet_mat *adjT_arr, const int32_t *info_dev, int32_t *status_dev, int flags,
+                            void *stream) {
+    if (!h || batch < 0) return MPDET_EINVAL;
+    if (batch == 0) return MPDET_OK;
+    if (!LU_arr || !D_arr || !adjT_arr || !info_dev) return MPDET_EINVAL;
+    if (flags & ~MPDET_BATCH_LOCKSTEP) return MPDET_EINVAL;
+    const int P = LU_arr[0].nlimbs;
+    for (int64_t b = 0; b < batch; ++b) {
+        const mpdet_mat &LU = LU_arr[b], &D = D_arr[b], &T = adjT_arr[b];
+        const int64_t n = LU.rows;
+        if (n < 1 || LU.cols != n || !mat_ok(LU, true) || !mat_ok(D, true) || !mat_ok(T, true) || LU.nlimbs != P ||
+            D.nlimbs != P || T.nlimbs != P || D.cols < n || T.rows != n || T.cols != n)
+            return MPDET_EINVAL;
+    }
+    DeviceGuard g(h->device);
+    if (!g.ok) return MPDET_EHIP;
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if (flags & MPDET_BATCH_LOCKSTEP) {  // one mp_det_adjugate call per matrix
+        for (int64_t b = 0; b < batch; ++b)
+            if ((rc = mp_det_adjugate(h, LU_arr[b], D_arr[b], adjT_arr[b], info_dev + b, stream))) return rc;
+        if (!status_dev) return MPDET_OK;
+        int64_t *nd = nullptr;
+        std::vector<int64_t> nv((size_t)batch);
+        for (int64_t b = 0; b < batch; ++b) nv[(size_t)b] = LU_arr[b].rows;
+        if ((rc = grow_device(&h->bw, &h->bw_bytes, sizeof(int64_t) * (size_t)batch))) return rc;
+        nd = (int64_t *)h->bw;
+        if (hipMemcpyAsync(nd, nv.data(), sizeof(int64_t) * (size_t)batch, hipMemcpyHostToDevice, s) != hipSuccess)
+            return MPDET_EHIP;
+        hipLaunchKernelGGL(k_adj_status, dim3((unsigned)((batch + 255) / 256)), dim3(256), 0, s, info_dev, nd,
+                           status_dev, batch);
+        rc = last_launch();
+        if (rc == MPDET_OK && hipStreamSynchronize(s) != hipSuccess) rc = MPDET_EHIP;  // nv is a host vector
+        return rc;
+    }
+    // one persistent launch over every matrix's phases (kernels_persist.h)
+    const bool lane = mpk::lane_update_ok(P);
+    std::vector<int32_t> order((size_t)batch);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return LU_arr[a].rows > LU_arr[b].rows; });
+    std::vector<int64_t> nv((size_t)batch);
+    for (int64_t b = 0; b < batch; ++b) nv[(size_t)b] = LU_arr[b].rows;
+    PersistPlan plan;
+    persist_plan_adj(nv, order, P, lane, &plan);
+    // per matrix: W and J (n x n each), S (n + 1), reciprocals (n x (P + 2)), gate, records
+    auto sizes = [&](int64_t n, size_t *ml, size_t *me, size_t *ms, size_t *sl, size_t *se, size_t *ss, size_t *rb,
+                     size_t *tb) {
+        const size_t nn = (size_t)n * (size_t)n;
+        *ml = up256(nn * (size_t)P * 4u);
+        *me = up256(nn * 8u);
+        *ms = up256(nn * 4u);
+        *sl = up256((size_t)(n + 1) * P * 4u);
+        *se = up256((size_t)(n + 1) * 8u);
+        *ss = up256((size_t)(n + 1) * 4u);
+        *rb = up256((size_t)n * (P + 2) * 4u);
+        *tb = lane ? up256(mfma_rec_bytes(n, n, P)) : 0;
+        return 2 * (*ml + *me + *ms) + *sl + *se + *ss + *rb + 256 + *tb;
+    };
+    std::vector<size_t> scratch((size_t)batch);
+    size_t total_scratch = 0;
+    for (int64_t b = 0; b < batch; ++b) {
+        size_t a[8];
+        scratch[(size_t)b] = sizes(nv[(size_t)b], &a[0], &a[1], &a[2], &a[3], &a[4], &a[5], &a[6], &a[7]);
+        total_scratch += scratch[(size_t)b];
+    }
+    PersistStage st;
+    if ((rc = persist_alloc(h, sizeof(mpk::AdjMat) * (size_t)batch, plan, batch, total_scratch, &st))) return rc;
+    mpk::AdjMat *hm = (mpk::AdjMat *)st.host_desc;
+    uint8_t *sp = st.scratch;
+    for (int64_t b = 0; b < batch; ++b) {
+        const int64_t n = nv[(size_t)b];
+        size_t ml, me, ms, sl, se, ss, rb, tb;
+        (void)sizes(n, &ml, &me, &ms, &sl, &se, &ss, &rb, &tb);
+        uint8_t *q = sp;
+        auto carve = [&](size_t bytes) {
+            uint8_t *p = q;
+            q += bytes;
+            return p;
+        };
+        mpk::AdjMat &M = hm[b];
+        M.LU = dev_mat(LU_arr[b]);
+        M.D = dev_mat(D_arr[b]);
+        M.adjT = dev_mat(adjT_arr[b]);
+        M.W = mpk::MatDev{(uint32_t *)carve(ml), (int64_t *)carve(me), (int32_t *)carve(ms), n};
+        M.J = mpk::MatDev{(uint32_t *)carve(ml), (int64_t *)carve(me), (int32_t *)carve(ms), n};
+        M.S = mpk::MatDev{(uint32_t *)carve(sl), (int64_t *)carve(se), (int32_t *)carve(ss), n + 1};
+        M.rw = (uint32_t *)carve(rb);
+        M.gate = (int32_t *)carve(256);
+        M.T = lane ? (uint32_t *)carve(tb) : nullptr;
+        M.info = info_dev + b;
+        M.n = n;
+        sp += scratch[(size_t)b];
+    }
+    const size_t lds = persist_lds_bytes(P, lane);
+    int64_t grid = 0;
+    uint64_t limit = 0;
+    if ((rc = persist_upload(h, plan, &st, s)) ||
+        (rc = persist_shape(h, (const void *)mpk::k_persist_adj, lds, plan.pre.back(), &grid, &limit)))
+        return rc;
+    const unsigned bb = (unsigned)((batch + 255) / 256);
+    hipLaunchKernelGGL(mpk::k_persist_begin, dim3(bb), dim3(256), 0, s, st.ctl, st.done, st.skipped, batch);
+    if ((rc = last_launch())) return rc;
+    const mpk::AdjMat *dmats = (const mpk::AdjMat *)st.dev_desc;
+    {
+        Prof pr(h, s, K_BATCH_PERSIST);
+        hipLaunchKernelGGL(mpk::k_persist_adj, dim3((unsigned)grid), dim3(64 * mpk::kPersistWaves), lds, s, dmats,
+                           st.recs, st.pre, (int64_t)plan.recs.size(), st.done, st.skipped, st.ctl, P,
+                           persist_lds_wave(P, lane), limit);
+    }
+    if ((rc = last_launch())) return rc;
+    if (status_dev) {
+        hipLaunchKernelGGL(mpk::k_persist_adj_end, dim3(bb), dim3(256), 0, s, dmats, (const int32_t *)st.skipped,
+                           status_dev, batch);
+        rc = last_launch();
+    }
+    return rc;
 }
 
 int mp_to_f64(mpdet_handle *h, mpdet_mat x, double *mant_dev, int64_t *exp_dev, void *stream) {

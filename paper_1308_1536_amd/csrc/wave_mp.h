@@ -25,8 +25,15 @@ namespace mpw {
 
 __device__ __forceinline__ int lane() { return (int)(threadIdx.x & 63u); }
 
-// LDS visibility between lanes of the (single-wave) workgroup.
-__device__ __forceinline__ void wsync() { __syncthreads(); }
+// LDS and memory visibility between the lanes of one wave: the memory fences
+// of a workgroup barrier without the barrier itself, so a wave can run these
+// routines on its own while the other waves of its workgroup run something
+// else (in a one-wave workgroup this is exactly __syncthreads()).
+__device__ __forceinline__ void wsync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
 
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
