@@ -674,6 +674,7 @@ def bench_segmented(args):
     c = binding.DeviceMp.empty(1, N, P)
     info = torch.zeros(1, dtype=torch.int32, device="cuda")
     path = args.path or DEFAULT_PATH[args.config]
+    binding.set_overlap(args.overlap)
 
     def reset():
         for t, f in zip((work.limbs, work.exp, work.sign), (pristine.limbs, pristine.exp, pristine.sign)):
@@ -769,7 +770,8 @@ def bench_segmented(args):
                       "step": "one of K consecutive segments of one whole solve (elimination steps b_s..b_{s+1}-1; "
                               "the last also runs the minors): the K steps are one time to solution",
                       "segment_bounds": b, "segment_seconds": [round(v, 3) for v in seg_s],
-                      "time_to_solution_s": secs, "updates": upd, "limb_macs": macs},
+                      "time_to_solution_s": secs, "updates": upd, "limb_macs": macs,
+                      "overlap_panels": args.overlap},
            "end_to_end_frac_of_int8_peak": value / PEAK_INT8_MAC,
            "roofline": roof}
     Dh, ch = D.row(0), c.row(0)
@@ -830,6 +832,9 @@ def main():
     ap.add_argument("--schedule", default="auto", choices=["auto", "persistent", "lockstep"],
                     help="schedule of a batched call (configs 2 and 4): one persistent launch over a task "
                          "queue, or one launch per phase per step (lockstep, the default)")
+    ap.add_argument("--overlap", type=int, default=0, metavar="S",
+                    help="MFMA path: S row panels per step, each panel's finish on a second stream beside the "
+                         "next panel's update (0: off)")
     ap.add_argument("--backward-schedule", default="persistent", choices=["persistent", "streams"],
                     help="--backward on a batch: one persistent launch over every matrix "
                          "(mp_det_adjugate_batched) or one mp_det_adjugate call per matrix on 16 streams")

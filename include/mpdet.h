@@ -137,6 +137,27 @@ int mp_det_extend(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, 
                   void *stream);
 
 /*
+ * mp_det_factor_ball -- mp_det_factor (same bits) and rigorous error bounds
+ * for every leading determinant (the rigorous results the paper's future-work
+ * section asks for, by ball arithmetic instead of intervals): after the call
+ *   |D_k - D*_k| <= rad_mant[k-1] * 2^rad_exp[k-1],  k = 1..n,
+ * where D*_k is the exact leading determinant of the input (with
+ * MPDET_BALL_INPUT_ULP, of any matrix whose entries are within one unit in
+ * the last place of the input's: inputs rounded from exact values).  Every
+ * number of the elimination carries a radius m 2^e (32-bit m, int64 e)
+ * propagated with upward rounding through the divisions, products and
+ * differences; rad_exp[k-1] == INT64_MAX means no bound (a pivot's ball may
+ * contain zero; the elimination stopped at or before step k; an exponent
+ * overflow, info = -1, leaves every D_k without a bound).  The bound is worst-case, so it is looser than the actual
+ * error.  rad_mant_dev uint32[n], rad_exp_dev int64[n] (device).  The handle
+ * keeps 12 n^2 bytes of radii; the steps run one per call of
+ * mp_det_factor_steps, each followed by two small radius kernels.
+ */
+enum { MPDET_BALL_INPUT_ULP = 1 };
+int mp_det_factor_ball(mpdet_handle *h, mpdet_mat A, mpdet_mat D, uint32_t *rad_mant_dev, int64_t *rad_exp_dev,
+                       int32_t *info_dev, int flags, int path, void *stream);
+
+/*
  * mp_truncate -- y = RZ to 32*y.nlimbs bits of x, element by element
  * (y.nlimbs <= x.nlimbs; same rows and cols, each its own ld): the top
  * y.nlimbs limbs of every mantissa, the same exponent and sign.
@@ -222,6 +243,16 @@ int mp_det_factor_noalloc(mpdet_mat A, mpdet_mat D, int32_t *info_dev, int path,
  * The persistent batched launches keep 4 waves per workgroup.
  */
 int mpdet_set_tuning(mpdet_handle *h, int32_t lane_rows, int32_t mfma_waves);
+
+/*
+ * mpdet_set_overlap -- the MFMA path's trailing update split into `panels`
+ * row panels per step, the finish of each panel (its rounding and subtraction,
+ * bound by memory) on a second stream of the handle while the next panel's
+ * update (bound by the matrix cores) runs; two record buffers alternate.
+ * 0 or 1: off (the default).  Same bits for every value.
+ *   0 <= panels <= 64, else MPDET_EINVAL.
+ */
+int mpdet_set_overlap(mpdet_handle *h, int32_t panels);
 
 /*
  * mp_det_minors -- signed last-column cofactors c_i = (-1)^(i+n) M_{i,n}
@@ -369,7 +400,8 @@ int mp_det_all_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat C,
  * (C = mp_det_minors' 1 x n vector gives delta_{N,n} = c_n / c_1; C =
  * mp_det_all_minors' n x n output gives them for every leading block).
  *   C    rows x cols input (read only);  out  rows x cols output, its own
- *        ld, same nlimbs, not overlapping C (else MPDET_EINVAL).
+ *        ld, same nlimbs; none of out's three arrays may share a byte with
+ *        any of C's over the spans the shapes give (else MPDET_EINVAL).
  * A row whose first entry is zero is written as zeros.
  */
 int mp_det_normalize_minors(mpdet_handle *h, mpdet_mat C, mpdet_mat out, void *stream);

@@ -83,6 +83,9 @@ def _load():
         lib.mpref_truncate.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _u32p, _i64p, _i32p,
                                        _u32p, _i64p, _i32p]
         lib.mpref_truncate.restype = ctypes.c_int
+        lib.mpref_factor_ball.argtypes = mat + [_u32p, _i64p, _i32p, _i32p, ctypes.c_int32, _u32p, _i64p,
+                                                ctypes.c_int32]
+        lib.mpref_factor_ball.restype = ctypes.c_int
         lib.mpref_minors.argtypes = mat + [_u32p, _i64p, _i32p, _u32p, _i64p, _i32p,
                                            ctypes.c_int32]
         lib.mpref_minors.restype = ctypes.c_int
@@ -314,6 +317,28 @@ def factor_range(f: Factorization, k_begin: int, k_end: int, threads: int | None
     if rc != 0:
         raise ValueError("mpref_factor_range: bad argument")
     return Factorization(LU, D, int(info))
+
+
+RAD_INF = np.iinfo(np.int64).max
+
+
+def factor_ball(A, input_ulp: bool = False, threads: int | None = None):
+    """factor(A) and a rigorous radius per leading determinant: |D_k - D*_k| <=
+    rad_m[k] * 2^rad_e[k] (D*_k exact; rad_e == RAD_INF: no bound).  Returns
+    (Factorization, rad_m uint32[n], rad_e int64[n])."""
+    A = _as_mp(A).copy()
+    n = int(A.exp.shape[0])
+    P = A.P
+    D = _zeros((n,), P)
+    info = np.zeros((), np.int32)
+    rm = np.zeros(n, np.uint32)
+    re = np.zeros(n, np.int64)
+    rc = _load().mpref_factor_ball(n, P, _p(A.limbs, _u32p), _p(A.exp, _i64p), _p(A.sign, _i32p),
+                                   _p(D.limbs, _u32p), _p(D.exp, _i64p), _p(D.sign, _i32p), _p(info, _i32p),
+                                   1 if input_ulp else 0, _p(rm, _u32p), _p(re, _i64p), threads or default_threads())
+    if rc != 0:
+        raise ValueError("mpref_factor_ball: bad argument")
+    return Factorization(A, D, int(info)), rm, re
 
 
 def truncate(x, P2: int) -> Mp:

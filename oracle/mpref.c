@@ -677,3 +677,167 @@ int mpref_truncate(int64_t count, int32_t P, int32_t P2, const uint32_t *limbs, 
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Rigorous error bounds by ball arithmetic (the future-work section's
+ * rigorous results: instead of the interval endpoints of MPFI, each number
+ * carries a radius bounding its distance to the value the same sequence of
+ * operations gives in exact arithmetic on the exact input).
+ *
+ * A radius is m 2^e with m a 32-bit integer (0, or 2^31 <= m < 2^32), e an
+ * int64; every operation on radii rounds up, so every bound holds; the
+ * arithmetic is integer, so it is reproducible bit for bit.  e == RAD_INF:
+ * no bound (a pivot whose ball may contain zero).
+ * ---------------------------------------------------------------------- */
+#define RAD_INF INT64_MAX
+
+typedef struct {
+    uint32_t m;
+    int64_t e;
+} rad_t;
+
+static rad_t rad_make(uint32_t m, int64_t e) { rad_t r; r.m = m; r.e = e; return r; }
+static rad_t rad_zero(void) { return rad_make(0u, 0); }
+static rad_t rad_inf(void) { return rad_make(0xFFFFFFFFu, RAD_INF); }
+static int rad_isinf(rad_t a) { return a.e == RAD_INF; }
+
+/* the 64-bit value v 2^e, rounded up to a 32-bit mantissa */
+static rad_t rad_round_up(uint64_t v, int64_t e)
+{
+    if (v == 0) return rad_zero();
+    int n = 0;
+    for (uint64_t t = v; t; t >>= 1) n++;
+    if (n <= 32) return rad_make((uint32_t)(v << (32 - n)), e - (32 - n));
+    int s = n - 32;
+    uint64_t m = v >> s;
+    if (v & ((((uint64_t)1) << s) - 1)) m++;   /* a dropped bit: round up */
+    if (m == (((uint64_t)1) << 32)) { m >>= 1; s++; }
+    return rad_make((uint32_t)m, e + s);
+}
+
+static rad_t rad_two_to(int64_t k) { return rad_make(0x80000000u, k - 31); }
+
+static rad_t rad_sum(rad_t a, rad_t b)
+{
+    if (rad_isinf(a) || rad_isinf(b)) return rad_inf();
+    if (a.m == 0) return b;
+    if (b.m == 0) return a;
+    if (a.e < b.e) { rad_t t = a; a = b; b = t; }
+    uint64_t gap = (uint64_t)(a.e - b.e);
+    /* both on the scale 2^(a.e - 31): a exactly, b rounded up */
+    uint64_t A = (uint64_t)a.m << 31, B;
+    if (gap >= 63) {
+        B = 1;
+    } else {
+        uint64_t bb = (uint64_t)b.m << 31;
+        B = bb >> gap;
+        if (bb & ((((uint64_t)1) << gap) - 1)) B++;
+    }
+    return rad_round_up(A + B, a.e - 31);
+}
+
+static rad_t rad_prod(rad_t a, rad_t b)
+{
+    if (a.m == 0 || b.m == 0) return rad_zero();
+    if (rad_isinf(a) || rad_isinf(b)) return rad_inf();
+    return rad_round_up((uint64_t)a.m * (uint64_t)b.m, a.e + b.e);
+}
+
+/* |x| < 2^e for a nonzero number of exponent e; 0 for zero */
+static rad_t rad_abs_bound(const uint32_t *m, int64_t e, int32_t P)
+{
+    return num_is_zero(m, P) ? rad_zero() : rad_two_to(e);
+}
+
+/* the truncation error of a result: below one unit in its last place, 0 if it is zero */
+static rad_t rad_unit(const uint32_t *m, int64_t e, int32_t P)
+{
+    return num_is_zero(m, P) ? rad_zero() : rad_two_to(e - 32 * (int64_t)P);
+}
+
+/*
+ * mpref_factor_ball: mpref_factor, and for every leading determinant D_k a
+ * radius rd[k] = rdm[k] 2^rde[k] with |D_k - D*_k| <= rd[k], D*_k the exact
+ * leading determinant of the input (input_ulp: each input entry is itself
+ * within one unit in its last place of an exact value).  Per step k, with
+ * u = a_kk, l_i the multiplier of row i and q_i = a_ik / u before rounding:
+ *   r(D_1) = r(a_11);  r(D_k) = |D_{k-1}| r(u) + |u| r(D_{k-1}) + r(D_{k-1}) r(u) + ulp(D_k);
+ *   r(l_i) = (r(a_ik) + |q_i| r(u)) / (|u| - r(u)) + ulp(l_i), where
+ *            |q_i| <= 2^e(l_i) and |u| - r(u) >= 2^(e(u) - 2) provided
+ *            r(u) <= 2^(e(u) - 2) (otherwise no bound);
+ *   r(a_ij) += |l_i| r(u_kj) + |u_kj| r(l_i) + r(l_i) r(u_kj)
+ *              [+ ulp of the product + ulp of the new a_ij, where both were formed].
+ */
+int mpref_factor_ball(int64_t n, int32_t P, uint32_t *limbs, int64_t *exp, int32_t *sign,
+                      uint32_t *Dl, int64_t *De, int32_t *Ds, int32_t *info, int32_t input_ulp,
+                      uint32_t *rdm, int64_t *rde, int32_t threads)
+{
+    if (n < 0 || P < 1 || !info || (n > 0 && (!limbs || !exp || !sign || !Dl || !De || !Ds || !rdm || !rde)))
+        return -1;
+    rad_t *R = (rad_t *)malloc(sizeof(rad_t) * (size_t)(n > 0 ? n * n : 1));
+    rad_t *LR = (rad_t *)malloc(sizeof(rad_t) * (size_t)(n > 0 ? n : 1));
+    if (!R || !LR) { free(R); free(LR); return -1; }
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t j = 0; j < n; j++)
+            R[i * n + j] = input_ulp ? rad_unit(EL(i, j), EE(i, j), P) : rad_zero();
+    *info = 0;
+    for (int64_t k = 0; k < n; k++) {
+        /* the radii of the pivot and of column k before the step */
+        rad_t ru = R[k * n + k];
+        int64_t eu = EE(k, k);
+        int uz = num_is_zero(EL(k, k), P);
+        int rc = mpref_factor_range(n, P, limbs, exp, sign, Dl, De, Ds, info, k, k + 1, threads);
+        if (rc != 0) { free(R); free(LR); return rc; }
+        if (*info != 0) {  /* the elimination stopped: no bound from here on */
+            for (int64_t t = k; t < n; t++) { rdm[t] = 0xFFFFFFFFu; rde[t] = RAD_INF; }
+            break;
+        }
+        /* D_k */
+        rad_t rd;
+        if (k == 0) {
+            rd = ru;
+        } else {
+            rad_t rp = rad_make(rdm[k - 1], rde[k - 1]);
+            rad_t t1 = rad_prod(rad_abs_bound(Dl + (k - 1) * P, De[k - 1], P), ru);
+            rad_t t2 = rad_prod(uz ? rad_zero() : rad_two_to(eu), rp);
+            rad_t t3 = rad_prod(rp, ru);
+            rd = rad_sum(rad_sum(t1, t2), rad_sum(t3, rad_unit(Dl + k * P, De[k], P)));
+        }
+        rdm[k] = rd.m;
+        rde[k] = rd.e;
+        /* the multipliers (now in column k) */
+        for (int64_t i = k + 1; i < n; i++) {
+            if (uz || !(ru.m == 0 || (!rad_isinf(ru) && ru.e + 32 <= eu - 2))) {
+                LR[i] = rad_inf();
+                continue;
+            }
+            rad_t num = rad_sum(R[i * n + k], rad_prod(rad_abs_bound(EL(i, k), EE(i, k), P), ru));
+            if (num.m != 0 && !rad_isinf(num)) num.e += 2 - eu;   /* times 2^(2 - e(u)), exact */
+            LR[i] = rad_sum(num, rad_unit(EL(i, k), EE(i, k), P));
+        }
+        /* the trailing block */
+        for (int64_t i = k + 1; i < n; i++) {
+            rad_t rl = LR[i];
+            int lz = num_is_zero(EL(i, k), P);
+            for (int64_t j = k + 1; j < n; j++) {
+                int ukz = num_is_zero(EL(k, j), P);
+                rad_t ruj = R[k * n + j];
+                rad_t r = R[i * n + j];
+                r = rad_sum(r, rad_prod(lz ? rad_zero() : rad_two_to(EE(i, k)), ruj));
+                r = rad_sum(r, rad_prod(ukz ? rad_zero() : rad_two_to(EE(k, j)), rl));
+                r = rad_sum(r, rad_prod(rl, ruj));
+                if (!lz && !ukz) {
+                    r = rad_sum(r, rad_two_to(EE(i, k) + EE(k, j) - 32 * (int64_t)P));
+                    r = rad_sum(r, rad_unit(EL(i, j), EE(i, j), P));
+                }
+                R[i * n + j] = r;
+            }
+            R[i * n + k] = rl;
+        }
+    }
+    if (*info < 0)  /* an exponent overflow: no bound anywhere */
+        for (int64_t t = 0; t < n; t++) { rdm[t] = 0xFFFFFFFFu; rde[t] = RAD_INF; }
+    free(R);
+    free(LR);
+    return 0;
+}

@@ -63,6 +63,14 @@ int mpref_factor(int64_t n, int32_t P, uint32_t *limbs, int64_t *exp, int32_t *s
 int mpref_factor_range(int64_t n, int32_t P, uint32_t *limbs, int64_t *exp, int32_t *sign,
                        uint32_t *Dl, int64_t *De, int32_t *Ds, int32_t *info, int64_t k_begin,
                        int64_t k_end, int32_t threads);
+/* mpref_factor and, for every leading determinant, a rigorous radius:
+ * |D_k - D*_k| <= rdm[k] 2^rde[k] with D*_k the exact leading determinant of
+ * the input (input_ulp: every input entry within one unit in its last place of
+ * an exact value); rde[k] == INT64_MAX: no bound.  Ball arithmetic with
+ * radii rounded up (see mpref.c). */
+int mpref_factor_ball(int64_t n, int32_t P, uint32_t *limbs, int64_t *exp, int32_t *sign,
+                      uint32_t *Dl, int64_t *De, int32_t *Ds, int32_t *info, int32_t input_ulp,
+                      uint32_t *rdm, int64_t *rde, int32_t threads);
 /* RZ to 32*P2 bits (P2 <= P) of `count` numbers: the top P2 limbs. */
 int mpref_truncate(int64_t count, int32_t P, int32_t P2, const uint32_t *limbs, const int64_t *exp,
                    const int32_t *sign, uint32_t *ol, int64_t *oe, int32_t *os);

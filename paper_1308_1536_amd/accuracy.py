@@ -97,3 +97,32 @@ def report(make_input, n_max: int, P: int, rows=None, path: str = "auto") -> dic
     return {"bits": 32 * P, "N": N, "min_agree_bits": mins, "mean_agree_bits": means,
             "fit": {"slope_bits_per_row": slope, "intercept_bits": intercept,
                     "bits_lost_per_row_operation": -slope}}
+
+
+def main(argv=None) -> None:
+    """python -m paper_1308_1536_amd.accuracy --kind hilbert|cauchy --n N --limbs P
+    prints the report as one JSON line (p = 32P bits against 2p)."""
+    import argparse
+    import json
+
+    from . import inputs
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--kind", choices=["hilbert", "cauchy"], default="cauchy")
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--limbs", type=int, default=64)
+    ap.add_argument("--seed", type=int, default=1308_0200)
+    ap.add_argument("--points", type=int, default=24)
+    a = ap.parse_args(argv)
+    if a.kind == "hilbert":
+        make = inputs.hilbert
+    else:  # the nearly singular Cauchy generator of config 2 (nodes on [0, 1000])
+        def make(n, P):
+            return inputs.cauchy_dyadic(n, P, a.seed)[0]
+    rows = sorted(set(np.linspace(1, a.n - 1, a.points).astype(int).tolist()))
+    r = report(make, a.n, a.limbs, rows=rows)
+    r["kind"] = a.kind
+    print(json.dumps(r), flush=True)
+
+
+if __name__ == "__main__":
+    main()

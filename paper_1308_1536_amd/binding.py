@@ -67,11 +67,15 @@ def lib() -> ctypes.CDLL:
         L.mp_det_factor.argtypes = [vp, MpdetMat, MpdetMat, vp, ctypes.c_int, vp]
         L.mp_det_factor_steps.argtypes = [vp, MpdetMat, MpdetMat, vp, i64, i64, ctypes.c_int, vp]
         L.mpdet_set_panel_rows.argtypes = [vp, i64]
+        L.mp_det_factor_ball.argtypes = [vp, MpdetMat, MpdetMat, vp, vp, vp, ctypes.c_int, ctypes.c_int, vp]
+        L.mp_det_factor_ball.restype = ctypes.c_int
         L.mp_truncate.argtypes = [vp, MpdetMat, MpdetMat, vp]
         L.mp_truncate.restype = ctypes.c_int
         L.mp_det_factor_reduced.argtypes = [vp, MpdetMat, MpdetMat, MpdetMat, MpdetMat, vp, i64, ctypes.c_int,
                                             ctypes.c_int, vp]
         L.mp_det_factor_reduced.restype = ctypes.c_int
+        L.mpdet_set_overlap.argtypes = [vp, i32]
+        L.mpdet_set_overlap.restype = ctypes.c_int
         L.mpdet_set_tuning.argtypes = [vp, i32, i32]
         L.mpdet_set_tuning.restype = ctypes.c_int
         L.mp_det_extend.argtypes = [vp, MpdetMat, MpdetMat, vp, i64, ctypes.c_int, vp]
@@ -298,6 +302,26 @@ def extend(A: DeviceMp, D: DeviceMp, info, n_old: int, path: str = "auto", strea
     return D, info
 
 
+RAD_INF = (1 << 63) - 1
+
+
+def factor_ball(A: DeviceMp, input_ulp: bool = False, path: str = "auto", stream=None):
+    """mp_det_factor_ball in place on A: returns (D, rad_mant uint32 [n], rad_exp
+    int64 [n], info) device tensors; |D_k - D*_k| <= rad_mant * 2^rad_exp."""
+    import torch
+    n = A.rows
+    dev = A.limbs.device
+    D = DeviceMp.empty(1, n, A.P, dev)
+    rm = torch.zeros(max(n, 1), dtype=torch.int32, device=dev)
+    re = torch.zeros(max(n, 1), dtype=torch.int64, device=dev)
+    info = torch.zeros(1, dtype=torch.int32, device=dev)
+    h = handle(dev.index or 0)
+    _check("mp_det_factor_ball", lib().mp_det_factor_ball(h.ptr, A.mat(), D.mat(), rm.data_ptr(), re.data_ptr(),
+                                                          info.data_ptr(), 1 if input_ulp else 0,
+                                                          _resolve(path, n, A.P), _stream(stream)))
+    return D, rm, re, info
+
+
 def truncate(x: DeviceMp, P2: int, stream=None) -> DeviceMp:
     """mp_truncate: x rounded toward zero to P2 limbs (a new array)."""
     y = DeviceMp.empty(x.rows, x.cols, P2, x.limbs.device)
@@ -332,6 +356,12 @@ def set_tuning(lane_rows: int = 0, mfma_waves: int = 0, panel_rows: int | None =
     _check("mpdet_set_tuning", lib().mpdet_set_tuning(h, int(lane_rows), int(mfma_waves)))
     if panel_rows is not None:
         _check("mpdet_set_panel_rows", lib().mpdet_set_panel_rows(h, int(panel_rows)))
+
+
+def set_overlap(panels: int, device: int = 0):
+    """mpdet_set_overlap on the device's handle: MFMA row panels per step whose
+    finish runs on a second stream beside the next panel's update (0: off)."""
+    _check("mpdet_set_overlap", lib().mpdet_set_overlap(handle(device).ptr, int(panels)))
 
 
 def set_panel_rows(rows: int, device: int = 0):

@@ -16,6 +16,7 @@
 #include "kernels_batch.h"
 #include "kernels_lane.h"
 #include "kernels_persist.h"
+#include "kernels_ball.h"
 #include "peaks.h"
 #include <algorithm>
 #include <mutex>
@@ -64,6 +65,15 @@ struct mpdet_handle {
     size_t bh_bytes;
     hipEvent_t bh_done;
     bool bh_pending;
+    // radii of the ball-arithmetic factorisation: R (n x n) and the
+    // multipliers' radii (n)
+    void *radw;
+    size_t radw_bytes;
+    // MFMA path: row panels per step whose finish runs on a second stream
+    // beside the next panel's update (0 or 1: off), that stream and its events
+    int32_t overlap_panels;
+    hipStream_t side;
+    hipEvent_t ev_upd[2], ev_fin[2], ev_join;
     // tuning (0: the defaults): rows per workgroup of the VALU lane product
     // (2, 4, 8) and waves per workgroup of the MFMA update (1, 2, 4)
     int32_t lane_rows, mfma_waves;
@@ -86,6 +96,26 @@ bool mat_ok(const mpdet_mat &m, bool need_ptrs) {
 }
 
 mpk::MatDev dev(const mpdet_mat &m) { return mpk::MatDev{m.limbs, m.exp, m.sign, m.ld}; }
+
+// the byte ranges a rows x cols matrix spans (limbs, exponents, signs) of x
+// and y intersect anywhere (addresses compared as integers; rows, cols > 0)
+bool mats_overlap(const mpdet_mat &x, const mpdet_mat &y) {
+    auto span = [](const void *p, int64_t rows, int64_t ld, int64_t cols, size_t elem, uintptr_t *lo,
+                   uintptr_t *hi) {
+        *lo = (uintptr_t)p;
+        *hi = *lo + (size_t)((rows - 1) * ld + cols) * elem;
+    };
+    const void *px[3] = {x.limbs, x.exp, x.sign}, *py[3] = {y.limbs, y.exp, y.sign};
+    const size_t ex_[3] = {(size_t)x.nlimbs * 4u, 8u, 4u}, ey_[3] = {(size_t)y.nlimbs * 4u, 8u, 4u};
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) {
+            uintptr_t l1, h1, l2, h2;
+            span(px[a], x.rows, x.ld, x.cols, ex_[a], &l1, &h1);
+            span(py[b], y.rows, y.ld, y.cols, ey_[b], &l2, &h2);
+            if (l1 < h2 && l2 < h1) return true;
+        }
+    return false;
+}
 mpk::MatDev dev_mat(const mpdet_mat &m) { return dev(m); }
 
 dim3 grid_for(int64_t blocks) {
@@ -396,16 +426,38 @@ int factor_valu(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     return pend_promote(info, rw, P, s);
 }
 
+// the second stream and events of the overlapped MFMA schedule
+int overlap_ready(mpdet_handle *h) {
+    if (!h->side && hipStreamCreateWithFlags(&h->side, hipStreamNonBlocking) != hipSuccess) {
+        h->side = nullptr;
+        return MPDET_EHIP;
+    }
+    for (int t = 0; t < 2; ++t) {
+        if (!h->ev_upd[t] && hipEventCreateWithFlags(&h->ev_upd[t], hipEventDisableTiming) != hipSuccess)
+            return MPDET_EHIP;
+        if (!h->ev_fin[t] && hipEventCreateWithFlags(&h->ev_fin[t], hipEventDisableTiming) != hipSuccess)
+            return MPDET_EHIP;
+    }
+    if (!h->ev_join && hipEventCreateWithFlags(&h->ev_join, hipEventDisableTiming) != hipSuccess) return MPDET_EHIP;
+    return MPDET_OK;
+}
+
 int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t *info, int64_t k_begin,
                 int64_t k_end, hipStream_t s, const Arena *ar = nullptr) {
     const int64_t n = A.rows;
     const int P = A.nlimbs;
     MfmaWs w;
     const int64_t m0 = n - k_begin - 1 > 1 ? n - k_begin - 1 : 1;
-    const int64_t R = panel_rows(h, m0, P, ar);
+    // overlapped schedule: S row panels per step, the finish of panel p on a
+    // second stream while the update of panel p + 1 runs, two record buffers
+    const int S = (!ar && h && h->overlap_panels > 1) ? h->overlap_panels : 1;
+    int64_t R = panel_rows(h, m0, P, ar);
     if (R < 1) return MPDET_ERANGE;
-    int rc = mfma_workspace(h, m0, P, R, &w, true, ar);
+    if (S > 1) R = std::min<int64_t>(R, (m0 + S - 1) / S);
+    int rc = mfma_workspace(h, m0, P, S > 1 ? 2 * R : R, &w, true, ar);
     if (rc) return rc;
+    if (S > 1 && (rc = overlap_ready(h))) return rc;
+    uint32_t *Tbuf[2] = {w.T, w.T + (size_t)mpk::rec_slots(R, m0) * (size_t)mpk::mfma_geom(P).TP};
     const int mw = mfma_waves_of(h);
     if (mpk::mfma_copies(P, mw) == 0) return MPDET_ENOTSUP;
     const size_t lds_mfma = mpk::mfma_lds_bytes(P, mw), lds_prep = (size_t)(P + 1) * 4;
@@ -427,23 +479,55 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
                                n, P);
         }
         if ((rc = last_launch())) return rc;
-        // row panels [ip0, ip0 + rows) share the record buffer, one after another
-        for (int64_t ip0 = 0; ip0 < m; ip0 += R) {
-            const int64_t rows = m - ip0 < R ? m - ip0 : R;
+        if (S == 1) {
+            // row panels [ip0, ip0 + rows) share the record buffer, one after another
+            for (int64_t ip0 = 0; ip0 < m; ip0 += R) {
+                const int64_t rows = m - ip0 < R ? m - ip0 : R;
+                {
+                    Prof pr(h, s, K_UPDATE_MFMA);
+                    hipLaunchKernelGGL(upd_kernel, grid_for(mpk::mfma_update_blocks(rows, m, mw)),
+                                       dim3(64 * mw), lds_mfma, s, a, (const uint8_t *)w.Lr,
+                                       (const uint8_t *)w.Ub, w.T, cinfo, k, n, P, ip0, rows);
+                }
+                if ((rc = last_launch())) return rc;
+                {
+                    Prof pr(h, s, K_UPDATE_FINISH);
+                    hipLaunchKernelGGL(fin_kernel, grid_for(mpk::finish_blocks(rows, m, P)), dim3(64), lds_fin, s,
+                                       a, w.T, cinfo, k, n, P, ip0, rows, d, ahead ? rw : nullptr);
+                }
+                if ((rc = last_launch())) return rc;
+            }
+            continue;
+        }
+        // overlapped: update p on s into buffer p % 2, then its finish on the
+        // side stream; update p + 2 waits for finish p to release the buffer;
+        // the step ends when s has waited for the last finish
+        const int64_t Rk = std::min<int64_t>(R, (m + S - 1) / S);
+        int64_t p = 0;
+        for (int64_t ip0 = 0; ip0 < m; ip0 += Rk, ++p) {
+            const int64_t rows = m - ip0 < Rk ? m - ip0 : Rk;
+            const int b = (int)(p & 1);
+            if (p >= 2 && hipStreamWaitEvent(s, h->ev_fin[b], 0) != hipSuccess) return MPDET_EHIP;
             {
                 Prof pr(h, s, K_UPDATE_MFMA);
-                hipLaunchKernelGGL(upd_kernel, grid_for(mpk::mfma_update_blocks(rows, m, mw)),
-                                   dim3(64 * mw), lds_mfma, s, a, (const uint8_t *)w.Lr,
-                                   (const uint8_t *)w.Ub, w.T, cinfo, k, n, P, ip0, rows);
+                hipLaunchKernelGGL(upd_kernel, grid_for(mpk::mfma_update_blocks(rows, m, mw)), dim3(64 * mw),
+                                   lds_mfma, s, a, (const uint8_t *)w.Lr, (const uint8_t *)w.Ub, Tbuf[b], cinfo, k,
+                                   n, P, ip0, rows);
             }
             if ((rc = last_launch())) return rc;
+            if (hipEventRecord(h->ev_upd[b], s) != hipSuccess ||
+                hipStreamWaitEvent(h->side, h->ev_upd[b], 0) != hipSuccess)
+                return MPDET_EHIP;
             {
-                Prof pr(h, s, K_UPDATE_FINISH);
-                hipLaunchKernelGGL(fin_kernel, grid_for(mpk::finish_blocks(rows, m, P)), dim3(64), lds_fin, s, a,
-                                   w.T, cinfo, k, n, P, ip0, rows, d, ahead ? rw : nullptr);
+                Prof pr(h, h->side, K_UPDATE_FINISH);
+                hipLaunchKernelGGL(fin_kernel, grid_for(mpk::finish_blocks(rows, m, P)), dim3(64), lds_fin, h->side,
+                                   a, Tbuf[b], cinfo, k, n, P, ip0, rows, d, ahead ? rw : nullptr);
             }
             if ((rc = last_launch())) return rc;
+            if (hipEventRecord(h->ev_fin[b], h->side) != hipSuccess) return MPDET_EHIP;
         }
+        if (hipEventRecord(h->ev_join, h->side) != hipSuccess || hipStreamWaitEvent(s, h->ev_join, 0) != hipSuccess)
+            return MPDET_EHIP;
     }
     return pend_promote(info, rw, P, s);
 }
@@ -522,8 +606,15 @@ int mpdet_destroy(mpdet_handle *h) {
     if (h->rw) (void)hipFree(h->rw);
     if (h->aw) (void)hipFree(h->aw);
     if (h->bw) (void)hipFree(h->bw);
+    if (h->radw) (void)hipFree(h->radw);
     if (h->bh) (void)hipHostFree(h->bh);
     if (h->bh_done) (void)hipEventDestroy(h->bh_done);
+    for (int t = 0; t < 2; ++t) {
+        if (h->ev_upd[t]) (void)hipEventDestroy(h->ev_upd[t]);
+        if (h->ev_fin[t]) (void)hipEventDestroy(h->ev_fin[t]);
+    }
+    if (h->ev_join) (void)hipEventDestroy(h->ev_join);
+    if (h->side) (void)hipStreamDestroy(h->side);
     free(h);
     return MPDET_OK;
 }
@@ -725,6 +816,54 @@ int mp_det_extend(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, 
     }
     // steps n_old .. N-1 as a factorisation continued from n_old
     return use_mfma ? factor_mfma(h, A, D, info_dev, n_old, N, s) : factor_valu(h, A, D, info_dev, n_old, N, s);
+}
+
+}  // extern "C"
+namespace {
+int grow_device(void **p, size_t *have, size_t need);
+}
+extern "C" {
+
+int mp_det_factor_ball(mpdet_handle *h, mpdet_mat A, mpdet_mat D, uint32_t *rad_mant_dev, int64_t *rad_exp_dev,
+                       int32_t *info_dev, int flags, int path, void *stream) {
+    if (!h) return MPDET_EINVAL;
+    bool use_mfma = false;
+    if (int rc = factor_args(A, D, info_dev, 0, A.rows, path, &use_mfma)) return rc;
+    if (flags & ~MPDET_BALL_INPUT_ULP) return MPDET_EINVAL;
+    const int64_t n = A.rows;
+    if (n > 0 && (!rad_mant_dev || !rad_exp_dev)) return MPDET_EINVAL;
+    DeviceGuard g(h->device);
+    if (!g.ok) return MPDET_EHIP;
+    hipStream_t s = (hipStream_t)stream;
+    int rc;
+    if (n == 0) return mp_det_factor_steps(h, A, D, info_dev, 0, 0, path, stream);
+    const size_t nn = (size_t)n * (size_t)n;
+    const size_t need = up256(nn * 4u) + up256(nn * 8u) + up256((size_t)n * 4u) + up256((size_t)n * 8u);
+    if ((rc = grow_device(&h->radw, &h->radw_bytes, need))) return rc;
+    uint8_t *base = (uint8_t *)h->radw;
+    mpk::RadMat R{(uint32_t *)base, (int64_t *)(base + up256(nn * 4u)), n};
+    uint32_t *LRm = (uint32_t *)(base + up256(nn * 4u) + up256(nn * 8u));
+    int64_t *LRe = (int64_t *)((uint8_t *)LRm + up256((size_t)n * 4u));
+    mpk::MatDev a = dev(A), d = dev(D);
+    hipLaunchKernelGGL(mpk::k_ball_init, grid_for(((int64_t)nn + 255) / 256), dim3(256), 0, s, a, R, n, A.nlimbs,
+                       (flags & MPDET_BALL_INPUT_ULP) ? 1 : 0);
+    if ((rc = last_launch())) return rc;
+    // one elimination step at a time, each followed by its radii (same bits as
+    // one mp_det_factor call: every range continues the state)
+    for (int64_t k = 0; k < n; ++k) {
+        if ((rc = mp_det_factor_steps(h, A, D, info_dev, k, k + 1, path, stream))) return rc;
+        const int64_t m = n - k - 1;
+        hipLaunchKernelGGL(mpk::k_ball_mult, grid_for((std::max<int64_t>(m, 1) + 255) / 256), dim3(256), 0, s, a, d,
+                           R, LRm, LRe, rad_mant_dev, rad_exp_dev, (const int32_t *)info_dev, k, n, A.nlimbs);
+        if (m > 0)
+            hipLaunchKernelGGL(mpk::k_ball_update, grid_for((m * (m + 1) + 255) / 256), dim3(256), 0, s, a, R,
+                               (const uint32_t *)LRm, (const int64_t *)LRe, (const int32_t *)info_dev, k, n,
+                               A.nlimbs);
+        if ((rc = last_launch())) return rc;
+    }
+    hipLaunchKernelGGL(mpk::k_ball_end, grid_for((n + 255) / 256), dim3(256), 0, s, (const int32_t *)info_dev,
+                       rad_mant_dev, rad_exp_dev, n);
+    return last_launch();
 }
 
 int mp_truncate(mpdet_handle *h, mpdet_mat x, mpdet_mat y, void *stream) {
@@ -1084,6 +1223,12 @@ int persist_shape(mpdet_handle *h, const void *kernel, size_t lds, int64_t ticke
 }  // namespace
 
 extern "C" {
+
+int mpdet_set_overlap(mpdet_handle *h, int32_t panels) {
+    if (!h || panels < 0 || panels > 64) return MPDET_EINVAL;
+    h->overlap_panels = panels;
+    return MPDET_OK;
+}
 
 int mpdet_set_tuning(mpdet_handle *h, int32_t lane_rows, int32_t mfma_waves) {
     if (!h) return MPDET_EINVAL;
@@ -1494,7 +1639,7 @@ int mp_det_normalize_minors(mpdet_handle *h, mpdet_mat C, mpdet_mat out, void *s
     if (!mat_ok(C, cnt > 0) || !mat_ok(out, cnt > 0)) return MPDET_EINVAL;
     if (out.rows != C.rows || out.cols != C.cols || out.nlimbs != C.nlimbs) return MPDET_EINVAL;
     if (cnt == 0) return MPDET_OK;
-    if (out.limbs == C.limbs || out.exp == C.exp || out.sign == C.sign) return MPDET_EINVAL;
+    if (mats_overlap(C, out)) return MPDET_EINVAL;
     DeviceGuard g(h->device);
     if (!g.ok) return MPDET_EHIP;
     const int P = C.nlimbs;

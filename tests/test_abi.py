@@ -98,3 +98,27 @@ def test_product_path_has_no_oracle_dependency():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "mpref" not in text, f
+
+
+def test_normalize_minors_rejects_any_overlap_on_host(lib):
+    """mp_det_normalize_minors refuses an output sharing any byte with its
+    input (not only the same start), before it touches a device."""
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("checks the host-side rejection without a device")
+    fake = ctypes.create_string_buffer(4096)  # never dereferenced before the checks
+    h = ctypes.cast(fake, ctypes.c_void_p)
+    rows, cols, P = 3, 4, 2
+    base = 1 << 32  # addresses only compared, never read
+    limbs, exps, signs = base, base + (1 << 20), base + (2 << 20)
+    C = binding.MpdetMat(limbs, exps, signs, rows, cols, cols, P)
+    for shift in (4, 8 * P * 4, (rows * cols - 1) * P * 4):  # partial overlaps of the limbs
+        out = binding.MpdetMat(limbs + shift, base + (3 << 20), base + (4 << 20), rows, cols, cols, P)
+        assert lib.mp_det_normalize_minors(h, C, out, None) == binding.MPDET_EINVAL, shift
+    out = binding.MpdetMat(base + (3 << 20), exps + 8, base + (4 << 20), rows, cols, cols, P)
+    assert lib.mp_det_normalize_minors(h, C, out, None) == binding.MPDET_EINVAL
+    out = binding.MpdetMat(base + (3 << 20), base + (4 << 20), limbs, rows, cols, cols, P)  # signs over limbs
+    assert lib.mp_det_normalize_minors(h, C, out, None) == binding.MPDET_EINVAL
+    # disjoint: passes the checks and fails only at the device (none here)
+    out = binding.MpdetMat(base + (3 << 20), base + (4 << 20), base + (5 << 20), rows, cols, cols, P)
+    assert lib.mp_det_normalize_minors(h, C, out, None) == binding.MPDET_EHIP

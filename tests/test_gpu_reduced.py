@@ -39,6 +39,9 @@ def test_reduced_matches_oracle(n, P, P2, k, path, path2):
 def test_truncate_matches_oracle():
     from paper_1308_1536_amd import binding
     x = inputs.random_mantissas((7, 9), 12, 3)
-    for P2 in (1, 5, 12):
+    for P2 in (2, 5, 12):
         y = binding.truncate(binding.DeviceMp.from_host(x), P2)
         assert_same(y.to_host(), oracle.truncate(x, P2), f"P2={P2}")
+    with pytest.raises(binding.MpdetError) as e:  # the format needs at least 2 limbs
+        binding.truncate(binding.DeviceMp.from_host(x), 1)
+    assert e.value.status == binding.MPDET_EINVAL

@@ -81,3 +81,23 @@ def test_factor_steps_rejects_bad_ranges():
         with pytest.raises(binding.MpdetError) as e:
             binding.factor_steps(A, D, info, a, b, "valu")
         assert e.value.status == binding.MPDET_EINVAL
+
+
+@pytest.mark.parametrize("panels", [2, 3, 5])
+@pytest.mark.parametrize("N,P", [(45, 64), (21, 264), (24, 1024)])
+def test_mfma_overlapped_panels(panels, N, P):
+    """The finish of each row panel on a second stream beside the next panel's
+    update, two record buffers alternating: the oracle's bits."""
+    from paper_1308_1536_amd import binding
+    A = inputs.random_mantissas((N, N), P, 700 + panels + N)
+    say(f"[overlap] panels={panels} N={N} P={P}")
+    binding.set_overlap(panels)
+    try:
+        LU, D, c, info = gpu_det(A, "mfma")
+    finally:
+        binding.set_overlap(0)
+    f, cw = oracle.det_pipeline(A)
+    assert info == f.info
+    assert_same(D, f.D, "D")
+    assert_same(LU, f.LU, "LU")
+    assert_same(c, cw, "c")

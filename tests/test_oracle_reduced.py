@@ -17,7 +17,7 @@ from paper_1308_1536_amd import inputs
 def test_truncate_is_rz_of_the_exact_value():
     rng = np.random.default_rng(5)
     x = inputs.random_mantissas((40,), 6, 3)
-    for P2 in (1, 2, 3, 6):
+    for P2 in (1, 2, 3, 6):  # the oracle takes any limb count
         y = oracle.truncate(x, P2)
         for i in range(40):
             v = exact.value(x.limbs[i], x.exp[i], x.sign[i])
