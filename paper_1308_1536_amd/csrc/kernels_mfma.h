@@ -557,17 +557,17 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
 // limbs in an order that never reads a location after writing it.
 // ---------------------------------------------------------------------------
 // Streaming variant (finish_stream_body), for P above kFinStreamMinP: the tile
-// is always 64 elements and LDS holds only 32-limb chunks, so occupancy and
-// lane use no longer fall with P (measured: 2.1x faster than the LDS tile at
-// 32K bits, 1.3x slower at 4K bits, where the tile keeps all 64 lanes busy).
+// is always 64 elements and LDS holds one 32-limb chunk of each, so occupancy
+// and lane use no longer fall with P.
 constexpr int kFinStreamMinP = 256;
-constexpr int kFinC = 32;  // limbs per chunk of the streaming finish
+constexpr int kFinC = 32;   // limbs per chunk of the streaming finish
+constexpr int kFinCP = 36;  // LDS words per element row of a chunk (one spare, 16-byte aligned)
 __host__ __device__ inline bool finish_streams(int P) { return P > kFinStreamMinP; }
 __host__ __device__ inline int finish_tile(int P) {
     return finish_streams(P) ? 64 : (P <= 256 ? 64 : (P <= 512 ? 32 : 16));
 }
 __host__ __device__ inline size_t finish_lds_bytes(int P) {
-    if (finish_streams(P)) return (size_t)(2 * kFinC * 65 + 128) * 4u;
+    if (finish_streams(P)) return (size_t)(64 * kFinCP + 128) * 4u;
     return (size_t)(P + 1) * (size_t)(finish_tile(P) + 1) * 4u;
 }
 // workgroups of the finish for `rows` rows of an m x m trailing block
@@ -903,19 +903,30 @@ k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T, const
 // word rw[P + 2] rather than to info, which the launch's other workgroups are
 // reading; step k+1's divide kernel moves it into info.  rw == nullptr: no
 // look-ahead.
-// The same finish with 64 elements per wave for any P.  The elements' limbs
-// move between HBM and LDS in chunks of kFinC limbs (a chunk of one element is
-// one contiguous run, so 32 lanes load or store 128 bytes), the exact p+2-bit
-// intermediate G is kept in the element's own record words (word q is read
-// before G[q] overwrites it), and the normalised result goes back through an
-// LDS chunk.  LDS: two chunk buffers and the per-element offsets.
+// The same finish with 64 elements per wave for any P: lane e carries the
+// chain of element j0 + e, and the elements' limbs move between HBM and LDS in
+// chunks of 32 limbs (8 lanes move one element's chunk as four 16-byte
+// pieces, so 8 elements share one load or store instruction and every line
+// is used whole).  Step q of the chain forms G limb q and emits result limb
+// q - 1, so chunk c (steps 32c + 1 .. 32c + 32) holds the limbs of a it
+// consumes and, in the same LDS cells, the result limbs 32c .. 32c + 31 it
+// produces.  The next chunk's limbs of a are loaded into registers while a
+// chunk is computed, and the record words come from a ring of 32 registers
+// filled 32 steps ahead (lanes of one 32-column block read one line), so the
+// chain never waits for HBM.  No limb of a is stored before its load has
+// been consumed.  An element whose result length is not known from the top
+// limbs keeps G in its record (word q written after every read of it) and is
+// normalised by a second pass.
+typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
+typedef u32x4v u32x4u __attribute__((aligned(4)));  // 16 bytes at a 4-byte offset
+
 __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint32_t *__restrict__ T, int64_t k,
                                                    int64_t n, int P, int64_t ip0, int64_t rows, int64_t bx) {
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
     const int64_t njb = (m + 31) / 32;
-    constexpr int FT = 64, FTP = 65, C = kFinC;
-    static_assert(C == 32 && FT == 64, "the chunk copies map 64 elements x 32 limbs onto 32 lane passes");
+    constexpr int FT = 64, CP = kFinCP, C = kFinC;
+    static_assert(C == 32 && FT == 64, "a chunk move is 8 lanes x 4 limbs per element, 8 elements per pass");
     const int64_t ntile = (m + FT - 1) / FT;
     const int64_t ip = ip0 + bx / ntile, j0 = (bx % ntile) * FT;
     if (bx / ntile >= rows || ip >= m) return;
@@ -923,11 +934,13 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
     if (el(A, i, k, P)[P - 1] == 0u) return;  // zero multiplier: the row keeps its values
     const int cnt = (int)min((int64_t)FT, m - j0);
     uint32_t *arow = el(A, i, k + 1 + j0, P);  // element e2's limbs at arow + e2 * P
-    uint32_t *achunk = lds;                    // C rows x FTP: a's limbs of the current chunk
-    uint32_t *ochunk = lds + C * FTP;          // C rows x FTP: result limbs of the current chunk
-    int32_t *eoff = (int32_t *)(lds + 2 * C * FTP);  // per element: a's limb offset, or -1: not written
-    int32_t *fwoff = eoff + FT;  // per element: the single pass's limb shift w0 (0 or -1), 2: none
-    const int lane = mpw::lane(), e = lane;
+    // LDS: element e's chunk at chunk + e CP (limbs 0..C-1, then a spare
+    // word); rows of 36 words keep the 16-byte accesses of 8 lanes on
+    // distinct banks
+    uint32_t *chunk = lds;
+    int32_t *eoff = (int32_t *)(lds + FT * CP);  // per element: 1 + its offset into a, or -1: not live
+    int32_t *sflag = eoff + FT;                  // per element: its result is stored from the chunks
+    const int e = mpw::lane();
     const bool in = e < cnt;
     const int64_t jp = j0 + (in ? e : 0), j = k + 1 + jp;
     uint32_t *am = arow + (int64_t)(in ? e : 0) * P;
@@ -935,7 +948,7 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
     const bool live = in && el(A, k, j, P)[P - 1] != 0u;  // u_j = 0: a_ij is left as it is
     const int pbits = 32 * P;
 
-    // ---- per element: operands, alignment, sticky ----
+    // ---- operands, alignment, sticky ----
     int oa = 0, ot = 0, gsh = 0, b = 0, w = 0, sh = 0;
     bool a_is_x = true;
     uint32_t ymask = 0u, cy = 0u;
@@ -949,9 +962,8 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
     };
     auto al = [&](int q) -> uint32_t { return (q >= 0 && q < P) ? am[q] : 0u; };
     uint32_t ylo = 0u, wlo = 0u;
-    bool fast = false;  // single pass: the result is written while G is formed
-    int fw0 = 0, fbb = 0, flen = 0;
-    int64_t feout = 0;
+    bool fast = false;
+    int flen = 0;
     if (live) {
         const int top = (int)(rw(P) >> 31);
         sh = 1 - top;
@@ -969,18 +981,13 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
         } else {
             subtract = sa != sy;
             a_is_x = ea > et || (ea == et && !subtract);
-            bool zero = false;
             if (ea == et && subtract) {
                 int c = 0;
                 for (int q = P - 1; q >= 0 && c == 0; --q) {
                     const uint32_t x = al(q), y = tl(q);
                     c = x > y ? 1 : (x < y ? -1 : 0);
                 }
-                zero = c == 0;
-                a_is_x = c > 0;
-            }
-            if (zero) {  // a = t exactly: X = a, Y = t, G = 0
-                a_is_x = true;
+                a_is_x = c >= 0;  // c == 0: a = t exactly, X = a, Y = t, G = 0
             }
             eX = a_is_x ? ea : et;
             const int64_t eY = a_is_x ? et : ea;
@@ -1009,143 +1016,182 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
         wlo = rw(ot);
         fast = lza_length(P, gsh, w, b, subtract, [&](int q) { return a_is_x ? al(q) : tl(q); },
                           [&](int q) { return a_is_x ? tl(q) : al(q); }, &flen);
-        if (fast) {
-            const int sr = flen - pbits;  // -32 .. 3
-            fw0 = sr >= 0 ? 0 : -1;
-            fbb = sr - 32 * fw0;
-            feout = eX - gsh - pbits + flen;
-        }
     }
-    eoff[e] = live ? oa : -1;
-    fwoff[e] = (live && fast) ? fw0 : 2;  // 2: not written in pass 1
+    // single pass: result limb r = bits of G limbs r + fw0 + 1 and r + fw0
+    // (fw0 = 0 or -1) shifted right by fbb; it is emitted at step r + 1
+    const int fsr = flen - pbits;  // -32 .. 3
+    const bool f0 = fsr >= 0;      // fw0 == 0
+    const int fbb = f0 ? fsr : fsr + 32;
+    if (!live) fast = true;  // (stores nothing: sflag is 0)
+    const bool keep_g = __builtin_amdgcn_ballot_w64(!fast) != 0ull;  // some element needs pass 2
+    eoff[e] = live ? 1 + oa : -1;
+    sflag[e] = live && fast ? 1 : 0;
 
-    // ---- pass 1: G = X 2^gsh +- (Y >> rs) -+ sticky, limbs 0..P, into the record ----
-    constexpr int PF = 16;  // record words fetched PF steps ahead (C is a multiple of PF)
-    uint32_t ring[PF];
-    const uint32_t *rp = raw + (int64_t)(ot + 1) * 32;
-    const int xlim = P - ot - 1;  // step q uses a real record word iff q <= xlim
+    // ---- pass 1: G = X 2^gsh +- (Y >> rs) -+ sticky, limbs 0..P ----
+    const int xlim = P - ot - 1;  // step q uses a real record word (ot + 1 + q) iff q <= xlim
+    auto recw = [&](int q) -> uint32_t { return raw[(int64_t)min(ot + 1 + q, P) * 32]; };
+    uint32_t xprev = 0u, gprev = 0u, gprev2 = 0u;
+    // one step of the chain: G limb q from record word wr and a limb ar;
+    // returns result limb q - 1
+    auto step = [&](int q, uint32_t wr, uint32_t ar, auto store_g) __attribute__((always_inline)) -> uint32_t {
+        const uint32_t whi = q <= xlim ? wr : 0u;
+        const uint32_t tsh = sh ? __builtin_amdgcn_alignbit(whi, wlo, 31) : whi;
+        const uint32_t tv = q + ot < P ? tsh : 0u;
+        wlo = whi;
+        const uint32_t av = q + oa < P ? ar : 0u;
+        const uint32_t xq = a_is_x ? av : tv;
+        const uint32_t yhi = a_is_x ? tv : av;
+        const uint32_t xg = gsh ? __builtin_amdgcn_alignbit(xq, xprev, 32 - gsh) : xq;
+        const uint32_t ysh = __builtin_amdgcn_alignbit(yhi, ylo, b);
+        const uint64_t t = (uint64_t)xg + (ysh ^ ymask) + cy;
+        const uint32_t gq = (uint32_t)t;
+        cy = (uint32_t)(t >> 32);
+        xprev = xq;
+        ylo = yhi;
+        const uint32_t rhi = f0 ? gq : gprev, rlo = f0 ? gprev : gprev2;
+        const uint32_t r = __builtin_amdgcn_alignbit(rhi, rlo, fbb);
+        // G limb q to record word q (read at step q - ot - 1 or before)
+        if (decltype(store_g)::value && !fast && q <= P) raw[(int64_t)q * 32] = gq;
+        gprev2 = gprev;
+        gprev = gq;
+        return r;
+    };
+    // Every lane runs the chain, and every chunk, the last included, issues
+    // the same loads (addresses clamped into the element and its record;
+    // what lies past limb P - 1 or word P is never used): one body, no
+    // branch around its loads, so the ring stays in its registers and each
+    // step waits only for its own word.  A lane with no element is "fast"
+    // and stores nothing.
+    mpw::wsync();  // eoff and sflag are visible
+    // this lane moves limbs 4 sub .. 4 sub + 3 of the chunks of elements
+    // 8 s + grp, s = 0..7
+    const int sub = e & 7, grp = e >> 3;
+    int aoff[8];
+    uint32_t st_mask = 0u;
 #pragma unroll
-    for (int u = 0; u < PF; ++u) ring[u] = rp[(int64_t)min(u, max(xlim, 0)) * 32];
-    uint32_t xprev = 0u, gprev = 0u;
-    for (int c0 = 0; c0 <= P; c0 += C) {
-        mpw::wsync();  // the previous chunk is consumed; eoff is visible
-        // a's limbs [c0 + off, c0 + off + C) of every element, 8 loads per
-        // lane in flight: pass t covers element t >> 5, limb t & 31
+    for (int s = 0; s < 8; ++s) {
+        aoff[s] = eoff[8 * s + grp];
+        st_mask |= sflag[8 * s + grp] ? 1u << s : 0u;
+    }
+    // element 8 s + grp's limbs of a for the chunk whose first step is q0:
+    // limbs x .. x + 3, x = q0 + oa + 4 sub, read from x - d (d > 0 only where
+    // x > P - 4, so that every address stays inside the element; limbs at or
+    // past P are masked by the step).  One 16-byte load per element and no
+    // branch, so no load waits for another.
+    auto a_at = [&](int s, int q0) -> int { return q0 - 1 + aoff[s] + 4 * sub; };
+    auto load_a = [&](u32x4v *v, int q0) __attribute__((always_inline)) {
 #pragma unroll
-        for (int h4 = 0; h4 < 4; ++h4) {
-            uint32_t v[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int t = (h4 * 8 + u) * MP_WAVE + lane;
-                const int e2 = t >> 5, r = t & 31;
-                const int off = eoff[e2];
-                const int q = c0 + off + r;
-                v[u] = (off >= 0 && q < P) ? arow[(int64_t)e2 * P + q] : 0u;
-            }
-#pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int t = (h4 * 8 + u) * MP_WAVE + lane;
-                achunk[(t & 31) * FTP + (t >> 5)] = v[u];
-            }
+        for (int s = 0; s < 8; ++s) {
+            const int es = min(8 * s + grp, cnt - 1);  // (columns past the row are not read)
+            v[s] = *(const u32x4u *)(arow + (int64_t)es * P + min(a_at(s, q0), P - 4));
         }
-        mpw::wsync();
-        if (live) {
-            auto step1 = [&](int q, int u) __attribute__((always_inline)) {
-                const uint32_t wr = ring[u % PF];
-                ring[u % PF] = rp[(int64_t)min(q + PF, max(xlim, 0)) * 32];
-                const uint32_t whi = q <= xlim ? wr : 0u;
-                const uint32_t tsh = sh ? __builtin_amdgcn_alignbit(whi, wlo, 31) : whi;
-                const uint32_t tv = q + ot < P ? tsh : 0u;
-                wlo = whi;
-                const uint32_t av = achunk[u * FTP + e];
-                const uint32_t xq = a_is_x ? av : tv;
-                const uint32_t yhi = a_is_x ? tv : av;
-                const uint32_t xg = gsh ? __builtin_amdgcn_alignbit(xq, xprev, 32 - gsh) : xq;
-                const uint32_t ysh = __builtin_amdgcn_alignbit(yhi, ylo, b);
-                const uint64_t t = (uint64_t)xg + (ysh ^ ymask) + cy;
-                const uint32_t gq = (uint32_t)t;
-                // single pass: result limb q - w0 - 1 from G limbs q, q - 1 (the
-                // row is stored only for single-pass elements); two passes: G
-                // into record word q, which an earlier step has read
-                ochunk[u * FTP + e] = __builtin_amdgcn_alignbit(gq, gprev, fbb);
-                if (!fast) raw[(int64_t)q * 32] = gq;
-                gprev = gq;
-                cy = (uint32_t)(t >> 32);
-                xprev = xq;
-                ylo = yhi;
-            };
-            if (c0 + C <= P + 1) {
+    };
+    // the first chunk's limbs of a, then the record words (the order in
+    // which every later chunk issues them)
+    u32x4v va[8];
+    load_a(va, 1);
+    uint32_t ring[C];
+    using no_g = std::integral_constant<bool, false>;
+    using with_g = std::integral_constant<bool, true>;
+    if (keep_g) (void)step(0, recw(0), al(oa), with_g{});
+    else (void)step(0, recw(0), al(oa), no_g{});
+    // in step order, as the chunks reload them (the wait for word u then
+    // counts the loads issued after it)
 #pragma unroll
-                for (int u = 0; u < C; ++u) step1(c0 + u, u);
-            } else {
-#pragma unroll
-                for (int u = 0; u < C; ++u) {
-                    if (c0 + u > P) break;
-                    step1(c0 + u, u);
+    for (int u = 0; u < C; ++u) {
+        ring[u] = recw(1 + u);
+        asm volatile("" ::: "memory");
+    }
+    // the chunks: a loop of its own for waves that keep G (no branch on it
+    // inside the loop, whose registers then stay put)
+    auto chunks = [&](auto store_g) __attribute__((always_inline)) {
+        for (int q0 = 1; q0 <= P; q0 += C) {
+            mpw::wsync();  // the previous chunk's results have left LDS
+    #pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                const int d = a_at(s, q0) - min(a_at(s, q0), P - 4);
+                uint32_t *row = chunk + (8 * s + grp) * CP;
+                if (__builtin_amdgcn_ballot_w64(d != 0) == 0ull) {
+                    *(u32x4v *)(row + 4 * sub) = va[s];
+                } else {
+                    // limb x - d + z belongs at 4 sub + z - d; limbs before the
+                    // chunk (consumed already) go to the spare word C
+                    const int rb = 4 * sub - d;
+                    row[rb >= 0 ? rb : C] = va[s].x;
+                    row[rb + 1 >= 0 ? rb + 1 : C] = va[s].y;
+                    row[rb + 2 >= 0 ? rb + 2 : C] = va[s].z;
+                    row[rb + 3 >= 0 ? rb + 3 : C] = va[s].w;
+                }
+            }
+            load_a(va, q0 + C);
+            mpw::wsync();
+            // four steps per 16-byte LDS read and write of the lane's own row
+            // (steps past P, in the last chunk, produce limbs that are not stored)
+            uint32_t *mine = chunk + e * CP;
+    #pragma unroll
+            for (int t4 = 0; t4 < C / 4; ++t4) {
+                const u32x4v a4 = *(const u32x4v *)(mine + 4 * t4);
+                u32x4v r4;
+    #pragma unroll
+                for (int z = 0; z < 4; ++z) {
+                    const int u = 4 * t4 + z, q = q0 + u;
+                    r4[z] = step(q, ring[u], a4[z], store_g);
+                    ring[u] = recw(q + C);
+                }
+                *(u32x4v *)(mine + 4 * t4) = r4;
+            }
+            mpw::wsync();
+            // results: limbs q0 - 1 + 4 sub .. + 3 of the single-pass elements
+            const int r0 = q0 - 1 + 4 * sub;
+    #pragma unroll
+            for (int s = 0; s < 8; ++s) {
+                if (!(st_mask >> s & 1u) || r0 >= P) continue;
+                const u32x4v c = *(const u32x4v *)(chunk + (8 * s + grp) * CP + 4 * sub);
+                uint32_t *dst = arow + (int64_t)(8 * s + grp) * P + r0;
+                if (r0 + 3 < P) {
+                    *(u32x4u *)dst = c;
+                } else {
+    #pragma unroll
+                    for (int z = 0; z < 4; ++z)
+                        if (r0 + z < P) dst[z] = c[z];
                 }
             }
         }
-        // the single pass's result limbs of this chunk: row r of element e2 is
-        // limb c0 + r - w0 - 1 (every a limb it overwrites has been read)
-        mpw::wsync();
-#pragma unroll 4
-        for (int u = 0; u < 32; ++u) {
-            const int t = u * MP_WAVE + lane;
-            const int e2 = t >> 5, r = t & 31;
-            const int wo = fwoff[e2];
-            const int q = c0 + r - wo - 1;
-            if (wo != 2 && q >= 0 && q < P) arow[(int64_t)e2 * P + q] = ochunk[r * FTP + e2];
-        }
-    }
+    };
+    if (keep_g) chunks(with_g{});
+    else chunks(no_g{});
     if (live && fast) {
-        ex(A, i, j) = feout;
+        ex(A, i, j) = eX - gsh - pbits + flen;
         sg(A, i, j) = sX;
     }
-    // the two-pass elements only from here on
-    const bool slow = live && !fast;
-    if (__builtin_amdgcn_ballot_w64(slow) == 0ull) return;
-    mpw::wsync();
-    eoff[e] = slow ? 0 : -1;
+    if (!keep_g) return;
 
-    // ---- pass 2: normalise G to p bits, chunk by chunk into a_ij ----
-    int w0 = 0, bb = 0;
-    bool gzero = true;
-    int64_t eout = 0;
-    if (slow) {
-        auto gw = [&](int x) -> uint32_t { return (x >= 0 && x <= P) ? raw[(int64_t)x * 32] : 0u; };
-        int qt = P;
-        while (qt >= 0 && gw(qt) == 0u) --qt;
-        if (qt >= 0) {
-            gzero = false;
-            const int L = 32 * qt + 32 - __clz(gw(qt));
-            const int sr = L - pbits;  // bits to drop (negative: shift left)
-            w0 = sr >= 0 ? 0 : -((-sr + 31) / 32);
-            bb = sr - 32 * w0;
-            eout = eX - gsh - pbits + L;
-        }
-        ex(A, i, j) = gzero ? 0 : eout;
-        sg(A, i, j) = gzero ? 0 : sX;
+    // ---- pass 2: normalise G (record words 0..P) to p bits, per element ----
+    mpw::wsync();  // G's stores precede these loads
+    if (!live || fast) return;
+    auto gw = [&](int x) -> uint32_t { return (x >= 0 && x <= P) ? raw[(int64_t)x * 32] : 0u; };
+    int qt = P;
+    while (qt >= 0 && gw(qt) == 0u) --qt;
+    if (qt < 0) {
+        for (int r = 0; r < P; ++r) am[r] = 0u;
+        ex(A, i, j) = 0;
+        sg(A, i, j) = 0;
+        return;
     }
-    for (int c0 = 0; c0 < P; c0 += C) {
-        if (slow) {
-#pragma unroll 8
-            for (int u = 0; u < C; ++u) {
-                const int x = c0 + u + w0;  // result limb c0+u = bits of G limbs x, x+1
-                const uint32_t lo = (!gzero && x >= 0 && x <= P) ? raw[(int64_t)x * 32] : 0u;
-                const uint32_t hi = (!gzero && x + 1 >= 0 && x + 1 <= P) ? raw[(int64_t)(x + 1) * 32] : 0u;
-                ochunk[u * FTP + e] = __builtin_amdgcn_alignbit(hi, lo, bb);
-            }
-        }
-        mpw::wsync();
+    const int L = 32 * qt + 32 - __clz(gw(qt));
+    const int sr = L - pbits;  // bits to drop (negative: shift left)
+    const int w0 = sr >= 0 ? 0 : -((-sr + 31) / 32);
+    const int bb = sr - 32 * w0;
+    for (int r0 = 0; r0 < P; r0 += C) {
+        uint32_t gv[C + 1];
 #pragma unroll
-        for (int u = 0; u < 32; ++u) {
-            const int t = u * MP_WAVE + lane;
-            const int e2 = t >> 5, r = t & 31;
-            const int q = c0 + r;
-            if (eoff[e2] >= 0 && q < P) arow[(int64_t)e2 * P + q] = ochunk[r * FTP + e2];
-        }
-        mpw::wsync();
+        for (int u = 0; u <= C; ++u) gv[u] = gw(r0 + u + w0);  // result limb r = G limbs r + w0, r + w0 + 1
+#pragma unroll
+        for (int u = 0; u < C; ++u)
+            if (r0 + u < P) am[r0 + u] = __builtin_amdgcn_alignbit(gv[u + 1], gv[u], bb);
     }
+    ex(A, i, j) = eX - gsh - pbits + L;
+    sg(A, i, j) = sX;
 }
 
 // STREAM must equal finish_streams(P); the two forms are separate kernels so
