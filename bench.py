@@ -738,7 +738,9 @@ def bench_segmented(args):
         kms, kn = prof["update_mfma"]
         mp = binding.measure_peak("mfma_i8")
         ach = macs / (kms / 1e3)
-        kern = f"k_update_mfma<{mfma_copies(P)}>"
+        # above 256 limbs the update launch finishes its own products (no finish launch)
+        fused = P > 256 and not prof["update_finish"][1]
+        kern = f"k_update_mfma<{mfma_copies(P)}>" + (" with the finish" if fused else "")
         roof = {"bound": "mfma", "achieved": 2 * ach / 1e12, "peak": PEAK_INT8_MFMA_TOPS / 1e12, "unit": "TOP/s",
                 "frac": ach / PEAK_INT8_MAC, "kernel": kern, "measured_peak": 2 * mp / 1e12,
                 "frac_of_measured_peak": ach / mp, "traffic": traffic(kern), "avg_launch_ms": kms / kn,

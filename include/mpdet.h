@@ -245,12 +245,17 @@ int mp_det_factor_noalloc(mpdet_mat A, mpdet_mat D, int32_t *info_dev, int path,
 int mpdet_set_tuning(mpdet_handle *h, int32_t lane_rows, int32_t mfma_waves);
 
 /*
- * mpdet_set_overlap -- the MFMA path's trailing update split into `panels`
- * row panels per step, the finish of each panel (its rounding and subtraction,
- * bound by memory) on a second stream of the handle while the next panel's
- * update (bound by the matrix cores) runs; two record buffers alternate.
- * 0 or 1: off (the default).  Same bits for every value.
- *   0 <= panels <= 64, else MPDET_EINVAL.
+ * mpdet_set_overlap -- how the MFMA path schedules the finish of the trailing
+ * update (the rounding and subtraction, bound by memory) against the integer
+ * products (bound by the matrix cores).  Same bits for every value.
+ *   0  (the default) above 256 limbs, each wave of the update launch
+ *      finishes its own 32 products as soon as they are formed, while other
+ *      waves keep the matrix cores busy; otherwise as 1;
+ *   1  the finish is a launch of its own after each panel's products;
+ *   2 .. 64  the update split into that many row panels per step, the finish
+ *      of each panel on a second stream of the handle while the next panel's
+ *      update runs; two record buffers alternate.
+ *   Else MPDET_EINVAL.
  */
 int mpdet_set_overlap(mpdet_handle *h, int32_t panels);
 

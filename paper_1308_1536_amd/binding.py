@@ -359,8 +359,10 @@ def set_tuning(lane_rows: int = 0, mfma_waves: int = 0, panel_rows: int | None =
 
 
 def set_overlap(panels: int, device: int = 0):
-    """mpdet_set_overlap on the device's handle: MFMA row panels per step whose
-    finish runs on a second stream beside the next panel's update (0: off)."""
+    """mpdet_set_overlap on the device's handle: how the MFMA path schedules
+    the finish -- 0 inside the update launch above 256 limbs (the default), 1
+    a launch of its own, 2..64 row panels whose finish runs on a second stream
+    beside the next panel's update."""
     _check("mpdet_set_overlap", lib().mpdet_set_overlap(handle(device).ptr, int(panels)))
 
 

@@ -267,7 +267,20 @@ __device__ __forceinline__ uint32_t partner_of(uint32_t a, uint32_t b, int h) {
 // T[((i' njb + jb) TP + x) 32 + j].
 // WAVES: waves (= consecutive rows of one column block) per workgroup; any
 // value gives the same bits.
-template <int NC, int WAVES = kMfmaWaves>
+template <int NE>
+__device__ __forceinline__ void finish_stream_tile(uint32_t *lds, MatDev A, uint32_t *__restrict__ T, int64_t k,
+                                                   int64_t n, int P, int64_t ip0, int64_t ip, int64_t ip2,
+                                                   int64_t j0, int cnt);
+
+template <int NC>
+__device__ __forceinline__ void mfma_task(uint8_t *lr, MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T,
+                                          int64_t k, int64_t n, int P, int64_t ip0, int64_t ip, int64_t jb);
+
+// FUSE (P > kFinStreamMinP): each wave then finishes its own 32 elements
+// from its records (finish_stream_tile), so no finish launch follows; the
+// finish of one wave (vector ALU, memory) can run beside the products of
+// another on the same SIMD.
+template <int NC, int WAVES = kMfmaWaves, bool FUSE = false>
 __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, const uint8_t *Lr, const uint8_t *Ub,
                                                  uint32_t *T, const int32_t *info, int64_t k, int64_t n, int P,
                                                  int64_t ip0, int64_t rows, int64_t bx, bool xcd_aware) {
@@ -291,16 +304,36 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
         jb = bx % njb;
     }
     // wave w of the workgroup takes row i' = ip0 + WAVES rg + w of the
-    // panel [ip0, ip0 + rows) and fills its own part of LDS; after the one
-    // barrier, which every wave reaches, a wave without a row (or with a zero
-    // multiplier) leaves
+    // panel [ip0, ip0 + rows)
     const int wave = (int)(threadIdx.x >> 6);
     const int64_t ip = ip0 + rg * WAVES + wave;
-    const bool inrow = ip < ip0 + rows && ip < m;
-    const bool active = inrow && el(A, k + 1 + (inrow ? ip : 0), k, P)[P - 1] != 0u;
+    const bool valid = ip < ip0 + rows && ip < m;
+    uint8_t *lr = (uint8_t *)lds_raw + (size_t)wave * NC * g.LR;
+    if (!valid) return;
+    mfma_task<NC>(lr, A, Lr, Ub, T, k, n, P, ip0, ip, jb);
+    if constexpr (FUSE) {
+        // the records are complete and visible to every lane of the wave,
+        // and the wave's LDS is free
+        __builtin_amdgcn_s_waitcnt(0);
+        mpw::wsync();
+        finish_stream_tile<32>((uint32_t *)lr, A, T, k, n, P, ip0, ip, -1, jb * 32,
+                               (int)min((int64_t)32, m - jb * 32));
+    }
+}
+
+// One task of the update: row i' = ip of the trailing block (its record slot
+// ip - ip0 of the panel) times the 32 columns of block jb, in one wave with
+// its own LDS (NC copies of the row's digits).
+template <int NC>
+__device__ __forceinline__ void mfma_task(uint8_t *lr, MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T,
+                                          int64_t k, int64_t n, int P, int64_t ip0, int64_t ip, int64_t jb) {
+    const MfmaGeom g = mfma_geom(P);
+    const int64_t m = n - k - 1;
+    const int64_t njb = (m + 31) / 32;
+    // a zero multiplier leaves the row as it is
+    if (el(A, k + 1 + ip, k, P)[P - 1] == 0u) return;
     const int LR = g.LR;
-    uint8_t *lr = (uint8_t *)lds_raw + (size_t)wave * NC * LR;
-    if (active) {
+    {
         const uint32_t *src = (const uint32_t *)(Lr + ip * (int64_t)LR);
         const int nw = LR / 4;
         for (int w = mpw::lane(); w < nw; w += MP_WAVE) {
@@ -309,8 +342,7 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
             for (int a = 0; a < NC; ++a) ((uint32_t *)(lr + a * LR))[w] = __builtin_amdgcn_alignbyte(x1, x0, a);
         }
     }
-    __syncthreads();
-    if (!active) return;
+    mpw::wsync();
 
     const int lane = mpw::lane();
     const int j = lane & 31, h = lane >> 5;
@@ -562,12 +594,22 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
 constexpr int kFinStreamMinP = 256;
 constexpr int kFinC = 32;   // limbs per chunk of the streaming finish
 constexpr int kFinCP = 36;  // LDS words per element row of a chunk (one spare, 16-byte aligned)
+// LDS of the streaming finish of NE elements per wave: NE + 1 element rows, two
+// words per lane
+__host__ __device__ inline size_t finish_tile_lds(int NE) { return (size_t)((NE + 1) * kFinCP + 128) * 4u; }
+// the update launch can finish its own products (FUSE): the streaming finish
+// applies and the LDS of a wave (its digit-row copies) holds a 32-element
+// finish tile
+__host__ __device__ inline bool mfma_fuse_ok(int P, int waves) {
+    const size_t per_wave = (size_t)mfma_copies(P, waves) * (size_t)mfma_geom(P).LR;
+    return P > kFinStreamMinP && per_wave >= finish_tile_lds(32);
+}
 __host__ __device__ inline bool finish_streams(int P) { return P > kFinStreamMinP; }
 __host__ __device__ inline int finish_tile(int P) {
     return finish_streams(P) ? 64 : (P <= 256 ? 64 : (P <= 512 ? 32 : 16));
 }
 __host__ __device__ inline size_t finish_lds_bytes(int P) {
-    if (finish_streams(P)) return (size_t)(64 * kFinCP + 128) * 4u;
+    if (finish_streams(P)) return finish_tile_lds(64);
     return (size_t)(P + 1) * (size_t)(finish_tile(P) + 1) * 4u;
 }
 // workgroups of the finish for `rows` rows of an m x m trailing block
@@ -887,12 +929,12 @@ __global__ void __launch_bounds__(64) k_mfma_prep(MatDev A, uint8_t *Lr, uint8_t
     mfma_prep_body(lds_raw, A, Lr, Ub, info, k, n, P, flat_block());
 }
 
-template <int NC, int WAVES>
+template <int NC, int WAVES, bool FUSE = false>
 __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(2, 2)))
 k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T, const int32_t *info, int64_t k, int64_t n,
               int P, int64_t ip0, int64_t rows) {
     extern __shared__ uint32_t lds_raw[];
-    update_mfma_body<NC, WAVES>(lds_raw, A, Lr, Ub, T, info, k, n, P, ip0, rows, flat_block(), true);
+    update_mfma_body<NC, WAVES, FUSE>(lds_raw, A, Lr, Ub, T, info, k, n, P, ip0, rows, flat_block(), true);
 }
 
 // The finish of step k, and the first part of step k+1: the workgroup that
@@ -920,32 +962,41 @@ k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T, const
 typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
 typedef u32x4v u32x4u __attribute__((aligned(4)));  // 16 bytes at a 4-byte offset
 
-__device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint32_t *__restrict__ T, int64_t k,
-                                                   int64_t n, int P, int64_t ip0, int64_t rows, int64_t bx) {
+// NE (64 or 32) elements of the trailing block, records of panel
+// [ip0, ...): with ip2 < 0 the columns j0 .. j0 + cnt - 1 (cnt <= NE) of row
+// ip; with ip2 >= 0 (NE = 64) the columns j0 .. j0 + cnt - 1 (cnt <= 32) of
+// rows ip (elements 0..31) and ip2 (elements 32..63).  LDS finish_tile_lds(NE)
+// bytes.
+template <int NE>
+__device__ __forceinline__ void finish_stream_tile(uint32_t *lds, MatDev A, uint32_t *__restrict__ T, int64_t k,
+                                                   int64_t n, int P, int64_t ip0, int64_t ip, int64_t ip2,
+                                                   int64_t j0, int cnt) {
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
     const int64_t njb = (m + 31) / 32;
     constexpr int FT = 64, CP = kFinCP, C = kFinC;
-    static_assert(C == 32 && FT == 64, "a chunk move is 8 lanes x 4 limbs per element, 8 elements per pass");
-    const int64_t ntile = (m + FT - 1) / FT;
-    const int64_t ip = ip0 + bx / ntile, j0 = (bx % ntile) * FT;
-    if (bx / ntile >= rows || ip >= m) return;
-    const int64_t i = k + 1 + ip;
-    if (el(A, i, k, P)[P - 1] == 0u) return;  // zero multiplier: the row keeps its values
-    const int cnt = (int)min((int64_t)FT, m - j0);
-    uint32_t *arow = el(A, i, k + 1 + j0, P);  // element e2's limbs at arow + e2 * P
+    static_assert(C == 32 && (NE == 64 || NE == 32), "a chunk move is 8 lanes x 4 limbs per element, 8 elements per pass");
+    const bool two = ip2 >= 0;
+    // element e2: row erow, column offset ecol; ein: e2 is a column of the block
+    auto erow = [&](int e2) -> int64_t { return two && e2 >= 32 ? ip2 : ip; };
+    auto ecol = [&](int e2) -> int { return two ? (e2 & 31) : e2; };
+    auto eclamp = [&](int e2) -> int { return two ? ((e2 & 32) | min(e2 & 31, cnt - 1)) : min(e2, cnt - 1); };
+    auto eptr = [&](int e2) -> uint32_t * { return el(A, k + 1 + erow(e2), k + 1 + j0 + ecol(e2), P); };
+    if (!two && el(A, k + 1 + ip, k, P)[P - 1] == 0u) return;  // zero multiplier: the row keeps its values
     // LDS: element e's chunk at chunk + e CP (limbs 0..C-1, then a spare
     // word); rows of 36 words keep the 16-byte accesses of 8 lanes on
-    // distinct banks
+    // distinct banks; lanes past NE use row NE
     uint32_t *chunk = lds;
-    int32_t *eoff = (int32_t *)(lds + FT * CP);  // per element: 1 + its offset into a, or -1: not live
+    int32_t *eoff = (int32_t *)(lds + (NE + 1) * CP);  // per element (lane): 1 + its offset into a, or -1: not live
     int32_t *sflag = eoff + FT;                  // per element: its result is stored from the chunks
     const int e = mpw::lane();
-    const bool in = e < cnt;
-    const int64_t jp = j0 + (in ? e : 0), j = k + 1 + jp;
-    uint32_t *am = arow + (int64_t)(in ? e : 0) * P;
-    uint32_t *raw = T + ((ip - ip0) * njb + jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
-    const bool live = in && el(A, k, j, P)[P - 1] != 0u;  // u_j = 0: a_ij is left as it is
+    const bool in = e < NE && ecol(e) < cnt;
+    const int ee = in ? e : 0;
+    const int64_t i = k + 1 + erow(ee), jp = j0 + ecol(ee), j = k + 1 + jp;
+    uint32_t *am = eptr(ee);
+    uint32_t *raw = T + ((erow(ee) - ip0) * njb + jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
+    // a zero multiplier or u_j = 0 leaves a_ij as it is
+    const bool live = in && el(A, k, j, P)[P - 1] != 0u && el(A, i, k, P)[P - 1] != 0u;
     const int pbits = 32 * P;
 
     // ---- operands, alignment, sticky ----
@@ -1064,12 +1115,13 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
     // and stores nothing.
     mpw::wsync();  // eoff and sflag are visible
     // this lane moves limbs 4 sub .. 4 sub + 3 of the chunks of elements
-    // 8 s + grp, s = 0..7
+    // 8 s + grp, s < NE / 8
+    constexpr int NS = NE / 8;
     const int sub = e & 7, grp = e >> 3;
-    int aoff[8];
+    int aoff[NS];
     uint32_t st_mask = 0u;
 #pragma unroll
-    for (int s = 0; s < 8; ++s) {
+    for (int s = 0; s < NS; ++s) {
         aoff[s] = eoff[8 * s + grp];
         st_mask |= sflag[8 * s + grp] ? 1u << s : 0u;
     }
@@ -1081,14 +1133,14 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
     auto a_at = [&](int s, int q0) -> int { return q0 - 1 + aoff[s] + 4 * sub; };
     auto load_a = [&](u32x4v *v, int q0) __attribute__((always_inline)) {
 #pragma unroll
-        for (int s = 0; s < 8; ++s) {
-            const int es = min(8 * s + grp, cnt - 1);  // (columns past the row are not read)
-            v[s] = *(const u32x4u *)(arow + (int64_t)es * P + min(a_at(s, q0), P - 4));
+        for (int s = 0; s < NS; ++s) {
+            // (columns past the block are not read)
+            v[s] = *(const u32x4u *)(eptr(eclamp(8 * s + grp)) + min(a_at(s, q0), P - 4));
         }
     };
     // the first chunk's limbs of a, then the record words (the order in
     // which every later chunk issues them)
-    u32x4v va[8];
+    u32x4v va[NS];
     load_a(va, 1);
     uint32_t ring[C];
     using no_g = std::integral_constant<bool, false>;
@@ -1108,7 +1160,7 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
         for (int q0 = 1; q0 <= P; q0 += C) {
             mpw::wsync();  // the previous chunk's results have left LDS
     #pragma unroll
-            for (int s = 0; s < 8; ++s) {
+            for (int s = 0; s < NS; ++s) {
                 const int d = a_at(s, q0) - min(a_at(s, q0), P - 4);
                 uint32_t *row = chunk + (8 * s + grp) * CP;
                 if (__builtin_amdgcn_ballot_w64(d != 0) == 0ull) {
@@ -1127,7 +1179,7 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
             mpw::wsync();
             // four steps per 16-byte LDS read and write of the lane's own row
             // (steps past P, in the last chunk, produce limbs that are not stored)
-            uint32_t *mine = chunk + e * CP;
+            uint32_t *mine = chunk + min(e, NE) * CP;
     #pragma unroll
             for (int t4 = 0; t4 < C / 4; ++t4) {
                 const u32x4v a4 = *(const u32x4v *)(mine + 4 * t4);
@@ -1144,10 +1196,10 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
             // results: limbs q0 - 1 + 4 sub .. + 3 of the single-pass elements
             const int r0 = q0 - 1 + 4 * sub;
     #pragma unroll
-            for (int s = 0; s < 8; ++s) {
+            for (int s = 0; s < NS; ++s) {
                 if (!(st_mask >> s & 1u) || r0 >= P) continue;
                 const u32x4v c = *(const u32x4v *)(chunk + (8 * s + grp) * CP + 4 * sub);
-                uint32_t *dst = arow + (int64_t)(8 * s + grp) * P + r0;
+                uint32_t *dst = eptr(8 * s + grp) + r0;
                 if (r0 + 3 < P) {
                     *(u32x4u *)dst = c;
                 } else {
@@ -1192,6 +1244,16 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
     }
     ex(A, i, j) = eX - gsh - pbits + L;
     sg(A, i, j) = sX;
+}
+
+// the finish launch: workgroup bx takes 64 consecutive elements of a row
+__device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint32_t *__restrict__ T, int64_t k,
+                                                   int64_t n, int P, int64_t ip0, int64_t rows, int64_t bx) {
+    const int64_t m = n - k - 1;
+    const int64_t ntile = (m + 63) / 64;
+    const int64_t ip = ip0 + bx / ntile, j0 = (bx % ntile) * 64;
+    if (bx / ntile >= rows || ip >= m) return;
+    finish_stream_tile<64>(lds, A, T, k, n, P, ip0, ip, -1, j0, (int)min((int64_t)64, m - j0));
 }
 
 // STREAM must equal finish_streams(P); the two forms are separate kernels so

@@ -350,7 +350,14 @@ LaneR1Kernel lane_r1_kernel(int rows) {
 BatchKernel batch_lane_kernel(int rows) {
     return rows == 2 ? mpk::k_batch_prod_lane<2> : rows == 8 ? mpk::k_batch_prod_lane<8> : mpk::k_batch_prod_lane<4>;
 }
-MfmaKernel mfma_kernel(int copies, int waves) {
+MfmaKernel mfma_kernel(int copies, int waves, bool fuse = false) {
+    if (fuse) {
+        if (copies == 4)
+            return waves == 1 ? mpk::k_update_mfma<4, 1, true>
+                              : waves == 4 ? mpk::k_update_mfma<4, 4, true> : mpk::k_update_mfma<4, 2, true>;
+        return waves == 1 ? mpk::k_update_mfma<1, 1, true>
+                          : waves == 4 ? mpk::k_update_mfma<1, 4, true> : mpk::k_update_mfma<1, 2, true>;
+    }
     if (copies == 4) return waves == 1 ? mpk::k_update_mfma<4, 1> : waves == 4 ? mpk::k_update_mfma<4, 4>
                                                                                 : mpk::k_update_mfma<4, 2>;
     return waves == 1 ? mpk::k_update_mfma<1, 1> : waves == 4 ? mpk::k_update_mfma<1, 4> : mpk::k_update_mfma<1, 2>;
@@ -451,6 +458,10 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     // overlapped schedule: S row panels per step, the finish of panel p on a
     // second stream while the update of panel p + 1 runs, two record buffers
     const int S = (!ar && h && h->overlap_panels > 1) ? h->overlap_panels : 1;
+    // the finish inside the update launch (the default where it applies;
+    // overlap setting 1 keeps it a launch of its own)
+    const int mw = mfma_waves_of(h);
+    const bool fuse = S == 1 && !(h && h->overlap_panels == 1) && mpk::mfma_fuse_ok(P, mw);
     int64_t R = panel_rows(h, m0, P, ar);
     if (R < 1) return MPDET_ERANGE;
     if (S > 1) R = std::min<int64_t>(R, (m0 + S - 1) / S);
@@ -458,17 +469,16 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
     if (rc) return rc;
     if (S > 1 && (rc = overlap_ready(h))) return rc;
     uint32_t *Tbuf[2] = {w.T, w.T + (size_t)mpk::rec_slots(R, m0) * (size_t)mpk::mfma_geom(P).TP};
-    const int mw = mfma_waves_of(h);
     if (mpk::mfma_copies(P, mw) == 0) return MPDET_ENOTSUP;
     const size_t lds_mfma = mpk::mfma_lds_bytes(P, mw), lds_prep = (size_t)(P + 1) * 4;
     const size_t lds_fin = mpk::finish_launch_lds(P);
     auto fin_kernel = mpk::finish_streams(P) ? mpk::k_finish<true> : mpk::k_finish<false>;
-    auto upd_kernel = mfma_kernel(mpk::mfma_copies(P, mw), mw);
+    auto upd_kernel = mfma_kernel(mpk::mfma_copies(P, mw), mw, fuse);
     mpk::MatDev a = dev(A), d = dev(D);
     const int32_t *cinfo = info;
     uint32_t *rw = nullptr;
     if ((rc = recip_ws(h, P, &rw, ar)) || (rc = pend_clear(rw, P, s))) return rc;
-    const bool ahead = mpk::finish_lookahead_ok(P);  // the finish launch examines the next pivot
+    const bool ahead = !fuse && mpk::finish_lookahead_ok(P);  // the finish launch examines the next pivot
     for (int64_t k = k_begin; k < k_end; ++k) {
         if ((rc = pivot_step(h, a, d, info, rw, k, n, P, ahead && k > k_begin, s))) return rc;
         const int64_t m = n - k - 1;
@@ -490,6 +500,7 @@ int factor_mfma(mpdet_handle *h, const mpdet_mat &A, const mpdet_mat &D, int32_t
                                        (const uint8_t *)w.Ub, w.T, cinfo, k, n, P, ip0, rows);
                 }
                 if ((rc = last_launch())) return rc;
+                if (fuse) continue;
                 {
                     Prof pr(h, s, K_UPDATE_FINISH);
                     hipLaunchKernelGGL(fin_kernel, grid_for(mpk::finish_blocks(rows, m, P)), dim3(64), lds_fin, s,

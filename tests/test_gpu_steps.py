@@ -83,6 +83,27 @@ def test_factor_steps_rejects_bad_ranges():
         assert e.value.status == binding.MPDET_EINVAL
 
 
+@pytest.mark.parametrize("N,P", [(70, 264), (45, 520), (40, 1024)])
+def test_mfma_finish_in_update_launch(N, P):
+    """Above 256 limbs each wave of the update launch finishes its own 32
+    products (the default); overlap setting 1 keeps the finish a launch of its
+    own.  Both give the oracle's bits (several 32-column blocks, a ragged one)."""
+    from paper_1308_1536_amd import binding
+    A = inputs.random_mantissas((N, N), P, 900 + N)
+    f, cw = oracle.det_pipeline(A)
+    for setting in (0, 1):
+        say(f"[finish] overlap setting {setting} N={N} P={P}")
+        binding.set_overlap(setting)
+        try:
+            LU, D, c, info = gpu_det(A, "mfma")
+        finally:
+            binding.set_overlap(0)
+        assert info == f.info
+        assert_same(D, f.D, "D")
+        assert_same(LU, f.LU, "LU")
+        assert_same(c, cw, "c")
+
+
 @pytest.mark.parametrize("panels", [2, 3, 5])
 @pytest.mark.parametrize("N,P", [(45, 64), (21, 264), (24, 1024)])
 def test_mfma_overlapped_panels(panels, N, P):
