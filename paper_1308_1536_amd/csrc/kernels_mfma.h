@@ -269,8 +269,7 @@ __device__ __forceinline__ uint32_t partner_of(uint32_t a, uint32_t b, int h) {
 // value gives the same bits.
 template <int NE>
 __device__ __forceinline__ void finish_stream_tile(uint32_t *lds, MatDev A, uint32_t *__restrict__ T, int64_t k,
-                                                   int64_t n, int P, int64_t ip0, int64_t ip, int64_t ip2,
-                                                   int64_t j0, int cnt);
+                                                   int64_t n, int P, int64_t ip0, int64_t ip, int64_t j0, int cnt);
 
 template <int NC>
 __device__ __forceinline__ void mfma_task(uint8_t *lr, MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T,
@@ -316,8 +315,7 @@ __device__ __forceinline__ void update_mfma_body(uint32_t *lds_raw, MatDev A, co
         // and the wave's LDS is free
         __builtin_amdgcn_s_waitcnt(0);
         mpw::wsync();
-        finish_stream_tile<32>((uint32_t *)lr, A, T, k, n, P, ip0, ip, -1, jb * 32,
-                               (int)min((int64_t)32, m - jb * 32));
+        finish_stream_tile<32>((uint32_t *)lr, A, T, k, n, P, ip0, ip, jb * 32, (int)min((int64_t)32, m - jb * 32));
     }
 }
 
@@ -962,27 +960,21 @@ k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T, const
 typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
 typedef u32x4v u32x4u __attribute__((aligned(4)));  // 16 bytes at a 4-byte offset
 
-// NE (64 or 32) elements of the trailing block, records of panel
-// [ip0, ...): with ip2 < 0 the columns j0 .. j0 + cnt - 1 (cnt <= NE) of row
-// ip; with ip2 >= 0 (NE = 64) the columns j0 .. j0 + cnt - 1 (cnt <= 32) of
-// rows ip (elements 0..31) and ip2 (elements 32..63).  LDS finish_tile_lds(NE)
+// NE (64 or 32) elements of the trailing block, the columns j0 .. j0 + cnt - 1
+// (cnt <= NE) of row ip, records of panel [ip0, ...).  LDS finish_tile_lds(NE)
 // bytes.
 template <int NE>
 __device__ __forceinline__ void finish_stream_tile(uint32_t *lds, MatDev A, uint32_t *__restrict__ T, int64_t k,
-                                                   int64_t n, int P, int64_t ip0, int64_t ip, int64_t ip2,
-                                                   int64_t j0, int cnt) {
+                                                   int64_t n, int P, int64_t ip0, int64_t ip, int64_t j0, int cnt) {
     const MfmaGeom g = mfma_geom(P);
     const int64_t m = n - k - 1;
     const int64_t njb = (m + 31) / 32;
     constexpr int FT = 64, CP = kFinCP, C = kFinC;
     static_assert(C == 32 && (NE == 64 || NE == 32), "a chunk move is 8 lanes x 4 limbs per element, 8 elements per pass");
-    const bool two = ip2 >= 0;
-    // element e2: row erow, column offset ecol; ein: e2 is a column of the block
-    auto erow = [&](int e2) -> int64_t { return two && e2 >= 32 ? ip2 : ip; };
-    auto ecol = [&](int e2) -> int { return two ? (e2 & 31) : e2; };
-    auto eclamp = [&](int e2) -> int { return two ? ((e2 & 32) | min(e2 & 31, cnt - 1)) : min(e2, cnt - 1); };
-    auto eptr = [&](int e2) -> uint32_t * { return el(A, k + 1 + erow(e2), k + 1 + j0 + ecol(e2), P); };
-    if (!two && el(A, k + 1 + ip, k, P)[P - 1] == 0u) return;  // zero multiplier: the row keeps its values
+    const int64_t i = k + 1 + ip;
+    if (el(A, i, k, P)[P - 1] == 0u) return;  // zero multiplier: the row keeps its values
+    // element e2's limbs (e2 < cnt)
+    auto eptr = [&](int e2) -> uint32_t * { return el(A, i, k + 1 + j0 + e2, P); };
     // LDS: element e's chunk at chunk + e CP (limbs 0..C-1, then a spare
     // word); rows of 36 words keep the 16-byte accesses of 8 lanes on
     // distinct banks; lanes past NE use row NE
@@ -990,13 +982,13 @@ __device__ __forceinline__ void finish_stream_tile(uint32_t *lds, MatDev A, uint
     int32_t *eoff = (int32_t *)(lds + (NE + 1) * CP);  // per element (lane): 1 + its offset into a, or -1: not live
     int32_t *sflag = eoff + FT;                  // per element: its result is stored from the chunks
     const int e = mpw::lane();
-    const bool in = e < NE && ecol(e) < cnt;
+    const bool in = e < cnt;
     const int ee = in ? e : 0;
-    const int64_t i = k + 1 + erow(ee), jp = j0 + ecol(ee), j = k + 1 + jp;
+    const int64_t jp = j0 + ee, j = k + 1 + jp;
     uint32_t *am = eptr(ee);
-    uint32_t *raw = T + ((erow(ee) - ip0) * njb + jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
-    // a zero multiplier or u_j = 0 leaves a_ij as it is
-    const bool live = in && el(A, k, j, P)[P - 1] != 0u && el(A, i, k, P)[P - 1] != 0u;
+    uint32_t *trow = T + (ip - ip0) * njb * (int64_t)g.TP * 32;  // the row's records
+    uint32_t *raw = trow + (jp / 32) * (int64_t)g.TP * 32 + (jp % 32);
+    const bool live = in && el(A, k, j, P)[P - 1] != 0u;  // u_j = 0: a_ij is left as it is
     const int pbits = 32 * P;
 
     // ---- operands, alignment, sticky ----
@@ -1064,7 +1056,7 @@ __device__ __forceinline__ void finish_stream_tile(uint32_t *lds, MatDev A, uint
         ymask = subtract ? 0xFFFFFFFFu : 0u;
         cy = subtract ? 1u - st : 0u;
         ylo = a_is_x ? tl(w) : al(w);
-        wlo = rw(ot);
+        wlo = rw(ot + 1 - sh);
         fast = lza_length(P, gsh, w, b, subtract, [&](int q) { return a_is_x ? al(q) : tl(q); },
                           [&](int q) { return a_is_x ? tl(q) : al(q); }, &flen);
     }
@@ -1079,17 +1071,32 @@ __device__ __forceinline__ void finish_stream_tile(uint32_t *lds, MatDev A, uint
     sflag[e] = live && fast ? 1 : 0;
 
     // ---- pass 1: G = X 2^gsh +- (Y >> rs) -+ sticky, limbs 0..P ----
-    const int xlim = P - ot - 1;  // step q uses a real record word (ot + 1 + q) iff q <= xlim
-    auto recw = [&](int q) -> uint32_t { return raw[(int64_t)min(ot + 1 + q, P) * 32]; };
-    uint32_t xprev = 0u, gprev = 0u, gprev2 = 0u;
+    // Limb q of t is bits 31 sh .. of the record words ot + 1 + q and
+    // ot + 2 + q, that is alignbit(w_hi, w_lo, 31 sh) of the words
+    // ot + 2 - sh + q (w_hi) and ot + 1 - sh + q (w_lo): the lane reads its
+    // words from ot + 2 - sh on, so one alignbit serves both cases.  Words
+    // past P count as 0.  The words come through a buffer resource over the
+    // row's records: the lane's offset in a VGPR, the step's in an SGPR, no
+    // address arithmetic per step, and a read past the records returns 0.
+    const int rbase = ot + 2 - sh;
+    const uint32_t sb = sh ? 31u : 0u;
+    const __amdgpu_buffer_rsrc_t trs =
+        __builtin_amdgcn_make_buffer_rsrc((void *)trow, (short)0, (int)(njb * g.TP * 32 * 4), kBufferRsrcWord3);
+    const uint32_t roff = (uint32_t)(((jp / 32) * (int64_t)g.TP * 32 + (jp % 32) + (int64_t)rbase * 32) * 4);
+    auto recw = [&](int q) -> uint32_t { return __builtin_amdgcn_raw_buffer_load_b32(trs, roff, q * 128, 0); };
+    uint32_t xprev = 0u, gprev = 0u, hprev = 0u;
     // one step of the chain: G limb q from record word wr and a limb ar;
-    // returns result limb q - 1
-    auto step = [&](int q, uint32_t wr, uint32_t ar, auto store_g) __attribute__((always_inline)) -> uint32_t {
-        const uint32_t whi = q <= xlim ? wr : 0u;
-        const uint32_t tsh = sh ? __builtin_amdgcn_alignbit(whi, wlo, 31) : whi;
-        const uint32_t tv = q + ot < P ? tsh : 0u;
-        wlo = whi;
-        const uint32_t av = q + oa < P ? ar : 0u;
+    // returns result limb q - 1.  INTERIOR: q + ot + 2 <= P and q + oa < P,
+    // so no operand needs masking.
+    // (wr, wl: the words for steps q and q - 1, i.e. record words rbase + q
+    // and rbase + q - 1)
+    auto step = [&](int q, uint32_t wr, uint32_t wl, uint32_t ar, auto store_g, auto interior)
+                    __attribute__((always_inline)) -> uint32_t {
+        const uint32_t whi = (decltype(interior)::value || rbase + q <= P) ? wr : 0u;
+        const uint32_t wlo = (decltype(interior)::value || rbase + q - 1 <= P) ? wl : 0u;
+        const uint32_t tsh = __builtin_amdgcn_alignbit(whi, wlo, sb);
+        const uint32_t tv = (decltype(interior)::value || q + ot < P) ? tsh : 0u;
+        const uint32_t av = (decltype(interior)::value || q + oa < P) ? ar : 0u;
         const uint32_t xq = a_is_x ? av : tv;
         const uint32_t yhi = a_is_x ? tv : av;
         const uint32_t xg = gsh ? __builtin_amdgcn_alignbit(xq, xprev, 32 - gsh) : xq;
@@ -1099,20 +1106,23 @@ __device__ __forceinline__ void finish_stream_tile(uint32_t *lds, MatDev A, uint
         cy = (uint32_t)(t >> 32);
         xprev = xq;
         ylo = yhi;
-        const uint32_t rhi = f0 ? gq : gprev, rlo = f0 ? gprev : gprev2;
-        const uint32_t r = __builtin_amdgcn_alignbit(rhi, rlo, fbb);
-        // G limb q to record word q (read at step q - ot - 1 or before)
+        // result limb q - 1: G limbs q, q - 1 (fw0 = 0) or q - 1, q - 2
+        const uint32_t hq = f0 ? gq : gprev;
+        const uint32_t r = __builtin_amdgcn_alignbit(hq, hprev, fbb);
+        // G limb q to record word q (read at step q - ot - 2 or before)
         if (decltype(store_g)::value && !fast && q <= P) raw[(int64_t)q * 32] = gq;
-        gprev2 = gprev;
+        hprev = hq;
         gprev = gq;
         return r;
     };
     // Every lane runs the chain, and every chunk, the last included, issues
-    // the same loads (addresses clamped into the element and its record;
-    // what lies past limb P - 1 or word P is never used): one body, no
-    // branch around its loads, so the ring stays in its registers and each
-    // step waits only for its own word.  A lane with no element is "fast"
-    // and stores nothing.
+    // the same loads (addresses clamped into the element; record reads past
+    // the row's records return 0; what lies past limb P - 1 or word P is
+    // never used): no branch around the loads, so the ring stays in its
+    // registers and each step waits only for its own word.  A lane with no
+    // element is "fast" and stores nothing.
+    // Chunks whose steps need no masking on any lane of the wave come first.
+    const int need = __builtin_amdgcn_readfirstlane(mpw::wave_max(live ? max(ot + 2, oa + 1) : 0));
     mpw::wsync();  // eoff and sflag are visible
     // this lane moves limbs 4 sub .. 4 sub + 3 of the chunks of elements
     // 8 s + grp, s < NE / 8
@@ -1135,7 +1145,7 @@ __device__ __forceinline__ void finish_stream_tile(uint32_t *lds, MatDev A, uint
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
             // (columns past the block are not read)
-            v[s] = *(const u32x4u *)(eptr(eclamp(8 * s + grp)) + min(a_at(s, q0), P - 4));
+            v[s] = *(const u32x4u *)(eptr(min(8 * s + grp, cnt - 1)) + min(a_at(s, q0), P - 4));
         }
     };
     // the first chunk's limbs of a, then the record words (the order in
@@ -1145,19 +1155,28 @@ __device__ __forceinline__ void finish_stream_tile(uint32_t *lds, MatDev A, uint
     uint32_t ring[C];
     using no_g = std::integral_constant<bool, false>;
     using with_g = std::integral_constant<bool, true>;
-    if (keep_g) (void)step(0, recw(0), al(oa), with_g{});
-    else (void)step(0, recw(0), al(oa), no_g{});
-    // in step order, as the chunks reload them (the wait for word u then
-    // counts the loads issued after it)
+    using masked = std::integral_constant<bool, false>;
+    using inner = std::integral_constant<bool, true>;
+    // ring slot u holds the word of step q0 + u of the current chunk, slot
+    // C - 1 that of step q0 - 1 until step q0 has read it (as w_lo); after
+    // step q0 + u the slot read as w_lo, (u + C - 1) mod C, takes the word of
+    // step q0 + u + C - 1 (a word is read as w_hi, then as w_lo, then
+    // replaced, so no register is needed twice)
+    if (keep_g) (void)step(0, recw(0), wlo, al(oa), with_g{}, masked{});
+    else (void)step(0, recw(0), wlo, al(oa), no_g{}, masked{});
+    // in the order in which the chunks reload them (the wait for a word
+    // then counts the loads issued after it)
+    ring[C - 1] = recw(0);
+    asm volatile("" ::: "memory");
 #pragma unroll
-    for (int u = 0; u < C; ++u) {
+    for (int u = 0; u < C - 1; ++u) {
         ring[u] = recw(1 + u);
         asm volatile("" ::: "memory");
     }
     // the chunks: a loop of its own for waves that keep G (no branch on it
     // inside the loop, whose registers then stay put)
-    auto chunks = [&](auto store_g) __attribute__((always_inline)) {
-        for (int q0 = 1; q0 <= P; q0 += C) {
+    auto chunk_at = [&](int q0, auto store_g, auto interior) __attribute__((always_inline)) {
+        {
             mpw::wsync();  // the previous chunk's results have left LDS
     #pragma unroll
             for (int s = 0; s < NS; ++s) {
@@ -1187,8 +1206,12 @@ __device__ __forceinline__ void finish_stream_tile(uint32_t *lds, MatDev A, uint
     #pragma unroll
                 for (int z = 0; z < 4; ++z) {
                     const int u = 4 * t4 + z, q = q0 + u;
-                    r4[z] = step(q, ring[u], a4[z], store_g);
-                    ring[u] = recw(q + C);
+                    const int ul = (u + C - 1) % C;
+                    r4[z] = step(q, ring[u], ring[ul], a4[z], store_g, interior);
+                    ring[ul] = recw(q + C - 1);
+                    // one reload per step, in step order: the ring keeps its
+                    // registers across the loop edge, so no wait gathers there
+                    __builtin_amdgcn_sched_barrier(0);
                 }
                 *(u32x4v *)(mine + 4 * t4) = r4;
             }
@@ -1209,6 +1232,11 @@ __device__ __forceinline__ void finish_stream_tile(uint32_t *lds, MatDev A, uint
                 }
             }
         }
+    };
+    auto chunks = [&](auto store_g) __attribute__((always_inline)) {
+        int q0 = 1;
+        for (; q0 + C - 1 + need <= P; q0 += C) chunk_at(q0, store_g, inner{});
+        for (; q0 <= P; q0 += C) chunk_at(q0, store_g, masked{});
     };
     if (keep_g) chunks(with_g{});
     else chunks(no_g{});
@@ -1253,7 +1281,7 @@ __device__ __forceinline__ void finish_stream_body(uint32_t *lds, MatDev A, uint
     const int64_t ntile = (m + 63) / 64;
     const int64_t ip = ip0 + bx / ntile, j0 = (bx % ntile) * 64;
     if (bx / ntile >= rows || ip >= m) return;
-    finish_stream_tile<64>(lds, A, T, k, n, P, ip0, ip, -1, j0, (int)min((int64_t)64, m - j0));
+    finish_stream_tile<64>(lds, A, T, k, n, P, ip0, ip, j0, (int)min((int64_t)64, m - j0));
 }
 
 // STREAM must equal finish_streams(P); the two forms are separate kernels so
