@@ -212,13 +212,22 @@ def test_valu_large_limbs(N, P):
     check_against_oracle(A, "valu", f"valu shape N={N} P={P}")
 
 
-@pytest.mark.parametrize("case", ["wide_exponents", "cancellation", "zero_entries", "zero_pivot", "patterns"])
-def test_streaming_finish_cases(case):
+@pytest.mark.parametrize("setting", [0, 1])
+@pytest.mark.parametrize("case", ["wide_exponents", "limb_shifts", "cancellation", "zero_entries", "zero_pivot",
+                                  "patterns"])
+def test_streaming_finish_cases(case, setting):
     """P > 256 takes the streaming finish (chunked a_ij, intermediate kept in
-    the record buffer): the sticky, cancellation, 0 - t and zero-pivot cases."""
+    the record buffer): the sticky, cancellation, 0 - t and zero-pivot cases,
+    and operands a few limbs apart (so that the last chunks of a wave need the
+    range checks the others skip), with the finish inside the update launch
+    (setting 0) and in a launch of its own (setting 1)."""
+    from paper_1308_1536_amd import binding
     P, N = 264, 22
     if case == "wide_exponents":
         A = inputs.random_mantissas((N, N), P, 91, emin=-30000, emax=30000)
+    elif case == "limb_shifts":
+        P, N = 520, 40
+        A = inputs.random_mantissas((N, N), P, 97, emin=-200, emax=200)
     elif case == "cancellation":
         base = inputs.random_mantissas((1, N), P, 92)
         A = inputs.random_mantissas((N, N), P, 93)
@@ -255,7 +264,11 @@ def test_streaming_finish_cases(case):
         A, L, U = inputs.triangular_product(12, P, 8)
         U[6, 6] = 0
         A = inputs.from_values((L.astype(object) @ U.astype(object)), P)
-    check_against_oracle(A, "mfma", f"streaming finish {case}")
+    binding.set_overlap(setting)
+    try:
+        check_against_oracle(A, "mfma", f"streaming finish {case} (overlap setting {setting})")
+    finally:
+        binding.set_overlap(0)
 
 
 @pytest.mark.parametrize("path", ["valu", "mfma"])
