@@ -294,6 +294,23 @@ def full_size_checks(cfg, name, A_host, LU_dev, D_host, c_host, size, steps_done
     return out
 
 
+def minors_invariant(lastcol, D_host, c_host, N: int, P: int) -> dict:
+    """sum_i c_i a_iN = det(A) = D_N, exactly, relative to sum_i |c_i a_iN| in
+    bits (lastcol: the input's last column as an N x 1 host array)."""
+    import math
+    terms = []
+    for i in range(N):
+        mc, ec = _mp_int(c_host.limbs[i], c_host.exp[i], c_host.sign[i], P)
+        ma, ea = _mp_int(lastcol.limbs[i, 0], lastcol.exp[i, 0], lastcol.sign[i, 0], P)
+        terms.append((mc * ma, ec + ea))
+    md, ed = _mp_int(D_host.limbs[N - 1], D_host.exp[N - 1], D_host.sign[N - 1], P)
+    emin = min([e for _, e in terms] + [ed])
+    S = sum(v << (e - emin) for v, e in terms)
+    absS = sum(abs(v) << (e - emin) for v, e in terms)
+    diff = abs(S - (md << (ed - emin)))
+    return {"minors_invariant_rel_err_bits": (math.log2(diff) - math.log2(absS)) if diff else float("-inf")}
+
+
 def cpu_baseline(A, gpu_D, budget_s: float):
     """Time the oracle (factor + minors) on the leading K x K block of A, K
     grown until one run takes at least a third of the budget (or K = N)."""
@@ -327,8 +344,10 @@ def bench_elimination_steps(args):
     """--factor-steps K: time elimination steps W .. W+K-1 of the workload's
     first matrix in place (mp_det_factor_steps; the first W steps run untimed,
     with the workspace allocation), for matrices too large to repeat whole
-    steps of the path on (configuration 5: 155 GB, about 23 minutes a
-    factorisation).  The JSON line is marked as a partial run: `value` is the
+    steps of the path on (configuration 5: 155 GB, about 13 minutes a
+    factorisation).  With --warmup 0 and K = N the run is the whole
+    factorisation, then the minors: its time is the time to solution and the
+    minors' invariant is checked exactly.  The JSON line is marked as a partial run: `value` is the
     algorithmic limb-MACs of the K timed elimination steps over their time,
     and `extrapolated_factor_s` scales each kernel's time to the whole
     factorisation by its work (trailing-block kernels by the sum of m^2, the
@@ -344,6 +363,10 @@ def bench_elimination_steps(args):
     K = max(1, min(args.factor_steps, N - W))
     lead = min(N, 64)
     Alead = MpArray(Ah.limbs[:lead, :lead].copy(), Ah.exp[:lead, :lead].copy(), Ah.sign[:lead, :lead].copy())
+    whole = W == 0 and K == N  # the whole factorisation: the minors and their invariant follow
+    # the last column, for the minors' invariant sum_i c_i a_iN = det (the
+    # factorisation overwrites A on the device)
+    lastcol = MpArray(Ah.limbs[:, N - 1:].copy(), Ah.exp[:, N - 1:].copy(), Ah.sign[:, N - 1:].copy())
     print(f"[bench] {desc}: uploading", file=sys.stderr, flush=True)
 
     import torch
@@ -369,6 +392,11 @@ def bench_elimination_steps(args):
         binding.factor_steps(A, D, info, k0, min(W + K, k0 + chunk), path)
         torch.cuda.synchronize()
         print(f"[bench] elimination steps {k0}..{min(W + K, k0 + chunk) - 1} done", file=sys.stderr, flush=True)
+    c = None
+    if whole:
+        c = binding.minors(A, D, info)
+        torch.cuda.synchronize()
+        print("[bench] minors done", file=sys.stderr, flush=True)
     secs = time.perf_counter() - t0
     prof = binding.profile_end()
     if int(info.item()) != 0:
@@ -404,17 +432,24 @@ def bench_elimination_steps(args):
             roof = {"bound": "alu", "achieved": ach / 1e12, "peak": PEAK_VALU_MAC32 / 1e12, "unit": "Tmac32/s",
                     "frac": ach / PEAK_VALU_MAC32, "kernel": "k_update_valu", "traffic": None,
                     "avg_launch_ms": kms / kn, "launches": kn}
+    what = (f"{desc} -- the whole factorisation and the minors, one pass" if whole else
+            f"{desc} -- elimination steps {W}..{W + K - 1} of {N - 1} only (partial run)")
     out = {"metric": METRIC, "value": macs / secs, "unit": "limb-MAC/s", "n_gpus": 1, "steps": 1, "warmup": W,
            "ms_per_step": secs * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
            "dtype": "i8" if path == "mfma" else "u32", "data": "synthetic",
-           "config": {"workload": f"{desc} -- elimination steps {W}..{W + K - 1} of {N - 1} only (partial run)",
-                      "N": N, "bits": 32 * P, "matrices": 1, "path": path, "partial": True,
-                      "elimination_steps_timed": K, "limb_macs_timed": macs},
-           "extrapolated_factor_s": ext, "roofline": roof,
-           "kernel_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]}}
+           "config": {"workload": what, "N": N, "bits": 32 * P, "matrices": 1, "path": path,
+                      "partial": not whole, "elimination_steps_timed": K, "limb_macs_timed": macs},
+           "roofline": roof, "kernel_ms": {k: round(v[0], 3) for k, v in prof.items() if v[1]}}
+    if whole:
+        out["time_to_solution_s"] = secs
+    else:
+        out["extrapolated_factor_s"] = ext
     if not args.no_checks:
-        out["full_size_checks"] = {name: full_size_checks(args.config, name, Alead_full, A, None, None, 0,
-                                                          steps_done=W + K)}
+        chk = full_size_checks(args.config, name, Alead_full, A, None, None, 0, steps_done=W + K)
+        if whole:
+            # the minors' invariant, exactly: last column against c and D_N
+            chk.update(minors_invariant(lastcol, D.row(0), c.row(0), N, P))
+        out["full_size_checks"] = {name: chk}
     if not args.no_cpu_baseline:
         Dh = D.row(0)
         done = W + K
