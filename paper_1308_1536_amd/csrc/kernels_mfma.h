@@ -943,7 +943,7 @@ k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T, const
 // word rw[P + 2] rather than to info, which the launch's other workgroups are
 // reading; step k+1's divide kernel moves it into info.  rw == nullptr: no
 // look-ahead.
-// The same finish with 64 elements per wave for any P: lane e carries the
+// The same finish for any P, up to 64 elements per wave: lane e carries the
 // chain of element j0 + e, and the elements' limbs move between HBM and LDS in
 // chunks of 32 limbs (8 lanes move one element's chunk as four 16-byte
 // pieces, so 8 elements share one load or store instruction and every line
@@ -952,11 +952,10 @@ k_update_mfma(MatDev A, const uint8_t *Lr, const uint8_t *Ub, uint32_t *T, const
 // consumes and, in the same LDS cells, the result limbs 32c .. 32c + 31 it
 // produces.  The next chunk's limbs of a are loaded into registers while a
 // chunk is computed, and the record words come from a ring of 32 registers
-// filled 32 steps ahead (lanes of one 32-column block read one line), so the
-// chain never waits for HBM.  No limb of a is stored before its load has
-// been consumed.  An element whose result length is not known from the top
-// limbs keeps G in its record (word q written after every read of it) and is
-// normalised by a second pass.
+// filled 31 steps ahead (lanes of one 32-column block read one line).  No
+// limb of a is stored before its load has been consumed.  An element whose
+// result length is not known from the top limbs keeps G in its record (word
+// q written after every read of it) and is normalised by a second pass.
 typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
 typedef u32x4v u32x4u __attribute__((aligned(4)));  // 16 bytes at a 4-byte offset
 
