@@ -424,7 +424,8 @@ def bench_elimination_steps(args):
             ach = macs / (kms / 1e3)
             roof = {"bound": "mfma", "achieved": 2 * ach / 1e12, "peak": PEAK_INT8_MFMA_TOPS / 1e12,
                     "unit": "TOP/s", "frac": ach / PEAK_INT8_MAC, "kernel": f"k_update_mfma<{mfma_copies(P)}>",
-                    "measured_peak": 2 * mp / 1e12, "frac_of_measured_peak": ach / mp, "traffic": None,
+                    "measured_peak": 2 * mp / 1e12, "frac_of_measured_peak": ach / mp,
+                    "measured_clock_ghz": binding.measure_peak("mfma_clock") / 1e9, "traffic": None,
                     "avg_launch_ms": kms / kn, "launches": kn}
             roof.update(issued("mfma", P, roof["frac"]))
         else:
@@ -778,8 +779,8 @@ def bench_segmented(args):
         kern = f"k_update_mfma<{mfma_copies(P)}>" + (" with the finish" if fused else "")
         roof = {"bound": "mfma", "achieved": 2 * ach / 1e12, "peak": PEAK_INT8_MFMA_TOPS / 1e12, "unit": "TOP/s",
                 "frac": ach / PEAK_INT8_MAC, "kernel": kern, "measured_peak": 2 * mp / 1e12,
-                "frac_of_measured_peak": ach / mp, "traffic": traffic(kern), "avg_launch_ms": kms / kn,
-                "launches": kn}
+                "frac_of_measured_peak": ach / mp, "measured_clock_ghz": binding.measure_peak("mfma_clock") / 1e9,
+                "traffic": traffic(kern), "avg_launch_ms": kms / kn, "launches": kn}
         roof.update(issued("mfma", P, roof["frac"]))
     elif prof["update_valu"][1]:
         kms, kn = prof["update_valu"]

@@ -439,10 +439,14 @@ int mp_to_f64_scaled(mpdet_handle *h, mpdet_mat x, const int64_t *shift_dev, dou
  *   MPDET_PEAK_MAD64    32x32->64-bit multiply-adds per second (v_mad_u64_u32,
  *                       the VALU path's limb product);
  *   MPDET_PEAK_MFMA_I8  int8 multiply-adds per second (v_mfma_i32_32x32x32_i8,
- *                       the MFMA path's limb product).
+ *                       the MFMA path's limb product);
+ *   MPDET_PEAK_MFMA_CLOCK  the shader clock in Hz while that probe runs (its
+ *                       first wave's clock counter against the constant
+ *                       100 MHz real-time counter), the clock that the
+ *                       published peak's 2.4 GHz is to be compared with.
  * The probe allocates and frees a small output buffer.
  */
-enum { MPDET_PEAK_MAD64 = 0, MPDET_PEAK_MFMA_I8 = 1 };
+enum { MPDET_PEAK_MAD64 = 0, MPDET_PEAK_MFMA_I8 = 1, MPDET_PEAK_MFMA_CLOCK = 2 };
 int mpdet_measure_peak(mpdet_handle *h, int kind, double *per_second);
 
 /*

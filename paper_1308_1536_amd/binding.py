@@ -526,12 +526,13 @@ def to_f64_scaled(x: DeviceMp, shift, stream=None):
     return val
 
 
-PEAK_KINDS = {"mad64": 0, "mfma_i8": 1}
+PEAK_KINDS = {"mad64": 0, "mfma_i8": 1, "mfma_clock": 2}
 
 
 def measure_peak(kind: str, device: int = 0) -> float:
     """mpdet_measure_peak: measured multiply-adds per second of one unit
-    ("mad64": 32x32->64 VALU, "mfma_i8": int8 MFMA)."""
+    ("mad64": 32x32->64 VALU, "mfma_i8": int8 MFMA), or the shader clock in
+    Hz while the MFMA probe runs ("mfma_clock")."""
     out = ctypes.c_double()
     _check("mpdet_measure_peak", lib().mpdet_measure_peak(handle(device).ptr, PEAK_KINDS[kind], ctypes.byref(out)))
     return out.value

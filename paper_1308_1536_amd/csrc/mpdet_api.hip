@@ -631,7 +631,8 @@ int mpdet_destroy(mpdet_handle *h) {
 }
 
 int mpdet_measure_peak(mpdet_handle *h, int kind, double *per_second) {
-    if (!h || !per_second || (kind != MPDET_PEAK_MAD64 && kind != MPDET_PEAK_MFMA_I8)) return MPDET_EINVAL;
+    if (!h || !per_second || (kind != MPDET_PEAK_MAD64 && kind != MPDET_PEAK_MFMA_I8 && kind != MPDET_PEAK_MFMA_CLOCK))
+        return MPDET_EINVAL;
     DeviceGuard g(h->device);
     if (!g.ok) return MPDET_EHIP;
     int cus = 0;
@@ -639,30 +640,40 @@ int mpdet_measure_peak(mpdet_handle *h, int kind, double *per_second) {
         return MPDET_EHIP;
     const unsigned blocks = (unsigned)cus * 8u, threads = 256u;
     uint32_t *out = nullptr;
-    if (hipMalloc(&out, (size_t)blocks * threads * 4u) != hipSuccess) {
+    // the checksum words, then 4 clock stamps (8-byte aligned)
+    const size_t out_bytes = (size_t)blocks * threads * 4u;
+    if (hipMalloc(&out, out_bytes + 32u) != hipSuccess) {
         (void)hipGetLastError();
         return MPDET_ENOMEM;
     }
+    uint64_t *clk = (uint64_t *)((char *)out + out_bytes);
     hipEvent_t e0 = nullptr, e1 = nullptr;
     int rc = MPDET_OK;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) rc = MPDET_EHIP;
     const uint32_t iters = kind == MPDET_PEAK_MAD64 ? 8192u : 512u;
+    const bool clock = kind == MPDET_PEAK_MFMA_CLOCK;
     float ms = 0.f;
     for (int pass = 0; pass < 2 && rc == MPDET_OK; ++pass) {  // pass 0 warms up
         if (hipEventRecord(e0, nullptr) != hipSuccess) rc = MPDET_EHIP;
         if (kind == MPDET_PEAK_MAD64)
             hipLaunchKernelGGL(mpk::k_peak_mad64, dim3(blocks), dim3(threads), 0, nullptr, iters, 12345u, out);
         else
-            hipLaunchKernelGGL(mpk::k_peak_mfma_i8, dim3(blocks), dim3(threads), 0, nullptr, iters, 12345u, out);
+            hipLaunchKernelGGL(mpk::k_peak_mfma_i8, dim3(blocks), dim3(threads), 0, nullptr, iters, 12345u, out,
+                               clock ? clk : nullptr);
         if (rc == MPDET_OK) rc = last_launch();
         if (rc == MPDET_OK && hipEventRecord(e1, nullptr) != hipSuccess) rc = MPDET_EHIP;
         if (rc == MPDET_OK && hipEventSynchronize(e1) != hipSuccess) rc = MPDET_EHIP;
         if (rc == MPDET_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = MPDET_EHIP;
     }
-    if (rc == MPDET_OK) {
+    if (rc == MPDET_OK && clock) {
+        uint64_t c[4] = {0, 0, 0, 0};
+        if (hipMemcpy(c, clk, sizeof c, hipMemcpyDeviceToHost) != hipSuccess) rc = MPDET_EHIP;
+        // shader clocks over 100 MHz real-time ticks
+        *per_second = (rc == MPDET_OK && c[3] > c[2]) ? (double)(c[1] - c[0]) / (double)(c[3] - c[2]) * 1e8 : 0.0;
+    } else if (rc == MPDET_OK) {
         const double threads_total = (double)blocks * threads;
         const double ops = kind == MPDET_PEAK_MAD64 ? threads_total * 8.0 * iters
-                                                    : threads_total / 64.0 * 4.0 * iters * 32768.0;
+                                                    : threads_total / 64.0 * 8.0 * iters * 32768.0;
         *per_second = ms > 0.f ? ops / (ms * 1e-3) : 0.0;
     }
     if (e0) (void)hipEventDestroy(e0);
