@@ -75,3 +75,53 @@ def test_config4_backward_sample_against_oracle(batch, factored):
         adjT = binding.adjugate(mats[b], Ds[b], torch.tensor(info[b:b + 1], device="cuda"))
         torch.cuda.synchronize()
         assert digest(adjT.to_host()) == want, f"adj(A)^T of matrix {b}"
+
+
+def test_config4_persistent_launch_against_oracle(batch):
+    """The whole batch in one persistent launch (the task queue of Sec. 4.1)
+    gives the oracle's stored bits for every matrix, as the lockstep launches
+    do."""
+    import torch
+    from paper_1308_1536_amd import binding
+    g, hosts = batch
+    say(f"[config4] one persistent launch over {len(hosts)} matrices")
+    mats = [binding.DeviceMp.from_host(h) for h in hosts]
+    Ds, cs, info = binding.batched(mats, "valu", schedule="persistent")
+    torch.cuda.synchronize()
+    info = info.cpu().numpy()
+    bad = []
+    for b, want in enumerate(g["matrices"]):
+        if int(info[b]) != want["info"]:
+            bad.append((b, "info"))
+            continue
+        if entry_hashes(Ds[b].row(0)) != want["D"]:
+            bad.append((b, "D"))
+        if want["c"] is not None and entry_hashes(cs[b].row(0)) != want["c"]:
+            bad.append((b, "c"))
+        if digest(mats[b].to_host()) != want["LU_sha256"]:
+            bad.append((b, "LU"))
+    assert not bad, f"{len(bad)} mismatches, first {bad[:6]}"
+
+
+def test_config4_batched_backward_sample_against_oracle(batch, factored):
+    """The batched backward (one persistent launch over every matrix) on the
+    whole batch; the stored sample of adj(A)^T digests must match."""
+    import torch
+    from paper_1308_1536_amd import binding
+    g, _ = batch
+    mats, Ds, cs, info = factored
+    say(f"[config4] batched backward over {len(mats)} matrices")
+    adjTs, status = binding.adjugate_batched(mats, Ds, torch.tensor(info, device="cuda"))
+    torch.cuda.synchronize()
+    st = status.cpu().numpy()
+    # 0 where the factors are complete, else the factorisation's info; never
+    # an expired wait (-2)
+    assert all(int(st[b]) == (0 if int(info[b]) in (0, mats[b].rows) else int(info[b])) for b in range(len(mats)))
+    checked = 0
+    for b in g["adjugate_sample"]:
+        want = g["matrices"][b].get("adjT_sha256")
+        if want is None:
+            continue
+        assert digest(adjTs[b].to_host()) == want, f"adj(A)^T of matrix {b}"
+        checked += 1
+    assert checked > 0
