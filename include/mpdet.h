@@ -37,7 +37,11 @@
  *   k>0 the pivot of step k (1-based) is exactly zero: D_k..D_n are written as
  *       zero and the matrix holds the state after k-1 elimination steps;
  *   -1  a pivot or a leading determinant has |exp| > 2^62: D_k..D_n are zero
- *       and the matrix contents are unspecified.
+ *       and the matrix contents are unspecified;
+ *   -2  a bounded wait inside a launch ran out (an internal failure: waves of
+ *       one workgroup lost step with each other, or a persistent launch's
+ *       dependency never completed); the outputs are unspecified.  No correct
+ *       run waits long enough for this (the bounds are seconds).
  * One handle per host thread; calls on one handle must not overlap in time on
  * different streams (the handle's workspace is shared).
  */
@@ -266,11 +270,12 @@ int mpdet_set_overlap(mpdet_handle *h, int32_t panels);
  * s_i <- RZ(s_i - RZ(x_j l_ji)) for i < j (x_n = 1, x_{j-1} = s_{j-1}), then
  * c_i = RZ(D_{n-1} x_i), c_n = D_{n-1} (n = 1: c_1 = 1).  sum_i c_i a_in = det.
  *   LU    n x n factor output (read only);  D  1 x n from mp_det_factor;
- *   c     1 x n output;  info_dev  the factorisation's info: when it is not 0,
- *         c is written as all zeros.
+ *   c     1 x n output;  info_dev  the factorisation's info: when it is not 0
+ *         (or n), c is written as all zeros; set to -2 (see above) if a wait
+ *         inside the sweeps runs out.
  */
 int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c,
-                  const int32_t *info_dev, void *stream);
+                  int32_t *info_dev, void *stream);
 
 /*
  * mp_det_batched -- mp_det_factor (and, with MPDET_WANT_MINORS, mp_det_minors)

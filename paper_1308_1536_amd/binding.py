@@ -58,6 +58,11 @@ def lib() -> ctypes.CDLL:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with "
                                "`python -m paper_1308_1536_amd.build` (no CPU fallback exists)")
+        # torch's own HIP runtime (it ships one) must be loaded before the
+        # library: the library then binds to that runtime instead of loading
+        # the system's, and torch and the library share devices, streams and
+        # memory (two runtimes in one process leave one of them without a device)
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         vp, i32, i64 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64
         L.mpdet_create.argtypes = [ctypes.POINTER(vp), ctypes.c_int]

@@ -49,7 +49,7 @@ __device__ __forceinline__ mpw::Hdr load_y(uint32_t *ypad, const uint32_t *src, 
     }
     mpw::gload(ypad + MP_YPAD, src, P);
     mpw::wsync();
-    bool z = ypad[MP_YPAD + P - 1] == 0u;
+    const bool z = __builtin_amdgcn_readfirstlane(ypad[MP_YPAD + P - 1]) == 0u;
     return z ? mpw::zero_hdr() : mpw::Hdr{e, s, false};
 }
 
@@ -73,18 +73,31 @@ __host__ __device__ inline size_t pivot_lds_bytes(int P) {
     return a > b ? a : b;
 }
 
+// Waves of k_pivot_recip, k_divide and k_minors_sweep (a team, see
+// wave_mp.h): one per round
+// of 64 windows of a P x P product, at most 4 (one below 224 limbs or so).
+__host__ __device__ inline int team_waves(int P) {
+    const int cols = (64 * P + 27) / 28, windows = (cols + 7) / 8, rounds = (windows + 63) / 64;
+    return rounds < 1 ? 1 : (rounds > 4 ? 4 : rounds);
+}
+
+// a wave-uniform copy of a value every lane read from the same address
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
 // info_out receives the zero-pivot / overflow code (info itself, or a pending
 // word when this runs inside the previous step's launch, see finish_body)
+// tm: the team forming the products with this wave (nullptr: it alone)
 __device__ __forceinline__ void pivot_recip_body(uint32_t *lds_raw, MatDev A, MatDev D, const int32_t *info,
                                                  int32_t *info_out, uint32_t *rw, int64_t k, int64_t n, int P,
-                                                 int role) {
-    if (*info != 0) return;
+                                                 int role, mpw::TeamCtl *tm = nullptr) {
+    if (uni((uint32_t)*info) != 0u) return;
     const uint32_t *pm = el(A, k, k, P);
-    const bool piv_zero = pm[P - 1] == 0u;
+    const bool piv_zero = uni(pm[P - 1]) == 0u;
     const int64_t pe = ex(A, k, k);
     const int32_t ps = sg(A, k, k);
     if (role == 0) {
         Lds L(lds_raw, P);
+        L.sc.team = tm;
         bool bad = false;
         int32_t code = 0;
         mpw::Hdr hd{0, 0, true};
@@ -116,6 +129,7 @@ __device__ __forceinline__ void pivot_recip_body(uint32_t *lds_raw, MatDev A, Ma
     }
     if (piv_zero || n - k - 1 <= 0) return;
     mpw::DivBufs B = mpw::div_bufs(lds_raw, P);
+    B.team = tm;
     mpw::gload(B.v, pm, P);
     mpw::wsync();
     const bool ok = mpw::recip(B, P);
@@ -127,22 +141,23 @@ __device__ __forceinline__ void pivot_recip_body(uint32_t *lds_raw, MatDev A, Ma
 // examined inside the previous step's launch: a nonzero code stops the step,
 // and block 0 moves it into info for the launches that follow.
 __device__ __forceinline__ void divide_body(uint32_t *lds_raw, MatDev A, const uint32_t *rw, int32_t *info, int64_t k,
-                                            int64_t n, int P, int64_t blk) {
-    const int32_t pend = (int32_t)rw[P + 2];
-    if (*info != 0 || pend != 0) {
+                                            int64_t n, int P, int64_t blk, mpw::TeamCtl *tm = nullptr) {
+    const int32_t pend = (int32_t)uni(rw[P + 2]);
+    if (uni((uint32_t)*info) != 0u || pend != 0) {
         if (blk == 0 && mpw::lane() == 0 && *info == 0) *info = pend;
         return;
     }
     const uint32_t *pm = el(A, k, k, P);
-    if (pm[P - 1] == 0u) return;
+    if (uni(pm[P - 1]) == 0u) return;
     const int64_t i = k + 1 + blk;
     uint32_t *am = el(A, i, k, P);
     mpw::DivBufs B = mpw::div_bufs(lds_raw, P);
+    B.team = tm;
     mpw::Hdr ha = mpw::load(B.a, am, ex(A, i, k), sg(A, i, k), P);
     mpw::Hdr hp = mpw::load(B.v, pm, ex(A, k, k), sg(A, k, k), P);
     mpw::Hdr hq;
     bool done = false;
-    if (rw[P + 1] != 0u) done = mpw::div_by_recip(B.t3, hq, ha, hp, rw, B, P);
+    if (uni(rw[P + 1]) != 0u) done = mpw::div_by_recip(B.t3, hq, ha, hp, rw, B, P);
     if (!done) {
         // long division: U = prod (2P+2), LO = t0, HI = t1, Q = t2, out = t3
         hq = mpw::div(B.t3, B.a, ha, B.v, hp, B.prod, B.t0, B.t1, B.t2, P);
@@ -197,12 +212,14 @@ __global__ void k_minors_init(MatDev c, int64_t n, int P) {
 
 // sweep j: s_i = RZ_p(s_i - RZ_p(x_j l_ji)), i < j; x_{n-1} = 1, x_j = s_j otherwise
 // (nothing unless the factors are complete; k_minors_init wrote zeros)
+// (tm: the team forming the product with this wave; nullptr: it alone)
 __device__ __forceinline__ void minors_sweep_body(uint32_t *lds_raw, MatDev LU, MatDev c, const int32_t *info, int64_t j,
-                                  int64_t n, int P, int64_t i) {
-    if (!factors_complete(*info, n)) return;
+                                  int64_t n, int P, int64_t i, mpw::TeamCtl *tm = nullptr) {
+    if (!factors_complete((int32_t)uni((uint32_t)*info), n)) return;
     Lds L(lds_raw, P);
+    L.sc.team = tm;
     const uint32_t *lm = el(LU, j, i, P);
-    if (lm[P - 1] == 0u) return;
+    if (uni(lm[P - 1]) == 0u) return;
     mpw::Hdr ht;
     if (j == n - 1) {
         ht = mpw::load(L.sc.t3, lm, ex(LU, j, i), sg(LU, j, i), P);  // 1 * l_ji, exact
@@ -255,10 +272,24 @@ __device__ __forceinline__ int64_t flat_block() {
     return (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
 }
 
-__global__ void __launch_bounds__(64) k_pivot_recip(MatDev A, MatDev D, int32_t *info, uint32_t *rw, int64_t k,
-                                                    int64_t n, int P) {
+// A wave that runs out of a team wait (never in a correct run) stops the
+// factorisation with info = -2 instead of hanging the launch.
+__device__ __forceinline__ void team_report(mpw::TeamCtl *tm, int32_t *info) {
+    if (!mpw::team_close(tm) && mpw::lane() == 0) atomicCAS(info, 0, -2);
+}
+
+// blockDim.x = 64 team_waves(P) (or 64: one wave)
+__global__ void __launch_bounds__(256) k_pivot_recip(MatDev A, MatDev D, int32_t *info, uint32_t *rw, int64_t k,
+                                                     int64_t n, int P) {
     extern __shared__ uint32_t lds_raw[];
-    pivot_recip_body(lds_raw, A, D, info, info, rw, k, n, P, (int)blockIdx.x);
+    __shared__ mpw::TeamCtl ctl;
+    mpw::team_open(&ctl);
+    if (mpw::team_wave() != 0) {
+        mpw::team_serve(&ctl);
+        return;
+    }
+    pivot_recip_body(lds_raw, A, D, info, info, rw, k, n, P, (int)blockIdx.x, &ctl);
+    team_report(&ctl, info);
 }
 
 // clear the pending pivot code (rw[P + 2]) before a factorisation, and move a
@@ -270,18 +301,33 @@ __global__ void k_pend_promote(int32_t *info, const uint32_t *rw, int P) {
     if (threadIdx.x == 0 && blockIdx.x == 0 && *info == 0) *info = (int32_t)rw[P + 2];
 }
 
-__global__ void __launch_bounds__(64) k_divide(MatDev A, const uint32_t *rw, int32_t *info, int64_t k,
-                                               int64_t n, int P) {
+// blockDim.x = 64 team_waves(P) (or 64: one wave)
+__global__ void __launch_bounds__(256) k_divide(MatDev A, const uint32_t *rw, int32_t *info, int64_t k,
+                                                int64_t n, int P) {
     extern __shared__ uint32_t lds_raw[];
-    divide_body(lds_raw, A, rw, info, k, n, P, flat_block());
+    __shared__ mpw::TeamCtl ctl;
+    mpw::team_open(&ctl);
+    if (mpw::team_wave() != 0) {
+        mpw::team_serve(&ctl);
+        return;
+    }
+    divide_body(lds_raw, A, rw, info, k, n, P, flat_block(), &ctl);
+    team_report(&ctl, info);
 }
 
 // multipliers of rows row0 .. n-1 only (growing a factorisation: the rows
-// added after the leading block was factored)
-__global__ void __launch_bounds__(64) k_divide_from(MatDev A, const uint32_t *rw, int32_t *info, int64_t k,
-                                                    int64_t n, int P, int64_t row0) {
+// added after the leading block was factored); blockDim.x as for k_divide
+__global__ void __launch_bounds__(256) k_divide_from(MatDev A, const uint32_t *rw, int32_t *info, int64_t k,
+                                                     int64_t n, int P, int64_t row0) {
     extern __shared__ uint32_t lds_raw[];
-    divide_body(lds_raw, A, rw, info, k, n, P, row0 - k - 1 + (int64_t)blockIdx.x);
+    __shared__ mpw::TeamCtl ctl;
+    mpw::team_open(&ctl);
+    if (mpw::team_wave() != 0) {
+        mpw::team_serve(&ctl);
+        return;
+    }
+    divide_body(lds_raw, A, rw, info, k, n, P, row0 - k - 1 + (int64_t)blockIdx.x, &ctl);
+    team_report(&ctl, info);
 }
 
 __global__ void __launch_bounds__(64) k_update_valu(MatDev A, const int32_t *info, int64_t k, int64_t n, int P) {
@@ -289,10 +335,18 @@ __global__ void __launch_bounds__(64) k_update_valu(MatDev A, const int32_t *inf
     update_valu_body(lds_raw, A, info, k, n, P, flat_block());
 }
 
-__global__ void __launch_bounds__(64) k_minors_sweep(MatDev LU, MatDev c, const int32_t *info, int64_t j,
-                                                     int64_t n, int P) {
+// blockDim.x = 64 team_waves(P) (or 64: one wave)
+__global__ void __launch_bounds__(256) k_minors_sweep(MatDev LU, MatDev c, int32_t *info, int64_t j, int64_t n,
+                                                      int P) {
     extern __shared__ uint32_t lds_raw[];
-    minors_sweep_body(lds_raw, LU, c, info, j, n, P, flat_block());
+    __shared__ mpw::TeamCtl ctl;
+    mpw::team_open(&ctl);
+    if (mpw::team_wave() != 0) {
+        mpw::team_serve(&ctl);
+        return;
+    }
+    minors_sweep_body(lds_raw, LU, c, info, j, n, P, flat_block(), &ctl);
+    team_report(&ctl, info);
 }
 
 __global__ void __launch_bounds__(64) k_minors_final(MatDev D, MatDev c, const int32_t *info, int64_t n, int P) {

@@ -227,7 +227,8 @@ int pivot_step(mpdet_handle *h, const mpk::MatDev &a, const mpk::MatDev &d, int3
     if (!pivot_done) {
         {
             Prof pr(h, s, K_PIVOT_DIVIDE);
-            hipLaunchKernelGGL(mpk::k_pivot_recip, dim3(2), dim3(64), lds, s, a, d, info, rw, k, n, P);
+            hipLaunchKernelGGL(mpk::k_pivot_recip, dim3(2), dim3(64 * mpk::team_waves(P)), lds, s, a, d, info, rw,
+                               k, n, P);
         }
         if ((rc = last_launch())) return rc;
     }
@@ -235,8 +236,8 @@ int pivot_step(mpdet_handle *h, const mpk::MatDev &a, const mpk::MatDev &d, int3
     if (m <= 0) return MPDET_OK;
     {
         Prof pr(h, s, K_DIVIDE);
-        hipLaunchKernelGGL(mpk::k_divide, dim3((unsigned)m), dim3(64), lds, s, a, (const uint32_t *)rw, info, k, n,
-                           P);
+        hipLaunchKernelGGL(mpk::k_divide, dim3((unsigned)m), dim3(64 * mpk::team_waves(P)), lds, s, a,
+                           (const uint32_t *)rw, info, k, n, P);
     }
     return last_launch();
 }
@@ -822,9 +823,10 @@ int mp_det_extend(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, 
         };
         for (int64_t k = 0; k < n_old; ++k) {
             // the pivot's reciprocal (D_k is written again with the same bits)
-            hipLaunchKernelGGL(mpk::k_pivot_recip, dim3(2), dim3(64), lds, s, a, d, info_dev, rw, k, N, P);
+            hipLaunchKernelGGL(mpk::k_pivot_recip, dim3(2), dim3(64 * mpk::team_waves(P)), lds, s, a, d, info_dev,
+                               rw, k, N, P);
             if ((rc = last_launch())) return rc;
-            hipLaunchKernelGGL(mpk::k_divide_from, dim3((unsigned)(N - n_old)), dim3(64), lds, s, a,
+            hipLaunchKernelGGL(mpk::k_divide_from, dim3((unsigned)(N - n_old)), dim3(64 * mpk::team_waves(P)), lds, s, a,
                                (const uint32_t *)rw, info_dev, k, N, P, n_old);
             if ((rc = last_launch())) return rc;
             // (a) rows n_old.. x columns k+1..: x = column k below, y = row k
@@ -969,8 +971,7 @@ int mpdet_set_panel_rows(mpdet_handle *h, int64_t rows) {
     return MPDET_OK;
 }
 
-int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c, const int32_t *info_dev,
-                  void *stream) {
+int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c, int32_t *info_dev, void *stream) {
     if (!h || !info_dev) return MPDET_EINVAL;
     const int64_t n = LU.rows;
     if (n < 1 || !mat_ok(LU, true) || !mat_ok(D, true) || !mat_ok(c, true)) return MPDET_EINVAL;
@@ -989,8 +990,8 @@ int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c, const
     for (int64_t j = n - 1; j >= 1; --j) {
         {
             Prof pr(h, s, K_MINORS_SWEEP);
-            hipLaunchKernelGGL(mpk::k_minors_sweep, dim3((unsigned)j), dim3(64), lds, s, lu, cv, info_dev, j, n,
-                               P);
+            hipLaunchKernelGGL(mpk::k_minors_sweep, dim3((unsigned)j), dim3(64 * mpk::team_waves(P)), lds, s, lu, cv,
+                               info_dev, j, n, P);
         }
         rc = last_launch();
         if (rc) return rc;

@@ -66,7 +66,7 @@ __device__ __forceinline__ int top_nonzero(const uint32_t *a, int n) {
     int best = -1;
     for (int q = lane(); q < n; q += MP_WAVE)
         if (a[q]) best = q;
-    return wave_max(best);
+    return __builtin_amdgcn_readfirstlane(wave_max(best));  // the same in every lane
 }
 
 // number of significant bits of a (0 when a == 0)
@@ -238,6 +238,98 @@ __device__ void mul_cols(uint32_t *prod, int ncols, const uint32_t *x, int nx, c
 
 
 // ---------------------------------------------------------------------------
+// Teams: the waves of one workgroup forming the products of one operation
+// together.  Wave 0 runs the operation as a single wave would; for each
+// windowed product (mul_win) it posts the arguments in an LDS command block,
+// and waves 1..nw-1, waiting in team_serve, join it: every wave converts its
+// share of the digits and takes the rounds of 64 windows whose index is its
+// own modulo nw.  Which wave forms a window does not change its bits.  The
+// waves meet at team barriers (an LDS arrival counter); every wait is
+// bounded by wall-clock time, and a wait that runs out sets `fail` (which
+// every later wait sees at once), so a lost wave cannot hang the launch.
+// Wave 0 posts and waits only in uniform control flow and closes the team
+// (team_close) on every path.
+// ---------------------------------------------------------------------------
+struct TeamCtl {
+    uint32_t seq;   // commands posted
+    uint32_t op;    // 1: a product, 0: close
+    uint32_t bar;   // arrivals at team barriers (two per product)
+    uint32_t fail;  // a wait ran out
+    int32_t ncols, nx, ny, unused;
+    uint64_t prod, x, y, ws;  // LDS addresses of the product's operands
+};
+constexpr uint64_t kTeamWaitTicks = 200000000ull;  // 2 s of the 100 MHz wall clock
+
+__device__ __forceinline__ int team_size() { return (int)(blockDim.x / MP_WAVE); }
+__device__ __forceinline__ int team_wave() { return (int)__builtin_amdgcn_readfirstlane(threadIdx.x / MP_WAVE); }
+
+__device__ __forceinline__ uint32_t team_read(const uint32_t *p) {
+    return __builtin_amdgcn_readfirstlane(__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP));
+}
+
+// wait until *p - v >= 0 (mod 2^32); false when it, or an earlier wait, ran out
+__device__ __forceinline__ bool team_wait(TeamCtl *c, const uint32_t *p, uint32_t v) {
+    if (team_read(&c->fail) != 0u) return false;
+    if ((int32_t)(team_read(p) - v) >= 0) return true;
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        __builtin_amdgcn_s_sleep(1);
+        if ((int32_t)(team_read(p) - v) >= 0) return true;
+        if (team_read(&c->fail) != 0u) return false;
+        if (wall_clock64() - t0 > kTeamWaitTicks) {
+            if (lane() == 0) __hip_atomic_store(&c->fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return false;
+        }
+    }
+}
+
+// the team barrier that completes when the arrival count reaches `target`:
+// every wave's LDS writes before it are visible to every wave after it
+__device__ __forceinline__ void team_bar(TeamCtl *c, uint32_t target) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane() == 0) __hip_atomic_fetch_add(&c->bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    (void)team_wait(c, &c->bar, target);
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// every wave, at the start of the kernel: the team is the whole workgroup
+__device__ __forceinline__ void team_open(TeamCtl *c) {
+    if (threadIdx.x == 0) {
+        c->seq = 0u;
+        c->op = 0u;
+        c->bar = 0u;
+        c->fail = 0u;
+    }
+    __syncthreads();
+}
+
+// wave 0: post a command (op 1 with a product's arguments, op 0: close);
+// returns its number (1, 2, ...)
+__device__ __forceinline__ uint32_t team_post(TeamCtl *c, uint32_t op, uint32_t *prod, int ncols, const uint32_t *x,
+                                              int nx, const uint32_t *y, int ny, uint32_t *ws) {
+    const uint32_t cmd = team_read(&c->seq) + 1u;  // wave 0 is the only writer
+    if (lane() == 0) {
+        c->op = op;
+        c->ncols = ncols;
+        c->nx = nx;
+        c->ny = ny;
+        c->prod = (uint64_t)(uintptr_t)prod;
+        c->x = (uint64_t)(uintptr_t)x;
+        c->y = (uint64_t)(uintptr_t)y;
+        c->ws = (uint64_t)(uintptr_t)ws;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    if (lane() == 0) __hip_atomic_store(&c->seq, cmd, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return cmd;
+}
+
+// wave 0, on every path: release the other waves; true when no wait ran out
+__device__ __forceinline__ bool team_close(TeamCtl *c) {
+    if (team_size() > 1) (void)team_post(c, 0u, nullptr, 0, nullptr, 0, nullptr, 0, nullptr);
+    return team_read(&c->fail) == 0u;
+}
+
+// ---------------------------------------------------------------------------
 // The same product in radix 2^28 with register windows (the form every
 // product of a few dozen limbs or more takes).  Both operands are cut into
 // 28-bit digits in LDS, so a digit product is below 2^56 and one
@@ -283,21 +375,28 @@ struct WinGeom {
     __device__ int words() const { return 3 + ov + dx + len; }  // 3: 16-byte alignment of the base
 };
 
-__device__ void mul_win(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *y, int ny,
-                        uint32_t *ws) {
+// One wave's share of the windowed product (tm == nullptr: all of it): the
+// digits t with t / 64 = wv mod nw, then the rounds of 64 windows with the
+// same property; it leaves the window limbs in prod and the overflow vector
+// at the aligned start of ws.  cmd: the product's command number (team
+// barriers 2 cmd - 1 and 2 cmd).
+__device__ __forceinline__ void mul_win_part(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *y,
+                                             int ny, uint32_t *ws, TeamCtl *tm, uint32_t cmd) {
     const WinGeom g(ncols, nx, ny);
+    const int nw = tm ? team_size() : 1, wv = tm ? team_wave() : 0;
     uint32_t *base = (uint32_t *)(((uintptr_t)ws + 15u) & ~(uintptr_t)15u);
     uint32_t *OV = base, *DX = base + g.ov, *DY = DX + g.dx;
-    for (int t = lane(); t < g.dx; t += MP_WAVE) DX[t] = t < g.NXd ? digit_of(x, nx, t) : 0u;
-    for (int t = lane(); t < g.len; t += MP_WAVE) {
+    for (int t = wv * MP_WAVE + lane(); t < g.dx; t += nw * MP_WAVE) DX[t] = t < g.NXd ? digit_of(x, nx, t) : 0u;
+    for (int t = wv * MP_WAVE + lane(); t < g.len; t += nw * MP_WAVE) {
         const int b = g.K - t;
         DY[t] = (b >= 0 && b < g.NYd) ? digit_of(y, ny, b) : 0u;
     }
-    wsync();
+    if (tm) team_bar(tm, (2u * cmd - 1u) * (uint32_t)nw);
+    else wsync();
     // a 16-byte read DY[t..t+3] with t clamped into [lo_c, hi_c]: outside
     // that range every digit it stands for is zero, and so are the clamped words
     const int lo_c = ((g.K - g.NYd + 1) & ~3) - 4, hi_c = g.K + 4;
-    for (int w0 = 0; w0 < g.W; w0 += MP_WAVE) {
+    for (int w0 = wv * MP_WAVE; w0 < g.W; w0 += nw * MP_WAVE) {
         const int w = w0 + lane();
         const int r0 = 8 * w;
         const int wl = min(g.W, w0 + MP_WAVE) - 1;
@@ -373,25 +472,56 @@ __device__ void mul_win(uint32_t *prod, int ncols, const uint32_t *x, int nx, co
             }
         }
     }
-    wsync();
+    if (tm) team_bar(tm, 2u * cmd * (uint32_t)nw);
+    else wsync();
+}
+
+// the waves of team tm (nullptr: this wave alone) form it; called by wave 0
+__device__ void mul_win(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *y, int ny,
+                        uint32_t *ws, TeamCtl *tm = nullptr) {
+    uint32_t cmd = 0u;
+    if (tm != nullptr && team_size() > 1) cmd = team_post(tm, 1u, prod, ncols, x, nx, y, ny, ws);
+    else tm = nullptr;
+    mul_win_part(prod, ncols, x, nx, y, ny, ws, tm, cmd);
+    uint32_t *OV = (uint32_t *)(((uintptr_t)ws + 15u) & ~(uintptr_t)15u);
     add(prod, prod, OV, ncols, 0u);
     wsync();
+}
+
+// waves 1..nw-1 of a team: join wave 0's products until it closes the team
+__device__ __forceinline__ void team_serve(TeamCtl *c) {
+    uint32_t seen = 0u;
+    for (;;) {
+        if (!team_wait(c, &c->seq, seen + 1u)) return;
+        seen += 1u;
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+        if (team_read(&c->op) == 0u) return;
+        auto ptr = [&](const uint64_t *f) -> uint32_t * {
+            const uint32_t *w = (const uint32_t *)f;
+            return (uint32_t *)(uintptr_t)(((uint64_t)team_read(w + 1) << 32) | team_read(w));
+        };
+        const int ncols = (int)team_read((const uint32_t *)&c->ncols);
+        const int nx = (int)team_read((const uint32_t *)&c->nx);
+        const int ny = (int)team_read((const uint32_t *)&c->ny);
+        mul_win_part(ptr(&c->prod), ncols, ptr(&c->x), nx, ptr(&c->y), ny, ptr(&c->ws), c, seen);
+    }
 }
 
 // prod[0..ncols) = (x * y) mod 2^(32 ncols); t0..t3 are one contiguous
 // scratch block of 4 * tsz words (the layouts in use place them so).
 __device__ __forceinline__ void mul_gen(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *ypad,
-                                        int ny, uint32_t *t0, uint32_t *t1, uint32_t *t2, uint32_t *t3, int tsz) {
+                                        int ny, uint32_t *t0, uint32_t *t1, uint32_t *t2, uint32_t *t3, int tsz,
+                                        TeamCtl *tm = nullptr) {
     if (WinGeom(ncols, nx, ny).words() <= 4 * tsz && ncols >= 16)
-        mul_win(prod, ncols, x, nx, ypad + MP_YPAD, ny, t0);
+        mul_win(prod, ncols, x, nx, ypad + MP_YPAD, ny, t0, tm);
     else
         mul_cols(prod, ncols, x, nx, ypad, ny, t0, t1, t2, t3);
 }
 
 // prod[0..2P) = x * y for two P-limb integers
 __device__ __forceinline__ void mul_full(uint32_t *prod, const uint32_t *x, const uint32_t *ypad, int P,
-                                         uint32_t *t0, uint32_t *t1, uint32_t *t2, uint32_t *t3) {
-    mul_gen(prod, 2 * P, x, P, ypad, P, t0, t1, t2, t3, 2 * P + 2);
+                                         uint32_t *t0, uint32_t *t1, uint32_t *t2, uint32_t *t3, TeamCtl *tm = nullptr) {
+    mul_gen(prod, 2 * P, x, P, ypad, P, t0, t1, t2, t3, 2 * P + 2, tm);
 }
 
 // place n limbs of src as the y operand of mul_gen (zero pads around)
@@ -408,6 +538,7 @@ struct Scratch {
     uint32_t *ypad;  // P + 2*MP_YPAD
     uint32_t *prod;  // 2P + 2
     uint32_t *t0, *t1, *t2, *t3;  // 2P + 2 each
+    TeamCtl *team = nullptr;         // the waves that form the products with this one
 };
 
 // Copy n limbs global -> LDS.  Lanes move 16-byte chunks when both sides
@@ -447,7 +578,7 @@ __device__ __forceinline__ void gstore(uint32_t *dst, const uint32_t *src, int n
 __device__ __forceinline__ Hdr load(uint32_t *dst, const uint32_t *src, int64_t e, int32_t s, int P) {
     gload(dst, src, P);
     wsync();
-    bool z = dst[P - 1] == 0u;
+    const bool z = __builtin_amdgcn_readfirstlane(dst[P - 1]) == 0u;
     return z ? zero_hdr() : Hdr{e, s, false};
 }
 
@@ -467,7 +598,7 @@ __device__ __forceinline__ void store(uint32_t *dst_limbs, int64_t *dst_e, int32
 // out = RZ_p(x * y).  x in sc.x, y in sc.ypad + MP_YPAD (pads must be zero).
 __device__ Hdr mul(uint32_t *out, Hdr hx, Hdr hy, int P, const Scratch &sc) {
     if (hx.zero || hy.zero) return zero_hdr();
-    mul_full(sc.prod, sc.x, sc.ypad, P, sc.t0, sc.t1, sc.t2, sc.t3);
+    mul_full(sc.prod, sc.x, sc.ypad, P, sc.t0, sc.t1, sc.t2, sc.t3, sc.team);
     int top = (int)(sc.prod[2 * P - 1] >> 31);
     shift(out, P, sc.prod, 2 * P, -(32LL * P - 1 + top));
     wsync();
@@ -682,6 +813,7 @@ struct DivBufs {
     uint32_t *t0, *t1, *t2, *t3;  // 2P + 4 each
     uint32_t *a;     // P + 4
     uint32_t *v;     // P + 4
+    TeamCtl *team = nullptr;  // the waves that form the products with this one
 };
 
 __host__ __device__ constexpr size_t div_lds_limbs(int P) { return (size_t)(14 * P + 2 * MP_YPAD + 36); }
@@ -728,7 +860,7 @@ __device__ bool recip(const DivBufs &B, int P) {
         }
         wsync();
         const int nT = nV + nX;
-        mul_gen(B.prod, nT, B.x, nX, B.ypad, nV, B.t0, B.t1, B.t2, B.t3, 2 * P + 4);
+        mul_gen(B.prod, nT, B.x, nX, B.ypad, nV, B.t0, B.t1, B.t2, B.t3, 2 * P + 4, B.team);
         // e = 2^(f+g) - T modulo 2^(32 nT): power of two minus the product
         fill(B.t0, nT, 0u);
         wsync();
@@ -749,7 +881,7 @@ __device__ bool recip(const DivBufs &B, int P) {
         set_y(B.ypad, B.prod, ne, max(nV, ne));
         wsync();
         const int nD = nX + ne;
-        mul_gen(B.prod, nD, B.x, nX, B.ypad, ne, B.t0, B.t1, B.t2, B.t3, 2 * P + 4);
+        mul_gen(B.prod, nD, B.x, nX, B.ypad, ne, B.t0, B.t1, B.t2, B.t3, 2 * P + 4, B.team);
         // X' = X 2^(f'-f) +- (X |e|) >> (2f + g - f')
         const int nX2 = limbs_for_bits(f2 + 2) + 1;
         shift(B.t0, nX2, B.x, nX, f2 - f);
@@ -766,7 +898,7 @@ __device__ bool recip(const DivBufs &B, int P) {
     fill(B.x + nX, P + 4 - nX, 0u);
     set_y(B.ypad, B.v, P, P + 4);
     wsync();
-    mul_gen(B.prod, nE, B.x, P + 2, B.ypad, P, B.t0, B.t1, B.t2, B.t3, 2 * P + 4);
+    mul_gen(B.prod, nE, B.x, P + 2, B.ypad, P, B.t0, B.t1, B.t2, B.t3, 2 * P + 4, B.team);
     fill(B.t0, nE, 0u);
     wsync();
     if (lane() == 0) B.t0[2 * P] = 1u;
@@ -820,12 +952,12 @@ __device__ bool div_by_recip(uint32_t *out, Hdr &hq, Hdr ha, Hdr hb, const uint3
         B.ypad[q] = (kq >= 0 && kq < P + 1) ? R[kq] : 0u;
     }
     wsync();
-    mul_gen(B.prod, 2 * P + 1, B.x, P, B.ypad, P + 1, B.t0, B.t1, B.t2, B.t3, 2 * P + 4);
+    mul_gen(B.prod, 2 * P + 1, B.x, P, B.ypad, P + 1, B.t0, B.t1, B.t2, B.t3, 2 * P + 4, B.team);
     shift(B.x, n2, B.prod, 2 * P + 1, -(p - 1));  // Q0 (P + 2 limbs)
     set_y(B.ypad, B.v, P, P + 4);
     wsync();
     // low half of Q0 m_b
-    mul_gen(B.prod, n2, B.x, n2, B.ypad, P, B.t0, B.t1, B.t2, B.t3, 2 * P + 4);
+    mul_gen(B.prod, n2, B.x, n2, B.ypad, P, B.t0, B.t1, B.t2, B.t3, 2 * P + 4, B.team);
     // rem = (m_a 2^(p+1) - Q0 m_b) mod 2^(32 n2)
     shift(B.t0, n2, B.a, P, p + 1);
     fill(B.t1, n2, 0u);
