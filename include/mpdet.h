@@ -315,11 +315,16 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
                    const mpdet_mat *c_arr, int32_t *info_dev, int flags, int path, void *stream);
 
 /*
- * mpdet_set_wait_limit -- bound, in seconds, on every wait of the persistent
- * batched launch (default 10 s; no correct run waits more than one phase of
- * one matrix).  A wait that expires stops the launch: every later ticket is
- * skipped and the matrices it touched report info = -2.  0 makes any wait
- * that is not already satisfied expire (a test of that path).
+ * mpdet_set_wait_limit -- bound, in seconds, on every wait inside a launch
+ * (default 10 s): the persistent batched launch's waits for earlier phases
+ * (no correct run waits more than one phase of one matrix), and the waits
+ * between the waves of one workgroup of the pivot, divide and minors-sweep
+ * kernels above about 224 limbs (no correct run waits more than one
+ * multiprecision product).  A persistent-launch wait that expires stops the
+ * launch: every later ticket is skipped and the matrices it touched report
+ * info = -2.  A workgroup wait that expires makes mp_det_factor and its
+ * variants, mp_det_extend and mp_det_minors report info = -2.  0 makes any
+ * wait that is not already satisfied expire (a test of those paths).
  *   0 <= seconds <= 3600, else MPDET_EINVAL.
  */
 int mpdet_set_wait_limit(mpdet_handle *h, double seconds);

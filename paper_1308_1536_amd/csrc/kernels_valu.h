@@ -272,18 +272,19 @@ __device__ __forceinline__ int64_t flat_block() {
     return (int64_t)blockIdx.x + (int64_t)blockIdx.y * (int64_t)gridDim.x;
 }
 
-// A wave that runs out of a team wait (never in a correct run) stops the
-// factorisation with info = -2 instead of hanging the launch.
+// A wave that runs out of a team wait (never in a correct run: the bound is
+// the handle's wait limit, 10 s by default) stops the factorisation with
+// info = -2 instead of hanging the launch.
 __device__ __forceinline__ void team_report(mpw::TeamCtl *tm, int32_t *info) {
     if (!mpw::team_close(tm) && mpw::lane() == 0) atomicCAS(info, 0, -2);
 }
 
 // blockDim.x = 64 team_waves(P) (or 64: one wave)
 __global__ void __launch_bounds__(256) k_pivot_recip(MatDev A, MatDev D, int32_t *info, uint32_t *rw, int64_t k,
-                                                     int64_t n, int P) {
+                                                     int64_t n, int P, uint64_t wait_ticks) {
     extern __shared__ uint32_t lds_raw[];
     __shared__ mpw::TeamCtl ctl;
-    mpw::team_open(&ctl);
+    mpw::team_open(&ctl, wait_ticks);
     if (mpw::team_wave() != 0) {
         mpw::team_serve(&ctl);
         return;
@@ -303,10 +304,10 @@ __global__ void k_pend_promote(int32_t *info, const uint32_t *rw, int P) {
 
 // blockDim.x = 64 team_waves(P) (or 64: one wave)
 __global__ void __launch_bounds__(256) k_divide(MatDev A, const uint32_t *rw, int32_t *info, int64_t k,
-                                                int64_t n, int P) {
+                                                int64_t n, int P, uint64_t wait_ticks) {
     extern __shared__ uint32_t lds_raw[];
     __shared__ mpw::TeamCtl ctl;
-    mpw::team_open(&ctl);
+    mpw::team_open(&ctl, wait_ticks);
     if (mpw::team_wave() != 0) {
         mpw::team_serve(&ctl);
         return;
@@ -318,10 +319,10 @@ __global__ void __launch_bounds__(256) k_divide(MatDev A, const uint32_t *rw, in
 // multipliers of rows row0 .. n-1 only (growing a factorisation: the rows
 // added after the leading block was factored); blockDim.x as for k_divide
 __global__ void __launch_bounds__(256) k_divide_from(MatDev A, const uint32_t *rw, int32_t *info, int64_t k,
-                                                     int64_t n, int P, int64_t row0) {
+                                                     int64_t n, int P, int64_t row0, uint64_t wait_ticks) {
     extern __shared__ uint32_t lds_raw[];
     __shared__ mpw::TeamCtl ctl;
-    mpw::team_open(&ctl);
+    mpw::team_open(&ctl, wait_ticks);
     if (mpw::team_wave() != 0) {
         mpw::team_serve(&ctl);
         return;
@@ -337,10 +338,10 @@ __global__ void __launch_bounds__(64) k_update_valu(MatDev A, const int32_t *inf
 
 // blockDim.x = 64 team_waves(P) (or 64: one wave)
 __global__ void __launch_bounds__(256) k_minors_sweep(MatDev LU, MatDev c, int32_t *info, int64_t j, int64_t n,
-                                                      int P) {
+                                                      int P, uint64_t wait_ticks) {
     extern __shared__ uint32_t lds_raw[];
     __shared__ mpw::TeamCtl ctl;
-    mpw::team_open(&ctl);
+    mpw::team_open(&ctl, wait_ticks);
     if (mpw::team_wave() != 0) {
         mpw::team_serve(&ctl);
         return;

@@ -77,10 +77,12 @@ struct mpdet_handle {
     // tuning (0: the defaults): rows per workgroup of the VALU lane product
     // (2, 4, 8) and waves per workgroup of the MFMA update (1, 2, 4)
     int32_t lane_rows, mfma_waves;
-    // persistent batched launch: the bound on each of its waits in seconds
-    // (10 s before the first setting)
+    // the bound on each wait inside a launch (the persistent batched launch,
+    // the teams of the step-serial kernels) in seconds (10 s before the first
+    // setting), and the wall clock's rate
     double wait_limit_s;
     bool wait_limit_set;
+    int wall_khz;
 };
 
 namespace {
@@ -88,6 +90,20 @@ namespace {
 constexpr int kMaxLimbs = 1024;
 
 int check(hipError_t e) { return e == hipSuccess ? MPDET_OK : MPDET_EHIP; }
+
+// the handle's wait limit in wall-clock ticks (no handle: 10 s on the
+// current device's clock)
+uint64_t wait_ticks(const mpdet_handle *h) {
+    const double lim_s = h && h->wait_limit_set ? h->wait_limit_s : 10.0;
+    int khz = h ? h->wall_khz : 0;
+    if (khz < 1) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) != hipSuccess || khz < 1)
+            khz = 100000;
+    }
+    return (uint64_t)(lim_s * (double)khz * 1000.0);
+}
 
 bool mat_ok(const mpdet_mat &m, bool need_ptrs) {
     if (m.rows < 0 || m.cols < 0 || m.ld < m.cols || m.nlimbs < 2 || m.nlimbs > kMaxLimbs) return false;
@@ -228,7 +244,7 @@ int pivot_step(mpdet_handle *h, const mpk::MatDev &a, const mpk::MatDev &d, int3
         {
             Prof pr(h, s, K_PIVOT_DIVIDE);
             hipLaunchKernelGGL(mpk::k_pivot_recip, dim3(2), dim3(64 * mpk::team_waves(P)), lds, s, a, d, info, rw,
-                               k, n, P);
+                               k, n, P, wait_ticks(h));
         }
         if ((rc = last_launch())) return rc;
     }
@@ -237,7 +253,7 @@ int pivot_step(mpdet_handle *h, const mpk::MatDev &a, const mpk::MatDev &d, int3
     {
         Prof pr(h, s, K_DIVIDE);
         hipLaunchKernelGGL(mpk::k_divide, dim3((unsigned)m), dim3(64 * mpk::team_waves(P)), lds, s, a,
-                           (const uint32_t *)rw, info, k, n, P);
+                           (const uint32_t *)rw, info, k, n, P, wait_ticks(h));
     }
     return last_launch();
 }
@@ -597,7 +613,9 @@ int mpdet_create(mpdet_handle **h, int device) {
     {
         // resolve the device's scratch address for mp_det_factor_noalloc
         DeviceGuard g(device);
-        if (!g.ok || !scratch_on(device)) {
+        if (!g.ok || !scratch_on(device) ||
+            hipDeviceGetAttribute(&p->wall_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess ||
+            p->wall_khz < 1) {
             free(p);
             return MPDET_EHIP;
         }
@@ -824,10 +842,10 @@ int mp_det_extend(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, 
         for (int64_t k = 0; k < n_old; ++k) {
             // the pivot's reciprocal (D_k is written again with the same bits)
             hipLaunchKernelGGL(mpk::k_pivot_recip, dim3(2), dim3(64 * mpk::team_waves(P)), lds, s, a, d, info_dev,
-                               rw, k, N, P);
+                               rw, k, N, P, wait_ticks(h));
             if ((rc = last_launch())) return rc;
-            hipLaunchKernelGGL(mpk::k_divide_from, dim3((unsigned)(N - n_old)), dim3(64 * mpk::team_waves(P)), lds, s, a,
-                               (const uint32_t *)rw, info_dev, k, N, P, n_old);
+            hipLaunchKernelGGL(mpk::k_divide_from, dim3((unsigned)(N - n_old)), dim3(64 * mpk::team_waves(P)), lds, s,
+                               a, (const uint32_t *)rw, info_dev, k, N, P, n_old, wait_ticks(h));
             if ((rc = last_launch())) return rc;
             // (a) rows n_old.. x columns k+1..: x = column k below, y = row k
             if ((rc = rank1(mpk::Rank1{a, a, a, n_old, k, 1, 0, k, k + 1, 0, 1, n_old, k + 1, N - n_old, N - k - 1, 0})))
@@ -991,7 +1009,7 @@ int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c, int32
         {
             Prof pr(h, s, K_MINORS_SWEEP);
             hipLaunchKernelGGL(mpk::k_minors_sweep, dim3((unsigned)j), dim3(64 * mpk::team_waves(P)), lds, s, lu, cv,
-                               info_dev, j, n, P);
+                               info_dev, j, n, P, wait_ticks(h));
         }
         rc = last_launch();
         if (rc) return rc;

@@ -245,8 +245,9 @@ __device__ void mul_cols(uint32_t *prod, int ncols, const uint32_t *x, int nx, c
 // share of the digits and takes the rounds of 64 windows whose index is its
 // own modulo nw.  Which wave forms a window does not change its bits.  The
 // waves meet at team barriers (an LDS arrival counter); every wait is
-// bounded by wall-clock time, and a wait that runs out sets `fail` (which
-// every later wait sees at once), so a lost wave cannot hang the launch.
+// bounded by wall-clock time (the caller's limit), and a wait that runs out
+// sets `fail` (which every later wait sees at once), so a lost wave cannot
+// hang the launch.
 // Wave 0 posts and waits only in uniform control flow and closes the team
 // (team_close) on every path.
 // ---------------------------------------------------------------------------
@@ -257,8 +258,8 @@ struct TeamCtl {
     uint32_t fail;  // a wait ran out
     int32_t ncols, nx, ny, unused;
     uint64_t prod, x, y, ws;  // LDS addresses of the product's operands
+    uint64_t limit;           // bound on each wait, in wall-clock ticks
 };
-constexpr uint64_t kTeamWaitTicks = 200000000ull;  // 2 s of the 100 MHz wall clock
 
 __device__ __forceinline__ int team_size() { return (int)(blockDim.x / MP_WAVE); }
 __device__ __forceinline__ int team_wave() { return (int)__builtin_amdgcn_readfirstlane(threadIdx.x / MP_WAVE); }
@@ -271,15 +272,17 @@ __device__ __forceinline__ uint32_t team_read(const uint32_t *p) {
 __device__ __forceinline__ bool team_wait(TeamCtl *c, const uint32_t *p, uint32_t v) {
     if (team_read(&c->fail) != 0u) return false;
     if ((int32_t)(team_read(p) - v) >= 0) return true;
+    const uint32_t *lw = (const uint32_t *)&c->limit;
+    const uint64_t limit = ((uint64_t)team_read(lw + 1) << 32) | team_read(lw);
     const uint64_t t0 = wall_clock64();
     for (;;) {
-        __builtin_amdgcn_s_sleep(1);
-        if ((int32_t)(team_read(p) - v) >= 0) return true;
-        if (team_read(&c->fail) != 0u) return false;
-        if (wall_clock64() - t0 > kTeamWaitTicks) {
+        if (wall_clock64() - t0 >= limit) {
             if (lane() == 0) __hip_atomic_store(&c->fail, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             return false;
         }
+        __builtin_amdgcn_s_sleep(1);
+        if ((int32_t)(team_read(p) - v) >= 0) return true;
+        if (team_read(&c->fail) != 0u) return false;
     }
 }
 
@@ -292,13 +295,16 @@ __device__ __forceinline__ void team_bar(TeamCtl *c, uint32_t target) {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
-// every wave, at the start of the kernel: the team is the whole workgroup
-__device__ __forceinline__ void team_open(TeamCtl *c) {
+// every wave, at the start of the kernel: the team is the whole workgroup;
+// limit bounds each wait (wall-clock ticks; 0: any wait not already
+// satisfied runs out)
+__device__ __forceinline__ void team_open(TeamCtl *c, uint64_t limit) {
     if (threadIdx.x == 0) {
         c->seq = 0u;
         c->op = 0u;
         c->bar = 0u;
         c->fail = 0u;
+        c->limit = limit;
     }
     __syncthreads();
 }
