@@ -256,7 +256,7 @@ struct TeamCtl {
     uint32_t op;    // 1: a product, 0: close
     uint32_t bar;   // arrivals at team barriers (two per product)
     uint32_t fail;  // a wait ran out
-    int32_t ncols, nx, ny, unused;
+    int32_t ncols, nx, ny, wlo;
     uint64_t prod, x, y, ws;  // LDS addresses of the product's operands
     uint64_t limit;           // bound on each wait, in wall-clock ticks
 };
@@ -312,13 +312,14 @@ __device__ __forceinline__ void team_open(TeamCtl *c, uint64_t limit) {
 // wave 0: post a command (op 1 with a product's arguments, op 0: close);
 // returns its number (1, 2, ...)
 __device__ __forceinline__ uint32_t team_post(TeamCtl *c, uint32_t op, uint32_t *prod, int ncols, const uint32_t *x,
-                                              int nx, const uint32_t *y, int ny, uint32_t *ws) {
+                                              int nx, const uint32_t *y, int ny, uint32_t *ws, int wlo) {
     const uint32_t cmd = team_read(&c->seq) + 1u;  // wave 0 is the only writer
     if (lane() == 0) {
         c->op = op;
         c->ncols = ncols;
         c->nx = nx;
         c->ny = ny;
+        c->wlo = wlo;
         c->prod = (uint64_t)(uintptr_t)prod;
         c->x = (uint64_t)(uintptr_t)x;
         c->y = (uint64_t)(uintptr_t)y;
@@ -331,7 +332,7 @@ __device__ __forceinline__ uint32_t team_post(TeamCtl *c, uint32_t op, uint32_t 
 
 // wave 0, on every path: release the other waves; true when no wait ran out
 __device__ __forceinline__ bool team_close(TeamCtl *c) {
-    if (team_size() > 1) (void)team_post(c, 0u, nullptr, 0, nullptr, 0, nullptr, 0, nullptr);
+    if (team_size() > 1) (void)team_post(c, 0u, nullptr, 0, nullptr, 0, nullptr, 0, nullptr, 0);
     return team_read(&c->fail) == 0u;
 }
 
@@ -382,12 +383,12 @@ struct WinGeom {
 };
 
 // One wave's share of the windowed product (tm == nullptr: all of it): the
-// digits t with t / 64 = wv mod nw, then the rounds of 64 windows with the
-// same property; it leaves the window limbs in prod and the overflow vector
-// at the aligned start of ws.  cmd: the product's command number (team
-// barriers 2 cmd - 1 and 2 cmd).
+// digits t with t / 64 = wv mod nw, then the rounds of 64 windows from window
+// wlo on with the same property; it leaves the window limbs in prod and the
+// overflow vector at the aligned start of ws.  cmd: the product's command
+// number (team barriers 2 cmd - 1 and 2 cmd).
 __device__ __forceinline__ void mul_win_part(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *y,
-                                             int ny, uint32_t *ws, TeamCtl *tm, uint32_t cmd) {
+                                             int ny, uint32_t *ws, TeamCtl *tm, uint32_t cmd, int wlo) {
     const WinGeom g(ncols, nx, ny);
     const int nw = tm ? team_size() : 1, wv = tm ? team_wave() : 0;
     uint32_t *base = (uint32_t *)(((uintptr_t)ws + 15u) & ~(uintptr_t)15u);
@@ -402,7 +403,7 @@ __device__ __forceinline__ void mul_win_part(uint32_t *prod, int ncols, const ui
     // a 16-byte read DY[t..t+3] with t clamped into [lo_c, hi_c]: outside
     // that range every digit it stands for is zero, and so are the clamped words
     const int lo_c = ((g.K - g.NYd + 1) & ~3) - 4, hi_c = g.K + 4;
-    for (int w0 = wv * MP_WAVE; w0 < g.W; w0 += nw * MP_WAVE) {
+    for (int w0 = wlo + wv * MP_WAVE; w0 < g.W; w0 += nw * MP_WAVE) {
         const int w = w0 + lane();
         const int r0 = 8 * w;
         const int wl = min(g.W, w0 + MP_WAVE) - 1;
@@ -472,9 +473,9 @@ __device__ __forceinline__ void mul_win_part(uint32_t *prod, int ncols, const ui
 #pragma unroll
             for (int i = 2; i < 9; ++i)
                 if (q0 + i < ncols) OV[q0 + i] = i >= 7 ? L[i] : 0u;
-            if (w == 0) {
-                OV[0] = 0u;
-                if (ncols > 1) OV[1] = 0u;
+            if (w == wlo) {  // nothing carries in from below the first window
+                OV[q0] = 0u;
+                if (q0 + 1 < ncols) OV[q0 + 1] = 0u;
             }
         }
     }
@@ -482,15 +483,20 @@ __device__ __forceinline__ void mul_win_part(uint32_t *prod, int ncols, const ui
     else wsync();
 }
 
-// the waves of team tm (nullptr: this wave alone) form it; called by wave 0
+// the waves of team tm (nullptr: this wave alone) form it; called by wave 0.
+// wlo > 0 (7 wlo < ncols): only the digit columns from 8 wlo on are formed, so
+// limbs 7 wlo .. ncols - 1 of prod hold (x y - E) / 2^(224 wlo) mod
+// 2^(32 (ncols - 7 wlo)) for the dropped part 0 <= E < 2^(224 wlo) m 2^56
+// (m: digits of the shorter operand), and limbs below 7 wlo are left as they
+// are.
 __device__ void mul_win(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *y, int ny,
-                        uint32_t *ws, TeamCtl *tm = nullptr) {
+                        uint32_t *ws, TeamCtl *tm = nullptr, int wlo = 0) {
     uint32_t cmd = 0u;
-    if (tm != nullptr && team_size() > 1) cmd = team_post(tm, 1u, prod, ncols, x, nx, y, ny, ws);
+    if (tm != nullptr && team_size() > 1) cmd = team_post(tm, 1u, prod, ncols, x, nx, y, ny, ws, wlo);
     else tm = nullptr;
-    mul_win_part(prod, ncols, x, nx, y, ny, ws, tm, cmd);
+    mul_win_part(prod, ncols, x, nx, y, ny, ws, tm, cmd, wlo);
     uint32_t *OV = (uint32_t *)(((uintptr_t)ws + 15u) & ~(uintptr_t)15u);
-    add(prod, prod, OV, ncols, 0u);
+    add(prod + 7 * wlo, prod + 7 * wlo, OV + 7 * wlo, ncols - 7 * wlo, 0u);
     wsync();
 }
 
@@ -509,17 +515,20 @@ __device__ __forceinline__ void team_serve(TeamCtl *c) {
         const int ncols = (int)team_read((const uint32_t *)&c->ncols);
         const int nx = (int)team_read((const uint32_t *)&c->nx);
         const int ny = (int)team_read((const uint32_t *)&c->ny);
-        mul_win_part(ptr(&c->prod), ncols, ptr(&c->x), nx, ptr(&c->y), ny, ptr(&c->ws), c, seen);
+        const int wlo = (int)team_read((const uint32_t *)&c->wlo);
+        mul_win_part(ptr(&c->prod), ncols, ptr(&c->x), nx, ptr(&c->y), ny, ptr(&c->ws), c, seen, wlo);
     }
 }
 
 // prod[0..ncols) = (x * y) mod 2^(32 ncols); t0..t3 are one contiguous
 // scratch block of 4 * tsz words (the layouts in use place them so).
+// wlo: as for mul_win (the column form forms every column, which is always
+// allowed)
 __device__ __forceinline__ void mul_gen(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *ypad,
                                         int ny, uint32_t *t0, uint32_t *t1, uint32_t *t2, uint32_t *t3, int tsz,
-                                        TeamCtl *tm = nullptr) {
+                                        TeamCtl *tm = nullptr, int wlo = 0) {
     if (WinGeom(ncols, nx, ny).words() <= 4 * tsz && ncols >= 16)
-        mul_win(prod, ncols, x, nx, ypad + MP_YPAD, ny, t0, tm);
+        mul_win(prod, ncols, x, nx, ypad + MP_YPAD, ny, t0, tm, wlo);
     else
         mul_cols(prod, ncols, x, nx, ypad, ny, t0, t1, t2, t3);
 }
@@ -939,10 +948,13 @@ __device__ bool recip(const DivBufs &B, int P) {
 
 // out = RZ_p(a / b) given R = floor(2^(2p) / m_b) (P + 1 limbs, in global
 // memory).  Q = floor(m_a 2^(p+1) / m_b) lies in [Q0, Q0 + 2] for
-// Q0 = floor(m_a R / 2^(p-1)); the remainder m_a 2^(p+1) - Q0 m_b, formed
-// modulo 2^(32(P+2)) from the low half of Q0 m_b, moves Q0 up to Q.  a (P
-// limbs) must be in B.a, b in B.v.  Returns false if the remainder check did
-// not settle (callers then fall back to long division).
+// Q0 = floor(m_a R / 2^(p-1)).  The product m_a R is formed only from digit
+// window wlo on (mul_win), which leaves out less than 2^(p-1), so the Q0' it
+// gives is Q0 or Q0 - 1 and Q lies in [Q0', Q0' + 3]; the remainder
+// m_a 2^(p+1) - Q0' m_b (in [0, 4 m_b)), formed modulo 2^(32(P+2)) from the
+// low half of Q0' m_b, moves Q0' up to Q.  a (P limbs) must be in B.a, b in
+// B.v.  Returns false if the remainder check did not settle (callers then fall
+// back to long division).
 __device__ bool div_by_recip(uint32_t *out, Hdr &hq, Hdr ha, Hdr hb, const uint32_t *R, const DivBufs &B,
                              int P) {
     const int64_t p = 32LL * P;
@@ -958,8 +970,12 @@ __device__ bool div_by_recip(uint32_t *out, Hdr &hq, Hdr ha, Hdr hb, const uint3
         B.ypad[q] = (kq >= 0 && kq < P + 1) ? R[kq] : 0u;
     }
     wsync();
-    mul_gen(B.prod, 2 * P + 1, B.x, P, B.ypad, P + 1, B.t0, B.t1, B.t2, B.t3, 2 * P + 4, B.team);
-    shift(B.x, n2, B.prod, 2 * P + 1, -(p - 1));  // Q0 (P + 2 limbs)
+    // windows below wlo hold digit columns below 8 wlo: what they leave out is
+    // below 2^(224 wlo + 68) <= 2^(p - 1) (column sums below 2^67 for up to
+    // 2^11 digits), and the limbs read below (from P - 1 on) are above 7 wlo
+    const int wlo = P <= 1024 ? max(0, (32 * P - 69) / 224) : 0;
+    mul_gen(B.prod, 2 * P + 1, B.x, P, B.ypad, P + 1, B.t0, B.t1, B.t2, B.t3, 2 * P + 4, B.team, wlo);
+    shift(B.x, n2, B.prod, 2 * P + 1, -(p - 1));  // Q0' (P + 2 limbs)
     set_y(B.ypad, B.v, P, P + 4);
     wsync();
     // low half of Q0 m_b
@@ -974,7 +990,7 @@ __device__ bool div_by_recip(uint32_t *out, Hdr &hq, Hdr ha, Hdr hb, const uint3
     if (lane() == 0) B.t2[0] = 1u;
     wsync();
     bool ok = false;
-    for (int it = 0; it < 4; ++it) {
+    for (int it = 0; it < 6; ++it) {
         if ((B.t0[n2 - 1] >> 31) != 0u) break;  // negative: R was not exact
         if (cmp(B.t0, B.t1, n2) < 0) {
             ok = true;
