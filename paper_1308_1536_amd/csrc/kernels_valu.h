@@ -73,6 +73,11 @@ __host__ __device__ inline size_t pivot_lds_bytes(int P) {
     return a > b ? a : b;
 }
 
+// LDS of k_divide (and k_divide_from): the lean layout from 16 limbs on
+__host__ __device__ inline size_t divide_lds_bytes(int P) {
+    return P >= 16 ? mpw::div_lean_words(P) * 4u : pivot_lds_bytes(P);
+}
+
 // Waves of k_pivot_recip, k_divide and k_minors_sweep (a team, see
 // wave_mp.h): one per round
 // of 64 windows of a P x P product, at most 4 (one below 224 limbs or so).
@@ -151,6 +156,19 @@ __device__ __forceinline__ void divide_body(uint32_t *lds_raw, MatDev A, const u
     if (uni(pm[P - 1]) == 0u) return;
     const int64_t i = k + 1 + blk;
     uint32_t *am = el(A, i, k, P);
+    if (P >= 16) {  // the lean layout (divide_lds_bytes)
+        mpw::DivLean L = mpw::div_lean(lds_raw, P);
+        L.team = tm;
+        mpw::Hdr ha = mpw::load(L.a, am, ex(A, i, k), sg(A, i, k), P);
+        mpw::Hdr hp = mpw::load(L.v, pm, ex(A, k, k), sg(A, k, k), P);
+        mpw::Hdr hq;
+        bool done = false;
+        if (uni(rw[P + 1]) != 0u) done = mpw::div_by_recip_lean(hq, ha, hp, rw, L, P);
+        // long division: U = prod (2P+2), Q = the scratch's first P + 2 words
+        if (!done) hq = mpw::div(L.out, L.a, ha, L.v, hp, L.prod, L.ws, L.ws, L.ws, P);
+        mpw::store(am, &ex(A, i, k), &sg(A, i, k), L.out, hq, P);
+        return;
+    }
     mpw::DivBufs B = mpw::div_bufs(lds_raw, P);
     B.team = tm;
     mpw::Hdr ha = mpw::load(B.a, am, ex(A, i, k), sg(A, i, k), P);

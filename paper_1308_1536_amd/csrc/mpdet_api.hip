@@ -252,7 +252,7 @@ int pivot_step(mpdet_handle *h, const mpk::MatDev &a, const mpk::MatDev &d, int3
     if (m <= 0) return MPDET_OK;
     {
         Prof pr(h, s, K_DIVIDE);
-        hipLaunchKernelGGL(mpk::k_divide, dim3((unsigned)m), dim3(64 * mpk::team_waves(P)), lds, s, a,
+        hipLaunchKernelGGL(mpk::k_divide, dim3((unsigned)m), dim3(64 * mpk::team_waves(P)), mpk::divide_lds_bytes(P), s, a,
                            (const uint32_t *)rw, info, k, n, P, wait_ticks(h));
     }
     return last_launch();
@@ -844,7 +844,8 @@ int mp_det_extend(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, 
             hipLaunchKernelGGL(mpk::k_pivot_recip, dim3(2), dim3(64 * mpk::team_waves(P)), lds, s, a, d, info_dev,
                                rw, k, N, P, wait_ticks(h));
             if ((rc = last_launch())) return rc;
-            hipLaunchKernelGGL(mpk::k_divide_from, dim3((unsigned)(N - n_old)), dim3(64 * mpk::team_waves(P)), lds, s,
+            hipLaunchKernelGGL(mpk::k_divide_from, dim3((unsigned)(N - n_old)), dim3(64 * mpk::team_waves(P)),
+                               mpk::divide_lds_bytes(P), s,
                                a, (const uint32_t *)rw, info_dev, k, N, P, n_old, wait_ticks(h));
             if ((rc = last_launch())) return rc;
             // (a) rows n_old.. x columns k+1..: x = column k below, y = row k

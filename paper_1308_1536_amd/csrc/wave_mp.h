@@ -366,6 +366,14 @@ __device__ __forceinline__ uint32_t digit_of(const uint32_t *a, int n, int d) {
     return v & kDigMask;
 }
 
+// WinGeom(ncols, nx, ny).words(), also on the host
+__host__ __device__ constexpr int win_words(int ncols, int nx, int ny) {
+    const int nc = (32 * ncols + 27) / 28;
+    const int nxd = (32 * nx + 27) / 28 < nc ? (32 * nx + 27) / 28 : nc;
+    const int nyd = (32 * ny + 27) / 28 < nc ? (32 * ny + 27) / 28 : nc;
+    return 3 + ((ncols + 3) & ~3) + ((nxd + 15 + 3) & ~3) + ((nyd + 3 + 3) & ~3) + 8;
+}
+
 struct WinGeom {
     int NC, NXd, NYd, W;   // digit columns, digits of x and y taken, windows
     int ov, dx, K, len;    // words: overflow vector, x digits, reversed y (DYR[K - b] = y_b), its length
@@ -489,7 +497,7 @@ __device__ __forceinline__ void mul_win_part(uint32_t *prod, int ncols, const ui
 // 2^(32 (ncols - 7 wlo)) for the dropped part 0 <= E < 2^(224 wlo) m 2^56
 // (m: digits of the shorter operand), and limbs below 7 wlo are left as they
 // are.
-__device__ void mul_win(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *y, int ny,
+__device__ __forceinline__ void mul_win(uint32_t *prod, int ncols, const uint32_t *x, int nx, const uint32_t *y, int ny,
                         uint32_t *ws, TeamCtl *tm = nullptr, int wlo = 0) {
     uint32_t cmd = 0u;
     if (tm != nullptr && team_size() > 1) cmd = team_post(tm, 1u, prod, ncols, x, nx, y, ny, ws, wlo);
@@ -1002,6 +1010,81 @@ __device__ bool div_by_recip(uint32_t *out, Hdr &hq, Hdr ha, Hdr hb, const uint3
     }
     if (!ok) return false;
     hq = normalise(out, B.x, n2, ha.e - hb.e - p - 1, ha.s ^ hb.s, P);
+    return true;
+}
+
+// The multipliers' own layout (k_divide): a, v, Q0 and the product in LDS,
+// the windowed products' scratch (digits, overflow vector) reused afterwards
+// for the remainder, v padded, one, the quotient and the result; R is read
+// from global memory where the digits are formed.  About 9.3P words against
+// the 14P of DivBufs, so twice as many workgroups of the launch share a CU.
+// Needs P >= 16 (every product windowed).
+struct DivLean {
+    uint32_t *a, *v, *x;  // P + 4 each (x: Q0, P + 2 limbs)
+    uint32_t *prod;       // 2P + 4
+    uint32_t *ws;         // ws_words(P): the products' scratch, then t0 t1 t2 (P + 2 each) and out (P)
+    uint32_t *out;
+    TeamCtl *team = nullptr;
+};
+__host__ __device__ constexpr int div_lean_ws_words(int P) {
+    const int w = win_words(2 * P + 1, P, P + 1), t = 4 * P + 8;
+    return ((w > t ? w : t) + 3) & ~3;
+}
+__host__ __device__ constexpr size_t div_lean_words(int P) {
+    return (size_t)(3 * ((P + 4 + 3) & ~3) + ((2 * P + 4 + 3) & ~3) + div_lean_ws_words(P));
+}
+__device__ __forceinline__ DivLean div_lean(uint32_t *base, int P) {
+    const int n1 = (P + 4 + 3) & ~3, n2 = (2 * P + 4 + 3) & ~3;
+    DivLean L;
+    L.a = base;
+    L.v = L.a + n1;
+    L.x = L.v + n1;
+    L.prod = L.x + n1;
+    L.ws = L.prod + n2;
+    L.out = L.ws + 3 * (P + 2);
+    return L;
+}
+
+// div_by_recip on the lean layout: the same steps and bits.  a in L.a, b in
+// L.v; the quotient goes to L.out.
+__device__ bool div_by_recip_lean(Hdr &hq, Hdr ha, Hdr hb, const uint32_t *R, const DivLean &L, int P) {
+    const int64_t p = 32LL * P;
+    if (ha.zero) {
+        hq = zero_hdr();
+        return true;
+    }
+    const int n2 = P + 2;
+    // Q0' = (m_a R) >> (p - 1), the product from digit window wlo on (the bound
+    // as in div_by_recip)
+    const int wlo = P <= 1024 ? max(0, (32 * P - 69) / 224) : 0;
+    mul_win(L.prod, 2 * P + 1, L.a, P, R, P + 1, L.ws, L.team, wlo);
+    shift(L.x, n2, L.prod, 2 * P + 1, -(p - 1));
+    wsync();
+    // low half of Q0' m_b
+    mul_win(L.prod, n2, L.x, n2, L.v, P, L.ws, L.team);
+    // rem = (m_a 2^(p+1) - Q0' m_b) mod 2^(32 n2), in [0, 4 m_b)
+    uint32_t *t0 = L.ws, *t1 = t0 + n2, *t2 = t1 + n2;
+    shift(t0, n2, L.a, P, p + 1);
+    fill(t1, n2, 0u);
+    fill(t2, n2, 0u);
+    wsync();
+    sub(t0, t0, L.prod, n2, 0u);
+    copy(t1, L.v, P);  // v padded to n2 limbs
+    if (lane() == 0) t2[0] = 1u;
+    wsync();
+    bool ok = false;
+    for (int it = 0; it < 6; ++it) {
+        if ((t0[n2 - 1] >> 31) != 0u) break;  // negative: R was not exact
+        if (cmp(t0, t1, n2) < 0) {
+            ok = true;
+            break;
+        }
+        add(L.x, L.x, t2, n2, 0u);
+        sub(t0, t0, t1, n2, 0u);
+        wsync();
+    }
+    if (!ok) return false;
+    hq = normalise(L.out, L.x, n2, ha.e - hb.e - p - 1, ha.s ^ hb.s, P);
     return true;
 }
 
