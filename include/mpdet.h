@@ -330,6 +330,18 @@ int mp_det_batched(mpdet_handle *h, int64_t batch, const mpdet_mat *A_arr, const
 int mpdet_set_wait_limit(mpdet_handle *h, double seconds);
 
 /*
+ * mpdet_set_long_division -- 1: the single-matrix calls (mp_det_factor and
+ * its variants, mp_det_extend) form every multiplier l_ik = RZ_p(a_ik / a_kk)
+ * (Algorithm 1 step 2.2.1) by long division (Knuth's Algorithm D on one wave,
+ * the path the shared reciprocal's exact remainder check otherwise takes only
+ * when it does not settle); 0 (the default): through the pivot's reciprocal.
+ * Both give the exact RZ_p quotient, so the bits are the same; long division
+ * is slower.  It lets a test reach the fallback.
+ *   on is 0 or 1, else MPDET_EINVAL.
+ */
+int mpdet_set_long_division(mpdet_handle *h, int32_t on);
+
+/*
  * mpdet_batched_plan -- the persistent launch's schedule for matrices of sizes
  * n_host[0..batch) (host only; touches no device): *nrec phase records and
  * *ntickets tickets (a lane-product ticket is one tile for the whole

@@ -102,6 +102,7 @@ def lib() -> ctypes.CDLL:
                                      ctypes.POINTER(MpdetMat), vp, ctypes.c_int, ctypes.c_int, vp]
         L.mp_det_batched.restype = ctypes.c_int
         L.mpdet_set_wait_limit.argtypes = [vp, ctypes.c_double]
+        L.mpdet_set_long_division.argtypes = [vp, i32]
         L.mpdet_set_wait_limit.restype = ctypes.c_int
         L.mpdet_batched_plan.argtypes = [i64, ctypes.POINTER(ctypes.c_int64), i32, ctypes.c_int, ctypes.c_int, vp, i64,
                                          ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]
@@ -472,6 +473,13 @@ def batched_plan(sizes, P: int, path: str = "auto", minors: bool = True):
     _check("mpdet_batched_plan", lib().mpdet_batched_plan(B, n, int(P), pid, flags, out.ctypes.data, nrec.value,
                                                           ctypes.byref(nrec), ctypes.byref(nt)))
     return out, nt.value
+
+
+def set_long_division(on: bool, device: int = 0):
+    """mpdet_set_long_division on the device's handle: every multiplier of the
+    single-matrix calls by long division instead of the pivot's reciprocal
+    (the same bits; the reciprocal's fallback path)."""
+    _check("mpdet_set_long_division", lib().mpdet_set_long_division(handle(device).ptr, 1 if on else 0))
 
 
 def set_wait_limit(seconds: float, device: int = 0):

@@ -144,9 +144,11 @@ __device__ __forceinline__ void pivot_recip_body(uint32_t *lds_raw, MatDev A, Ma
 
 // rw[P + 2] is the pending code of step k's pivot when that pivot was
 // examined inside the previous step's launch: a nonzero code stops the step,
-// and block 0 moves it into info for the launches that follow.
+// and block 0 moves it into info for the launches that follow.  long_div:
+// every row by long division (the reciprocal's fallback; same bits).
 __device__ __forceinline__ void divide_body(uint32_t *lds_raw, MatDev A, const uint32_t *rw, int32_t *info, int64_t k,
-                                            int64_t n, int P, int64_t blk, mpw::TeamCtl *tm = nullptr) {
+                                            int64_t n, int P, int64_t blk, mpw::TeamCtl *tm = nullptr,
+                                            bool long_div = false) {
     const int32_t pend = (int32_t)uni(rw[P + 2]);
     if (uni((uint32_t)*info) != 0u || pend != 0) {
         if (blk == 0 && mpw::lane() == 0 && *info == 0) *info = pend;
@@ -163,7 +165,7 @@ __device__ __forceinline__ void divide_body(uint32_t *lds_raw, MatDev A, const u
         mpw::Hdr hp = mpw::load(L.v, pm, ex(A, k, k), sg(A, k, k), P);
         mpw::Hdr hq;
         bool done = false;
-        if (uni(rw[P + 1]) != 0u) done = mpw::div_by_recip_lean(hq, ha, hp, rw, L, P);
+        if (!long_div && uni(rw[P + 1]) != 0u) done = mpw::div_by_recip_lean(hq, ha, hp, rw, L, P);
         // long division: U = prod (2P+2), Q = the scratch's first P + 2 words
         if (!done) hq = mpw::div(L.out, L.a, ha, L.v, hp, L.prod, L.ws, L.ws, L.ws, P);
         mpw::store(am, &ex(A, i, k), &sg(A, i, k), L.out, hq, P);
@@ -175,7 +177,7 @@ __device__ __forceinline__ void divide_body(uint32_t *lds_raw, MatDev A, const u
     mpw::Hdr hp = mpw::load(B.v, pm, ex(A, k, k), sg(A, k, k), P);
     mpw::Hdr hq;
     bool done = false;
-    if (uni(rw[P + 1]) != 0u) done = mpw::div_by_recip(B.t3, hq, ha, hp, rw, B, P);
+    if (!long_div && uni(rw[P + 1]) != 0u) done = mpw::div_by_recip(B.t3, hq, ha, hp, rw, B, P);
     if (!done) {
         // long division: U = prod (2P+2), LO = t0, HI = t1, Q = t2, out = t3
         hq = mpw::div(B.t3, B.a, ha, B.v, hp, B.prod, B.t0, B.t1, B.t2, P);
@@ -322,7 +324,7 @@ __global__ void k_pend_promote(int32_t *info, const uint32_t *rw, int P) {
 
 // blockDim.x = 64 team_waves(P) (or 64: one wave)
 __global__ void __launch_bounds__(256) k_divide(MatDev A, const uint32_t *rw, int32_t *info, int64_t k,
-                                                int64_t n, int P, uint64_t wait_ticks) {
+                                                int64_t n, int P, uint64_t wait_ticks, int long_div) {
     extern __shared__ uint32_t lds_raw[];
     __shared__ mpw::TeamCtl ctl;
     mpw::team_open(&ctl, wait_ticks);
@@ -330,14 +332,15 @@ __global__ void __launch_bounds__(256) k_divide(MatDev A, const uint32_t *rw, in
         mpw::team_serve(&ctl);
         return;
     }
-    divide_body(lds_raw, A, rw, info, k, n, P, flat_block(), &ctl);
+    divide_body(lds_raw, A, rw, info, k, n, P, flat_block(), &ctl, long_div != 0);
     team_report(&ctl, info);
 }
 
 // multipliers of rows row0 .. n-1 only (growing a factorisation: the rows
 // added after the leading block was factored); blockDim.x as for k_divide
 __global__ void __launch_bounds__(256) k_divide_from(MatDev A, const uint32_t *rw, int32_t *info, int64_t k,
-                                                     int64_t n, int P, int64_t row0, uint64_t wait_ticks) {
+                                                     int64_t n, int P, int64_t row0, uint64_t wait_ticks,
+                                                     int long_div) {
     extern __shared__ uint32_t lds_raw[];
     __shared__ mpw::TeamCtl ctl;
     mpw::team_open(&ctl, wait_ticks);
@@ -345,7 +348,7 @@ __global__ void __launch_bounds__(256) k_divide_from(MatDev A, const uint32_t *r
         mpw::team_serve(&ctl);
         return;
     }
-    divide_body(lds_raw, A, rw, info, k, n, P, row0 - k - 1 + (int64_t)blockIdx.x, &ctl);
+    divide_body(lds_raw, A, rw, info, k, n, P, row0 - k - 1 + (int64_t)blockIdx.x, &ctl, long_div != 0);
     team_report(&ctl, info);
 }
 

@@ -83,6 +83,8 @@ struct mpdet_handle {
     double wait_limit_s;
     bool wait_limit_set;
     int wall_khz;
+    // every multiplier by long division (mpdet_set_long_division)
+    int32_t long_div;
 };
 
 namespace {
@@ -253,7 +255,7 @@ int pivot_step(mpdet_handle *h, const mpk::MatDev &a, const mpk::MatDev &d, int3
     {
         Prof pr(h, s, K_DIVIDE);
         hipLaunchKernelGGL(mpk::k_divide, dim3((unsigned)m), dim3(64 * mpk::team_waves(P)), mpk::divide_lds_bytes(P), s, a,
-                           (const uint32_t *)rw, info, k, n, P, wait_ticks(h));
+                           (const uint32_t *)rw, info, k, n, P, wait_ticks(h), h ? h->long_div : 0);
     }
     return last_launch();
 }
@@ -846,7 +848,7 @@ int mp_det_extend(mpdet_handle *h, mpdet_mat A, mpdet_mat D, int32_t *info_dev, 
             if ((rc = last_launch())) return rc;
             hipLaunchKernelGGL(mpk::k_divide_from, dim3((unsigned)(N - n_old)), dim3(64 * mpk::team_waves(P)),
                                mpk::divide_lds_bytes(P), s,
-                               a, (const uint32_t *)rw, info_dev, k, N, P, n_old, wait_ticks(h));
+                               a, (const uint32_t *)rw, info_dev, k, N, P, n_old, wait_ticks(h), h->long_div);
             if ((rc = last_launch())) return rc;
             // (a) rows n_old.. x columns k+1..: x = column k below, y = row k
             if ((rc = rank1(mpk::Rank1{a, a, a, n_old, k, 1, 0, k, k + 1, 0, 1, n_old, k + 1, N - n_old, N - k - 1, 0})))
@@ -1278,6 +1280,12 @@ int mpdet_set_tuning(mpdet_handle *h, int32_t lane_rows, int32_t mfma_waves) {
     if (mfma_waves != 0 && mfma_waves != 1 && mfma_waves != 2 && mfma_waves != 4) return MPDET_EINVAL;
     h->lane_rows = lane_rows;
     h->mfma_waves = mfma_waves;
+    return MPDET_OK;
+}
+
+int mpdet_set_long_division(mpdet_handle *h, int32_t on) {
+    if (!h || (on != 0 && on != 1)) return MPDET_EINVAL;
+    h->long_div = on;
     return MPDET_OK;
 }
 

@@ -78,6 +78,8 @@ def test_null_handle_and_bad_args_rejected_on_host(lib):
     bad = binding.MpdetMat(None, None, None, 4, 5, 5, 8)  # not square
     assert lib.mp_det_factor_noalloc(bad, m, 8, 0, None) == binding.MPDET_EINVAL
     assert lib.mpdet_destroy(None) == binding.MPDET_EINVAL
+    assert lib.mpdet_set_long_division(None, 1) == binding.MPDET_EINVAL
+    assert lib.mpdet_set_wait_limit(None, 1.0) == binding.MPDET_EINVAL
 
 
 def test_create_without_gpu_fails_cleanly(lib):

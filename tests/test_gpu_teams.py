@@ -88,3 +88,25 @@ def test_team_waits_run_out_into_info():
     assert_same(D2, f.D, "D")
     assert_same(LU, f.LU, "LU")
     assert_same(c, cw, "c")
+
+
+@pytest.mark.parametrize("P", [8, 64, 264, 1024])
+def test_long_division_fallback_against_oracle(P):
+    """Every multiplier by long division (the shared reciprocal's fallback),
+    on the general layout (8 limbs) and the divide's lean one (64, 264 with a
+    team of two, 1024 with four): the oracle's bits, and the same bits as the
+    reciprocal path."""
+    from paper_1308_1536_amd import binding
+    N = 14
+    A = inputs.random_mantissas((N, N), P, 7500 + P)
+    say(f"[long division] P={P} N={N}")
+    binding.set_long_division(True)
+    try:
+        LU, D, c, info = gpu_det(A, "mfma" if P % 8 == 0 and P > 64 else "valu")
+    finally:
+        binding.set_long_division(False)
+    f, cw = oracle.det_pipeline(A)
+    assert info == f.info == 0
+    assert_same(D, f.D, "D")
+    assert_same(LU, f.LU, "LU")
+    assert_same(c, cw, "c")
