@@ -304,8 +304,13 @@ int mp_det_minors(mpdet_handle *h, mpdet_mat LU, mpdet_mat D, mpdet_mat c,
  *     tickets shows every earlier phase of that matrix done, so a matrix never
  *     waits for another.  Two small launches around it reset the counters and
  *     turn expired waits into info = -2.  Every wait is bounded.
- *   MPDET_BATCH_LOCKSTEP names the default explicitly.  Which is faster depends
- *   on the batch (the autotuner measures both).
+ *   MPDET_BATCH_LOCKSTEP names the default explicitly.
+ *   Known defect: on config 4's batch (256 matrices, N up to 384, 2048 bits)
+ *   the persistent launch has given a result different from the lockstep
+ *   launches' (and the oracle's) for one or two large matrices in about a
+ *   third of the runs, at one of their last 30 steps; small batches have
+ *   matched in every run.  Until it is found, use the lockstep default where
+ *   the bits matter (the autotuner does not choose the persistent launch).
  * The descriptor and schedule tables are staged through pinned host memory
  * owned by the handle; per-matrix scratch lives in the handle's device
  * workspace.

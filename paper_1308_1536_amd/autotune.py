@@ -9,8 +9,9 @@ order whatever the tiling), so tuning only changes speed.  Candidates:
   per workgroup;
 - the MFMA update's waves (= rows of one 32-column block) per workgroup: 1, 2
   or 4 (where their LDS fits);
-- for a batch, the schedule: one launch per phase per step (lockstep) or one
-  persistent launch over a task queue (VALU path).
+- for a batch, the schedule: one launch per phase per step (lockstep; the
+  persistent launch over a task queue is left out while a defect in it on
+  large batches is open).
 For a key (arch, limbs P, size bucket[, batch]) the tuner times the
 candidates on seeded random-mantissa matrices of the bucket's size (capped)
 and caches the fastest in a JSON file (``MPDET_AUTOTUNE_CACHE``, default
@@ -71,14 +72,13 @@ def mfma_waves_ok(P: int, waves: int) -> bool:
 def candidates(P: int, batch: bool = False) -> list[dict]:
     """Every launch configuration to try for P-limb numbers."""
     out = []
+    # (the persistent schedule is not a candidate: on config 4's batch it has
+    # given a different result for one or two large matrices in some runs, a
+    # defect not found yet; `batch` keeps the signature for when it returns)
     if lane_ok(P):
         out += [{"path": "valu", "lane_rows": r} for r in LANE_ROWS]
-        if batch:
-            out.append({"path": "valu", "lane_rows": 4, "schedule": "persistent"})
     else:
         out.append({"path": "valu", "lane_rows": 0})
-        if batch:
-            out.append({"path": "valu", "lane_rows": 0, "schedule": "persistent"})
     out += [{"path": "mfma", "mfma_waves": w} for w in MFMA_WAVES if mfma_waves_ok(P, w)]
     return out
 
